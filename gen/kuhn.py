@@ -1,0 +1,316 @@
+"""Structured Kuhn-tetrahedra box meshes and P1 finite element assembly.
+
+Mesh: vertex (i, j, k) of an ``nx x ny x nz`` grid with spacing ``h`` has id
+``v = i + nx*(j + ny*k)`` and position ``(i h, j h, k h)``.  Each grid cell with
+lower corner ``o`` is split into the six Kuhn tetrahedra
+``(o, o+e_p0, o+e_p0+e_p1, o+(1,1,1))``, one per permutation ``p`` of (0,1,2) in
+lexicographic order.  Every interior vertex then has 14 neighbours.
+
+Assembly (paper section "fem", Problems prob:gg and prob:epseps): standard conforming P1.
+For linear elasticity the bilinear form is ``int 2 mu_L eps(u):eps(v) + lambda div u div v``
+(Hooke's law; the paper writes ``mu eps:eps`` with ``mu = 2 mu_L``).  The element matrix
+entry for test function ``phi_a e_m`` and trial ``phi_b e_n`` is
+``V (mu_L (delta_mn g_a.g_b + g_a[n] g_b[m]) + lambda g_a[m] g_b[n])`` with the constant P1
+gradients ``g``.  The matrix is returned without boundary conditions ("A_N"), as a block
+CSR with 3x3 (elasticity) or 1x1 (Poisson) row-major blocks, sorted column indices and the
+full mesh pattern (a block exists iff the two vertices share a tetrahedron).
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+from typing import Optional
+
+import numpy as np
+
+_PERMS = list(itertools.permutations(range(3)))
+
+
+def lame_from_young(E: float, nu: float):
+    """Return (mu_L, lambda) from Young's modulus and Poisson ratio."""
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return mu, lam
+
+
+def _tet_offsets() -> np.ndarray:
+    """(6, 4, 3) integer vertex offsets (x, y, z) of the six Kuhn tetrahedra of a cell."""
+    eye = np.eye(3, dtype=np.int64)
+    out = []
+    for p in _PERMS:
+        out.append(np.stack([np.zeros(3, np.int64), eye[p[0]], eye[p[0]] + eye[p[1]],
+                             np.ones(3, np.int64)]))
+    return np.array(out)
+
+
+def _p1_gradients(P: np.ndarray):
+    """Gradients (4, 3) of the barycentric functions and the volume of tetrahedron P (4, 3)."""
+    X = (P[1:] - P[0]).T
+    Xinv = np.linalg.inv(X)
+    g = np.empty((4, 3))
+    g[1:] = Xinv
+    g[0] = -Xinv.sum(axis=0)
+    return g, abs(np.linalg.det(X)) / 6.0
+
+
+def _unit_element_matrices():
+    """Per Kuhn tet type, the unit-spacing element matrices.
+
+    Returns (offsets (6,4,3), Kmu (6,12,12), Klam (6,12,12), Klap (6,4,4)), where the
+    elasticity element matrix is ``h*(mu_L*Kmu + lambda*Klam)`` and the Laplacian one is
+    ``h*Klap`` for spacing ``h`` (gradients scale with 1/h, volume with h^3).
+    """
+    offs = _tet_offsets()
+    Kmu = np.zeros((6, 12, 12))
+    Klam = np.zeros((6, 12, 12))
+    Klap = np.zeros((6, 4, 4))
+    for t in range(6):
+        g, vol = _p1_gradients(offs[t].astype(np.float64))
+        Klap[t] = vol * g @ g.T
+        for a in range(4):
+            for b in range(4):
+                gg = g[a] @ g[b]
+                for m in range(3):
+                    for n in range(3):
+                        Kmu[t, 3 * a + m, 3 * b + n] = vol * ((m == n) * gg + g[a][n] * g[b][m])
+                        Klam[t, 3 * a + m, 3 * b + n] = vol * g[a][m] * g[b][n]
+    return offs, Kmu, Klam, Klap
+
+
+@dataclasses.dataclass
+class KuhnMesh:
+    nx: int
+    ny: int
+    nz: int
+    h: float
+
+    @property
+    def n_vertices(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def cell_shape(self):
+        return (self.nz - 1, self.ny - 1, self.nx - 1)
+
+    def coords(self) -> np.ndarray:
+        k, j, i = np.meshgrid(np.arange(self.nz), np.arange(self.ny), np.arange(self.nx),
+                              indexing="ij")
+        return np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.float64) * self.h
+
+    def tet_centroids(self, t: int) -> np.ndarray:
+        """Centroids (cells..., 3) of Kuhn tet type t in every cell, array indexed [k, j, i]."""
+        off = _tet_offsets()[t].astype(np.float64).mean(axis=0)  # (x, y, z)
+        k, j, i = np.meshgrid(np.arange(self.nz - 1), np.arange(self.ny - 1),
+                              np.arange(self.nx - 1), indexing="ij")
+        return np.stack([(i + off[0]) * self.h, (j + off[1]) * self.h, (k + off[2]) * self.h],
+                        axis=-1)
+
+
+def kuhn_mesh(n: int, ny: Optional[int] = None, nz: Optional[int] = None,
+              h: Optional[float] = None) -> KuhnMesh:
+    """Box mesh with n (x) by ny by nz vertices; default a unit cube with n vertices per side."""
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    if min(n, ny, nz) < 2:
+        raise ValueError("need at least 2 vertices per direction")
+    if h is None:
+        h = 1.0 / (n - 1)
+    return KuhnMesh(n, ny, nz, float(h))
+
+
+def _assemble(mesh: KuhnMesh, bs: int, blocks_fn):
+    """Stencil assembly.  ``blocks_fn(t, a, b)`` returns the (cells..., bs, bs) or (bs, bs)
+    contribution of local pair (a, b) of tet type t in every cell."""
+    offs = _tet_offsets()
+    nz, ny, nx = mesh.nz, mesh.ny, mesh.nx
+    stencil = {}
+    touched = {}
+    cz, cy, cx = mesh.cell_shape
+    for t in range(6):
+        for a in range(4):
+            oa = offs[t, a]
+            sl = (slice(oa[2], oa[2] + cz), slice(oa[1], oa[1] + cy), slice(oa[0], oa[0] + cx))
+            for b in range(4):
+                d = tuple(int(x) for x in (offs[t, b] - oa))
+                if d not in stencil:
+                    stencil[d] = np.zeros((nz, ny, nx, bs, bs))
+                    touched[d] = np.zeros((nz, ny, nx), dtype=bool)
+                stencil[d][sl] += blocks_fn(t, a, b)
+                touched[d][sl] = True
+    ds = sorted(stencil, key=lambda d: d[0] + nx * (d[1] + ny * d[2]))
+    dlin = np.array([d[0] + nx * (d[1] + ny * d[2]) for d in ds], dtype=np.int64)
+    n = mesh.n_vertices
+    valid = np.stack([touched[d].ravel() for d in ds], axis=1)
+    rows, which = np.nonzero(valid)
+    col = rows + dlin[which]
+    counts = valid.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    vals = np.empty((rows.size, bs, bs))
+    for w, d in enumerate(ds):
+        sel = which == w
+        vals[sel] = stencil[d].reshape(n, bs, bs)[rows[sel]]
+        del stencil[d]
+    return row_ptr.astype(np.int32), col.astype(np.int32), vals
+
+
+def _coef_array(mesh: KuhnMesh, c):
+    """Broadcast a coefficient to per-(tet type, cell) form: scalar or (6, cells...)."""
+    c = np.asarray(c, dtype=np.float64)
+    if c.ndim == 0:
+        return None, float(c)
+    if c.shape != (6,) + mesh.cell_shape:
+        raise ValueError("coefficient must be scalar or shaped (6, nz-1, ny-1, nx-1)")
+    return c, None
+
+
+def assemble_elasticity(mesh: KuhnMesh, mu, lam):
+    """Block CSR (3x3) of the P1 linear elasticity matrix without boundary conditions.
+
+    ``mu`` (= mu_L) and ``lam`` are scalars or per-(tet type, cell) arrays (6, nz-1, ny-1, nx-1).
+    """
+    _, Kmu, Klam, _ = _unit_element_matrices()
+    mu_arr, mu_s = _coef_array(mesh, mu)
+    lam_arr, lam_s = _coef_array(mesh, lam)
+    h = mesh.h
+
+    def blocks(t, a, b):
+        km = h * Kmu[t, 3 * a:3 * a + 3, 3 * b:3 * b + 3]
+        kl = h * Klam[t, 3 * a:3 * a + 3, 3 * b:3 * b + 3]
+        out = (mu_arr[t][..., None, None] * km) if mu_arr is not None else mu_s * km
+        out = out + ((lam_arr[t][..., None, None] * kl) if lam_arr is not None else lam_s * kl)
+        return out
+
+    return _assemble(mesh, 3, blocks)
+
+
+def assemble_poisson(mesh: KuhnMesh, alpha=1.0):
+    """Block CSR (1x1) of the P1 Laplacian ``int alpha grad u . grad v`` without BCs."""
+    _, _, _, Klap = _unit_element_matrices()
+    al_arr, al_s = _coef_array(mesh, alpha)
+    h = mesh.h
+
+    def blocks(t, a, b):
+        k = h * Klap[t, a, b]
+        if al_arr is not None:
+            return (al_arr[t] * k)[..., None, None]
+        return np.full((1, 1), al_s * k)
+
+    return _assemble(mesh, 1, blocks)
+
+
+def sphere_inclusions(mesh: KuhnMesh, count: int, seed: int, E_host=1.0, nu_host=0.3,
+                      E_inc=1.0e4, nu_lo=0.3, nu_hi=0.49, r_lo_cells=2.0, r_hi_cells=6.0):
+    """Per-(tet type, cell) (mu_L, lambda) for a host material with random spherical inclusions.
+
+    Sphere centres ~ U[0,1]^3, radii ~ U[r_lo h, r_hi h], inclusion Poisson ratio ~ U[nu_lo, nu_hi],
+    all drawn from ``default_rng(seed)`` in that order per sphere.  A tetrahedron takes the
+    material of the highest-index sphere containing its centroid.
+    """
+    rng = np.random.default_rng(seed)
+    centres = np.empty((count, 3))
+    radii = np.empty(count)
+    nus = np.empty(count)
+    for s in range(count):
+        centres[s] = rng.uniform(0.0, 1.0, 3)
+        radii[s] = rng.uniform(r_lo_cells * mesh.h, r_hi_cells * mesh.h)
+        nus[s] = rng.uniform(nu_lo, nu_hi)
+    mu_h, lam_h = lame_from_young(E_host, nu_host)
+    mu = np.full((6,) + mesh.cell_shape, mu_h)
+    lam = np.full((6,) + mesh.cell_shape, lam_h)
+    for t in range(6):
+        cen = mesh.tet_centroids(t)
+        for s in range(count):
+            inside = ((cen - centres[s]) ** 2).sum(axis=-1) <= radii[s] ** 2
+            m, l_ = lame_from_young(E_inc, nus[s])
+            mu[t][inside] = m
+            lam[t][inside] = l_
+    return mu, lam
+
+
+@dataclasses.dataclass
+class KuhnProblem:
+    """A generated problem: BC-free block matrix A_N, coordinates, Dirichlet mask, RHS."""
+    name: str
+    dim: int
+    n_vertices: int
+    coords: np.ndarray      # (n, 3) float64
+    row_ptr: np.ndarray     # (n+1,) int32
+    col_idx: np.ndarray     # (nnzb,) int32
+    vals: np.ndarray        # (nnzb, dim, dim) float64, row-major blocks
+    dirichlet: np.ndarray   # (n,) uint8, 1 = all components clamped
+    b: np.ndarray           # (n*dim,) float64, zero at Dirichlet dofs
+    meta: dict
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.col_idx.size)
+
+    @property
+    def n_dofs(self) -> int:
+        return self.n_vertices * self.dim
+
+    @property
+    def n_free_dofs(self) -> int:
+        return int((self.dirichlet == 0).sum()) * self.dim
+
+
+def random_rhs(n_dofs: int, dim: int, dirichlet: np.ndarray, seed) -> np.ndarray:
+    """b ~ U[-1, 1] from ``numpy.random.default_rng(seed)`` (PCG64), zero at Dirichlet dofs."""
+    b = np.random.default_rng(seed).uniform(-1.0, 1.0, n_dofs)
+    b.reshape(-1, dim)[dirichlet.astype(bool)] = 0.0
+    return b
+
+
+def make_problem(n: int, *, kind: str = "elasticity", E: float = 1.0, nu: float = 0.3,
+                 seed=0, clamp: str = "x0", inclusions: int = 0, geometry_seed: int = 5,
+                 ny: Optional[int] = None, nz: Optional[int] = None, h: Optional[float] = None,
+                 name: Optional[str] = None) -> KuhnProblem:
+    """Generate a Kuhn box problem.
+
+    kind: "elasticity" (dim 3) or "poisson" (dim 1).
+    clamp: "x0" clamps the vertices with x = 0; "all" clamps the whole boundary; "none"
+    gives a pure Neumann problem (singular A_N; only meaningful for setup checks).
+    """
+    mesh = kuhn_mesh(n, ny, nz, h)
+    if kind == "elasticity":
+        dim = 3
+        if inclusions:
+            mu, lam = sphere_inclusions(mesh, inclusions, geometry_seed, E_host=E, nu_host=nu)
+        else:
+            mu, lam = lame_from_young(E, nu)
+        row_ptr, col, vals = assemble_elasticity(mesh, mu, lam)
+    elif kind == "poisson":
+        dim = 1
+        row_ptr, col, vals = assemble_poisson(mesh, 1.0)
+    else:
+        raise ValueError(kind)
+    coords = mesh.coords()
+    nv = mesh.n_vertices
+    dirichlet = np.zeros(nv, dtype=np.uint8)
+    if clamp == "x0":
+        dirichlet[coords[:, 0] == 0.0] = 1
+    elif clamp == "all":
+        ijk = np.rint(coords / mesh.h).astype(np.int64)
+        top = np.array([mesh.nx - 1, mesh.ny - 1, mesh.nz - 1])
+        dirichlet[((ijk == 0) | (ijk == top)).any(axis=1)] = 1
+    elif clamp != "none":
+        raise ValueError(clamp)
+    b = random_rhs(nv * dim, dim, dirichlet, seed)
+    meta = dict(kind=kind, n=n, ny=mesh.ny, nz=mesh.nz, h=mesh.h, E=E, nu=nu, seed=seed,
+                clamp=clamp, inclusions=inclusions)
+    return KuhnProblem(name or f"{kind}{n}", dim, nv, coords, row_ptr, col, vals, dirichlet, b,
+                       meta)
+
+
+# Named workloads: 3D linear elasticity on the unit cube, clamped at x = 0.
+WORKLOADS = {
+    # 17^3 vertices = 14,739 dofs, E=1, nu=0.3, RHS seed 0
+    "cube17": dict(n=17, E=1.0, nu=0.3, seed=0),
+    # 64^3 vertices = 786,432 dofs, same material, RHS seed 1
+    "cube64": dict(n=64, E=1.0, nu=0.3, seed=1),
+    # 128^3 vertices = 6,291,456 dofs, nu = 0.45, RHS seed 3
+    "cube128_nu045": dict(n=128, E=1.0, nu=0.45, seed=3),
+    # 96^3 vertices, 200 stiff spherical inclusions (E=1e4), geometry and RHS seed 5
+    "spheres96": dict(n=96, E=1.0, nu=0.3, seed=5, inclusions=200, geometry_seed=5),
+}
