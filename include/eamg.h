@@ -1,0 +1,216 @@
+/*
+ * eamg.h -- C ABI of the MI355X edge-matrix AMG-PCG library (libeamg.so).
+ *
+ * The library solves A u = b for the symmetric positive definite block matrix A of a P1 finite
+ * element discretization (paper section "fem": Problem prob:gg, scalar, and Problem prob:epseps,
+ * linear elasticity) with conjugate gradients preconditioned by one V-cycle of auxiliary
+ * topology ("edge matrix") AMG (section "res"): coarsening by successive matching on edge and
+ * vertex weight matrices (Algorithm alg:pwagg; Thms thm:deng_elast and thm:cemats), auxiliary
+ * smoothed prolongation (Def. def:aux_sp), Galerkin coarse operators, a symmetric multicolour
+ * block Gauss-Seidel smoother with pseudo-inverted diagonal blocks and a regularized dense
+ * Cholesky coarsest level (section "sing2").
+ *
+ * Conventions shared by every entry point:
+ *  - Plain C types only.  Integers are int32_t unless stated, reals are IEEE double.
+ *  - "Host" pointers are CPU memory, "device" pointers are HIP device memory on the current
+ *    device.  All input arrays are borrowed for the duration of the call and never retained.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All device work of
+ *    a call is ordered on it.  eamg_setup and eamg_solve return after their work is complete.
+ *  - Errors are returned as eamg_status; no exception or abort crosses the ABI.  A message for
+ *    the last failure on the calling thread is available from eamg_last_error().
+ *  - A hierarchy handle must not be used by two threads at once.  Separate handles are
+ *    independent.
+ */
+#ifndef EAMG_H
+#define EAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eamg_hierarchy eamg_hierarchy; /* opaque, owned by the library */
+
+typedef enum {
+  EAMG_OK = 0,
+  EAMG_NOT_CONVERGED = 1,          /* warning: max_it reached, x holds the last iterate       */
+  EAMG_ERR_INVALID_ARG = -1,       /* malformed input (message says which)                    */
+  EAMG_ERR_UNSUPPORTED_KERNEL = -2,/* dim / k_kernel / kernel vectors not supported           */
+  EAMG_ERR_NOT_SPD = -3,           /* coarsest Cholesky met a non-positive pivot              */
+  EAMG_ERR_BREAKDOWN = -4,         /* non-finite value, p.Ap <= 0 or r.z <= 0 in PCG          */
+  EAMG_ERR_HIP = -5,               /* a HIP runtime call failed                               */
+  EAMG_ERR_OOM = -6                /* device or host allocation failed                        */
+} eamg_status;
+
+/*
+ * The problem (section "fem"; kernel vectors: section "amg", eq. qij_epseps).  HOST pointers.
+ *  dim         1 (scalar, kernel = constants, k = 1) or 3 (3D elasticity, kernel = the six rigid
+ *              body modes, k = 6).
+ *  n_vertices  number of mesh vertices n (block rows of A).
+ *  coords      n*3 vertex positions (x, y, z) of every vertex (also for dim = 1); they define the
+ *              transport maps Q^{i->j} of eq. qij_epseps.
+ *  row_ptr     n+1 block CSR row offsets of the boundary-condition-free matrix A_N.
+ *  col_idx     row_ptr[n] block column indices, strictly ascending within a row, diagonal present,
+ *              pattern symmetric.
+ *  vals        row_ptr[n]*dim*dim values, each block row-major.  A_N itself, without Dirichlet
+ *              conditions; the library replaces Dirichlet rows/columns by identity/zero blocks.
+ *  dirichlet   n flags, 1 = all dim components of that vertex are clamped (may be NULL = none).
+ *  kernel      optional (n*dim) x k_kernel column-major kernel vectors.  NULL = derived from
+ *              coords.  If given they must span the rigid body modes (dim 3) / constants (dim 1)
+ *              to 1e-10 relative, else EAMG_ERR_UNSUPPORTED_KERNEL.
+ *  k_kernel    6 for dim 3, 1 for dim 1.
+ *  edges       optional n_edges x 2 (i < j) auxiliary topology; NULL = every off-diagonal block
+ *              position of A_N.  Each edge must be an off-diagonal position of the pattern.
+ */
+typedef struct {
+  int32_t dim;
+  int32_t n_vertices;
+  const double *coords;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *vals;
+  const uint8_t *dirichlet;
+  const double *kernel;
+  int32_t k_kernel;
+  const int32_t *edges;
+  int64_t n_edges;
+} eamg_problem;
+
+/*
+ * Setup parameters (Algorithm alg:pwagg inputs sigma, delta, R, N; row caps of the smoothed
+ * prolongation of section "res").  Pass NULL for the defaults, or fill from
+ * eamg_default_setup_params().
+ *  sigma              matching threshold (default 20)
+ *  delta              1 (neighbour term in mu_g / mu_b; only 1 is supported)
+ *  R                  1 (candidate chosen by mu_s; only 1 is supported)
+ *  rounds             matching passes per level N (default 2, 1..4)
+ *  coarsest_max_dofs  level l is the coarsest once bs_l * n_l < this (default 500, <= 8000)
+ *  max_levels         maximum number of levels (default 25)
+ *  omega              prolongation smoothing damping (default 2/3)
+ *  cap_aux            columns per edge-matrix row of P_s (default 4, 1..16)
+ *  cap_std_l0, cap_std columns per real-matrix row of P_s, finest / coarser (defaults 8, 6; 1..16)
+ *  pinv_rtol          relative eigenvalue threshold of pseudo-inverses (default 1e-10)
+ *  tie_rtol           relative band in which mu_s values tie (default 1e-12)
+ */
+typedef struct {
+  double sigma;
+  int32_t delta, R, rounds, coarsest_max_dofs, max_levels;
+  double omega;
+  int32_t cap_aux, cap_std_l0, cap_std;
+  double pinv_rtol, tie_rtol;
+} eamg_setup_params;
+
+/* Solve parameters.  rtol: stop when ||r||_2 <= rtol ||b||_2 (recursive residual, x0 = 0 unless
+ * use_x0); max_it: iteration limit (>= 1); use_x0: 1 = start from the given x; precond: 0 none,
+ * 1 one V-cycle. */
+typedef struct {
+  double rtol;
+  int32_t max_it;
+  int32_t use_x0;
+  int32_t precond;
+} eamg_solve_params;
+
+/* Solve report: iterations done, final recursive and true relative residual, and the
+ * wall time of the solve in milliseconds measured with events on the stream. */
+typedef struct {
+  int32_t iterations;
+  double rel_res;
+  double rel_res_true;
+  double ms;
+} eamg_solve_info;
+
+/* Per-level sizes, for sizing eamg_export_level buffers. */
+typedef struct {
+  int32_t n;          /* vertices (block rows) of A_l                                    */
+  int32_t bs;         /* real dofs per vertex (block size of A_l)                        */
+  int64_t nnzb_A;     /* blocks of A_l                                                   */
+  int32_t n_coarse;   /* vertices of level l+1 (0 on the coarsest level)                 */
+  int32_t k_coarse;   /* columns per P_s block (dofs per coarse vertex)                  */
+  int64_t nnzb_P;     /* blocks of P_s (0 on the coarsest level)                         */
+  int32_t n_colors;   /* colours of the smoother (0 on the coarsest level)               */
+} eamg_level_info;
+
+/* Default parameters (all fields set). */
+void eamg_default_setup_params(eamg_setup_params *out);
+void eamg_default_solve_params(eamg_solve_params *out);
+
+/*
+ * Build the hierarchy (host coarsening; device P_s assembly, Galerkin products, smoother
+ * diagonals and coarsest factor).  On success *out owns all device memory of the hierarchy.
+ * Errors: INVALID_ARG (NULL pointers, sizes, unsorted/asymmetric pattern, missing diagonal,
+ * parameters out of range), UNSUPPORTED_KERNEL, NOT_SPD (coarsest level), HIP, OOM.
+ */
+eamg_status eamg_setup(const eamg_problem *problem, const eamg_setup_params *params,
+                       void *stream, eamg_hierarchy **out);
+
+/*
+ * Solve A x = b by PCG.  b_dev, x_dev: DEVICE arrays of n*dim doubles, caller-owned, may not
+ * alias.  b is ignored at Dirichlet dofs; x is 0 there on return.  Returns OK, NOT_CONVERGED
+ * (x = last iterate), BREAKDOWN (non-finite b or residual, or a non-positive curvature /
+ * preconditioned inner product), INVALID_ARG or HIP.  info may be NULL.
+ */
+eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
+                       const eamg_solve_params *params, void *stream, eamg_solve_info *info);
+
+/*
+ * Apply one V-cycle z = B^{-1} r (DEVICE arrays, n*dim doubles, level-0 natural order).
+ * Dirichlet dofs of r are treated as 0.
+ */
+eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, void *stream);
+
+/* Hierarchy statistics (HOST outputs, any may be NULL).  per_level_n / per_level_nnzb must hold
+ * max_levels entries.  vc = sum n_l / n_0, oc = sum nnz_l / nnz_0 counting scalar entries. */
+eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,
+                       int64_t *per_level_nnzb, double *vc, double *oc);
+
+eamg_status eamg_level_info_get(const eamg_hierarchy *h, int32_t level, eamg_level_info *out);
+
+/*
+ * Copy one level to HOST buffers in the level's natural vertex numbering (coarse vertex I is
+ * the I-th agglomerate of the matching).  Any pointer may be NULL to skip it.  Sizes from
+ * eamg_level_info_get:
+ *   agg      n       coarse vertex of each vertex, -1 for the dropped set D (coarsest: all -1)
+ *   P_rowptr n+1, P_col nnzb_P, P_val nnzb_P*bs*k_coarse (row-major blocks)
+ *   A_rowptr n+1, A_col nnzb_A, A_val nnzb_A*bs*bs
+ *   color    n       smoother colour of each vertex (coarsest: all -1)
+ */
+eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *agg,
+                              int32_t *P_rowptr, int32_t *P_col, double *P_val,
+                              int32_t *A_rowptr, int32_t *A_col, double *A_val, int32_t *color);
+
+/* Bytes of one V-cycle's algorithmic HBM traffic and of one PCG iteration (matrix and vector
+ * streams counted once per kernel), from the real per-level sizes. */
+eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes,
+                               double *iteration_bytes);
+
+/* Free a hierarchy (NULL-safe). */
+void eamg_destroy(eamg_hierarchy *h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *eamg_last_error(void);
+
+/*
+ * Host-only successive matching of one level (Algorithm alg:pwagg), exposed so the coarsening
+ * can be checked without a GPU.  HOST pointers; no device work.
+ *  k            1 or 6 (dofs of the auxiliary space)
+ *  n, coords    vertices and positions (n*3)
+ *  n_edges, edges, E   auxiliary edges (i < j, ascending (i, j)) and their k*k weights
+ *  M            n*k*k vertex weights
+ *  vd           n flags of V_D (may be NULL)
+ *  out_agg      n: coarse vertex or -1 (D)
+ *  out_nc       number of coarse vertices
+ *  out_ccoords  may be NULL, else n*3 capacity: coarse positions
+ *  out_margin   may be NULL: min |mu - sigma| / sigma over all threshold decisions
+ */
+eamg_status eamg_host_match(int32_t k, int32_t n, const double *coords, int64_t n_edges,
+                            const int32_t *edges, const double *E, const double *M,
+                            const uint8_t *vd, const eamg_setup_params *params,
+                            int32_t *out_agg, int32_t *out_nc, double *out_ccoords,
+                            double *out_margin);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EAMG_H */

@@ -11,8 +11,9 @@ Readings (the paper gives only the row caps):
 * S/A split: ``cols_S(i) = {agg(i)} U {agg(j) : A_ij structurally nonzero, j not in D}``;
   i is an S row iff ``|cols_S(i)| <= cap_S`` (8 on the finest level, 6 below).
 * Filtered neighbours of an A row: group the edge neighbours l not in D by agg(l); keep the group
-  agg(i) and the ``cap_A - 1`` other groups with the largest sum of tr E^il (ties: smaller coarse
-  id); F^i is the union of the kept groups.
+  agg(i) and the ``cap_A - 1`` other groups with the largest sum of tr E^il (picked one by one;
+  sums within a relative 1e-12 of the largest tie, smaller coarse id first); F^i is the union of
+  the kept groups.
 * A rows use ``Dhat^0_ii = sum_{l in F^i} Q^{il,T} E^il Q^il`` and
   ``Ahat^0_il = -Q^{il,T} E^il Q^li`` (eq. auxa restricted to F^i; the definition's printed
   Q^{li,T} E^il Q^li and M^ij are read this way, which keeps rigid-body modes in the range).
@@ -110,8 +111,12 @@ def row_split(A: BCSR, aux, agg_of, dmask, cap_S):
     return types, colsS
 
 
-def filtered_neighbors(aux, i, agg_of, dmask, cap_A):
-    """F^i (sorted vertex ids) and the kept coarse groups."""
+def filtered_neighbors(aux, i, agg_of, dmask, cap_A, tie_rtol=1e-12):
+    """F^i (sorted (vertex, edge) pairs) and the kept coarse groups.
+
+    Groups are picked one at a time by largest sum of tr E^il; sums within the relative band
+    ``tie_rtol`` of the largest tie and the smaller coarse id wins (the tie rule of the
+    matching), so that round-off cannot reorder mathematically equal weights."""
     nb, eid = aux.neighbors(i)
     wsum = {}
     mem = {}
@@ -122,8 +127,13 @@ def filtered_neighbors(aux, i, agg_of, dmask, cap_A):
         wsum[g] = wsum.get(g, 0.0) + float(np.trace(aux.E[e]))
         mem.setdefault(g, []).append((l, e))
     own = int(agg_of[i])
-    others = sorted((g for g in wsum if g != own), key=lambda g: (-wsum[g], g))
-    keep = [own] + others[:cap_A - 1]
+    others = [g for g in wsum if g != own]
+    keep = [own]
+    while others and len(keep) < cap_A:
+        wmax = max(wsum[g] for g in others)
+        g = min(g for g in others if wsum[g] >= wmax * (1.0 - tie_rtol))
+        keep.append(g)
+        others.remove(g)
     F = sorted(le for g in keep for le in mem.get(g, []))
     return F, sorted(keep)
 

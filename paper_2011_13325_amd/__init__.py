@@ -1,0 +1,313 @@
+"""Python binding of libeamg, the MI355X edge-matrix AMG-PCG library (C ABI in include/eamg.h).
+
+Argument marshalling only: every step of setup and solve runs in the library (host C++ setup,
+HIP kernels on the GPU).  Device buffers are torch tensors on a HIP device; host inputs are
+numpy arrays.  Importing works without a GPU (so the ABI can be checked); the library must be
+built (``python -m paper_2011_13325_amd.build``) or loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeamg.so")
+
+EAMG_OK = 0
+EAMG_NOT_CONVERGED = 1
+EAMG_ERR_INVALID_ARG = -1
+EAMG_ERR_UNSUPPORTED_KERNEL = -2
+EAMG_ERR_NOT_SPD = -3
+EAMG_ERR_BREAKDOWN = -4
+EAMG_ERR_HIP = -5
+EAMG_ERR_OOM = -6
+
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED_KERNEL",
+                -3: "NOT_SPD", -4: "BREAKDOWN", -5: "HIP", -6: "OOM"}
+
+# Every symbol include/eamg.h declares.
+EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
+            "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
+            "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match"]
+
+
+class eamg_problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_vertices", ctypes.c_int32),
+                ("coords", ctypes.c_void_p), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("vals", ctypes.c_void_p),
+                ("dirichlet", ctypes.c_void_p), ("kernel", ctypes.c_void_p),
+                ("k_kernel", ctypes.c_int32), ("edges", ctypes.c_void_p),
+                ("n_edges", ctypes.c_int64)]
+
+
+class eamg_setup_params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("delta", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("coarsest_max_dofs", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("cap_aux", ctypes.c_int32), ("cap_std_l0", ctypes.c_int32),
+                ("cap_std", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
+                ("tie_rtol", ctypes.c_double)]
+
+
+class eamg_solve_params(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("max_it", ctypes.c_int32),
+                ("use_x0", ctypes.c_int32), ("precond", ctypes.c_int32)]
+
+
+class eamg_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class eamg_level_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("bs", ctypes.c_int32), ("nnzb_A", ctypes.c_int64),
+                ("n_coarse", ctypes.c_int32), ("k_coarse", ctypes.c_int32),
+                ("nnzb_P", ctypes.c_int64), ("n_colors", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libeamg (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: the HIP library has not been built "
+                           "(python -m paper_2011_13325_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.eamg_default_setup_params.argtypes = [P(eamg_setup_params)]
+    L.eamg_default_setup_params.restype = None
+    L.eamg_default_solve_params.argtypes = [P(eamg_solve_params)]
+    L.eamg_default_solve_params.restype = None
+    L.eamg_setup.argtypes = [P(eamg_problem), P(eamg_setup_params), vp, P(vp)]
+    L.eamg_setup.restype = ctypes.c_int
+    L.eamg_solve.argtypes = [vp, vp, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
+    L.eamg_solve.restype = ctypes.c_int
+    L.eamg_vcycle.argtypes = [vp, vp, vp, vp]
+    L.eamg_vcycle.restype = ctypes.c_int
+    L.eamg_stats.argtypes = [vp, P(i32), vp, vp, P(dp), P(dp)]
+    L.eamg_stats.restype = ctypes.c_int
+    L.eamg_level_info_get.argtypes = [vp, i32, P(eamg_level_info)]
+    L.eamg_level_info_get.restype = ctypes.c_int
+    L.eamg_export_level.argtypes = [vp, i32] + [vp] * 8
+    L.eamg_export_level.restype = ctypes.c_int
+    L.eamg_traffic_model.argtypes = [vp, P(dp), P(dp)]
+    L.eamg_traffic_model.restype = ctypes.c_int
+    L.eamg_destroy.argtypes = [vp]
+    L.eamg_destroy.restype = None
+    L.eamg_last_error.argtypes = []
+    L.eamg_last_error.restype = ctypes.c_char_p
+    L.eamg_host_match.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp, P(eamg_setup_params), vp,
+                                  P(i32), vp, P(dp)]
+    L.eamg_host_match.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class EamgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().eamg_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def eamg_default_setup_params(**overrides) -> eamg_setup_params:
+    p = eamg_setup_params()
+    lib().eamg_default_setup_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def eamg_last_error() -> str:
+    return lib().eamg_last_error().decode()
+
+
+def _problem(dim, coords, row_ptr, col_idx, vals, dirichlet=None, kernel=None, edges=None):
+    keep = {
+        "coords": np.ascontiguousarray(coords, dtype=np.float64),
+        "row_ptr": np.ascontiguousarray(row_ptr, dtype=np.int32),
+        "col_idx": np.ascontiguousarray(col_idx, dtype=np.int32),
+        "vals": np.ascontiguousarray(vals, dtype=np.float64),
+        "dirichlet": None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8),
+        "kernel": None if kernel is None else np.asfortranarray(kernel, dtype=np.float64),
+        "edges": None if edges is None else np.ascontiguousarray(edges, dtype=np.int32),
+    }
+    pb = eamg_problem()
+    pb.dim = dim
+    pb.n_vertices = keep["coords"].shape[0]
+    pb.coords = _ptr(keep["coords"])
+    pb.row_ptr = _ptr(keep["row_ptr"])
+    pb.col_idx = _ptr(keep["col_idx"])
+    pb.vals = _ptr(keep["vals"])
+    pb.dirichlet = _ptr(keep["dirichlet"])
+    pb.kernel = _ptr(keep["kernel"])
+    pb.k_kernel = 6 if dim == 3 else 1
+    pb.edges = _ptr(keep["edges"])
+    pb.n_edges = 0 if edges is None else keep["edges"].shape[0]
+    return pb, keep
+
+
+def eamg_setup(dim, coords, row_ptr, col_idx, vals, dirichlet=None, params=None, stream=None,
+               kernel=None, edges=None):
+    """Returns an opaque handle (ctypes.c_void_p).  Raises EamgError on failure."""
+    pb, keep = _problem(dim, coords, row_ptr, col_idx, vals, dirichlet, kernel, edges)
+    h = ctypes.c_void_p()
+    st = lib().eamg_setup(ctypes.byref(pb), ctypes.byref(params) if params is not None else None,
+                          _stream(stream), ctypes.byref(h))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_setup")
+    return h
+
+
+def eamg_solve(h, b, x, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stream=None):
+    """b, x: float64 device tensors of n*dim entries.  Returns (status, info dict)."""
+    sp = eamg_solve_params(rtol, max_it, int(use_x0), int(precond))
+    info = eamg_solve_info()
+    st = lib().eamg_solve(h, _dptr(b), _dptr(x), ctypes.byref(sp), _stream(stream),
+                          ctypes.byref(info))
+    if st < 0:
+        raise EamgError(st, "eamg_solve")
+    return st, dict(iterations=info.iterations, rel_res=info.rel_res,
+                    rel_res_true=info.rel_res_true, ms=info.ms)
+
+
+def eamg_vcycle(h, r, z, stream=None):
+    st = lib().eamg_vcycle(h, _dptr(r), _dptr(z), _stream(stream))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_vcycle")
+
+
+def eamg_stats(h):
+    nl = ctypes.c_int32()
+    ns = np.zeros(64, dtype=np.int64)
+    nz = np.zeros(64, dtype=np.int64)
+    vc, oc = ctypes.c_double(), ctypes.c_double()
+    st = lib().eamg_stats(h, ctypes.byref(nl), _ptr(ns), _ptr(nz), ctypes.byref(vc), ctypes.byref(oc))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_stats")
+    return dict(n_levels=nl.value, n=ns[:nl.value].tolist(), nnzb=nz[:nl.value].tolist(),
+                vc=vc.value, oc=oc.value)
+
+
+def eamg_level_info_get(h, level):
+    info = eamg_level_info()
+    st = lib().eamg_level_info_get(h, level, ctypes.byref(info))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_level_info_get")
+    return {f: getattr(info, f) for f, _ in eamg_level_info._fields_}
+
+
+def eamg_export_level(h, level):
+    """Natural-order host copies of one level: agg, P (rowptr, col, val), A (...), color."""
+    li = eamg_level_info_get(h, level)
+    n, bs, kc = li["n"], li["bs"], li["k_coarse"]
+    out = dict(info=li,
+               agg=np.zeros(n, np.int32), color=np.zeros(n, np.int32),
+               P_rowptr=np.zeros(n + 1, np.int32), P_col=np.zeros(max(li["nnzb_P"], 1), np.int32),
+               P_val=np.zeros(max(li["nnzb_P"] * bs * kc, 1)),
+               A_rowptr=np.zeros(n + 1, np.int32), A_col=np.zeros(li["nnzb_A"], np.int32),
+               A_val=np.zeros(li["nnzb_A"] * bs * bs))
+    st = lib().eamg_export_level(h, level, _ptr(out["agg"]), _ptr(out["P_rowptr"]),
+                                 _ptr(out["P_col"]), _ptr(out["P_val"]), _ptr(out["A_rowptr"]),
+                                 _ptr(out["A_col"]), _ptr(out["A_val"]), _ptr(out["color"]))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_export_level")
+    out["P_col"] = out["P_col"][:li["nnzb_P"]]
+    out["P_val"] = out["P_val"][:li["nnzb_P"] * bs * kc].reshape(-1, bs, kc) if kc else None
+    out["A_val"] = out["A_val"].reshape(-1, bs, bs)
+    return out
+
+
+def eamg_traffic_model(h):
+    v, it = ctypes.c_double(), ctypes.c_double()
+    st = lib().eamg_traffic_model(h, ctypes.byref(v), ctypes.byref(it))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_traffic_model")
+    return v.value, it.value
+
+
+def eamg_destroy(h):
+    if h is not None:
+        lib().eamg_destroy(h)
+
+
+def eamg_host_match(k, coords, edges, E, M, vd=None, params=None):
+    """Host-only successive matching of one level; returns (agg, nc, coarse_coords, margin)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    n = coords.shape[0]
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    vdm = None if vd is None else np.ascontiguousarray(vd, dtype=np.uint8)
+    agg = np.zeros(n, np.int32)
+    cc = np.zeros((max(n, 1), 3))
+    nc = ctypes.c_int32()
+    margin = ctypes.c_double()
+    st = lib().eamg_host_match(k, n, _ptr(coords), edges.shape[0], _ptr(edges), _ptr(E), _ptr(M),
+                               _ptr(vdm), ctypes.byref(params) if params is not None else None,
+                               _ptr(agg), ctypes.byref(nc), _ptr(cc), ctypes.byref(margin))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_host_match")
+    return agg, nc.value, cc[:nc.value], margin.value
+
+
+class Hierarchy:
+    """Owning wrapper: setup on construction, solve(b) -> x on device tensors."""
+
+    def __init__(self, dim, coords, row_ptr, col_idx, vals, dirichlet=None, params=None,
+                 stream=None, **kw):
+        self.dim = dim
+        self.n_dofs = np.asarray(coords).shape[0] * dim
+        self.h = eamg_setup(dim, coords, row_ptr, col_idx, vals, dirichlet, params, stream, **kw)
+
+    def solve(self, b, x=None, **kw):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        st, info = eamg_solve(self.h, b, x, **kw)
+        info["status"] = st
+        return x, info
+
+    def stats(self):
+        return eamg_stats(self.h)
+
+    def export(self, level):
+        return eamg_export_level(self.h, level)
+
+    def close(self):
+        if self.h is not None:
+            eamg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

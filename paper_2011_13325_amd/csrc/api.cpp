@@ -1,0 +1,933 @@
+// C ABI of libeamg (include/eamg.h): input validation, the setup driver (host coarsening and
+// sparse structure, device numerics), the PCG / V-cycle drivers, statistics and export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/eamg.h"
+#include "coarsen.hpp"
+#include "dense.hpp"
+#include "kernels.hpp"
+#include "structure.hpp"
+
+namespace eamg {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+  eamg_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(eamg_status code, const std::string &msg) { throw Failure{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) fail(EAMG_ERR_OOM, std::string(what) + ": out of device memory");
+  fail(EAMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device allocations owned by a hierarchy; freed together.
+struct DevArena {
+  std::vector<void *> ptrs;
+  template <class T>
+  T *alloc(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+    ptrs.push_back(p);
+    return static_cast<T *>(p);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    return upload(v.data(), v.size(), s);
+  }
+  template <class T>
+  T *upload(const T *p, size_t count, hipStream_t s) {
+    // setup-time upload from pageable memory: wait so the source may be freed on return
+    T *d = alloc<T>(count);
+    if (count) {
+      hip_check(hipMemcpyAsync(d, p, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipStreamSynchronize(s), "sync");
+    }
+    return d;
+  }
+  void release(void *p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(p);
+      ptrs.erase(it);
+    }
+  }
+  ~DevArena() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <class T>
+std::vector<T> download(const T *d, size_t count, hipStream_t s) {
+  std::vector<T> h(count);
+  if (count) hip_check(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipStreamSynchronize(s), "sync");
+  return h;
+}
+
+int pick_group(int64_t nnz, int rows) {
+  const double avg = rows ? double(nnz) / rows : 1.0;
+  int g = 4;
+  while (g < 64 && g < avg) g <<= 1;
+  return g;
+}
+
+struct Level {
+  int n = 0, bs = 0;
+  Pattern A;                 // natural pattern
+  int64_t *A_rp = nullptr;   // natural pattern on the device
+  int *A_col = nullptr;
+  double *A_val = nullptr;   // natural AoS values (n_blocks * bs * bs)
+  // coarsening products (levels above the coarsest)
+  std::vector<int> agg;
+  Pattern P;
+  int kc = 0;
+  double *P_val = nullptr;   // natural AoS values (nnz * bs * kc)
+  std::vector<int> color;    // natural
+  int ncolors = 0;
+  // colour-major solve layout
+  std::vector<int> perm, inv, color_ptr;
+  int *perm_d = nullptr;
+  SoaMat Am, Pm, Rm;
+  double *Dinv = nullptr;
+  int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
+  double *x = nullptr, *b = nullptr, *r = nullptr;
+};
+
+}  // namespace
+}  // namespace eamg
+
+struct eamg_hierarchy {
+  int dim = 0, k = 0, n0 = 0;
+  eamg_setup_params prm{};
+  std::vector<eamg::Level> lv;
+  eamg::DevArena arena;
+  double *Ainv = nullptr;
+  int nL = 0;                 // coarsest dofs
+  uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
+  double *part = nullptr, *scal = nullptr;
+  double *scal_h = nullptr;   // pinned
+  ~eamg_hierarchy() {
+    if (scal_h) (void)hipHostFree(scal_h);
+  }
+};
+
+namespace eamg {
+namespace {
+
+eamg_setup_params defaults() {
+  eamg_setup_params p;
+  p.sigma = 20.0;
+  p.delta = 1;
+  p.R = 1;
+  p.rounds = 2;
+  p.coarsest_max_dofs = 500;
+  p.max_levels = 25;
+  p.omega = 2.0 / 3.0;
+  p.cap_aux = 4;
+  p.cap_std_l0 = 8;
+  p.cap_std = 6;
+  p.pinv_rtol = 1e-10;
+  p.tie_rtol = 1e-12;
+  return p;
+}
+
+void validate_params(const eamg_setup_params &p) {
+  if (!(p.sigma > 0.0) || !std::isfinite(p.sigma)) fail(EAMG_ERR_INVALID_ARG, "sigma must be positive");
+  if (p.delta != 1) fail(EAMG_ERR_INVALID_ARG, "only delta = 1 is supported");
+  if (p.R != 1) fail(EAMG_ERR_INVALID_ARG, "only R = 1 (mu_s candidate choice) is supported");
+  if (p.rounds < 1 || p.rounds > 4) fail(EAMG_ERR_INVALID_ARG, "rounds must be in 1..4");
+  if (p.coarsest_max_dofs < 1 || p.coarsest_max_dofs > 4000)
+    fail(EAMG_ERR_INVALID_ARG, "coarsest_max_dofs must be in 1..4000");
+  if (p.max_levels < 1 || p.max_levels > 64) fail(EAMG_ERR_INVALID_ARG, "max_levels must be in 1..64");
+  if (!std::isfinite(p.omega)) fail(EAMG_ERR_INVALID_ARG, "omega must be finite");
+  if (p.cap_aux < 1 || p.cap_aux > 16 || p.cap_std_l0 < 1 || p.cap_std_l0 > 16 || p.cap_std < 1 ||
+      p.cap_std > 16)
+    fail(EAMG_ERR_INVALID_ARG, "row caps must be in 1..16");
+  if (!(p.pinv_rtol > 0.0 && p.pinv_rtol <= 1e-2)) fail(EAMG_ERR_INVALID_ARG, "pinv_rtol must be in (0, 1e-2]");
+  if (!(p.tie_rtol >= 0.0 && p.tie_rtol <= 1e-6)) fail(EAMG_ERR_INVALID_ARG, "tie_rtol must be in [0, 1e-6]");
+}
+
+void validate_problem(const eamg_problem *pb) {
+  if (!pb) fail(EAMG_ERR_INVALID_ARG, "problem is NULL");
+  if (pb->dim != 1 && pb->dim != 3) fail(EAMG_ERR_UNSUPPORTED_KERNEL, "dim must be 1 or 3");
+  if (pb->k_kernel != (pb->dim == 3 ? 6 : 1))
+    fail(EAMG_ERR_UNSUPPORTED_KERNEL, "k_kernel must be 6 (dim 3) or 1 (dim 1)");
+  if (pb->n_vertices < 1) fail(EAMG_ERR_INVALID_ARG, "n_vertices must be positive");
+  if (!pb->coords || !pb->row_ptr || !pb->col_idx || !pb->vals)
+    fail(EAMG_ERR_INVALID_ARG, "coords, row_ptr, col_idx and vals are required");
+  const int n = pb->n_vertices;
+  if (pb->row_ptr[0] != 0) fail(EAMG_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int i = 0; i < n; ++i)
+    if (pb->row_ptr[i + 1] < pb->row_ptr[i]) fail(EAMG_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+  const int64_t nnz = pb->row_ptr[n];
+  for (int i = 0; i < n; ++i) {
+    bool has_diag = false;
+    for (int32_t p = pb->row_ptr[i]; p < pb->row_ptr[i + 1]; ++p) {
+      const int j = pb->col_idx[p];
+      if (j < 0 || j >= n) fail(EAMG_ERR_INVALID_ARG, "column index out of range in row " + std::to_string(i));
+      if (p > pb->row_ptr[i] && pb->col_idx[p - 1] >= j)
+        fail(EAMG_ERR_INVALID_ARG, "column indices must be strictly ascending (row " + std::to_string(i) + ")");
+      if (j == i) has_diag = true;
+    }
+    if (!has_diag) fail(EAMG_ERR_INVALID_ARG, "missing diagonal block in row " + std::to_string(i));
+  }
+  for (int i = 0; i < n; ++i)
+    for (int32_t p = pb->row_ptr[i]; p < pb->row_ptr[i + 1]; ++p) {
+      const int j = pb->col_idx[p];
+      const int32_t *b = pb->col_idx + pb->row_ptr[j], *e = pb->col_idx + pb->row_ptr[j + 1];
+      if (!std::binary_search(b, e, i)) fail(EAMG_ERR_INVALID_ARG, "block pattern is not symmetric");
+    }
+  const int64_t nv = nnz * pb->dim * pb->dim;
+  for (int64_t q = 0; q < nv; ++q)
+    if (!std::isfinite(pb->vals[q])) fail(EAMG_ERR_INVALID_ARG, "non-finite matrix entry");
+  for (int64_t q = 0; q < int64_t(3) * n; ++q)
+    if (!std::isfinite(pb->coords[q])) fail(EAMG_ERR_INVALID_ARG, "non-finite coordinate");
+  if (pb->edges && pb->n_edges < 0) fail(EAMG_ERR_INVALID_ARG, "n_edges must be >= 0");
+  if (pb->kernel) {
+    // the given kernel vectors must span the rigid body modes (or the constants)
+    const int dim = pb->dim, k = pb->k_kernel;
+    const int64_t N = int64_t(n) * dim;
+    std::vector<std::vector<double>> Q;   // orthonormalized given vectors
+    for (int c = 0; c < k; ++c) {
+      std::vector<double> v(pb->kernel + c * N, pb->kernel + (c + 1) * N);
+      double nv0 = 0.0;
+      for (double a : v) nv0 += a * a;
+      for (const auto &u : Q) {
+        double d = 0.0;
+        for (int64_t t = 0; t < N; ++t) d += u[t] * v[t];
+        for (int64_t t = 0; t < N; ++t) v[t] -= d * u[t];
+      }
+      double nv1 = 0.0;
+      for (double a : v) nv1 += a * a;
+      if (!(nv1 > 1e-20 * nv0) || !std::isfinite(nv1))
+        fail(EAMG_ERR_UNSUPPORTED_KERNEL, "kernel vectors are linearly dependent");
+      for (double &a : v) a /= std::sqrt(nv1);
+      Q.push_back(std::move(v));
+    }
+    for (int c = 0; c < k; ++c) {
+      std::vector<double> m(size_t(N), 0.0);
+      for (int i = 0; i < n; ++i) {
+        const double *x = pb->coords + 3 * int64_t(i);
+        if (dim == 1) {
+          m[i] = 1.0;
+        } else if (c < 3) {
+          m[3 * int64_t(i) + c] = 1.0;
+        } else {
+          double e[3] = {0, 0, 0};
+          e[c - 3] = 1.0;   // x cross e_m
+          m[3 * int64_t(i) + 0] = x[1] * e[2] - x[2] * e[1];
+          m[3 * int64_t(i) + 1] = x[2] * e[0] - x[0] * e[2];
+          m[3 * int64_t(i) + 2] = x[0] * e[1] - x[1] * e[0];
+        }
+      }
+      double n0 = 0.0;
+      for (double a : m) n0 += a * a;
+      for (const auto &u : Q) {
+        double d = 0.0;
+        for (int64_t t = 0; t < N; ++t) d += u[t] * m[t];
+        for (int64_t t = 0; t < N; ++t) m[t] -= d * u[t];
+      }
+      double n1 = 0.0;
+      for (double a : m) n1 += a * a;
+      if (n1 > 1e-20 * n0)
+        fail(EAMG_ERR_UNSUPPORTED_KERNEL, "kernel vectors do not span the rigid body modes / constants");
+    }
+  }
+}
+
+Pattern pattern_from_input(const eamg_problem *pb) {
+  Pattern P;
+  P.n_rows = P.n_cols = pb->n_vertices;
+  P.rp.assign(pb->row_ptr, pb->row_ptr + pb->n_vertices + 1);
+  P.col.assign(pb->col_idx, pb->col_idx + pb->row_ptr[pb->n_vertices]);
+  return P;
+}
+
+std::vector<int> crow_of(const Pattern &C) {
+  std::vector<int> r(size_t(C.nnz()));
+  for (int i = 0; i < C.n_rows; ++i)
+    for (int64_t q = C.rp[i]; q < C.rp[i + 1]; ++q) r[q] = i;
+  return r;
+}
+
+std::vector<int> to_i32(const std::vector<int64_t> &v) {
+  std::vector<int> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (v[i] > int64_t(2147483647)) fail(EAMG_ERR_INVALID_ARG, "a level exceeds 2^31 blocks");
+    o[i] = int(v[i]);
+  }
+  return o;
+}
+
+// Build one solve-phase SoA matrix from natural AoS values with a host permutation map.
+SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br, int bc,
+                const double *aos, hipStream_t s, std::vector<int> *diag_out = nullptr,
+                bool transpose_blocks = false) {
+  SoaMat M;
+  M.n_rows = Pp.n_rows;
+  M.n_cols = Pp.n_cols;
+  M.br = br;
+  M.bc = bc;
+  M.nnz = Pp.nnz();
+  M.group = pick_group(M.nnz, M.n_rows);
+  M.rp = ar.upload(to_i32(Pp.rp), s);
+  M.col = ar.upload(Pp.col, s);
+  int64_t *src_d = ar.upload(src, s);
+  double *v = ar.alloc<double>(size_t(M.nnz) * br * bc);
+  if (transpose_blocks) {
+    // input blocks are bc x br; transpose into a temporary AoS array, then to planes
+    double *tmp = ar.alloc<double>(size_t(M.nnz) * br * bc);
+    hip_check(launch_transpose_blocks(M.nnz, bc, br, src_d, aos, tmp, s), "transpose");
+    std::vector<int64_t> iota(size_t(M.nnz));
+    for (int64_t q = 0; q < M.nnz; ++q) iota[q] = q;
+    int64_t *id = ar.upload(iota, s);
+    hip_check(launch_gather_soa(M.nnz, br * bc, id, tmp, v, s), "gather_soa");
+    hip_check(hipStreamSynchronize(s), "sync");
+    ar.release(tmp);
+    ar.release(id);
+  } else {
+    hip_check(launch_gather_soa(M.nnz, br * bc, src_d, aos, v, s), "gather_soa");
+    hip_check(hipStreamSynchronize(s), "sync");
+  }
+  ar.release(src_d);
+  M.val = v;
+  if (diag_out) {
+    std::vector<int> dg(size_t(M.n_rows), -1);
+    for (int i = 0; i < M.n_rows; ++i)
+      for (int64_t q = Pp.rp[i]; q < Pp.rp[i + 1]; ++q)
+        if (Pp.col[q] == i) dg[i] = int(q);
+    *diag_out = dg;
+    M.diag = ar.upload(dg, s);
+  }
+  return M;
+}
+
+
+void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
+  Level &L = h->lv[l];
+  DevArena &ar = h->arena;
+  const bool coarsest = (l + 1 == h->lv.size());
+  const int bs = L.bs;
+  // colour-major numbering (identity on the coarsest level, which has no smoother)
+  L.perm.resize(size_t(L.n));
+  L.inv.resize(size_t(L.n));
+  if (coarsest) {
+    for (int i = 0; i < L.n; ++i) L.perm[i] = L.inv[i] = i;
+    L.ncolors = 0;
+    L.color.assign(size_t(L.n), -1);
+    L.color_ptr = {0, L.n};
+  } else {
+    L.color = greedy_coloring(L.A, L.ncolors);
+    L.color_ptr.assign(size_t(L.ncolors) + 1, 0);
+    for (int c : L.color) L.color_ptr[c + 1]++;
+    for (int c = 0; c < L.ncolors; ++c) L.color_ptr[c + 1] += L.color_ptr[c];
+    std::vector<int> fill(L.color_ptr.begin(), L.color_ptr.end() - 1);
+    for (int i = 0; i < L.n; ++i) L.perm[fill[L.color[i]]++] = i;
+    for (int r = 0; r < L.n; ++r) L.inv[L.perm[r]] = r;
+  }
+  L.perm_d = ar.upload(L.perm, s);
+  std::vector<int64_t> src;
+  const Pattern Ap = permute_pattern(L.A, L.perm, L.inv, src);
+  std::vector<int> dg;
+  L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg);
+  L.nnz_lower = 0;
+  for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
+  if (coarsest) {
+    L.b = ar.alloc<double>(size_t(L.n) * bs);
+    L.x = ar.alloc<double>(size_t(L.n) * bs);
+    return;
+  }
+  // smoother diagonals (natural), then rows gathered into colour-major order
+  double *Dn = ar.alloc<double>(size_t(L.n) * bs * bs);
+  hip_check(launch_diag_pinv(L.n, bs, L.A_rp, L.A_col, L.A_val, Dn, h->prm.pinv_rtol, s), "diag_pinv");
+  L.Dinv = ar.alloc<double>(size_t(L.n) * bs * bs);
+  hip_check(launch_gather_rows(L.n, bs * bs, L.perm_d, Dn, L.Dinv, s), "gather_rows");
+  hip_check(hipStreamSynchronize(s), "sync");
+  ar.release(Dn);
+  // transfers: fine rows colour-major, coarse columns in the coarse level's colour-major order
+  const Level &C = h->lv[l + 1];
+  std::vector<int64_t> srcP;
+  const Pattern Pp = permute_rect(L.P, L.perm, C.inv, srcP);
+  L.Pm = make_soa(ar, Pp, srcP, bs, L.kc, L.P_val, s);
+  std::vector<int64_t> srcT;
+  const Pattern Rp = transpose_pattern(Pp, srcT);
+  std::vector<int64_t> srcR(srcT.size());
+  for (size_t q = 0; q < srcT.size(); ++q) srcR[q] = srcP[size_t(srcT[q])];
+  L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true);
+  L.r = ar.alloc<double>(size_t(L.n) * bs);
+  if (l > 0) {
+    L.b = ar.alloc<double>(size_t(L.n) * bs);
+    L.x = ar.alloc<double>(size_t(L.n) * bs);
+  }
+}
+
+void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
+  Level &L = h->lv.back();
+  const int bs = L.bs;
+  const int N = L.n * bs;
+  if (N > 4000)
+    fail(EAMG_ERR_INVALID_ARG, "coarsening stalled: coarsest level has " + std::to_string(N) + " dofs");
+  const std::vector<double> vals = download(L.A_val, size_t(L.A.nnz()) * bs * bs, s);
+  Mat Ad(N, N);
+  for (int i = 0; i < L.n; ++i)
+    for (int64_t q = L.A.rp[i]; q < L.A.rp[i + 1]; ++q) {
+      const int j = L.A.col[q];
+      for (int a = 0; a < bs; ++a)
+        for (int c = 0; c < bs; ++c) Ad(i * bs + a, j * bs + c) = vals[size_t(q) * bs * bs + a * bs + c];
+    }
+  // regularization: add the projector onto the kernel of every diagonal block
+  for (int i = 0; i < L.n; ++i) {
+    Mat blk(bs, bs);
+    for (int a = 0; a < bs; ++a)
+      for (int c = 0; c < bs; ++c) blk(a, c) = Ad(i * bs + a, i * bs + c);
+    const Mat U0 = kernel_basis(blk, h->prm.pinv_rtol);
+    for (int a = 0; a < bs; ++a)
+      for (int c = 0; c < bs; ++c) {
+        double v = 0.0;
+        for (int t = 0; t < U0.c; ++t) v += U0(a, t) * U0(c, t);
+        Ad(i * bs + a, i * bs + c) += v;
+      }
+  }
+  if (!cholesky(Ad)) fail(EAMG_ERR_NOT_SPD, "coarsest level matrix is not positive definite");
+  // Y = L^{-1} (forward substitution on the identity), A^{-1} = Y^T Y
+  Mat Y(N, N);
+  for (int c = 0; c < N; ++c)
+    for (int i = c; i < N; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int t = c; t < i; ++t) v -= Ad(i, t) * Y(t, c);
+      Y(i, c) = v / Ad(i, i);
+    }
+  std::vector<double> inv(size_t(N) * N, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = i; j < N; ++j) {
+      double v = 0.0;
+      for (int t = std::max(i, j); t < N; ++t) v += Y(t, i) * Y(t, j);
+      inv[size_t(i) * N + j] = v;
+      inv[size_t(j) * N + i] = v;
+    }
+  h->nL = N;
+  h->Ainv = h->arena.upload(inv, s);
+  hip_check(hipStreamSynchronize(s), "sync");
+}
+
+void vcycle(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t s) {
+  Level &L = h->lv[l];
+  if (l + 1 == h->lv.size()) {
+    hip_check(launch_dense_gemv(h->nL, h->Ainv, b, x, s), "coarsest");
+    return;
+  }
+  for (int c = 0; c < L.ncolors; ++c)
+    hip_check(launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs_fwd");
+  hip_check(launch_resid_upper(L.Am, x, L.r, s), "resid_upper");
+  Level &C = h->lv[l + 1];
+  hip_check(launch_rect(L.Rm, L.r, C.b, false, s), "restrict");
+  vcycle(h, l + 1, C.b, C.x, s);
+  hip_check(launch_rect(L.Pm, C.x, x, true, s), "prolong");
+  for (int c = L.ncolors - 1; c >= 0; --c)
+    hip_check(launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs_bwd");
+}
+
+void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
+  hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s), "copy");
+  hip_check(hipStreamSynchronize(s), "sync");
+}
+
+template <class F>
+eamg_status guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return EAMG_OK;
+  } catch (const Failure &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return EAMG_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return EAMG_ERR_INVALID_ARG;
+  }
+}
+
+double bytes_bcsr(int64_t nnzb, int r, int c, int rows) {
+  return double(nnzb) * (r * c * 8.0 + 4.0) + 4.0 * (rows + 1);
+}
+
+}  // namespace
+}  // namespace eamg
+
+using namespace eamg;
+
+extern "C" {
+
+void eamg_default_setup_params(eamg_setup_params *out) {
+  if (out) *out = defaults();
+}
+
+void eamg_default_solve_params(eamg_solve_params *out) {
+  if (!out) return;
+  out->rtol = 1e-8;
+  out->max_it = 1000;
+  out->use_x0 = 0;
+  out->precond = 1;
+}
+
+const char *eamg_last_error(void) { return g_last_error.c_str(); }
+
+void eamg_destroy(eamg_hierarchy *h) { delete h; }
+
+eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, void *stream,
+                       eamg_hierarchy **out) {
+  return guarded([&] {
+    if (!out) fail(EAMG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    validate_problem(pb);
+    const eamg_setup_params prm = params ? *params : defaults();
+    validate_params(prm);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::unique_ptr<eamg_hierarchy> h(new eamg_hierarchy());
+    const int n = pb->n_vertices, dim = pb->dim;
+    h->dim = dim;
+    h->k = pb->k_kernel;
+    h->n0 = n;
+    h->prm = prm;
+    AuxLevel aux;
+    std::string err;
+    if (!finest_aux(dim, n, pb->coords, pb->row_ptr, pb->col_idx, pb->vals, pb->edges, pb->n_edges,
+                    aux, err))
+      fail(EAMG_ERR_INVALID_ARG, err);
+    DevArena &ar = h->arena;
+    {
+      Level L0;
+      L0.n = n;
+      L0.bs = dim;
+      L0.A = pattern_from_input(pb);
+      L0.A_rp = ar.upload(L0.A.rp, s);
+      L0.A_col = ar.upload(L0.A.col, s);
+      L0.A_val = ar.upload(pb->vals, size_t(L0.A.nnz()) * dim * dim, s);
+      std::vector<uint8_t> dir(static_cast<size_t>(n), 0);
+      if (pb->dirichlet)
+        for (int i = 0; i < n; ++i) dir[i] = pb->dirichlet[i] ? 1 : 0;
+      h->dir = ar.upload(dir, s);
+      hip_check(launch_dirichlet(n, dim, L0.A_rp, L0.A_col, L0.A_val, h->dir, s), "dirichlet");
+      hip_check(hipStreamSynchronize(s), "sync");
+      h->lv.push_back(std::move(L0));
+    }
+    std::vector<char> vd(static_cast<size_t>(n), 0);
+    if (pb->dirichlet)
+      for (int i = 0; i < n; ++i) vd[i] = pb->dirichlet[i] ? 1 : 0;
+    MatchParams mp;
+    mp.sigma = prm.sigma;
+    mp.rounds = prm.rounds;
+    mp.tie_rtol = prm.tie_rtol;
+    mp.tau = prm.pinv_rtol;
+    while (true) {
+      const size_t l = h->lv.size() - 1;
+      {
+        const Level &L = h->lv[l];
+        if (int64_t(L.bs) * L.n < prm.coarsest_max_dofs || int(h->lv.size()) >= prm.max_levels) break;
+      }
+      MatchResult mr = successive_matching(aux, l == 0 ? vd : std::vector<char>(), mp);
+      const int nc = int(mr.aggs.size());
+      if (nc == 0 || double(nc) > 0.9 * h->lv[l].n) break;
+      Level &L = h->lv[l];
+      const int bs = L.bs, kc = aux.k;
+      L.agg.assign(size_t(L.n), -1);
+      for (int I = 0; I < nc; ++I)
+        for (int i : mr.aggs[I]) L.agg[i] = I;
+      const ProlongPlan pl = plan_prolongation(L.A, aux, L.agg, mr.dmask,
+                                               l == 0 ? prm.cap_std_l0 : prm.cap_std, prm.cap_aux,
+                                               prm.tie_rtol);
+      L.P = pl.P;
+      L.kc = kc;
+      const int64_t nP = L.P.nnz();
+      // auxiliary smoothed prolongation, numeric (device)
+      int *type_d = ar.upload(pl.type, s);
+      int *agg_d = ar.upload(L.agg, s);
+      double *x_d = ar.upload(aux.x, s);
+      double *xc_d = ar.upload(mr.ccoords, s);
+      int64_t *Prp_d = ar.upload(L.P.rp, s);
+      int *Pcol_d = ar.upload(L.P.col, s);
+      int64_t *Fptr_d = ar.upload(pl.F_ptr, s);
+      int *Fvtx_d = ar.upload(pl.F_vtx, s);
+      int *Fedge_d = ar.upload(pl.F_edge, s);
+      double *E_d = ar.upload(aux.E, s);
+      L.P_val = ar.alloc<double>(size_t(nP) * bs * kc);
+      PsArgs a;
+      a.n = L.n;
+      a.k = kc;
+      a.bs = bs;
+      a.type = type_d;
+      a.agg = agg_d;
+      a.x = x_d;
+      a.xc = xc_d;
+      a.Prp = Prp_d;
+      a.Pcol = Pcol_d;
+      a.Arp = L.A_rp;
+      a.Acol = L.A_col;
+      a.Aval = L.A_val;
+      a.Fptr = Fptr_d;
+      a.Fvtx = Fvtx_d;
+      a.Fedge = Fedge_d;
+      a.E = E_d;
+      a.omega = prm.omega;
+      a.tau = prm.pinv_rtol;
+      a.Pval = L.P_val;
+      hip_check(launch_ps_numeric(a, s), "ps_numeric");
+      // Galerkin product A_{l+1} = R (A_l P_s), R = P_s^T (structural patterns on the host)
+      const Pattern AP = spgemm_symbolic(L.A, L.P);
+      std::vector<int64_t> srcT;
+      const Pattern Rt = transpose_pattern(L.P, srcT);
+      Pattern Ac = spgemm_symbolic(Rt, AP);
+      int *APcrow = ar.upload(crow_of(AP), s);
+      int *APcol = ar.upload(AP.col, s);
+      int64_t *APrp = ar.upload(AP.rp, s);
+      int64_t *Rrp = ar.upload(Rt.rp, s);
+      int *Rcol = ar.upload(Rt.col, s);
+      int64_t *srcT_d = ar.upload(srcT, s);
+      int *Accrow = ar.upload(crow_of(Ac), s);
+      double *R_val = ar.alloc<double>(size_t(nP) * kc * bs);
+      hip_check(launch_transpose_blocks(nP, bs, kc, srcT_d, L.P_val, R_val, s), "transpose");
+      double *AP_val = ar.alloc<double>(size_t(AP.nnz()) * bs * kc);
+      hip_check(launch_spgemm_numeric(AP.nnz(), bs, bs, kc, APcrow, APcol, L.A_rp, L.A_col, L.A_val,
+                                      Prp_d, Pcol_d, L.P_val, AP_val, s),
+                "spgemm AP");
+      Level C;
+      C.n = nc;
+      C.bs = kc;
+      C.A = std::move(Ac);
+      C.A_rp = ar.upload(C.A.rp, s);
+      C.A_col = ar.upload(C.A.col, s);
+      C.A_val = ar.alloc<double>(size_t(C.A.nnz()) * kc * kc);
+      hip_check(launch_spgemm_numeric(C.A.nnz(), kc, bs, kc, Accrow, C.A_col, Rrp, Rcol, R_val, APrp,
+                                      APcol, AP_val, C.A_val, s),
+                "spgemm RAP");
+      hip_check(hipStreamSynchronize(s), "sync");
+      for (void *p : {(void *)type_d, (void *)agg_d, (void *)x_d, (void *)xc_d, (void *)Prp_d,
+                      (void *)Pcol_d, (void *)Fptr_d, (void *)Fvtx_d, (void *)Fedge_d, (void *)E_d,
+                      (void *)APcrow, (void *)APcol, (void *)APrp, (void *)Rrp, (void *)Rcol,
+                      (void *)srcT_d, (void *)Accrow, (void *)R_val, (void *)AP_val})
+        ar.release(p);
+      aux = std::move(mr.coarse);
+      h->lv.push_back(std::move(C));
+    }
+    coarsest_factor(h.get(), s);
+    for (size_t l = h->lv.size(); l-- > 0;) build_level_layout(h.get(), l, s);
+    const int64_t N0 = int64_t(n) * dim;
+    h->x = ar.alloc<double>(size_t(N0));
+    h->r = ar.alloc<double>(size_t(N0));
+    h->z = ar.alloc<double>(size_t(N0));
+    h->p = ar.alloc<double>(size_t(N0));
+    h->q = ar.alloc<double>(size_t(N0));
+    h->bp = ar.alloc<double>(size_t(N0));
+    const SoaMat &A0 = h->lv[0].Am;
+    const int spmv_blocks = (A0.n_rows + (256 / A0.group) - 1) / (256 / A0.group);
+    h->part = ar.alloc<double>(size_t(std::max(dot_blocks(N0), spmv_blocks)));
+    h->scal = ar.alloc<double>(SC_COUNT);
+    hip_check(hipHostMalloc(reinterpret_cast<void **>(&h->scal_h), sizeof(double) * SC_COUNT, 0),
+              "hipHostMalloc");
+    hip_check(hipStreamSynchronize(s), "sync");
+    *out = h.release();
+  });
+}
+
+eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, void *stream) {
+  return guarded([&] {
+    if (!h || !r_dev || !z_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Level &L0 = h->lv[0];
+    hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, r_dev, h->bp, s), "perm_in");
+    vcycle(h, 0, h->bp, h->z, s);
+    hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, h->z, z_dev, s), "perm_out");
+    hip_check(hipStreamSynchronize(s), "sync");
+  });
+}
+
+eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
+                       const eamg_solve_params *params, void *stream, eamg_solve_info *info) {
+  int iters = 0;
+  double rel = 0.0, rel_true = 0.0, ms = 0.0;
+  bool converged = false;
+  const eamg_status st = guarded([&] {
+    if (!h || !b_dev || !x_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    if (b_dev == x_dev) fail(EAMG_ERR_INVALID_ARG, "b and x may not alias");
+    eamg_solve_params sp;
+    eamg_default_solve_params(&sp);
+    if (params) sp = *params;
+    if (sp.max_it < 1) fail(EAMG_ERR_INVALID_ARG, "max_it must be >= 1");
+    if (!(sp.rtol >= 0.0)) fail(EAMG_ERR_INVALID_ARG, "rtol must be >= 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Level &L0 = h->lv[0];
+    const int64_t N = int64_t(L0.n) * L0.bs;
+    const int nd = dot_blocks(N);
+    const SoaMat &A = L0.Am;
+    const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    struct EvGuard {
+      hipEvent_t a, b;
+      ~EvGuard() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } eg{e0, e1};
+    hip_check(hipEventRecord(e0, s), "event");
+    hip_check(launch_fill(SC_COUNT, 0.0, h->scal, s), "fill");
+    hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, b_dev, h->bp, s), "perm_in");
+    hip_check(launch_finite_check(N, h->bp, h->scal, SC_NONFINITE, s), "finite");
+    hip_check(launch_dot(N, h->bp, h->bp, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_BB, RED_STORE, s), "reduce");
+    if (sp.use_x0) {
+      hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, x_dev, h->x, s), "perm_in");
+      hip_check(launch_spmv(A, h->x, h->q, nullptr, s), "spmv");
+      hip_check(launch_sub(N, h->bp, h->q, h->r, s), "sub");
+    } else {
+      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
+      hip_check(launch_copy(N, h->bp, h->r, s), "copy");
+    }
+    fetch_scalars(h, s);
+    if (h->scal_h[SC_NONFINITE] != 0.0) fail(EAMG_ERR_BREAKDOWN, "right-hand side is not finite");
+    const double bnorm = std::sqrt(h->scal_h[SC_BB]);
+    if (bnorm == 0.0) {
+      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
+      converged = true;
+    } else {
+      auto precondition = [&]() {
+        if (sp.precond)
+          vcycle(h, 0, h->r, h->z, s);
+        else
+          hip_check(launch_copy(N, h->r, h->z, s), "copy");
+      };
+      precondition();
+      hip_check(launch_copy(N, h->z, h->p, s), "copy");
+      hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+      hip_check(launch_reduce(nd, h->part, h->scal, SC_RHO, RED_STORE, s), "reduce");
+      fetch_scalars(h, s);
+      const double rho0 = h->scal_h[SC_RHO];
+      if (!(rho0 > 0.0) || !std::isfinite(rho0)) {
+        // r = b - A x0 may already be zero (exact x0); otherwise the preconditioner is not SPD
+        hip_check(launch_dot(N, h->r, h->r, h->part, s), "dot");
+        hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+        fetch_scalars(h, s);
+        if (h->scal_h[SC_RR] != 0.0) fail(EAMG_ERR_BREAKDOWN, "r.z <= 0 at the start (preconditioner not SPD)");
+        converged = true;
+      }
+      while (!converged && iters < sp.max_it) {
+        hip_check(launch_spmv(A, h->p, h->q, h->part, s), "spmv");
+        hip_check(launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s), "reduce");
+        hip_check(launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s), "update_xr");
+        hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+        ++iters;
+        fetch_scalars(h, s);
+        if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
+        const double rr = h->scal_h[SC_RR];
+        if (!std::isfinite(rr)) fail(EAMG_ERR_BREAKDOWN, "residual is not finite");
+        rel = std::sqrt(rr) / bnorm;
+        if (std::sqrt(rr) <= sp.rtol * bnorm) {
+          converged = true;
+          break;
+        }
+        if (iters >= sp.max_it) break;
+        precondition();
+        hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+        hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
+        hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
+      }
+    }
+    // true residual
+    hip_check(launch_spmv(A, h->x, h->q, nullptr, s), "spmv");
+    hip_check(launch_sub(N, h->bp, h->q, h->z, s), "sub");
+    hip_check(launch_dot(N, h->z, h->z, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+    hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, h->x, x_dev, s), "perm_out");
+    hip_check(hipEventRecord(e1, s), "event");
+    fetch_scalars(h, s);
+    const double bn = std::sqrt(h->scal_h[SC_BB]);
+    rel_true = bn > 0.0 ? std::sqrt(h->scal_h[SC_RR]) / bn : 0.0;
+    if (bn == 0.0) rel = 0.0;
+    float fms = 0.0f;
+    hip_check(hipEventElapsedTime(&fms, e0, e1), "event");
+    ms = fms;
+  });
+  if (info) {
+    info->iterations = iters;
+    info->rel_res = rel;
+    info->rel_res_true = rel_true;
+    info->ms = ms;
+  }
+  if (st == EAMG_OK && !converged) {
+    g_last_error = "iteration limit reached";
+    return EAMG_NOT_CONVERGED;
+  }
+  return st;
+}
+
+eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,
+                       int64_t *per_level_nnzb, double *vc, double *oc) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (n_levels) *n_levels = int32_t(h->lv.size());
+    double sn = 0.0, snz = 0.0;
+    for (size_t l = 0; l < h->lv.size(); ++l) {
+      const Level &L = h->lv[l];
+      if (per_level_n) per_level_n[l] = L.n;
+      if (per_level_nnzb) per_level_nnzb[l] = L.A.nnz();
+      sn += L.n;
+      snz += double(L.A.nnz()) * L.bs * L.bs;
+    }
+    const Level &L0 = h->lv[0];
+    if (vc) *vc = sn / L0.n;
+    if (oc) *oc = snz / (double(L0.A.nnz()) * L0.bs * L0.bs);
+  });
+}
+
+eamg_status eamg_level_info_get(const eamg_hierarchy *h, int32_t level, eamg_level_info *out) {
+  return guarded([&] {
+    if (!h || !out) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    if (level < 0 || level >= int(h->lv.size())) fail(EAMG_ERR_INVALID_ARG, "level out of range");
+    const Level &L = h->lv[level];
+    const bool last = level + 1 == int(h->lv.size());
+    out->n = L.n;
+    out->bs = L.bs;
+    out->nnzb_A = L.A.nnz();
+    out->n_coarse = last ? 0 : h->lv[level + 1].n;
+    out->k_coarse = last ? 0 : L.kc;
+    out->nnzb_P = last ? 0 : L.P.nnz();
+    out->n_colors = last ? 0 : L.ncolors;
+  });
+}
+
+eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *agg,
+                              int32_t *P_rowptr, int32_t *P_col, double *P_val, int32_t *A_rowptr,
+                              int32_t *A_col, double *A_val, int32_t *color) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (level < 0 || level >= int(h->lv.size())) fail(EAMG_ERR_INVALID_ARG, "level out of range");
+    const Level &L = h->lv[level];
+    const bool last = level + 1 == int(h->lv.size());
+    hipStream_t s = nullptr;
+    if (agg)
+      for (int i = 0; i < L.n; ++i) agg[i] = last ? -1 : L.agg[i];
+    if (color)
+      for (int i = 0; i < L.n; ++i) color[i] = last ? -1 : L.color[i];
+    if (!last) {
+      if (P_rowptr)
+        for (int i = 0; i <= L.n; ++i) P_rowptr[i] = int32_t(L.P.rp[i]);
+      if (P_col) std::copy(L.P.col.begin(), L.P.col.end(), P_col);
+      if (P_val) {
+        const auto v = download(L.P_val, size_t(L.P.nnz()) * L.bs * L.kc, s);
+        std::copy(v.begin(), v.end(), P_val);
+      }
+    }
+    if (A_rowptr)
+      for (int i = 0; i <= L.n; ++i) A_rowptr[i] = int32_t(L.A.rp[i]);
+    if (A_col) std::copy(L.A.col.begin(), L.A.col.end(), A_col);
+    if (A_val) {
+      const auto v = download(L.A_val, size_t(L.A.nnz()) * L.bs * L.bs, s);
+      std::copy(v.begin(), v.end(), A_val);
+    }
+  });
+}
+
+eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes, double *iteration_bytes) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    double v = 0.0;
+    for (size_t l = 0; l < h->lv.size(); ++l) {
+      const Level &L = h->lv[l];
+      const double vec = double(L.n) * L.bs * 8.0;
+      const double blk = L.bs * L.bs * 8.0 + 4.0;
+      if (l + 1 == h->lv.size()) {
+        v += double(h->nL) * h->nL * 8.0 + 2.0 * vec;
+        break;
+      }
+      const double vecc = double(h->lv[l + 1].n) * L.kc * 8.0;
+      const double dinv = double(L.n) * L.bs * L.bs * 8.0;
+      const double upper = double(L.A.nnz() - L.nnz_lower - L.n);
+      // forward sweep: lower blocks + diagonal, row offsets + diag index, D^+, b, x (write and
+      // gather), r (write)
+      v += double(L.nnz_lower + L.n) * blk + 8.0 * (L.n + 1) + dinv + 4.0 * vec;
+      // residual completion: upper blocks, offsets, x gather, r read/write
+      v += upper * blk + 8.0 * (L.n + 1) + 3.0 * vec;
+      // restriction and prolongation
+      v += bytes_bcsr(L.P.nnz(), L.kc, L.bs, h->lv[l + 1].n) + vec + vecc;
+      v += bytes_bcsr(L.P.nnz(), L.bs, L.kc, L.n) + vecc + 2.0 * vec;
+      // backward sweep: full A, D^+, b, x (gather + read/write)
+      v += bytes_bcsr(L.A.nnz(), L.bs, L.bs, L.n) + dinv + 3.0 * vec;
+    }
+    const Level &L0 = h->lv[0];
+    const double vec0 = double(L0.n) * L0.bs * 8.0;
+    // PCG: SpMV (A_0, p, q), x/r update (x rw, r rw, p, q), r.z (r, z), p update (z, p rw)
+    const double it = bytes_bcsr(L0.A.nnz(), L0.bs, L0.bs, L0.n) + 2.0 * vec0 + 6.0 * vec0 +
+                      2.0 * vec0 + 3.0 * vec0;
+    if (vcycle_bytes) *vcycle_bytes = v;
+    if (iteration_bytes) *iteration_bytes = it + v;
+  });
+}
+
+eamg_status eamg_host_match(int32_t k, int32_t n, const double *coords, int64_t n_edges,
+                            const int32_t *edges, const double *E, const double *M,
+                            const uint8_t *vd, const eamg_setup_params *params, int32_t *out_agg,
+                            int32_t *out_nc, double *out_ccoords, double *out_margin) {
+  return guarded([&] {
+    if (k != 1 && k != 6) fail(EAMG_ERR_UNSUPPORTED_KERNEL, "k must be 1 or 6");
+    if (n < 0 || n_edges < 0 || !coords || !M || !out_agg || !out_nc || (n_edges && (!edges || !E)))
+      fail(EAMG_ERR_INVALID_ARG, "bad arguments");
+    const eamg_setup_params prm = params ? *params : defaults();
+    validate_params(prm);
+    AuxLevel lev;
+    lev.n = n;
+    lev.k = k;
+    lev.x.assign(coords, coords + size_t(3) * n);
+    lev.e0.resize(size_t(n_edges));
+    lev.e1.resize(size_t(n_edges));
+    for (int64_t e = 0; e < n_edges; ++e) {
+      lev.e0[e] = edges[2 * e];
+      lev.e1[e] = edges[2 * e + 1];
+      if (lev.e0[e] < 0 || lev.e1[e] >= n || lev.e0[e] >= lev.e1[e])
+        fail(EAMG_ERR_INVALID_ARG, "edges must satisfy 0 <= i < j < n");
+      if (e && (lev.e0[e - 1] > lev.e0[e] || (lev.e0[e - 1] == lev.e0[e] && lev.e1[e - 1] >= lev.e1[e])))
+        fail(EAMG_ERR_INVALID_ARG, "edges must be strictly ascending");
+    }
+    lev.E.assign(E, E + size_t(n_edges) * k * k);
+    lev.M.assign(M, M + size_t(n) * k * k);
+    lev.build_adjacency();
+    std::vector<char> vdm(static_cast<size_t>(n), 0);
+    if (vd)
+      for (int i = 0; i < n; ++i) vdm[i] = vd[i] ? 1 : 0;
+    MatchParams mp;
+    mp.sigma = prm.sigma;
+    mp.rounds = prm.rounds;
+    mp.tie_rtol = prm.tie_rtol;
+    mp.tau = prm.pinv_rtol;
+    const MatchResult mr = successive_matching(lev, vdm, mp);
+    for (int i = 0; i < n; ++i) out_agg[i] = -1;
+    for (size_t I = 0; I < mr.aggs.size(); ++I)
+      for (int i : mr.aggs[I]) out_agg[i] = int32_t(I);
+    *out_nc = int32_t(mr.aggs.size());
+    if (out_ccoords) std::copy(mr.ccoords.begin(), mr.ccoords.end(), out_ccoords);
+    if (out_margin) *out_margin = mr.min_margin;
+  });
+}
+
+}  // extern "C"

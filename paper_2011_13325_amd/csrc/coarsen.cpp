@@ -1,0 +1,727 @@
+// Host-side auxiliary topology, coarsening criteria and successive matching.
+// See coarsen.hpp for the passages each part follows.
+#include "coarsen.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <limits>
+#include <unordered_map>
+
+namespace eamg {
+
+namespace {
+
+const double kInf = std::numeric_limits<double>::infinity();
+
+// ---- small square matrices --------------------------------------------------------------
+
+Sq sq_mul(const Sq &A, const Sq &B) {
+  const int k = A.k;
+  Sq C(k);
+  for (int i = 0; i < k; ++i)
+    for (int l = 0; l < k; ++l) {
+      const double ail = A(i, l);
+      if (ail == 0.0) continue;
+      for (int j = 0; j < k; ++j) C(i, j) += ail * B(l, j);
+    }
+  return C;
+}
+
+Sq sq_t(const Sq &A) {
+  Sq T(A.k);
+  for (int i = 0; i < A.k; ++i)
+    for (int j = 0; j < A.k; ++j) T(j, i) = A(i, j);
+  return T;
+}
+
+// A^T B C
+Sq sq_t3(const Sq &A, const Sq &B, const Sq &C) { return sq_mul(sq_mul(sq_t(A), B), C); }
+
+void sq_axpy(Sq &Y, double s, const Sq &X) {
+  for (int i = 0; i < Y.k * Y.k; ++i) Y.a[i] += s * X.a[i];
+}
+
+Sq sq_sym(const Sq &X) {
+  Sq S(X.k);
+  for (int i = 0; i < X.k; ++i)
+    for (int j = 0; j < X.k; ++j) S(i, j) = 0.5 * (X(i, j) + X(j, i));
+  return S;
+}
+
+double sq_frob(const Sq &X) {
+  double s = 0.0;
+  for (int i = 0; i < X.k * X.k; ++i) s += X.a[i] * X.a[i];
+  return std::sqrt(s);
+}
+
+double sq_trace(const Sq &X) {
+  double s = 0.0;
+  for (int i = 0; i < X.k; ++i) s += X(i, i);
+  return s;
+}
+
+// Cyclic Jacobi, eigenvalues ascending in w, eigenvectors as columns of V.
+void sq_eigh(const Sq &Ain, double *w, Sq &V) {
+  const int n = Ain.k;
+  Sq A = Ain;
+  V = Sq(n);
+  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  double fro2 = 0.0;
+  for (int i = 0; i < n * n; ++i) fro2 += A.a[i] * A.a[i];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A(p, q) * A(p, q);
+    if (off <= 1e-40 * fro2 || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A(p, q);
+        if (apq == 0.0) continue;
+        const double theta = (A(q, q) - A(p, p)) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A(k, p), akq = A(k, q);
+          A(k, p) = cs * akp - sn * akq;
+          A(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A(p, k), aqk = A(q, k);
+          A(p, k) = cs * apk - sn * aqk;
+          A(q, k) = sn * apk + cs * aqk;
+        }
+        A(p, q) = 0.0;
+        A(q, p) = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V(k, p), vkq = V(k, q);
+          V(k, p) = cs * vkp - sn * vkq;
+          V(k, q) = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  int idx[6];
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx, idx + n, [&](int x, int y) { return A(x, x) < A(y, y); });
+  Sq Vs(n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = A(idx[j], idx[j]);
+    for (int i = 0; i < n; ++i) Vs(i, j) = V(i, idx[j]);
+  }
+  V = Vs;
+}
+
+Sq sq_pinv(const Sq &X, double tau) {
+  const int n = X.k;
+  double w[6];
+  Sq V;
+  sq_eigh(sq_sym(X), w, V);
+  Sq P(n);
+  const double lmax = w[n - 1];
+  if (lmax <= 0.0) return P;
+  for (int k = 0; k < n; ++k) {
+    if (!(w[k] > tau * lmax)) continue;
+    const double inv = 1.0 / w[k];
+    for (int i = 0; i < n; ++i) {
+      const double vi = V(i, k) * inv;
+      for (int j = 0; j < n; ++j) P(i, j) += vi * V(j, k);
+    }
+  }
+  return P;
+}
+
+Sq sq_harmonic(const Sq &A, const Sq &B, double tau) {
+  Sq S = A;
+  sq_axpy(S, 1.0, B);
+  return sq_sym(sq_mul(sq_mul(A, sq_pinv(S, tau)), B));
+}
+
+double sq_genmax(const Sq &Lin, const Sq &Rin, double tau) {
+  const Sq L = sq_sym(Lin), R = sq_sym(Rin);
+  const int n = L.k;
+  const double nL = sq_frob(L);
+  if (nL == 0.0) return 0.0;
+  double w[6];
+  Sq U;
+  sq_eigh(R, w, U);
+  const double lmax = w[n - 1];
+  int keep[6], drop[6], nk = 0, nd = 0;
+  for (int k = 0; k < n; ++k) {
+    if (lmax > 0.0 && w[k] > tau * lmax)
+      keep[nk++] = k;
+    else
+      drop[nd++] = k;
+  }
+  if (nd) {
+    // || U0^T L U0 ||_F
+    double s = 0.0;
+    for (int a = 0; a < nd; ++a)
+      for (int b = 0; b < nd; ++b) {
+        double v = 0.0;
+        for (int i = 0; i < n; ++i) {
+          double li = 0.0;
+          for (int j = 0; j < n; ++j) li += L(i, j) * U(j, drop[b]);
+          v += U(i, drop[a]) * li;
+        }
+        s += v * v;
+      }
+    if (std::sqrt(s) > tau * nL) return kInf;
+  }
+  if (!nk) return 0.0;
+  // W = U_keep / sqrt(w_keep); G = W^T L W
+  Sq G(nk);
+  for (int a = 0; a < nk; ++a)
+    for (int b = 0; b < nk; ++b) {
+      double v = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double li = 0.0;
+        for (int j = 0; j < n; ++j) li += L(i, j) * U(j, keep[b]);
+        v += U(i, keep[a]) * li;
+      }
+      G(a, b) = v / (std::sqrt(w[keep[a]]) * std::sqrt(w[keep[b]]));
+    }
+  double g[6];
+  Sq Gv;
+  sq_eigh(sq_sym(G), g, Gv);
+  return g[nk - 1];
+}
+
+Sq sq_q(const double *t, int k) {
+  Sq Q(k);
+  for (int i = 0; i < k; ++i) Q(i, i) = 1.0;
+  if (k == 6) {
+    double S[9];
+    skew3(t, S);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q(i, 3 + j) = S[3 * i + j];
+  }
+  return Q;
+}
+
+Sq sq_qtrans(const double *xa, const double *xb, int k) {
+  const double t[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
+  return sq_q(t, k);
+}
+
+Sq sq_qhalf(const double *xa, const double *xb, int k) {
+  const double t[3] = {0.5 * (xb[0] - xa[0]), 0.5 * (xb[1] - xa[1]), 0.5 * (xb[2] - xa[2])};
+  return sq_q(t, k);
+}
+
+void mean_pos(const AuxLevel &lev, const std::vector<int> &members, double *out) {
+  std::vector<int> s = members;
+  std::sort(s.begin(), s.end());
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int i : s)
+    for (int d = 0; d < 3; ++d) acc[d] = acc[d] + lev.x[size_t(3) * i + d];
+  for (int d = 0; d < 3; ++d) out[d] = acc[d] / double(s.size());
+}
+
+// Q^{ab,T} E Q^{ab} of edge e seen from endpoint `at`.
+Sq pulled(const AuxLevel &lev, int64_t e, int at) {
+  const int other = lev.e0[e] == at ? lev.e1[e] : lev.e0[e];
+  const Sq Q = sq_qhalf(lev.xp(at), lev.xp(other), lev.k);
+  return sq_t3(Q, lev.Emat(e), Q);
+}
+
+}  // namespace
+
+// ---- AuxLevel -----------------------------------------------------------------------------
+
+void AuxLevel::build_adjacency() {
+  const int64_t mm = m();
+  nb_ptr.assign(size_t(n) + 1, 0);
+  for (int64_t e = 0; e < mm; ++e) {
+    nb_ptr[e0[e] + 1]++;
+    nb_ptr[e1[e] + 1]++;
+  }
+  for (int i = 0; i < n; ++i) nb_ptr[i + 1] += nb_ptr[i];
+  nb.assign(size_t(2 * mm), 0);
+  nb_e.assign(size_t(2 * mm), 0);
+  std::vector<int64_t> fill(nb_ptr.begin(), nb_ptr.end() - 1);
+  for (int64_t e = 0; e < mm; ++e) {
+    nb[fill[e0[e]]] = e1[e];
+    nb_e[fill[e0[e]]++] = int(e);
+    nb[fill[e1[e]]] = e0[e];
+    nb_e[fill[e1[e]]++] = int(e);
+  }
+  for (int i = 0; i < n; ++i) {
+    const int64_t s = nb_ptr[i], t = nb_ptr[i + 1];
+    std::vector<std::pair<int, int>> tmp;
+    tmp.reserve(size_t(t - s));
+    for (int64_t p = s; p < t; ++p) tmp.emplace_back(nb[p], nb_e[p]);
+    std::sort(tmp.begin(), tmp.end());
+    for (int64_t p = s; p < t; ++p) {
+      nb[p] = tmp[p - s].first;
+      nb_e[p] = tmp[p - s].second;
+    }
+  }
+}
+
+int AuxLevel::edge_id(int i, int j) const {
+  const int *b = nb.data() + nb_ptr[i], *e = nb.data() + nb_ptr[i + 1];
+  const int *p = std::lower_bound(b, e, j);
+  if (p == e || *p != j) return -1;
+  return nb_e[size_t(p - nb.data())];
+}
+
+Sq AuxLevel::Emat(int64_t e) const {
+  Sq S(k);
+  const double *p = &E[size_t(e) * k * k];
+  for (int i = 0; i < k * k; ++i) S.a[i] = p[i];
+  return S;
+}
+
+Sq AuxLevel::Mmat(int i) const {
+  Sq S(k);
+  const double *p = &M[size_t(i) * k * k];
+  for (int j = 0; j < k * k; ++j) S.a[j] = p[j];
+  return S;
+}
+
+// ---- finest level ---------------------------------------------------------------------------
+
+bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, const int32_t *col,
+                const double *vals, const int32_t *edges, int64_t n_edges, AuxLevel &out,
+                std::string &err) {
+  const int k = dim == 3 ? 6 : 1;
+  const int bs2 = dim * dim;
+  out = AuxLevel();
+  out.n = n;
+  out.k = k;
+  out.x.assign(coords, coords + size_t(3) * n);
+  auto find_block = [&](int i, int j) -> int64_t {
+    const int32_t *b = col + row_ptr[i], *e = col + row_ptr[i + 1];
+    const int32_t *p = std::lower_bound(b, e, j);
+    if (p == e || *p != j) return -1;
+    return int64_t(p - col);
+  };
+  std::vector<std::pair<int, int>> el;
+  if (edges) {
+    el.reserve(size_t(n_edges));
+    for (int64_t e = 0; e < n_edges; ++e) {
+      const int i = edges[2 * e], j = edges[2 * e + 1];
+      if (i < 0 || j < 0 || i >= n || j >= n || i >= j) {
+        err = "edges must satisfy 0 <= i < j < n_vertices";
+        return false;
+      }
+      if (find_block(i, j) < 0) {
+        err = "every edge must be an off-diagonal block position of A_N";
+        return false;
+      }
+      el.emplace_back(i, j);
+    }
+    std::sort(el.begin(), el.end());
+    if (std::adjacent_find(el.begin(), el.end()) != el.end()) {
+      err = "duplicate edge";
+      return false;
+    }
+  } else {
+    for (int i = 0; i < n; ++i)
+      for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+        if (col[p] > i) el.emplace_back(i, col[p]);
+  }
+  const int64_t m = int64_t(el.size());
+  out.e0.resize(size_t(m));
+  out.e1.resize(size_t(m));
+  out.E.assign(size_t(m) * k * k, 0.0);
+  out.M.assign(size_t(n) * k * k, 0.0);
+  for (int64_t e = 0; e < m; ++e) {
+    const int i = el[e].first, j = el[e].second;
+    out.e0[e] = i;
+    out.e1[e] = j;
+    const double *blk = vals + size_t(find_block(i, j)) * bs2;
+    double *Ee = &out.E[size_t(e) * k * k];
+    if (dim == 3) {
+      double c = 0.0;
+      for (int q = 0; q < 9; ++q) c += std::fabs(blk[q]);
+      c /= 9.0;
+      double t[3] = {coords[3 * j] - coords[3 * i], coords[3 * j + 1] - coords[3 * i + 1],
+                     coords[3 * j + 2] - coords[3 * i + 2]};
+      const double nt = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+      if (!(nt > 0.0)) {
+        err = "two vertices joined by an edge have the same position";
+        return false;
+      }
+      for (double &v : t) v /= nt;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Ee[6 * a + b] = c * t[a] * t[b];
+    } else {
+      Ee[0] = std::fabs(blk[0]);
+    }
+  }
+  if (dim == 1) {
+    for (int i = 0; i < n; ++i) {
+      double d = 0.0, off = 0.0;
+      for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        if (col[p] == i)
+          d = vals[p];
+        else
+          off += std::fabs(vals[p]);
+      }
+      out.M[i] = std::max(0.0, d - off);
+    }
+  }
+  out.build_adjacency();
+  return true;
+}
+
+// ---- coarse level (Thm thm:cemats) -------------------------------------------------------------
+
+AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &aggs,
+                    const std::vector<char> &dmask, const std::vector<double> &cc) {
+  const int k = lev.k, kk = k * k;
+  const int nc = int(aggs.size());
+  std::vector<int> agg_of(size_t(lev.n), -1);
+  for (int I = 0; I < nc; ++I)
+    for (int i : aggs[I]) agg_of[i] = I;
+  AuxLevel out;
+  out.n = nc;
+  out.k = k;
+  out.x = cc;
+  out.M.assign(size_t(nc) * kk, 0.0);
+  for (int I = 0; I < nc; ++I) {
+    std::vector<int> mem = aggs[I];
+    std::sort(mem.begin(), mem.end());
+    Sq acc(k);
+    for (int i : mem) {
+      Sq W = lev.Mmat(i);
+      for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p)
+        if (dmask[lev.nb[p]]) sq_axpy(W, 1.0, pulled(lev, lev.nb_e[p], i));
+      const Sq Q = sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k);
+      sq_axpy(acc, 1.0, sq_t3(Q, W, Q));
+    }
+    std::copy(acc.a, acc.a + kk, &out.M[size_t(I) * kk]);
+  }
+  std::unordered_map<int64_t, int64_t> slot;
+  slot.reserve(size_t(lev.m()));
+  std::vector<int64_t> keys;
+  std::vector<double> acc;
+  for (int64_t e = 0; e < lev.m(); ++e) {
+    const int i = lev.e0[e], j = lev.e1[e];
+    const int I = agg_of[i], J = agg_of[j];
+    if (I < 0 || J < 0 || I == J) continue;
+    const int a = std::min(I, J), b = std::max(I, J);
+    const Sq T = sq_mul(sq_mul(sq_qhalf(lev.xp(i), lev.xp(j), k),
+                               sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k)),
+                        sq_qhalf(&cc[size_t(3) * J], &cc[size_t(3) * I], k));
+    const Sq C = sq_t3(T, lev.Emat(e), T);
+    const int64_t key = int64_t(a) * nc + b;
+    auto it = slot.find(key);
+    if (it == slot.end()) {
+      slot.emplace(key, int64_t(keys.size()));
+      keys.push_back(key);
+      acc.insert(acc.end(), C.a, C.a + kk);
+    } else {
+      double *d = &acc[size_t(it->second) * kk];
+      for (int q = 0; q < kk; ++q) d[q] += C.a[q];
+    }
+  }
+  std::vector<int64_t> order(keys.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = int64_t(q);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return keys[x] < keys[y]; });
+  out.e0.resize(order.size());
+  out.e1.resize(order.size());
+  out.E.resize(order.size() * kk);
+  for (size_t q = 0; q < order.size(); ++q) {
+    const int64_t key = keys[order[q]];
+    out.e0[q] = int(key / nc);
+    out.e1[q] = int(key % nc);
+    std::copy(&acc[size_t(order[q]) * kk], &acc[size_t(order[q]) * kk] + kk, &out.E[q * kk]);
+  }
+  out.build_adjacency();
+  return out;
+}
+
+// ---- criteria ----------------------------------------------------------------------------------
+
+void dhat_all(const AuxLevel &lev, std::vector<Sq> &D) {
+  D.assign(size_t(lev.n), Sq(lev.k));
+  for (int i = 0; i < lev.n; ++i) {
+    Sq d = lev.Mmat(i);
+    for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) sq_axpy(d, 1.0, pulled(lev, lev.nb_e[p], i));
+    D[i] = d;
+  }
+}
+
+void trace_strength(const AuxLevel &lev, std::vector<double> &m) {
+  m.assign(size_t(lev.n), 0.0);
+  for (int i = 0; i < lev.n; ++i) m[i] = sq_trace(lev.Mmat(i));
+  for (int64_t e = 0; e < lev.m(); ++e) {
+    const double t = sq_trace(lev.Emat(e));
+    if (t > m[lev.e0[e]]) m[lev.e0[e]] = t;
+    if (t > m[lev.e1[e]]) m[lev.e1[e]] = t;
+  }
+}
+
+double mu_D(const AuxLevel &lev, int i, const std::vector<Sq> &D, double tau) {
+  return sq_genmax(D[i], lev.Mmat(i), tau);
+}
+
+double mu_s(const AuxLevel &lev, int i, int j, const std::vector<double> &mtr) {
+  const int e = lev.edge_id(i, j);
+  const double t = e >= 0 ? sq_trace(lev.Emat(e)) : 0.0;
+  if (t == 0.0) return kInf;
+  return std::sqrt(mtr[i] * mtr[j]) / t;
+}
+
+double mu_b(const AuxLevel &lev, int i, int j, const std::vector<Sq> &D, double tau) {
+  const int k = lev.k;
+  const double *xi = lev.xp(i), *xj = lev.xp(j);
+  const Sq Qij = sq_qhalf(xi, xj, k), Qji = sq_qhalf(xj, xi, k);
+  const Sq L = sq_harmonic(sq_t3(Qji, D[i], Qji), sq_t3(Qij, D[j], Qij), tau);
+  Sq R = lev.Emat(lev.edge_id(i, j));
+  for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) {
+    const int l = lev.nb[p];
+    if (l == j) continue;
+    const int ejl = lev.edge_id(j, l);
+    if (ejl < 0) continue;
+    const int eil = lev.nb_e[p];
+    const double *xl = lev.xp(l);
+    const Sq Qli = sq_qhalf(xl, xi, k), Qlj = sq_qhalf(xl, xj, k);
+    const Sq Hl = sq_harmonic(sq_t3(Qli, lev.Emat(eil), Qli), sq_t3(Qlj, lev.Emat(ejl), Qlj), tau);
+    const Sq T = sq_mul(sq_qtrans(xi, xl, k), Qji);
+    sq_axpy(R, 0.5, sq_t3(T, Hl, T));
+  }
+  return sq_genmax(L, R, tau);
+}
+
+double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<Sq> &D, double tau) {
+  const int k = lev.k;
+  std::vector<int> mem = Cin;
+  std::sort(mem.begin(), mem.end());
+  const int nC = int(mem.size());
+  double xH[3];
+  mean_pos(lev, mem, xH);
+  Mat PC(nC * k, k), DC(nC * k, nC * k), R(nC * k, nC * k);
+  auto put = [&](Mat &X, int a, int b, const Sq &S, double s) {
+    for (int u = 0; u < k; ++u)
+      for (int v = 0; v < k; ++v) X(a * k + u, b * k + v) += s * S(u, v);
+  };
+  for (int a = 0; a < nC; ++a) {
+    const Sq Q = sq_qtrans(xH, lev.xp(mem[a]), k);
+    for (int u = 0; u < k; ++u)
+      for (int v = 0; v < k; ++v) PC(a * k + u, v) = Q(u, v);
+    put(DC, a, a, D[mem[a]], 1.0);
+    put(R, a, a, lev.Mmat(mem[a]), 1.0);
+  }
+  const Mat DP = matmul(DC, PC);
+  Mat L = DC;
+  axpy_mat(L, -1.0, matmul(matmul(DP, pinv_tau(matmul(transpose(PC), DP), tau)), transpose(DP)));
+  // edges inside C (eq. auxa) and the outside neighbours
+  std::vector<std::pair<int, std::vector<std::pair<int, int>>>> outside;  // l -> (a, e)
+  std::unordered_map<int, size_t> opos;
+  for (int a = 0; a < nC; ++a) {
+    const int i = mem[a];
+    for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) {
+      const int l = lev.nb[p], e = lev.nb_e[p];
+      const auto it = std::lower_bound(mem.begin(), mem.end(), l);
+      if (it != mem.end() && *it == l) {
+        if (i < l) {
+          const int b = int(it - mem.begin());
+          const Sq Qil = sq_qhalf(lev.xp(i), lev.xp(l), k), Qli = sq_qhalf(lev.xp(l), lev.xp(i), k);
+          const Sq Ee = lev.Emat(e);
+          put(R, a, a, sq_t3(Qil, Ee, Qil), 1.0);
+          put(R, b, b, sq_t3(Qli, Ee, Qli), 1.0);
+          put(R, a, b, sq_t3(Qil, Ee, Qli), -1.0);
+          put(R, b, a, sq_t3(Qli, Ee, Qil), -1.0);
+        }
+      } else {
+        auto f = opos.find(l);
+        if (f == opos.end()) {
+          opos.emplace(l, outside.size());
+          outside.push_back({l, {{a, e}}});
+        } else {
+          outside[f->second].second.emplace_back(a, e);
+        }
+      }
+    }
+  }
+  std::sort(outside.begin(), outside.end(),
+            [](const auto &x, const auto &y) { return x.first < y.first; });
+  for (const auto &ol : outside) {
+    if (ol.second.size() < 2) continue;
+    const int l = ol.first;
+    Mat KCC(nC * k, nC * k), KCw(nC * k, k), Kww(k, k);
+    for (const auto &ae : ol.second) {
+      const int a = ae.first, e = ae.second, i = mem[a];
+      const Sq Qil = sq_qhalf(lev.xp(i), lev.xp(l), k), Qli = sq_qhalf(lev.xp(l), lev.xp(i), k);
+      const Sq Ee = lev.Emat(e);
+      put(KCC, a, a, sq_t3(Qil, Ee, Qil), 1.0);
+      const Sq X = sq_t3(Qil, Ee, Qli);
+      for (int u = 0; u < k; ++u)
+        for (int v = 0; v < k; ++v) KCw(a * k + u, v) -= X(u, v);
+      const Sq Y = sq_t3(Qli, Ee, Qli);
+      for (int u = 0; u < k; ++u)
+        for (int v = 0; v < k; ++v) Kww(u, v) += Y(u, v);
+    }
+    Mat S = KCC;
+    axpy_mat(S, -1.0, matmul(matmul(KCw, pinv_tau(Kww, tau)), transpose(KCw)));
+    axpy_mat(R, 0.5, sym(S));
+  }
+  return genmax(sym(L), sym(R), tau);
+}
+
+// ---- Algorithm alg:pwagg --------------------------------------------------------------------
+
+std::vector<int> cuthill_mckee(const AuxLevel &lev, const std::vector<char> &free_mask) {
+  const int n = lev.n;
+  std::vector<std::vector<int>> adj(static_cast<size_t>(n));
+  for (int64_t e = 0; e < lev.m(); ++e) {
+    const int i = lev.e0[e], j = lev.e1[e];
+    if (sq_trace(lev.Emat(e)) > 0.0 && free_mask[i] && free_mask[j]) {
+      adj[i].push_back(j);
+      adj[j].push_back(i);
+    }
+  }
+  std::vector<int> deg(static_cast<size_t>(n));
+  for (int v = 0; v < n; ++v) deg[v] = int(adj[v].size());
+  std::vector<std::pair<int, int>> starts;
+  for (int v = 0; v < n; ++v)
+    if (free_mask[v]) starts.emplace_back(deg[v], v);
+  std::sort(starts.begin(), starts.end());
+  std::vector<char> visited(static_cast<size_t>(n), 0);
+  std::vector<int> order;
+  order.reserve(starts.size());
+  size_t ptr = 0;
+  std::deque<int> queue;
+  std::vector<std::pair<int, int>> nbv;
+  while (order.size() < starts.size()) {
+    while (visited[starts[ptr].second]) ++ptr;
+    const int s = starts[ptr].second;
+    visited[s] = 1;
+    queue.push_back(s);
+    while (!queue.empty()) {
+      const int v = queue.front();
+      queue.pop_front();
+      order.push_back(v);
+      nbv.clear();
+      for (int u : adj[v])
+        if (!visited[u]) nbv.emplace_back(deg[u], u);
+      std::sort(nbv.begin(), nbv.end());
+      for (const auto &du : nbv) {
+        visited[du.second] = 1;
+        queue.push_back(du.second);
+      }
+    }
+  }
+  return order;
+}
+
+MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd,
+                                const MatchParams &prm) {
+  const int n = lev.n;
+  const double sigma = prm.sigma;
+  MatchResult res;
+  auto note = [&](double mu) {
+    if (std::isfinite(mu)) res.min_margin = std::min(res.min_margin, std::fabs(mu - sigma) / sigma);
+  };
+  std::vector<Sq> Dhat;
+  dhat_all(lev, Dhat);
+  res.dmask.assign(static_cast<size_t>(n), 0);
+  for (int i = 0; i < n; ++i) res.dmask[i] = vd.empty() ? 0 : vd[i];
+  for (int i = 0; i < n; ++i) {
+    if (res.dmask[i]) continue;
+    const double md = mu_D(lev, i, Dhat, prm.tau);
+    note(md);
+    if (md < sigma) res.dmask[i] = 1;
+  }
+  std::vector<char> in_T(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) in_T[i] = !res.dmask[i];
+  std::vector<int> order = cuthill_mckee(lev, in_T);
+
+  AuxLevel work_store;
+  const AuxLevel *work = &lev;
+  std::vector<Sq> wdhat_store;
+  const std::vector<Sq> *wdhat = &Dhat;
+  std::vector<std::vector<int>> members(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) members[i] = {i};
+  std::vector<std::vector<int>> entries;
+  std::vector<double> mtr;
+  std::vector<int> pos;
+  std::vector<std::pair<int, double>> cands;
+  for (int p = 1; p <= prm.rounds; ++p) {
+    pos.assign(size_t(work->n), 0);
+    for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
+    trace_strength(*work, mtr);
+    std::vector<std::pair<int, int>> pairs;
+    std::vector<int> singles;
+    for (int ci : order) {
+      if (!in_T[ci]) continue;
+      in_T[ci] = 0;
+      cands.clear();
+      for (int64_t q = work->nb_ptr[ci]; q < work->nb_ptr[ci + 1]; ++q) {
+        const int cj = work->nb[q];
+        if (!in_T[cj]) continue;
+        const double ms = mu_s(*work, ci, cj, mtr);
+        note(ms);
+        if (ms < sigma) cands.emplace_back(cj, ms);
+      }
+      int matched = -1;
+      while (!cands.empty()) {
+        double mmin = cands[0].second;
+        for (const auto &c : cands) mmin = std::min(mmin, c.second);
+        int best = -1, ntie = 0;
+        for (size_t c = 0; c < cands.size(); ++c)
+          if (cands[c].second <= mmin * (1.0 + prm.tie_rtol)) {
+            ++ntie;
+            if (best < 0 || pos[cands[c].first] < pos[cands[best].first]) best = int(c);
+          }
+        res.max_tie = std::max(res.max_tie, ntie);
+        const int cj = cands[best].first;
+        const double mu = mu_b(*work, ci, cj, *wdhat, prm.tau);
+        note(mu);
+        bool ok = mu < sigma;
+        if (ok && members[ci].size() + members[cj].size() > 2) {
+          std::vector<int> u = members[ci];
+          u.insert(u.end(), members[cj].begin(), members[cj].end());
+          const double mg = mu_g(lev, u, Dhat, prm.tau);
+          note(mg);
+          ok = mg < sigma;
+        }
+        if (ok) {
+          matched = cj;
+          break;
+        }
+        cands.erase(cands.begin() + best);
+      }
+      if (matched >= 0) {
+        pairs.emplace_back(ci, matched);
+        in_T[matched] = 0;
+      } else {
+        singles.push_back(ci);
+      }
+    }
+    std::vector<std::vector<int>> groups;
+    for (const auto &pq : pairs) groups.push_back({pq.first, pq.second});
+    for (int s : singles) groups.push_back({s});
+    entries.clear();
+    for (const auto &g : groups) {
+      std::vector<int> m = members[g[0]];
+      if (g.size() == 2) m.insert(m.end(), members[g[1]].begin(), members[g[1]].end());
+      entries.push_back(m);
+    }
+    if (p < prm.rounds) {
+      std::vector<double> ic(entries.size() * 3);
+      for (size_t I = 0; I < entries.size(); ++I) mean_pos(lev, entries[I], &ic[3 * I]);
+      std::vector<char> wmask = p == 1 ? res.dmask : std::vector<char>(size_t(work->n), 0);
+      AuxLevel next = coarse_aux(*work, groups, wmask, ic);
+      work_store = std::move(next);
+      work = &work_store;
+      dhat_all(*work, wdhat_store);
+      wdhat = &wdhat_store;
+      members = entries;
+      in_T.assign(entries.size(), 1);
+      order.resize(entries.size());
+      for (size_t a = 0; a < entries.size(); ++a) order[a] = int(entries.size() - 1 - a);
+    }
+  }
+  res.aggs = entries;
+  for (auto &a : res.aggs) std::sort(a.begin(), a.end());
+  res.ccoords.resize(res.aggs.size() * 3);
+  for (size_t I = 0; I < res.aggs.size(); ++I) mean_pos(lev, res.aggs[I], &res.ccoords[3 * I]);
+  res.coarse = coarse_aux(lev, res.aggs, res.dmask, res.ccoords);
+  return res;
+}
+
+}  // namespace eamg

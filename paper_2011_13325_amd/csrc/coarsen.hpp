@@ -1,0 +1,86 @@
+// Host-side auxiliary topology and coarsening (paper section "deng" and section "crs2").
+//
+//  * AuxLevel: vertices with k x k vertex weights M^i and edges (i < j) with k x k edge weights
+//    E^ij that define the auxiliary matrix of Def. def:deng (eq. auxa).
+//  * finest_aux: Thm thm:deng_elast (elasticity, E^ij = c^ij [[t t^T, 0], [0, 0]], M^i = 0, c^ij
+//    the mean absolute entry of (A_N)_ij, t the unit edge direction) and the scalar M-matrix
+//    splitting (E^ij = |A_ij|, M^i = max(0, A_ii - sum |A_ij|)).
+//  * coarse_aux: Thm thm:cemats.
+//  * mu_D / mu_s / mu_b / mu_g: Thm thm:mu1 (eqs. mu_a, mu_d), Lemma thm:mu2, Def. def:muc.
+//  * successive_matching: Algorithm alg:pwagg.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dense.hpp"
+
+namespace eamg {
+
+// Small square matrix, k <= 6, row-major.
+struct Sq {
+  int k = 0;
+  double a[36];
+  Sq() {}
+  explicit Sq(int k_) : k(k_) {
+    for (int i = 0; i < 36; ++i) a[i] = 0.0;
+  }
+  double &operator()(int i, int j) { return a[i * k + j]; }
+  double operator()(int i, int j) const { return a[i * k + j]; }
+};
+
+struct MatchParams {
+  double sigma = 20.0;
+  int rounds = 2;
+  double tie_rtol = 1e-12;
+  double tau = 1e-10;
+};
+
+struct AuxLevel {
+  int n = 0, k = 6;
+  std::vector<double> x;          // n*3 positions
+  std::vector<int> e0, e1;        // edges, e0 < e1, ascending (e0, e1)
+  std::vector<double> E;          // m*k*k
+  std::vector<double> M;          // n*k*k
+  std::vector<int64_t> nb_ptr;    // adjacency sorted by neighbour id
+  std::vector<int> nb, nb_e;
+
+  int64_t m() const { return int64_t(e0.size()); }
+  void build_adjacency();
+  int edge_id(int i, int j) const;   // -1 if absent
+  Sq Emat(int64_t e) const;
+  Sq Mmat(int i) const;
+  const double *xp(int i) const { return &x[size_t(3) * i]; }
+};
+
+struct MatchResult {
+  std::vector<std::vector<int>> aggs;   // sorted members, coarse id = position
+  std::vector<char> dmask;              // dropped set D
+  std::vector<double> ccoords;          // nc*3
+  AuxLevel coarse;
+  double min_margin = 1e300;
+  int max_tie = 0;
+};
+
+// Build the finest level.  Returns false with err set on malformed input.
+bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, const int32_t *col,
+                const double *vals, const int32_t *edges, int64_t n_edges, AuxLevel &out,
+                std::string &err);
+
+AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &aggs,
+                    const std::vector<char> &dmask, const std::vector<double> &ccoords);
+
+void dhat_all(const AuxLevel &lev, std::vector<Sq> &D);
+void trace_strength(const AuxLevel &lev, std::vector<double> &m);
+double mu_D(const AuxLevel &lev, int i, const std::vector<Sq> &D, double tau);
+double mu_s(const AuxLevel &lev, int i, int j, const std::vector<double> &mtr);
+double mu_b(const AuxLevel &lev, int i, int j, const std::vector<Sq> &D, double tau);
+double mu_g(const AuxLevel &lev, const std::vector<int> &C, const std::vector<Sq> &D, double tau);
+
+std::vector<int> cuthill_mckee(const AuxLevel &lev, const std::vector<char> &free_mask);
+
+MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd,
+                                const MatchParams &prm);
+
+}  // namespace eamg

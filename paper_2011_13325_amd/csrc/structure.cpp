@@ -1,0 +1,181 @@
+#include "structure.hpp"
+
+#include <algorithm>
+#include <map>
+
+namespace eamg {
+
+ProlongPlan plan_prolongation(const Pattern &A, const AuxLevel &aux, const std::vector<int> &agg_of,
+                              const std::vector<char> &dmask, int cap_S, int cap_A, double tie_rtol) {
+  const int n = A.n_rows;
+  const int k = aux.k;
+  ProlongPlan pl;
+  pl.type.assign(static_cast<size_t>(n), ROW_D);
+  pl.P.n_rows = n;
+  pl.P.rp.assign(size_t(n) + 1, 0);
+  pl.F_ptr.assign(size_t(n) + 1, 0);
+  int nc = 0;
+  for (int v : agg_of) nc = std::max(nc, v + 1);
+  pl.P.n_cols = nc;
+  std::vector<int> cs;
+  std::vector<std::pair<int, int>> F;         // (l, e)
+  for (int i = 0; i < n; ++i) {
+    pl.F_ptr[i + 1] = pl.F_ptr[i];
+    if (dmask[i]) {
+      pl.P.rp[i + 1] = pl.P.rp[i];
+      continue;
+    }
+    cs.clear();
+    cs.push_back(agg_of[i]);
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      const int j = A.col[p];
+      if (!dmask[j]) cs.push_back(agg_of[j]);
+    }
+    std::sort(cs.begin(), cs.end());
+    cs.erase(std::unique(cs.begin(), cs.end()), cs.end());
+    if (int(cs.size()) <= cap_S) {
+      pl.type[i] = ROW_S;
+      pl.P.col.insert(pl.P.col.end(), cs.begin(), cs.end());
+      pl.P.rp[i + 1] = pl.P.rp[i] + int64_t(cs.size());
+      continue;
+    }
+    pl.type[i] = ROW_A;
+    F.clear();
+    std::map<int, double> ws;
+    for (int64_t p = aux.nb_ptr[i]; p < aux.nb_ptr[i + 1]; ++p) {
+      const int l = aux.nb[p];
+      if (dmask[l]) continue;
+      const int e = aux.nb_e[p];
+      double tr = 0.0;
+      for (int d = 0; d < k; ++d) tr += aux.E[size_t(e) * k * k + size_t(d) * k + d];
+      ws[agg_of[l]] += tr;
+    }
+    const int own = agg_of[i];
+    std::vector<std::pair<int, double>> others;   // ascending group id
+    for (const auto &g : ws)
+      if (g.first != own) others.emplace_back(g.first, g.second);
+    std::vector<int> keep = {own};
+    while (!others.empty() && int(keep.size()) < cap_A) {
+      double wmax = others[0].second;
+      for (const auto &g : others) wmax = std::max(wmax, g.second);
+      size_t pick = 0;
+      while (!(others[pick].second >= wmax * (1.0 - tie_rtol))) ++pick;   // smallest id in band
+      keep.push_back(others[pick].first);
+      others.erase(others.begin() + long(pick));
+    }
+    std::sort(keep.begin(), keep.end());
+    for (int64_t p = aux.nb_ptr[i]; p < aux.nb_ptr[i + 1]; ++p) {
+      const int l = aux.nb[p];
+      if (dmask[l]) continue;
+      if (std::binary_search(keep.begin(), keep.end(), agg_of[l])) F.emplace_back(l, aux.nb_e[p]);
+    }
+    std::sort(F.begin(), F.end());
+    for (const auto &le : F) {
+      pl.F_vtx.push_back(le.first);
+      pl.F_edge.push_back(le.second);
+    }
+    pl.F_ptr[i + 1] = pl.F_ptr[i] + int64_t(F.size());
+    pl.P.col.insert(pl.P.col.end(), keep.begin(), keep.end());
+    pl.P.rp[i + 1] = pl.P.rp[i] + int64_t(keep.size());
+  }
+  return pl;
+}
+
+Pattern spgemm_symbolic(const Pattern &A, const Pattern &B) {
+  Pattern C;
+  C.n_rows = A.n_rows;
+  C.n_cols = B.n_cols;
+  C.rp.assign(size_t(A.n_rows) + 1, 0);
+  std::vector<int> mark(size_t(B.n_cols), -1);
+  std::vector<int> row;
+  for (int i = 0; i < A.n_rows; ++i) {
+    row.clear();
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      const int j = A.col[p];
+      for (int64_t q = B.rp[j]; q < B.rp[j + 1]; ++q) {
+        const int c = B.col[q];
+        if (mark[c] != i) {
+          mark[c] = i;
+          row.push_back(c);
+        }
+      }
+    }
+    std::sort(row.begin(), row.end());
+    C.col.insert(C.col.end(), row.begin(), row.end());
+    C.rp[i + 1] = C.rp[i] + int64_t(row.size());
+  }
+  return C;
+}
+
+Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src) {
+  Pattern T;
+  T.n_rows = P.n_cols;
+  T.n_cols = P.n_rows;
+  T.rp.assign(size_t(P.n_cols) + 1, 0);
+  for (int64_t q = 0; q < P.nnz(); ++q) T.rp[P.col[q] + 1]++;
+  for (int c = 0; c < P.n_cols; ++c) T.rp[c + 1] += T.rp[c];
+  T.col.resize(size_t(P.nnz()));
+  src.resize(size_t(P.nnz()));
+  std::vector<int64_t> fill(T.rp.begin(), T.rp.end() - 1);
+  for (int i = 0; i < P.n_rows; ++i)
+    for (int64_t q = P.rp[i]; q < P.rp[i + 1]; ++q) {
+      const int64_t d = fill[P.col[q]]++;
+      T.col[d] = i;
+      src[d] = q;
+    }
+  return T;
+}
+
+std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
+  const int n = A.n_rows;
+  std::vector<int> color(static_cast<size_t>(n), -1);
+  std::vector<int> used;
+  n_colors = 0;
+  for (int i = 0; i < n; ++i) {
+    used.clear();
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
+      const int j = A.col[p];
+      if (j != i && color[j] >= 0) used.push_back(color[j]);
+    }
+    std::sort(used.begin(), used.end());
+    int c = 0;
+    for (int u : used) {
+      if (u == c) ++c;
+      else if (u > c) break;
+    }
+    color[i] = c;
+    n_colors = std::max(n_colors, c + 1);
+  }
+  return color;
+}
+
+Pattern permute_pattern(const Pattern &A, const std::vector<int> &perm, const std::vector<int> &inv,
+                        std::vector<int64_t> &src) {
+  return permute_rect(A, perm, inv, src);
+}
+
+Pattern permute_rect(const Pattern &P, const std::vector<int> &perm_rows,
+                     const std::vector<int> &inv_cols, std::vector<int64_t> &src) {
+  Pattern R;
+  R.n_rows = P.n_rows;
+  R.n_cols = P.n_cols;
+  R.rp.assign(size_t(P.n_rows) + 1, 0);
+  R.col.resize(size_t(P.nnz()));
+  src.resize(size_t(P.nnz()));
+  std::vector<std::pair<int, int64_t>> row;
+  for (int r = 0; r < P.n_rows; ++r) {
+    const int o = perm_rows[r];
+    row.clear();
+    for (int64_t q = P.rp[o]; q < P.rp[o + 1]; ++q) row.emplace_back(inv_cols[P.col[q]], q);
+    std::sort(row.begin(), row.end());
+    const int64_t base = R.rp[r];
+    for (size_t t = 0; t < row.size(); ++t) {
+      R.col[size_t(base) + t] = row[t].first;
+      src[size_t(base) + t] = row[t].second;
+    }
+    R.rp[r + 1] = base + int64_t(row.size());
+  }
+  return R;
+}
+
+}  // namespace eamg

@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads and exports every symbol include/eamg.h
+declares; input validation returns the documented status before any device work; the
+host-side successive matching (Algorithm alg:pwagg) reproduces the oracle's agglomerates
+bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2011_13325_amd as E
+from gen import make_problem
+from oracle.auxtop import finest_aux
+from oracle.coarsen import successive_matching
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "eamg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(eamg_[a-z_]+)\s*\(", hdr))
+    assert declared == set(E.EXPORTED)
+    lib = ctypes.CDLL(E.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _setup_status(p, **kw):
+    pb, keep = E._problem(p["dim"], p["coords"], p["row_ptr"], p["col_idx"], p["vals"],
+                          p.get("dirichlet"), p.get("kernel"), p.get("edges"))
+    for k, v in kw.items():
+        setattr(pb, k, v)
+    h = ctypes.c_void_p()
+    prm = p.get("params")
+    st = E.lib().eamg_setup(ctypes.byref(pb), ctypes.byref(prm) if prm is not None else None,
+                            ctypes.c_void_p(0), ctypes.byref(h))
+    assert not h.value
+    return st, E.eamg_last_error()
+
+
+def _base():
+    g = make_problem(4)
+    return dict(dim=3, coords=g.coords, row_ptr=g.row_ptr.copy(), col_idx=g.col_idx.copy(),
+                vals=g.vals.copy(), dirichlet=g.dirichlet)
+
+
+def test_malformed_inputs_are_rejected_before_device_work():
+    p = _base()
+    p["col_idx"][[1, 2]] = p["col_idx"][[2, 1]]              # unsorted row
+    assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+    p = _base()
+    rp = p["row_ptr"]
+    p["col_idx"] = np.delete(p["col_idx"], 0)                # drop row 0's diagonal block
+    p["vals"] = np.delete(p["vals"], 0, axis=0)
+    p["row_ptr"] = np.concatenate([[0], rp[1:] - 1])
+    st, msg = _setup_status(p)
+    assert st == E.EAMG_ERR_INVALID_ARG and "diagonal" in msg
+    p = _base()
+    # asymmetric pattern: remove block (0, 1) but keep (1, 0)
+    s = p["row_ptr"][0]
+    j = np.nonzero(p["col_idx"][s:p["row_ptr"][1]] == 1)[0][0] + s
+    p["col_idx"] = np.delete(p["col_idx"], j)
+    p["vals"] = np.delete(p["vals"], j, axis=0)
+    p["row_ptr"] = np.concatenate([[0], p["row_ptr"][1:] - 1])
+    assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+    p = _base()
+    p["vals"][5, 1, 1] = np.nan
+    assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+    p = _base()
+    assert _setup_status(p, dim=2)[0] == E.EAMG_ERR_UNSUPPORTED_KERNEL
+    p = _base()
+    p["params"] = E.eamg_default_setup_params(delta=0)
+    assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+    p = _base()
+    p["params"] = E.eamg_default_setup_params(rounds=9)
+    assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+
+
+def test_kernel_vectors_must_span_rigid_body_modes():
+    p = _base()
+    n = p["coords"].shape[0]
+    rng = np.random.default_rng(0)
+    p["kernel"] = rng.standard_normal((3 * n, 6))
+    assert _setup_status(p)[0] == E.EAMG_ERR_UNSUPPORTED_KERNEL
+    p = _base()
+    p["kernel"] = np.zeros((3 * n, 6))
+    assert _setup_status(p)[0] == E.EAMG_ERR_UNSUPPORTED_KERNEL
+
+
+@pytest.mark.parametrize("n,kind", [(9, "elasticity"), (13, "elasticity"), (8, "poisson")])
+def test_host_matching_matches_oracle_bit_for_bit(n, kind):
+    p = make_problem(n, kind=kind, clamp="x0" if kind == "elasticity" else "all")
+    lev = finest_aux(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals)
+    vd = p.dirichlet.astype(bool)
+    for level in range(2):
+        res = successive_matching(lev, vd)
+        agg, nc, cc, margin = E.eamg_host_match(lev.k, lev.coords, lev.edges, lev.E, lev.M, vd)
+        ao = np.full(lev.n, -1)
+        for I, m in enumerate(res.aggs):
+            ao[m] = I
+        assert nc == len(res.aggs)
+        assert np.array_equal(agg, ao)
+        assert np.abs(cc - res.coarse_coords).max() <= 1e-15
+        lev, vd = res.coarse_level, np.zeros(res.coarse_level.n, bool)

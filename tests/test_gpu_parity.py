@@ -1,0 +1,251 @@
+"""GPU parity: the library (host coarsening + gfx950 kernels, called through the C ABI) against
+the FP64 CPU oracle on the same seeded inputs.
+
+* integers bit-exact: agglomerates (Algorithm alg:pwagg), P_s and A_l patterns, colours;
+* P_s (Def. def:aux_sp) and A_l = P_s^T A P_s per block within PS_TOL / A_TOL relative to the
+  largest block of the row;
+* one V-cycle and the PCG iterate at the oracle's iteration count within 1e-10 relative;
+* both solves reach ||b - A x|| <= 1e-8 ||b|| on their own (section "res");
+* edge cases: no coarsening (direct coarsest solve), non-cubic boxes, the scalar problem,
+  ragged sizes, x0, failure statuses; run-to-run bitwise reproducibility;
+* full size (64^3 vertices): properties that hold at any size.
+
+Tolerances.  P_s and the Galerkin products are computed with pseudo-inverses of 3x3 / 6x6
+blocks whose kept eigenvalues span up to ~1e5 (rotations scale like h^2 against
+displacements), so round-off of order eps * 1e5 ~ 1e-11 relative is expected between two
+correct implementations with different summation orders; PS_TOL / A_TOL = 1e-9 leave
+two orders of headroom.  The solution tolerance 1e-10 is the FP64 parity bar of the design.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import paper_2011_13325_amd as E
+from gen import make_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PS_TOL = 1e-9
+A_TOL = 1e-9
+X_TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _lib(p, **prm):
+    params = E.eamg_default_setup_params(**prm) if prm else None
+    return E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, params)
+
+
+def _oracle(p, **prm):
+    return oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                        oracle.SetupParams(**prm) if prm else None)
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _block_rel_err(rp, val_a, val_b):
+    """max over blocks of ||a - b||_F / max_block_in_row ||b||_F."""
+    worst = 0.0
+    na = np.linalg.norm(val_b.reshape(val_b.shape[0], -1), axis=1)
+    nd = np.linalg.norm((val_a - val_b).reshape(val_b.shape[0], -1), axis=1)
+    for i in range(rp.size - 1):
+        s, e = rp[i], rp[i + 1]
+        if e > s:
+            scale = na[s:e].max()
+            if scale > 0:
+                worst = max(worst, nd[s:e].max() / scale)
+    return worst
+
+
+CASES = {
+    "cube9": dict(n=9),
+    "cube17": dict(n=17),
+    "box_ragged": dict(n=11, ny=7, nz=5, h=0.1, nu=0.35, seed=4),
+    "poisson10": dict(n=10, kind="poisson", clamp="all", seed=2),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair(request):
+    kw = dict(CASES[request.param])
+    p = make_problem(**kw)
+    print(f"\n[case {request.param}] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
+    ho = _oracle(p)
+    hl = _lib(p)
+    yield request.param, p, ho, hl
+    hl.close()
+
+
+def test_hierarchy_parity(pair):
+    name, p, ho, hl = pair
+    st = hl.stats()
+    assert st["n_levels"] == ho.n_levels
+    worstP = worstA = 0.0
+    for l, lev in enumerate(ho.levels):
+        ex = hl.export(l)
+        assert ex["info"]["n"] == lev.n and ex["info"]["bs"] == lev.bs
+        assert np.array_equal(ex["A_rowptr"], lev.A.row_ptr)
+        assert np.array_equal(ex["A_col"], lev.A.col)
+        worstA = max(worstA, _block_rel_err(lev.A.row_ptr, ex["A_val"], lev.A.val))
+        if l + 1 < ho.n_levels:
+            assert np.array_equal(ex["agg"], lev.agg_of)
+            assert np.array_equal(ex["color"], lev.colors)
+            assert np.array_equal(ex["P_rowptr"], lev.P.row_ptr)
+            assert np.array_equal(ex["P_col"], lev.P.col)
+            worstP = max(worstP, _block_rel_err(lev.P.row_ptr, ex["P_val"], lev.P.val))
+    print(f"[{name}] levels={ho.n_levels} max rel err P_s={worstP:.2e} A_l={worstA:.2e}", flush=True)
+    assert worstP <= PS_TOL
+    assert worstA <= A_TOL
+
+
+def test_vcycle_parity(pair):
+    name, p, ho, hl = pair
+    r = np.random.default_rng(3).standard_normal(p.n_dofs)
+    r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    zo = oracle.vcycle(ho, r)
+    z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+    E.eamg_vcycle(hl.h, _dev(r), z)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"[{name}] V-cycle rel err {err:.2e}", flush=True)
+    assert err <= X_TOL
+
+
+def test_pcg_parity_and_convergence(pair):
+    name, p, ho, hl = pair
+    xo, it, rel, rel_true, conv = oracle.pcg(ho, p.b, rtol=1e-8)
+    assert conv and rel_true <= 1e-8
+    b = _dev(p.b)
+    x, info = hl.solve(b, rtol=1e-8)
+    assert info["status"] == E.EAMG_OK and info["rel_res_true"] <= 1e-8
+    xk, infok = hl.solve(b, rtol=0.0, max_it=it)
+    assert infok["iterations"] == it
+    err = np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"[{name}] its oracle={it} lib={info['iterations']} x rel err at k*={err:.2e}", flush=True)
+    assert err <= X_TOL
+    assert abs(info["iterations"] - it) <= 1
+
+
+def test_bitwise_reproducible(pair):
+    name, p, ho, hl = pair
+    b = _dev(p.b)
+    x1, _ = hl.solve(b)
+    x2, _ = hl.solve(b)
+    assert torch.equal(x1, x2)
+
+
+def test_no_coarsening_direct_solve():
+    p = make_problem(4)            # 192 dofs < 500: the finest level is the coarsest
+    hl = _lib(p)
+    assert hl.stats()["n_levels"] == 1
+    x, info = hl.solve(_dev(p.b))
+    assert info["status"] == E.EAMG_OK and info["iterations"] <= 2
+    A = sp.bsr_matrix((p.vals, p.col_idx, p.row_ptr), shape=(p.n_dofs,) * 2).toarray()
+    free = ~np.repeat(p.dirichlet.astype(bool), 3)
+    xs = np.zeros(p.n_dofs)
+    xs[free] = np.linalg.solve(A[np.ix_(free, free)], p.b[free])
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-10 * np.linalg.norm(xs)
+    hl.close()
+
+
+def test_initial_guess_and_statuses():
+    p = make_problem(9, seed=5)
+    hl = _lib(p)
+    b = _dev(p.b)
+    x, info = hl.solve(b, rtol=1e-8)
+    x0 = x.clone()
+    x1, info1 = hl.solve(b, x=x0.clone(), use_x0=True, rtol=1e-6)
+    assert info1["status"] == E.EAMG_OK and info1["iterations"] <= 1
+    # iteration limit
+    _, info2 = hl.solve(b, max_it=1, rtol=1e-12)
+    assert info2["status"] == E.EAMG_NOT_CONVERGED and info2["iterations"] == 1
+    # non-finite right-hand side
+    bn = b.clone()
+    bn[7] = float("nan")
+    with pytest.raises(E.EamgError) as ei:
+        hl.solve(bn)
+    assert ei.value.status == E.EAMG_ERR_BREAKDOWN
+    # zero right-hand side -> x = 0
+    xz, infoz = hl.solve(torch.zeros_like(b))
+    assert infoz["status"] == E.EAMG_OK and float(xz.abs().max()) == 0.0
+    # Dirichlet dofs: b ignored there, x = 0 there
+    bd = b.clone()
+    m = torch.tensor(np.repeat(p.dirichlet.astype(bool), 3), device="cuda")
+    bd[m] = 1.0
+    xd, _ = hl.solve(bd)
+    assert float(xd[m].abs().max()) == 0.0
+    assert torch.allclose(xd, x, rtol=0, atol=1e-7 * float(x.abs().max()))
+    hl.close()
+
+
+def test_indefinite_matrix_reports_not_spd():
+    p = make_problem(4)
+    vals = p.vals.copy()
+    rows = np.repeat(np.arange(p.n_vertices), np.diff(p.row_ptr))
+    diag = np.nonzero((rows == p.col_idx) & (p.dirichlet[rows] == 0))[0]
+    vals[diag[3]] *= -5.0
+    with pytest.raises(E.EamgError) as ei:
+        E.Hierarchy(3, p.coords, p.row_ptr, p.col_idx, vals, p.dirichlet)
+    assert ei.value.status == E.EAMG_ERR_NOT_SPD
+
+
+def test_full_size_cube64_properties():
+    p = make_problem(64, seed=1)
+    print(f"\n[cube64] dofs={p.n_dofs}", flush=True)
+    hl = _lib(p)
+    st = hl.stats()
+    print(f"[cube64] levels={st['n_levels']} n={st['n']} vc={st['vc']:.3f} oc={st['oc']:.3f}",
+          flush=True)
+    b = _dev(p.b)
+    x, info = hl.solve(b, rtol=1e-8)
+    print(f"[cube64] its={info['iterations']} rel_true={info['rel_res_true']:.2e} ms={info['ms']:.1f}",
+          flush=True)
+    assert info["status"] == E.EAMG_OK
+    A = sp.bsr_matrix((p.vals, p.col_idx, p.row_ptr), shape=(p.n_dofs,) * 2).tocsr()
+    dm = np.repeat(p.dirichlet.astype(bool), 3)
+    Dm = sp.diags((~dm).astype(float))
+    Ab = Dm @ A @ Dm + sp.diags(dm.astype(float))
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(p.b - Ab @ xh) <= 1e-8 * np.linalg.norm(p.b)
+    # level 0: agglomerates partition the free vertices, at most 4 each; rigid body modes are
+    # reproduced by P_s on rows whose stencil avoids D
+    ex = hl.export(0)
+    agg = ex["agg"]
+    free = p.dirichlet == 0
+    assert np.all(agg[free] >= 0) and np.all(agg[~free] == -1)
+    assert np.bincount(agg[free]).max() <= 4
+    ex1 = hl.export(1)
+    nc = ex1["info"]["n"]
+    cc = np.zeros((nc, 3))
+    np.add.at(cc, agg[free], p.coords[free])
+    cc /= np.bincount(agg[free])[:, None]
+    rng = np.random.default_rng(0)
+    d, r = rng.standard_normal(3), rng.standard_normal(3)
+    uc = np.concatenate([np.concatenate([d + np.cross(c, r), r]) for c in cc])
+    Pm = sp.bsr_matrix((ex["P_val"], ex["P_col"], ex["P_rowptr"]), shape=(p.n_dofs, 6 * nc))
+    uf = (Pm @ uc).reshape(-1, 3)
+    ref = d + np.cross(p.coords, r)
+    nearD = np.zeros(p.n_vertices, bool)
+    rows = np.repeat(np.arange(p.n_vertices), np.diff(p.row_ptr))
+    nearD[rows[p.dirichlet[p.col_idx] == 1]] = True
+    ok = ~nearD & free
+    assert np.abs(uf[ok] - ref[ok]).max() <= 1e-10 * np.abs(ref).max()
+    # A_1 = P_s^T A_0 P_s on sampled columns, and symmetric
+    A1 = sp.bsr_matrix((ex1["A_val"], ex1["A_col"], ex1["A_rowptr"]), shape=(6 * nc,) * 2).tocsr()
+    cols = rng.choice(6 * nc, 24, replace=False)
+    for c in cols:
+        e = np.zeros(6 * nc)
+        e[c] = 1.0
+        ref_col = Pm.T @ (Ab @ (Pm @ e))
+        assert np.abs(A1 @ e - ref_col).max() <= 1e-11 * np.abs(ref_col).max()
+    assert abs(A1 - A1.T).max() <= 1e-12 * abs(A1).max()
+    hl.close()
