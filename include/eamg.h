@@ -85,7 +85,7 @@ typedef struct {
  *  delta              1 (neighbour term in mu_g / mu_b; only 1 is supported)
  *  R                  1 (candidate chosen by mu_s; only 1 is supported)
  *  rounds             matching passes per level N (default 2, 1..4)
- *  coarsest_max_dofs  level l is the coarsest once bs_l * n_l < this (default 500, <= 8000)
+ *  coarsest_max_dofs  level l is the coarsest once bs_l * n_l < this (default 500, <= 4000)
  *  max_levels         maximum number of levels (default 25)
  *  omega              prolongation smoothing damping (default 2/3)
  *  cap_aux            columns per edge-matrix row of P_s (default 4, 1..16)
@@ -183,6 +183,26 @@ eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *a
  * streams counted once per kernel), from the real per-level sizes. */
 eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes,
                                double *iteration_bytes);
+
+/*
+ * Per-kernel timing, for measuring each kernel against its bandwidth roofline.  While enabled,
+ * every launch of eamg_solve / eamg_vcycle is bracketed by events on the solve stream and its
+ * algorithmic HBM bytes (matrix blocks and index arrays read once, vectors read or written
+ * once, gathered vector entries counted once per launch) are recorded.  eamg_profile_read
+ * synchronizes the device, aggregates the records by kernel name (the template instance, e.g.
+ * "k_gs_bwd<6>"), sorts them by total time, copies up to max_entries of them into out,
+ * stores the number of kernels in *n_out and clears the records.  Enabling resets them.
+ */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} eamg_kernel_stat;
+
+eamg_status eamg_profile_enable(eamg_hierarchy *h, int32_t on);
+eamg_status eamg_profile_read(eamg_hierarchy *h, int32_t max_entries, eamg_kernel_stat *out,
+                              int32_t *n_out);
 
 /* Free a hierarchy (NULL-safe). */
 void eamg_destroy(eamg_hierarchy *h);

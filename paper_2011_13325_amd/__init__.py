@@ -31,7 +31,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 # Every symbol include/eamg.h declares.
 EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
-            "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match"]
+            "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
+            "eamg_profile_enable", "eamg_profile_read"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -66,6 +67,11 @@ class eamg_level_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("bs", ctypes.c_int32), ("nnzb_A", ctypes.c_int64),
                 ("n_coarse", ctypes.c_int32), ("k_coarse", ctypes.c_int32),
                 ("nnzb_P", ctypes.c_int64), ("n_colors", ctypes.c_int32)]
+
+
+class eamg_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -107,6 +113,10 @@ def lib():
     L.eamg_host_match.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp, P(eamg_setup_params), vp,
                                   P(i32), vp, P(dp)]
     L.eamg_host_match.restype = ctypes.c_int
+    L.eamg_profile_enable.argtypes = [vp, i32]
+    L.eamg_profile_enable.restype = ctypes.c_int
+    L.eamg_profile_read.argtypes = [vp, i32, P(eamg_kernel_stat), P(i32)]
+    L.eamg_profile_read.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -251,6 +261,23 @@ def eamg_traffic_model(h):
     if st != EAMG_OK:
         raise EamgError(st, "eamg_traffic_model")
     return v.value, it.value
+
+
+def eamg_profile_enable(h, on=True):
+    st = lib().eamg_profile_enable(h, int(on))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_profile_enable")
+
+
+def eamg_profile_read(h, max_entries=64):
+    """Per-kernel records since enabling: list of dicts sorted by total time."""
+    buf = (eamg_kernel_stat * max_entries)()
+    n = ctypes.c_int32()
+    st = lib().eamg_profile_read(h, max_entries, buf, ctypes.byref(n))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_profile_read")
+    return [dict(name=buf[i].name.decode(), launches=buf[i].launches, total_ms=buf[i].total_ms,
+                 bytes=buf[i].bytes) for i in range(min(n.value, max_entries))]
 
 
 def eamg_destroy(h):

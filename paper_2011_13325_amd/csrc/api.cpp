@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -108,6 +109,18 @@ struct Level {
   double *Dinv = nullptr;
   int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
   double *x = nullptr, *b = nullptr, *r = nullptr;
+  // whole-level sweeps in one workgroup (small levels)
+  bool one_wg = false;
+  int *color_ptr_d = nullptr;
+  // algorithmic bytes of every launch (for the traffic model and the profiler)
+  std::vector<double> bytes_fwd, bytes_bwd;   // per colour
+  double bytes_resid = 0, bytes_R = 0, bytes_P = 0, bytes_spmv = 0;
+};
+
+struct ProfRec {
+  std::string name;
+  double bytes;
+  hipEvent_t a, b;
 };
 
 }  // namespace
@@ -124,8 +137,14 @@ struct eamg_hierarchy {
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;
   double *scal_h = nullptr;   // pinned
+  // profiler: events around every launch while enabled
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<eamg::ProfRec> prof;
   ~eamg_hierarchy() {
     if (scal_h) (void)hipHostFree(scal_h);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -321,6 +340,65 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
 }
 
 
+hipEvent_t next_event(eamg_hierarchy *h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "event");
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Launch through `f`; while profiling, bracket it with events and record its algorithmic bytes.
+template <class F>
+void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
+           hipStream_t s, F &&f) {
+  if (!h->prof_on) {
+    hip_check(f(), what);
+    return;
+  }
+  ProfRec r{name, bytes, next_event(h), next_event(h)};
+  hip_check(hipEventRecord(r.a, s), "event");
+  hip_check(f(), what);
+  hip_check(hipEventRecord(r.b, s), "event");
+  h->prof.push_back(r);
+}
+
+std::string tname(const char *base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }
+std::string tname(const char *base, int a, int b) {
+  return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
+}
+
+// Bytes of a row range [r0, r1) of a colour-major square level: blocks [lo(row), hi(row)) read,
+// plus `per_row` bytes per row and every distinct column of those blocks gathered once.
+double range_bytes(const Pattern &Ap, const std::vector<int> &dg, int bs, int r0, int r1, int part,
+                   double per_row, std::vector<int> &mark, int stamp) {
+  double blocks = 0.0, uniq = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const int64_t lo = part == 2 ? dg[i] + 1 : Ap.rp[i];
+    const int64_t hi = part == 0 ? dg[i] + 1 : Ap.rp[i + 1];
+    blocks += double(hi - lo);
+    for (int64_t q = lo; q < hi; ++q)
+      if (mark[Ap.col[q]] != stamp) {
+        mark[Ap.col[q]] = stamp;
+        uniq += 1.0;
+      }
+  }
+  return blocks * (bs * bs * 8.0 + 4.0) + double(r1 - r0) * per_row + uniq * bs * 8.0;
+}
+
+double rect_bytes(const Pattern &M, int br, int bc, bool accumulate) {
+  std::vector<char> seen(size_t(M.n_cols), 0);
+  double uniq = 0.0;
+  for (int c : M.col)
+    if (!seen[c]) {
+      seen[c] = 1;
+      uniq += 1.0;
+    }
+  return double(M.nnz()) * (br * bc * 8.0 + 4.0) + 4.0 * (M.n_rows + 1) + uniq * bc * 8.0 +
+         double(M.n_rows) * br * 8.0 * (accumulate ? 2.0 : 1.0);
+}
+
 void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   Level &L = h->lv[l];
   DevArena &ar = h->arena;
@@ -350,6 +428,38 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg);
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
+  {
+    std::vector<int> seen(size_t(L.n), 0);
+    double uniq = 0.0;
+    for (int c : Ap.col)
+      if (!seen[c]) {
+        seen[c] = 1;
+        uniq += 1.0;
+      }
+    L.bytes_spmv = double(Ap.nnz()) * (bs * bs * 8.0 + 4.0) + 4.0 * (L.n + 1) + uniq * bs * 8.0 +
+                   double(L.n) * bs * 8.0;
+  }
+  if (!coarsest) {
+    std::vector<int> mark(size_t(L.n), -1);
+    int stamp = 0;
+    const double rowb = 8.0 + bs * bs * 8.0;   // row offset + diagonal index, D^+ block
+    for (int c = 0; c < L.ncolors; ++c) {
+      const int r0 = L.color_ptr[c], r1 = L.color_ptr[c + 1];
+      // forward: lower blocks + diagonal; b read, x and r written
+      L.bytes_fwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 0, rowb + 3.0 * bs * 8.0, mark, stamp++));
+      // backward: whole rows; b read, x written
+      L.bytes_bwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb + 2.0 * bs * 8.0, mark, stamp++));
+    }
+    L.bytes_resid = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 8.0, mark, stamp++);
+    // small levels: one workgroup walks all colours (per-colour launches would be latency bound)
+    double wg_bytes = 0.0;
+    if (const char *e = std::getenv("EAMG_WG_BYTES")) wg_bytes = std::atof(e);
+    const double a_bytes = double(Ap.nnz()) * bs * bs * 8.0;
+    if (L.ncolors > 0 && a_bytes <= wg_bytes) {
+      L.one_wg = true;
+      L.color_ptr_d = ar.upload(L.color_ptr, s);
+    }
+  }
   if (coarsest) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
     L.x = ar.alloc<double>(size_t(L.n) * bs);
@@ -372,6 +482,8 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   std::vector<int64_t> srcR(srcT.size());
   for (size_t q = 0; q < srcT.size(); ++q) srcR[q] = srcP[size_t(srcT[q])];
   L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true);
+  L.bytes_R = rect_bytes(Rp, L.kc, bs, false);
+  L.bytes_P = rect_bytes(Pp, bs, L.kc, true);
   L.r = ar.alloc<double>(size_t(L.n) * bs);
   if (l > 0) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
@@ -431,18 +543,47 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
 void vcycle(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t s) {
   Level &L = h->lv[l];
   if (l + 1 == h->lv.size()) {
-    hip_check(launch_dense_gemv(h->nL, h->Ainv, b, x, s), "coarsest");
+    const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * 8.0;
+    timed(h, "coarsest", "k_dense_gemv", by, s, [&] { return launch_dense_gemv(h->nL, h->Ainv, b, x, s); });
     return;
   }
-  for (int c = 0; c < L.ncolors; ++c)
-    hip_check(launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs_fwd");
-  hip_check(launch_resid_upper(L.Am, x, L.r, s), "resid_upper");
+  const int bs = L.bs;
+  SweepArgs sw;
+  sw.A = L.Am;
+  sw.Dinv = L.Dinv;
+  sw.color_ptr = L.color_ptr_d;
+  sw.ncolors = L.ncolors;
+  sw.b = b;
+  sw.x = x;
+  sw.r = L.r;
+  if (L.one_wg) {
+    double by = L.bytes_resid;
+    for (double v : L.bytes_fwd) by += v;
+    timed(h, "gs_fwd_wg", tname("k_gs_fwd_wg", bs), by, s, [&] { return launch_gs_fwd_wg(sw, s); });
+  } else {
+    for (int c = 0; c < L.ncolors; ++c)
+      timed(h, "gs_fwd", tname("k_gs_fwd", bs), L.bytes_fwd[c], s, [&] {
+        return launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s);
+      });
+    timed(h, "resid_upper", tname("k_resid_upper", bs), L.bytes_resid, s,
+          [&] { return launch_resid_upper(L.Am, x, L.r, s); });
+  }
   Level &C = h->lv[l + 1];
-  hip_check(launch_rect(L.Rm, L.r, C.b, false, s), "restrict");
+  timed(h, "restrict", tname("k_rect", L.kc, bs), L.bytes_R, s,
+        [&] { return launch_rect(L.Rm, L.r, C.b, false, s); });
   vcycle(h, l + 1, C.b, C.x, s);
-  hip_check(launch_rect(L.Pm, C.x, x, true, s), "prolong");
-  for (int c = L.ncolors - 1; c >= 0; --c)
-    hip_check(launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs_bwd");
+  timed(h, "prolong", tname("k_rect", bs, L.kc), L.bytes_P, s,
+        [&] { return launch_rect(L.Pm, C.x, x, true, s); });
+  if (L.one_wg) {
+    double by = 0.0;
+    for (double v : L.bytes_bwd) by += v;
+    timed(h, "gs_bwd_wg", tname("k_gs_bwd_wg", bs), by, s, [&] { return launch_gs_bwd_wg(sw, s); });
+  } else {
+    for (int c = L.ncolors - 1; c >= 0; --c)
+      timed(h, "gs_bwd", tname("k_gs_bwd", bs), L.bytes_bwd[c], s, [&] {
+        return launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+      });
+  }
 }
 
 void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
@@ -643,6 +784,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     const int spmv_blocks = (A0.n_rows + (256 / A0.group) - 1) / (256 / A0.group);
     h->part = ar.alloc<double>(size_t(std::max(dot_blocks(N0), spmv_blocks)));
     h->scal = ar.alloc<double>(SC_COUNT);
+
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&h->scal_h), sizeof(double) * SC_COUNT, 0),
               "hipHostMalloc");
     hip_check(hipStreamSynchronize(s), "sync");
@@ -681,6 +823,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
     const int nd = dot_blocks(N);
     const SoaMat &A = L0.Am;
     const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
+    const double vecb = double(N) * 8.0;
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
@@ -733,10 +876,14 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
         converged = true;
       }
       while (!converged && iters < sp.max_it) {
-        hip_check(launch_spmv(A, h->p, h->q, h->part, s), "spmv");
-        hip_check(launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s), "reduce");
-        hip_check(launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s), "update_xr");
-        hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+        timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
+              [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
+        timed(h, "reduce", "k_reduce", 8.0 * ns, s,
+              [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
+        timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
+              [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+        timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+              [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
         ++iters;
         fetch_scalars(h, s);
         if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
@@ -749,9 +896,12 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
         }
         if (iters >= sp.max_it) break;
         precondition();
-        hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
-        hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
-        hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
+        timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
+              [&] { return launch_dot(N, h->r, h->z, h->part, s); });
+        timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+              [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
+        timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
+              [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
       }
     }
     // true residual
@@ -855,33 +1005,59 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes, do
     double v = 0.0;
     for (size_t l = 0; l < h->lv.size(); ++l) {
       const Level &L = h->lv[l];
-      const double vec = double(L.n) * L.bs * 8.0;
-      const double blk = L.bs * L.bs * 8.0 + 4.0;
       if (l + 1 == h->lv.size()) {
-        v += double(h->nL) * h->nL * 8.0 + 2.0 * vec;
+        v += double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * 8.0;
         break;
       }
-      const double vecc = double(h->lv[l + 1].n) * L.kc * 8.0;
-      const double dinv = double(L.n) * L.bs * L.bs * 8.0;
-      const double upper = double(L.A.nnz() - L.nnz_lower - L.n);
-      // forward sweep: lower blocks + diagonal, row offsets + diag index, D^+, b, x (write and
-      // gather), r (write)
-      v += double(L.nnz_lower + L.n) * blk + 8.0 * (L.n + 1) + dinv + 4.0 * vec;
-      // residual completion: upper blocks, offsets, x gather, r read/write
-      v += upper * blk + 8.0 * (L.n + 1) + 3.0 * vec;
-      // restriction and prolongation
-      v += bytes_bcsr(L.P.nnz(), L.kc, L.bs, h->lv[l + 1].n) + vec + vecc;
-      v += bytes_bcsr(L.P.nnz(), L.bs, L.kc, L.n) + vecc + 2.0 * vec;
-      // backward sweep: full A, D^+, b, x (gather + read/write)
-      v += bytes_bcsr(L.A.nnz(), L.bs, L.bs, L.n) + dinv + 3.0 * vec;
+      for (double x : L.bytes_fwd) v += x;
+      for (double x : L.bytes_bwd) v += x;
+      v += L.bytes_resid + L.bytes_R + L.bytes_P;
     }
     const Level &L0 = h->lv[0];
     const double vec0 = double(L0.n) * L0.bs * 8.0;
-    // PCG: SpMV (A_0, p, q), x/r update (x rw, r rw, p, q), r.z (r, z), p update (z, p rw)
-    const double it = bytes_bcsr(L0.A.nnz(), L0.bs, L0.bs, L0.n) + 2.0 * vec0 + 6.0 * vec0 +
-                      2.0 * vec0 + 3.0 * vec0;
+    // PCG: SpMV with p.q, x / r update (x rw, r rw, p, q), r.z, p update (z, p rw)
+    const double it = L0.bytes_spmv + 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0;
     if (vcycle_bytes) *vcycle_bytes = v;
     if (iteration_bytes) *iteration_bytes = it + v;
+  });
+}
+
+eamg_status eamg_profile_enable(eamg_hierarchy *h, int32_t on) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    h->prof_on = on != 0;
+    h->prof.clear();
+    h->ev_used = 0;
+  });
+}
+
+eamg_status eamg_profile_read(eamg_hierarchy *h, int32_t max_entries, eamg_kernel_stat *out,
+                              int32_t *n_out) {
+  return guarded([&] {
+    if (!h || !n_out || (max_entries > 0 && !out)) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    hip_check(hipDeviceSynchronize(), "sync");
+    std::vector<eamg_kernel_stat> agg;
+    for (const ProfRec &r : h->prof) {
+      float ms = 0.0f;
+      hip_check(hipEventElapsedTime(&ms, r.a, r.b), "event");
+      auto it = std::find_if(agg.begin(), agg.end(),
+                             [&](const eamg_kernel_stat &k) { return r.name == k.name; });
+      if (it == agg.end()) {
+        eamg_kernel_stat k{};
+        std::snprintf(k.name, sizeof(k.name), "%s", r.name.c_str());
+        agg.push_back(k);
+        it = agg.end() - 1;
+      }
+      it->launches += 1;
+      it->total_ms += ms;
+      it->bytes += r.bytes;
+    }
+    std::sort(agg.begin(), agg.end(),
+              [](const eamg_kernel_stat &x, const eamg_kernel_stat &y) { return x.total_ms > y.total_ms; });
+    *n_out = int32_t(agg.size());
+    for (int i = 0; i < std::min<int>(max_entries, int(agg.size())); ++i) out[i] = agg[i];
+    h->prof.clear();
+    h->ev_used = 0;
   });
 }
 

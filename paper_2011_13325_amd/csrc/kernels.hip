@@ -318,7 +318,7 @@ __device__ inline void group_reduce(double (&acc)[BR], int G) {
 template <int BR, int BC>
 __device__ inline void row_accumulate(int p0, int p1, int lane, int G, const int *__restrict__ col,
                                       const double *__restrict__ val, int64_t nnz,
-                                      const double *__restrict__ x, double (&acc)[BR]) {
+                                      const double *x, double (&acc)[BR]) {
   for (int p = p0 + lane; p < p1; p += G) {
     const int64_t c = col[p];
     double xv[BC];
@@ -467,6 +467,104 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
       else
         y[int64_t(row) * BR + r] = acc[r];
     }
+  }
+}
+
+// ---- whole-level sweeps in one workgroup ---------------------------------------------------
+// For small levels the colours are far too small to fill the chip one launch at a time; one
+// workgroup of kWgBlock threads walks all colours, with a workgroup barrier between them (all
+// waves share one compute unit, so x written by one wave is visible to the others after it).
+
+constexpr int kWgBlock = 1024;
+
+template <int B>
+__global__ __launch_bounds__(kWgBlock) void k_gs_fwd_wg(SweepArgs a) {
+  const int G = a.A.group, rpb = kWgBlock / G;
+  const int lane = threadIdx.x & (G - 1), sub = threadIdx.x / G;
+  const int *rp = a.A.rp, *col = a.A.col, *diag = a.A.diag;
+  const double *val = a.A.val;
+  const int64_t nnz = a.A.nnz;
+  for (int c = 0; c < a.ncolors; ++c) {
+    const int r0 = a.color_ptr[c], r1 = a.color_ptr[c + 1];
+    for (int base = r0; base < r1; base += rpb) {
+      const int row = base + sub;
+      double acc[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc[q] = 0.0;
+      if (row < r1) row_accumulate<B, B>(rp[row], diag[row], lane, G, col, val, nnz, a.x, acc);
+      group_reduce<B>(acc, G);
+      if (row < r1 && lane == 0) {
+        double t[B], xi[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) t[q] = a.b[int64_t(row) * B + q] - acc[q];
+        const double *D = a.Dinv + int64_t(row) * B * B;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          double sum = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < B; ++cc) sum = fma(D[q * B + cc], t[cc], sum);
+          xi[q] = sum;
+          a.x[int64_t(row) * B + q] = sum;
+        }
+        const int64_t dp = diag[row];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          double sum = t[q];
+#pragma unroll
+          for (int cc = 0; cc < B; ++cc) sum = fma(-val[int64_t(q * B + cc) * nnz + dp], xi[cc], sum);
+          a.r[int64_t(row) * B + q] = sum;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // r_i -= sum_{j > i} A_ij x_j on every row
+  const int n = a.A.n_rows;
+  for (int base = 0; base < n; base += rpb) {
+    const int row = base + sub;
+    double acc[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) acc[q] = 0.0;
+    if (row < n) row_accumulate<B, B>(diag[row] + 1, rp[row + 1], lane, G, col, val, nnz, a.x, acc);
+    group_reduce<B>(acc, G);
+    if (row < n && lane == 0) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) a.r[int64_t(row) * B + q] -= acc[q];
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kWgBlock) void k_gs_bwd_wg(SweepArgs a) {
+  const int G = a.A.group, rpb = kWgBlock / G;
+  const int lane = threadIdx.x & (G - 1), sub = threadIdx.x / G;
+  const int *rp = a.A.rp, *col = a.A.col;
+  const double *val = a.A.val;
+  const int64_t nnz = a.A.nnz;
+  for (int c = a.ncolors - 1; c >= 0; --c) {
+    const int r0 = a.color_ptr[c], r1 = a.color_ptr[c + 1];
+    for (int base = r0; base < r1; base += rpb) {
+      const int row = base + sub;
+      double acc[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc[q] = 0.0;
+      if (row < r1) row_accumulate<B, B>(rp[row], rp[row + 1], lane, G, col, val, nnz, a.x, acc);
+      group_reduce<B>(acc, G);
+      if (row < r1 && lane == 0) {
+        double t[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) t[q] = a.b[int64_t(row) * B + q] - acc[q];
+        const double *D = a.Dinv + int64_t(row) * B * B;
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          double sum = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < B; ++cc) sum = fma(D[q * B + cc], t[cc], sum);
+          a.x[int64_t(row) * B + q] += sum;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -679,6 +777,20 @@ hipError_t launch_gs_bwd(const SoaMat &A, const double *Dinv, int r0, int r1, co
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   EAMG_DISPATCH_SQ(A.br, k_gs_bwd, grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.val,
                    A.nnz, Dinv, b, x);
+  EAMG_LAUNCH_CHECK();
+}
+
+hipError_t launch_gs_fwd_wg(const SweepArgs &a, hipStream_t s) {
+  if (a.A.n_rows == 0) return hipSuccess;
+  if (a.A.group > 64 || (a.A.group & (a.A.group - 1))) return hipErrorInvalidValue;
+  EAMG_DISPATCH_SQ(a.A.br, k_gs_fwd_wg, dim3(1), dim3(kWgBlock), 0, s, a);
+  EAMG_LAUNCH_CHECK();
+}
+
+hipError_t launch_gs_bwd_wg(const SweepArgs &a, hipStream_t s) {
+  if (a.A.n_rows == 0) return hipSuccess;
+  if (a.A.group > 64 || (a.A.group & (a.A.group - 1))) return hipErrorInvalidValue;
+  EAMG_DISPATCH_SQ(a.A.br, k_gs_bwd_wg, dim3(1), dim3(kWgBlock), 0, s, a);
   EAMG_LAUNCH_CHECK();
 }
 

@@ -74,14 +74,36 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+_ORACLES = {}
+
+
+def _oracle_cached(name, p):
+    if name not in _ORACLES:
+        _ORACLES[name] = _oracle(p)
+    return _ORACLES[name]
+
+
+# "wg": every level sweeps all colours in one workgroup;
+# "launch": every colour of every level is its own launch (the default).
+@pytest.fixture(scope="module", params=[(c, m) for c in CASES for m in ("wg", "launch")],
+                ids=lambda cm: f"{cm[0]}-{cm[1]}")
 def pair(request):
-    kw = dict(CASES[request.param])
+    import os
+    name, mode = request.param
+    kw = dict(CASES[name])
     p = make_problem(**kw)
-    print(f"\n[case {request.param}] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
-    ho = _oracle(p)
-    hl = _lib(p)
-    yield request.param, p, ho, hl
+    print(f"\n[case {name} {mode}] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
+    ho = _oracle_cached(name, p)
+    old = os.environ.get("EAMG_WG_BYTES")
+    os.environ["EAMG_WG_BYTES"] = "1e12" if mode == "wg" else "0"
+    try:
+        hl = _lib(p)
+    finally:
+        if old is None:
+            del os.environ["EAMG_WG_BYTES"]
+        else:
+            os.environ["EAMG_WG_BYTES"] = old
+    yield f"{name}-{mode}", p, ho, hl
     hl.close()
 
 
