@@ -186,7 +186,9 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes,
 
 /*
  * Per-kernel timing, for measuring each kernel against its bandwidth roofline.  While enabled,
- * every launch of eamg_solve / eamg_vcycle is bracketed by events on the solve stream and its
+ * eamg_solve / eamg_vcycle launch eagerly (no graph) and every launch -- or run of back-to-back
+ * launches of one kernel, such as the colours of one smoother sweep -- is bracketed by events on
+ * the solve stream and its
  * algorithmic HBM bytes (matrix blocks and index arrays read once, vectors read or written
  * once, gathered vector entries counted once per launch) are recorded.  eamg_profile_read
  * synchronizes the device, aggregates the records by kernel name (the template instance, e.g.

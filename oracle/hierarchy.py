@@ -10,8 +10,8 @@
   (section "sing2": the regularization ``I - E E^T`` leaves the coarse correction unchanged),
   then a dense Cholesky factorization.
 * Colouring (not in the paper; needed by the multicolour Gauss-Seidel smoother): greedy in
-  ascending vertex id, smallest colour not used by an already coloured neighbour in the block
-  graph of A_l.
+  smallest-last order (min-degree removal, lowest id on ties, reversed), smallest colour not used
+  by an already coloured neighbour in the block graph of A_l.
 * Stop: level l is the coarsest when ``bs_l * n_l < coarsest_max_dofs``, when coarsening would
   keep more than 90 % of the vertices (or none), or when ``max_levels`` levels exist.
 """
@@ -118,10 +118,37 @@ def galerkin(A: BCSR, P: BCSR) -> BCSR:
     return BCSR(nc, nc, pc.indptr.astype(np.int64), cols.astype(np.int64), vals)
 
 
+def smallest_last_order(A: BCSR) -> list:
+    """Smallest-last vertex order of the block graph of A (self loops ignored): repeatedly remove
+    a vertex of minimum remaining degree (lowest id on ties); the order is the reverse of the
+    removal sequence."""
+    import heapq
+    n = A.n_rows
+    adj = [[int(j) for j in A.col[A.row_ptr[i]:A.row_ptr[i + 1]] if j != i] for i in range(n)]
+    deg = [len(a) for a in adj]
+    removed = [False] * n
+    heap = [(deg[v], v) for v in range(n)]
+    heapq.heapify(heap)
+    seq = []
+    while heap:
+        d, v = heapq.heappop(heap)
+        if removed[v] or d != deg[v]:
+            continue
+        removed[v] = True
+        seq.append(v)
+        for u in adj[v]:
+            if not removed[u]:
+                deg[u] -= 1
+                heapq.heappush(heap, (deg[u], u))
+    return seq[::-1]
+
+
 def greedy_coloring(A: BCSR) -> np.ndarray:
+    """Greedy colouring in smallest-last order: each vertex takes the smallest colour not used
+    by an already coloured neighbour."""
     n = A.n_rows
     colors = np.full(n, -1, dtype=np.int64)
-    for i in range(n):
+    for i in smallest_last_order(A):
         used = set()
         for j in A.col[A.row_ptr[i]:A.row_ptr[i + 1]]:
             if j != i and colors[j] >= 0:

@@ -109,9 +109,6 @@ struct Level {
   double *Dinv = nullptr;
   int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
   double *x = nullptr, *b = nullptr, *r = nullptr;
-  // whole-level sweeps in one workgroup (small levels)
-  bool one_wg = false;
-  int *color_ptr_d = nullptr;
   // algorithmic bytes of every launch (for the traffic model and the profiler)
   std::vector<double> bytes_fwd, bytes_bwd;   // per colour
   double bytes_resid = 0, bytes_R = 0, bytes_P = 0, bytes_spmv = 0;
@@ -120,6 +117,7 @@ struct Level {
 struct ProfRec {
   std::string name;
   double bytes;
+  int launches;
   hipEvent_t a, b;
 };
 
@@ -142,7 +140,13 @@ struct eamg_hierarchy {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<eamg::ProfRec> prof;
+  // PCG iteration captured as a graph (V-cycle .. r.r and the scalar copy), replayed per iteration
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t g_iter = nullptr;
+  bool graph_tried = false;
   ~eamg_hierarchy() {
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (scal_h) (void)hipHostFree(scal_h);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
@@ -349,19 +353,26 @@ hipEvent_t next_event(eamg_hierarchy *h) {
   return h->ev_pool[h->ev_used++];
 }
 
-// Launch through `f`; while profiling, bracket it with events and record its algorithmic bytes.
+// Run `f`, which enqueues `launches` back-to-back launches of one kernel; while profiling,
+// bracket them with one pair of events and record their algorithmic bytes.
 template <class F>
-void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
-           hipStream_t s, F &&f) {
+void timed_n(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
+             int launches, hipStream_t s, F &&f) {
   if (!h->prof_on) {
     hip_check(f(), what);
     return;
   }
-  ProfRec r{name, bytes, next_event(h), next_event(h)};
+  ProfRec r{name, bytes, launches, next_event(h), next_event(h)};
   hip_check(hipEventRecord(r.a, s), "event");
   hip_check(f(), what);
   hip_check(hipEventRecord(r.b, s), "event");
   h->prof.push_back(r);
+}
+
+template <class F>
+void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
+           hipStream_t s, F &&f) {
+  timed_n(h, what, name, bytes, 1, s, std::forward<F>(f));
 }
 
 std::string tname(const char *base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }
@@ -451,14 +462,6 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
       L.bytes_bwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb + 2.0 * bs * 8.0, mark, stamp++));
     }
     L.bytes_resid = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 8.0, mark, stamp++);
-    // small levels: one workgroup walks all colours (per-colour launches would be latency bound)
-    double wg_bytes = 0.0;
-    if (const char *e = std::getenv("EAMG_WG_BYTES")) wg_bytes = std::atof(e);
-    const double a_bytes = double(Ap.nnz()) * bs * bs * 8.0;
-    if (L.ncolors > 0 && a_bytes <= wg_bytes) {
-      L.one_wg = true;
-      L.color_ptr_d = ar.upload(L.color_ptr, s);
-    }
   }
   if (coarsest) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
@@ -548,42 +551,82 @@ void vcycle(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t
     return;
   }
   const int bs = L.bs;
-  SweepArgs sw;
-  sw.A = L.Am;
-  sw.Dinv = L.Dinv;
-  sw.color_ptr = L.color_ptr_d;
-  sw.ncolors = L.ncolors;
-  sw.b = b;
-  sw.x = x;
-  sw.r = L.r;
-  if (L.one_wg) {
-    double by = L.bytes_resid;
-    for (double v : L.bytes_fwd) by += v;
-    timed(h, "gs_fwd_wg", tname("k_gs_fwd_wg", bs), by, s, [&] { return launch_gs_fwd_wg(sw, s); });
-  } else {
-    for (int c = 0; c < L.ncolors; ++c)
-      timed(h, "gs_fwd", tname("k_gs_fwd", bs), L.bytes_fwd[c], s, [&] {
-        return launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s);
-      });
-    timed(h, "resid_upper", tname("k_resid_upper", bs), L.bytes_resid, s,
-          [&] { return launch_resid_upper(L.Am, x, L.r, s); });
+  double fwd_bytes = 0.0, bwd_bytes = 0.0;
+  for (int c = 0; c < L.ncolors; ++c) {
+    fwd_bytes += L.bytes_fwd[c];
+    bwd_bytes += L.bytes_bwd[c];
   }
+  // the colours of a sweep are back-to-back launches of one kernel: timed as one run
+  timed_n(h, "gs_fwd", tname("k_gs_color", bs, 1), fwd_bytes, L.ncolors, s, [&] {
+    for (int c = 0; c < L.ncolors; ++c) {
+      const hipError_t e = launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+  timed(h, "resid_upper", tname("k_resid_upper", bs), L.bytes_resid, s,
+        [&] { return launch_resid_upper(L.Am, x, L.r, s); });
   Level &C = h->lv[l + 1];
   timed(h, "restrict", tname("k_rect", L.kc, bs), L.bytes_R, s,
         [&] { return launch_rect(L.Rm, L.r, C.b, false, s); });
   vcycle(h, l + 1, C.b, C.x, s);
   timed(h, "prolong", tname("k_rect", bs, L.kc), L.bytes_P, s,
         [&] { return launch_rect(L.Pm, C.x, x, true, s); });
-  if (L.one_wg) {
-    double by = 0.0;
-    for (double v : L.bytes_bwd) by += v;
-    timed(h, "gs_bwd_wg", tname("k_gs_bwd_wg", bs), by, s, [&] { return launch_gs_bwd_wg(sw, s); });
-  } else {
-    for (int c = L.ncolors - 1; c >= 0; --c)
-      timed(h, "gs_bwd", tname("k_gs_bwd", bs), L.bytes_bwd[c], s, [&] {
-        return launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
-      });
+  timed_n(h, "gs_bwd", tname("k_gs_color", bs, 0), bwd_bytes, L.ncolors, s, [&] {
+    for (int c = L.ncolors - 1; c >= 0; --c) {
+      const hipError_t e = launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
+// One PCG iteration after the stopping test: z = V(r), beta, p = z + beta p, q = A p, alpha,
+// x += alpha p, r -= alpha q, r.r, and the scalars copied to pinned host memory.
+void enqueue_iteration(eamg_hierarchy *h, hipStream_t s) {
+  const Level &L0 = h->lv[0];
+  const SoaMat &A = L0.Am;
+  const int64_t N = int64_t(L0.n) * L0.bs;
+  const int nd = dot_blocks(N);
+  const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
+  vcycle(h, 0, h->r, h->z, s);
+  hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+  hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
+  hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
+  hip_check(launch_spmv(A, h->p, h->q, h->part, s), "spmv");
+  hip_check(launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s), "reduce");
+  hip_check(launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s), "update_xr");
+  hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+  hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s),
+            "copy");
+}
+
+// Capture enqueue_iteration once; on any failure fall back to eager launches.
+void try_build_graph(eamg_hierarchy *h) {
+  h->graph_tried = true;
+  if (const char *e = std::getenv("EAMG_GRAPH"))
+    if (std::atoi(e) == 0) return;
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    h->cap_stream = nullptr;
+    return;
   }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return;
+  bool ok = true;
+  try {
+    enqueue_iteration(h, h->cap_stream);
+  } catch (const Failure &) {
+    ok = false;
+  }
+  if (hipStreamEndCapture(h->cap_stream, &g) != hipSuccess || !ok) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) h->g_iter = ex;
+  (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
 }
 
 void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
@@ -848,6 +891,12 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
       hip_check(launch_fill(N, 0.0, h->x, s), "fill");
       hip_check(launch_copy(N, h->bp, h->r, s), "copy");
     }
+    auto precondition = [&]() {
+      if (sp.precond)
+        vcycle(h, 0, h->r, h->z, s);
+      else
+        hip_check(launch_copy(N, h->r, h->z, s), "copy");
+    };
     fetch_scalars(h, s);
     if (h->scal_h[SC_NONFINITE] != 0.0) fail(EAMG_ERR_BREAKDOWN, "right-hand side is not finite");
     const double bnorm = std::sqrt(h->scal_h[SC_BB]);
@@ -855,12 +904,6 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
       hip_check(launch_fill(N, 0.0, h->x, s), "fill");
       converged = true;
     } else {
-      auto precondition = [&]() {
-        if (sp.precond)
-          vcycle(h, 0, h->r, h->z, s);
-        else
-          hip_check(launch_copy(N, h->r, h->z, s), "copy");
-      };
       precondition();
       hip_check(launch_copy(N, h->z, h->p, s), "copy");
       hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
@@ -875,17 +918,22 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
         if (h->scal_h[SC_RR] != 0.0) fail(EAMG_ERR_BREAKDOWN, "r.z <= 0 at the start (preconditioner not SPD)");
         converged = true;
       }
-      while (!converged && iters < sp.max_it) {
-        timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
-              [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
-        timed(h, "reduce", "k_reduce", 8.0 * ns, s,
-              [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
-        timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
-              [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
-        timed(h, "reduce", "k_reduce", 8.0 * nd, s,
-              [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
+    }
+    if (!converged) {
+      // first iteration (p = z already set), then z = V(r) ... per further iteration
+      timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
+            [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
+      timed(h, "reduce", "k_reduce", 8.0 * ns, s,
+            [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
+      timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
+            [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+      timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+            [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
+      fetch_scalars(h, s);
+      const bool graphs = sp.precond && !h->prof_on;
+      if (graphs && !h->graph_tried) try_build_graph(h);
+      while (!converged) {
         ++iters;
-        fetch_scalars(h, s);
         if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
         const double rr = h->scal_h[SC_RR];
         if (!std::isfinite(rr)) fail(EAMG_ERR_BREAKDOWN, "residual is not finite");
@@ -895,13 +943,27 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
           break;
         }
         if (iters >= sp.max_it) break;
-        precondition();
-        timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
-              [&] { return launch_dot(N, h->r, h->z, h->part, s); });
-        timed(h, "reduce", "k_reduce", 8.0 * nd, s,
-              [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
-        timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
-              [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
+        if (graphs && h->g_iter) {
+          hip_check(hipGraphLaunch(h->g_iter, s), "graph launch");
+          hip_check(hipStreamSynchronize(s), "sync");
+        } else {
+          precondition();
+          timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
+                [&] { return launch_dot(N, h->r, h->z, h->part, s); });
+          timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+                [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
+          timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
+                [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
+          timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
+                [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
+          timed(h, "reduce", "k_reduce", 8.0 * ns, s,
+                [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
+          timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
+                [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+          timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+                [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
+          fetch_scalars(h, s);
+        }
       }
     }
     // true residual
@@ -1048,7 +1110,7 @@ eamg_status eamg_profile_read(eamg_hierarchy *h, int32_t max_entries, eamg_kerne
         agg.push_back(k);
         it = agg.end() - 1;
       }
-      it->launches += 1;
+      it->launches += r.launches;
       it->total_ms += ms;
       it->bytes += r.bytes;
     }

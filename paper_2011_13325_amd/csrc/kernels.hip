@@ -6,6 +6,7 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <cstdlib>
 
 namespace eamg {
 
@@ -359,43 +360,116 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n_rows, int G, const int *_
   }
 }
 
+// Butterfly all-reduce within the group: every lane ends with the group total.
 template <int B>
-__global__ __launch_bounds__(kBlock) void k_gs_fwd(int r0, int r1, int G, const int *__restrict__ rp,
-                                                  const int *__restrict__ col,
-                                                  const int *__restrict__ diag,
-                                                  const double *__restrict__ val, int64_t nnz,
-                                                  const double *__restrict__ Dinv,
-                                                  const double *__restrict__ b, double *x,
-                                                  double *__restrict__ r) {
-  const int lane = threadIdx.x & (G - 1);
-  const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
+__device__ inline void group_allreduce(double (&acc)[B], int G) {
+  for (int off = G >> 1; off > 0; off >>= 1)
+#pragma unroll
+    for (int r = 0; r < B; ++r) acc[r] += __shfl_xor(acc[r], off, G);
+}
+
+template <int B>
+__device__ inline double pick(const double (&v)[B], int i) {
+  double out = 0.0;
+#pragma unroll
+  for (int q = 0; q < B; ++q) out = (q == i) ? v[q] : out;
+  return out;
+}
+
+// One row of a multicolour block Gauss-Seidel sweep, computed by the G lanes of a row group.
+// FWD: x = 0 before the sweep, so only the blocks left of the diagonal (lower colours) are read;
+// also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row.
+// Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
+// together with the row's blocks, so a row costs one round of row loads plus the x gathers.
+template <int B, bool FWD>
+__device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
+                              const int *__restrict__ col, const int *__restrict__ diag,
+                              const double *__restrict__ val, int64_t nnz,
+                              const double *__restrict__ Dinv, const double *__restrict__ b,
+                              double *x, double *r) {
+  const bool own = valid && lane < B;
+  int p0 = 0, p1 = 0;
+  int64_t dp = 0;
+  if (valid) {
+    p0 = rp[row];
+    dp = diag[row];
+    p1 = FWD ? int(dp) : rp[row + 1];
+  }
+  double bq = 0.0, Dq[B], Aq[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    Dq[c] = 0.0;
+    Aq[c] = 0.0;
+  }
+  if (own) {
+    bq = b[int64_t(row) * B + lane];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      Dq[c] = Dinv[int64_t(row) * B * B + lane * B + c];
+      if (FWD) Aq[c] = val[int64_t(lane * B + c) * nnz + dp];
+    }
+  }
+  double acc[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) acc[q] = 0.0;
+  if (valid) row_accumulate<B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
+  group_allreduce<B>(acc, G);
+  const double tq = bq - pick<B>(acc, lane);   // t component of this lane (lanes < B)
+  double t[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) t[c] = __shfl(tq, c, G);
+  double xq = 0.0;
+#pragma unroll
+  for (int c = 0; c < B; ++c) xq = fma(Dq[c], t[c], xq);
+  if (FWD) {
+    double xi[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) xi[c] = __shfl(xq, c, G);
+    double rq = tq;
+#pragma unroll
+    for (int c = 0; c < B; ++c) rq = fma(-Aq[c], xi[c], rq);
+    if (own) {
+      x[int64_t(row) * B + lane] = xq;
+      r[int64_t(row) * B + lane] = rq;
+    }
+  } else {
+    if (own) x[int64_t(row) * B + lane] += xq;
+  }
+}
+
+// r_i -= sum_{j > i} A_ij x_j for one row.
+template <int B>
+__device__ inline void resid_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
+                                 const int *__restrict__ col, const int *__restrict__ diag,
+                                 const double *__restrict__ val, int64_t nnz, const double *x,
+                                 double *r) {
+  double rq = 0.0;
+  int p0 = 0, p1 = 0;
+  if (valid) {
+    p0 = diag[row] + 1;
+    p1 = rp[row + 1];
+    if (lane < B) rq = r[int64_t(row) * B + lane];
+  }
   double acc[B];
 #pragma unroll
   for (int a = 0; a < B; ++a) acc[a] = 0.0;
-  if (row < r1) row_accumulate<B, B>(rp[row], diag[row], lane, G, col, val, nnz, x, acc);
-  group_reduce<B>(acc, G);
-  if (row < r1 && lane == 0) {
-    double t[B], xi[B];
-#pragma unroll
-    for (int a = 0; a < B; ++a) t[a] = b[int64_t(row) * B + a] - acc[a];
-    const double *D = Dinv + int64_t(row) * B * B;
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < B; ++c) s = fma(D[a * B + c], t[c], s);
-      xi[a] = s;
-      x[int64_t(row) * B + a] = s;
-    }
-    const int64_t dp = diag[row];
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      double s = t[a];
-#pragma unroll
-      for (int c = 0; c < B; ++c) s = fma(-val[int64_t(a * B + c) * nnz + dp], xi[c], s);
-      r[int64_t(row) * B + a] = s;
-    }
-  }
+  if (valid) row_accumulate<B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
+  group_allreduce<B>(acc, G);
+  if (valid && lane < B) r[int64_t(row) * B + lane] = rq - pick<B>(acc, lane);
+}
+
+// One colour (rows [r0, r1)) per launch.
+template <int B, bool FWD>
+__global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const int *__restrict__ diag,
+                                                    const double *__restrict__ val, int64_t nnz,
+                                                    const double *__restrict__ Dinv,
+                                                    const double *__restrict__ b, double *x,
+                                                    double *r) {
+  const int lane = threadIdx.x & (G - 1);
+  const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  gs_row<B, FWD>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r);
 }
 
 template <int B>
@@ -403,47 +477,10 @@ __global__ __launch_bounds__(kBlock) void k_resid_upper(int n_rows, int G, const
                                                        const int *__restrict__ col,
                                                        const int *__restrict__ diag,
                                                        const double *__restrict__ val, int64_t nnz,
-                                                       const double *__restrict__ x,
-                                                       double *__restrict__ r) {
+                                                       const double *x, double *r) {
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  double acc[B];
-#pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = 0.0;
-  if (row < n_rows) row_accumulate<B, B>(diag[row] + 1, rp[row + 1], lane, G, col, val, nnz, x, acc);
-  group_reduce<B>(acc, G);
-  if (row < n_rows && lane == 0) {
-#pragma unroll
-    for (int a = 0; a < B; ++a) r[int64_t(row) * B + a] -= acc[a];
-  }
-}
-
-template <int B>
-__global__ __launch_bounds__(kBlock) void k_gs_bwd(int r0, int r1, int G, const int *__restrict__ rp,
-                                                  const int *__restrict__ col,
-                                                  const double *__restrict__ val, int64_t nnz,
-                                                  const double *__restrict__ Dinv,
-                                                  const double *__restrict__ b, double *x) {
-  const int lane = threadIdx.x & (G - 1);
-  const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  double acc[B];
-#pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = 0.0;
-  if (row < r1) row_accumulate<B, B>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
-  group_reduce<B>(acc, G);
-  if (row < r1 && lane == 0) {
-    double t[B];
-#pragma unroll
-    for (int a = 0; a < B; ++a) t[a] = b[int64_t(row) * B + a] - acc[a];
-    const double *D = Dinv + int64_t(row) * B * B;
-#pragma unroll
-    for (int a = 0; a < B; ++a) {
-      double s = 0.0;
-#pragma unroll
-      for (int c = 0; c < B; ++c) s = fma(D[a * B + c], t[c], s);
-      x[int64_t(row) * B + a] += s;
-    }
-  }
+  resid_row<B>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r);
 }
 
 template <int BR, int BC>
@@ -467,104 +504,6 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
       else
         y[int64_t(row) * BR + r] = acc[r];
     }
-  }
-}
-
-// ---- whole-level sweeps in one workgroup ---------------------------------------------------
-// For small levels the colours are far too small to fill the chip one launch at a time; one
-// workgroup of kWgBlock threads walks all colours, with a workgroup barrier between them (all
-// waves share one compute unit, so x written by one wave is visible to the others after it).
-
-constexpr int kWgBlock = 1024;
-
-template <int B>
-__global__ __launch_bounds__(kWgBlock) void k_gs_fwd_wg(SweepArgs a) {
-  const int G = a.A.group, rpb = kWgBlock / G;
-  const int lane = threadIdx.x & (G - 1), sub = threadIdx.x / G;
-  const int *rp = a.A.rp, *col = a.A.col, *diag = a.A.diag;
-  const double *val = a.A.val;
-  const int64_t nnz = a.A.nnz;
-  for (int c = 0; c < a.ncolors; ++c) {
-    const int r0 = a.color_ptr[c], r1 = a.color_ptr[c + 1];
-    for (int base = r0; base < r1; base += rpb) {
-      const int row = base + sub;
-      double acc[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) acc[q] = 0.0;
-      if (row < r1) row_accumulate<B, B>(rp[row], diag[row], lane, G, col, val, nnz, a.x, acc);
-      group_reduce<B>(acc, G);
-      if (row < r1 && lane == 0) {
-        double t[B], xi[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) t[q] = a.b[int64_t(row) * B + q] - acc[q];
-        const double *D = a.Dinv + int64_t(row) * B * B;
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-          double sum = 0.0;
-#pragma unroll
-          for (int cc = 0; cc < B; ++cc) sum = fma(D[q * B + cc], t[cc], sum);
-          xi[q] = sum;
-          a.x[int64_t(row) * B + q] = sum;
-        }
-        const int64_t dp = diag[row];
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-          double sum = t[q];
-#pragma unroll
-          for (int cc = 0; cc < B; ++cc) sum = fma(-val[int64_t(q * B + cc) * nnz + dp], xi[cc], sum);
-          a.r[int64_t(row) * B + q] = sum;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // r_i -= sum_{j > i} A_ij x_j on every row
-  const int n = a.A.n_rows;
-  for (int base = 0; base < n; base += rpb) {
-    const int row = base + sub;
-    double acc[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) acc[q] = 0.0;
-    if (row < n) row_accumulate<B, B>(diag[row] + 1, rp[row + 1], lane, G, col, val, nnz, a.x, acc);
-    group_reduce<B>(acc, G);
-    if (row < n && lane == 0) {
-#pragma unroll
-      for (int q = 0; q < B; ++q) a.r[int64_t(row) * B + q] -= acc[q];
-    }
-  }
-}
-
-template <int B>
-__global__ __launch_bounds__(kWgBlock) void k_gs_bwd_wg(SweepArgs a) {
-  const int G = a.A.group, rpb = kWgBlock / G;
-  const int lane = threadIdx.x & (G - 1), sub = threadIdx.x / G;
-  const int *rp = a.A.rp, *col = a.A.col;
-  const double *val = a.A.val;
-  const int64_t nnz = a.A.nnz;
-  for (int c = a.ncolors - 1; c >= 0; --c) {
-    const int r0 = a.color_ptr[c], r1 = a.color_ptr[c + 1];
-    for (int base = r0; base < r1; base += rpb) {
-      const int row = base + sub;
-      double acc[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) acc[q] = 0.0;
-      if (row < r1) row_accumulate<B, B>(rp[row], rp[row + 1], lane, G, col, val, nnz, a.x, acc);
-      group_reduce<B>(acc, G);
-      if (row < r1 && lane == 0) {
-        double t[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) t[q] = a.b[int64_t(row) * B + q] - acc[q];
-        const double *D = a.Dinv + int64_t(row) * B * B;
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-          double sum = 0.0;
-#pragma unroll
-          for (int cc = 0; cc < B; ++cc) sum = fma(D[q * B + cc], t[cc], sum);
-          a.x[int64_t(row) * B + q] += sum;
-        }
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -754,12 +693,20 @@ hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part
   EAMG_LAUNCH_CHECK();
 }
 
+#define EAMG_GS_LAUNCH(B_, FWD_, RPTR_)                                                          \
+  hipLaunchKernelGGL((k_gs_color<B_, FWD_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp,     \
+                     A.col, A.diag, A.val, A.nnz, Dinv, b, x, RPTR_)
+
 hipError_t launch_gs_fwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
                          double *x, double *r, hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
-  EAMG_DISPATCH_SQ(A.br, k_gs_fwd, grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag,
-                   A.val, A.nnz, Dinv, b, x, r);
+  switch (A.br) {
+    case 1: EAMG_GS_LAUNCH(1, true, r); break;
+    case 3: EAMG_GS_LAUNCH(3, true, r); break;
+    case 6: EAMG_GS_LAUNCH(6, true, r); break;
+    default: return hipErrorInvalidValue;
+  }
   EAMG_LAUNCH_CHECK();
 }
 
@@ -775,22 +722,13 @@ hipError_t launch_gs_bwd(const SoaMat &A, const double *Dinv, int r0, int r1, co
                          double *x, hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
-  EAMG_DISPATCH_SQ(A.br, k_gs_bwd, grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.val,
-                   A.nnz, Dinv, b, x);
-  EAMG_LAUNCH_CHECK();
-}
-
-hipError_t launch_gs_fwd_wg(const SweepArgs &a, hipStream_t s) {
-  if (a.A.n_rows == 0) return hipSuccess;
-  if (a.A.group > 64 || (a.A.group & (a.A.group - 1))) return hipErrorInvalidValue;
-  EAMG_DISPATCH_SQ(a.A.br, k_gs_fwd_wg, dim3(1), dim3(kWgBlock), 0, s, a);
-  EAMG_LAUNCH_CHECK();
-}
-
-hipError_t launch_gs_bwd_wg(const SweepArgs &a, hipStream_t s) {
-  if (a.A.n_rows == 0) return hipSuccess;
-  if (a.A.group > 64 || (a.A.group & (a.A.group - 1))) return hipErrorInvalidValue;
-  EAMG_DISPATCH_SQ(a.A.br, k_gs_bwd_wg, dim3(1), dim3(kWgBlock), 0, s, a);
+  double *none = nullptr;
+  switch (A.br) {
+    case 1: EAMG_GS_LAUNCH(1, false, none); break;
+    case 3: EAMG_GS_LAUNCH(3, false, none); break;
+    case 6: EAMG_GS_LAUNCH(6, false, none); break;
+    default: return hipErrorInvalidValue;
+  }
   EAMG_LAUNCH_CHECK();
 }
 

@@ -82,19 +82,6 @@ hipError_t launch_resid_upper(const SoaMat &A, const double *x, double *r, hipSt
 // Backward colour sweep on rows [r0, r1): x_i += Dinv_i (b_i - sum_j A_ij x_j).
 hipError_t launch_gs_bwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
                          double *x, hipStream_t s);
-// Whole-level sweeps in one workgroup (for small levels): the colours are processed in order
-// with a workgroup barrier between them; the forward sweep also completes r = b - A x.
-struct SweepArgs {
-  SoaMat A;
-  const double *Dinv = nullptr;
-  const int *color_ptr = nullptr;   // device, ncolors + 1 entries
-  int ncolors = 0;
-  const double *b = nullptr;
-  double *x = nullptr, *r = nullptr;
-};
-hipError_t launch_gs_fwd_wg(const SweepArgs &a, hipStream_t s);
-hipError_t launch_gs_bwd_wg(const SweepArgs &a, hipStream_t s);
-
 // y = M x (rectangular, overwrite) or y += M x (accumulate = true).
 hipError_t launch_rect(const SoaMat &M, const double *x, double *y, bool accumulate, hipStream_t s);
 // y = D x for a dense n x n row-major matrix.

@@ -1,7 +1,9 @@
 #include "structure.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <map>
+#include <queue>
 
 namespace eamg {
 
@@ -128,10 +130,32 @@ Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src) {
 
 std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
   const int n = A.n_rows;
+  // smallest-last order: remove a vertex of minimum remaining degree (lowest id on ties)
+  std::vector<int> deg(static_cast<size_t>(n), 0);
+  for (int i = 0; i < n; ++i)
+    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
+      if (A.col[p] != i) ++deg[i];
+  std::vector<char> removed(static_cast<size_t>(n), 0);
+  std::priority_queue<std::pair<int, int>, std::vector<std::pair<int, int>>, std::greater<>> heap;
+  for (int v = 0; v < n; ++v) heap.emplace(deg[v], v);
+  std::vector<int> seq;
+  seq.reserve(static_cast<size_t>(n));
+  while (!heap.empty()) {
+    const auto [d, v] = heap.top();
+    heap.pop();
+    if (removed[v] || d != deg[v]) continue;
+    removed[v] = 1;
+    seq.push_back(v);
+    for (int64_t p = A.rp[v]; p < A.rp[v + 1]; ++p) {
+      const int u = A.col[p];
+      if (u != v && !removed[u]) heap.emplace(--deg[u], u);
+    }
+  }
   std::vector<int> color(static_cast<size_t>(n), -1);
   std::vector<int> used;
   n_colors = 0;
-  for (int i = 0; i < n; ++i) {
+  for (auto it = seq.rbegin(); it != seq.rend(); ++it) {
+    const int i = *it;
     used.clear();
     for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
       const int j = A.col[p];

@@ -42,7 +42,8 @@ Pattern spgemm_symbolic(const Pattern &A, const Pattern &B);
 // Transposed pattern; src[q] = index in P of entry q of the transpose.
 Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src);
 
-// Greedy colouring in ascending vertex id (smallest colour unused by coloured neighbours).
+// Greedy colouring in smallest-last order (vertices removed by minimum remaining degree, lowest
+// id on ties; coloured in reverse removal order with the smallest colour unused by neighbours).
 std::vector<int> greedy_coloring(const Pattern &A, int &n_colors);
 
 // Symmetric permutation of a square pattern: row/col v -> inv[v].  Columns re-sorted;

@@ -83,27 +83,14 @@ def _oracle_cached(name, p):
     return _ORACLES[name]
 
 
-# "wg": every level sweeps all colours in one workgroup;
-# "launch": every colour of every level is its own launch (the default).
-@pytest.fixture(scope="module", params=[(c, m) for c in CASES for m in ("wg", "launch")],
-                ids=lambda cm: f"{cm[0]}-{cm[1]}")
+@pytest.fixture(scope="module", params=list(CASES))
 def pair(request):
-    import os
-    name, mode = request.param
-    kw = dict(CASES[name])
-    p = make_problem(**kw)
-    print(f"\n[case {name} {mode}] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
+    name = request.param
+    p = make_problem(**CASES[name])
+    print(f"\n[case {name}] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
     ho = _oracle_cached(name, p)
-    old = os.environ.get("EAMG_WG_BYTES")
-    os.environ["EAMG_WG_BYTES"] = "1e12" if mode == "wg" else "0"
-    try:
-        hl = _lib(p)
-    finally:
-        if old is None:
-            del os.environ["EAMG_WG_BYTES"]
-        else:
-            os.environ["EAMG_WG_BYTES"] = old
-    yield f"{name}-{mode}", p, ho, hl
+    hl = _lib(p)
+    yield name, p, ho, hl
     hl.close()
 
 
@@ -271,3 +258,30 @@ def test_full_size_cube64_properties():
         assert np.abs(A1 @ e - ref_col).max() <= 1e-11 * np.abs(ref_col).max()
     assert abs(A1 - A1.T).max() <= 1e-12 * abs(A1).max()
     hl.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """The captured PCG iteration replays the same kernels in the same order as the eager path:
+    every replay of the graph must reproduce the eager iterate bit for bit."""
+    import os
+    p = make_problem(13, seed=6)
+    b = _dev(p.b)
+    old = os.environ.get("EAMG_GRAPH")
+    os.environ["EAMG_GRAPH"] = "0"
+    try:
+        he = _lib(p)
+        xe, ie = he.solve(b)
+        xe_k = [he.solve(b, rtol=0.0, max_it=k)[0].clone() for k in (2, 5)]
+    finally:
+        if old is None:
+            del os.environ["EAMG_GRAPH"]
+        else:
+            os.environ["EAMG_GRAPH"] = old
+    hg = _lib(p)
+    for _ in range(3):
+        xg, ig = hg.solve(b)
+        assert ig["iterations"] == ie["iterations"] and torch.equal(xg, xe)
+    for k, ref in zip((2, 5), xe_k):
+        assert torch.equal(hg.solve(b, rtol=0.0, max_it=k)[0], ref)
+    he.close()
+    hg.close()
