@@ -3,7 +3,10 @@
 #include "coarsen.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <deque>
 #include <limits>
 #include <unordered_map>
@@ -13,6 +16,19 @@ namespace eamg {
 namespace {
 
 const double kInf = std::numeric_limits<double>::infinity();
+
+// Phase timing on stderr when EAMG_VERBOSE is set.
+struct PhaseTimer {
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  PhaseTimer() : on(std::getenv("EAMG_VERBOSE") != nullptr), t0(std::chrono::steady_clock::now()) {}
+  void mark(const char *what) {
+    if (!on) return;
+    const auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[eamg] %-28s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  }
+};
 
 // ---- small square matrices --------------------------------------------------------------
 
@@ -372,7 +388,7 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
                     const std::vector<char> &dmask, const std::vector<double> &cc) {
   const int k = lev.k, kk = k * k;
   const int nc = int(aggs.size());
-  std::vector<int> agg_of(size_t(lev.n), -1);
+  std::vector<int> agg_of(static_cast<size_t>(lev.n), -1);
   for (int I = 0; I < nc; ++I)
     for (int i : aggs[I]) agg_of[i] = I;
   AuxLevel out;
@@ -380,7 +396,7 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
   out.k = k;
   out.x = cc;
   out.M.assign(size_t(nc) * kk, 0.0);
-  for (int I = 0; I < nc; ++I) {
+  parallel_for(nc, [&](int64_t I) {
     std::vector<int> mem = aggs[I];
     std::sort(mem.begin(), mem.end());
     Sq acc(k);
@@ -392,43 +408,45 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
       sq_axpy(acc, 1.0, sq_t3(Q, W, Q));
     }
     std::copy(acc.a, acc.a + kk, &out.M[size_t(I) * kk]);
-  }
-  std::unordered_map<int64_t, int64_t> slot;
-  slot.reserve(size_t(lev.m()));
-  std::vector<int64_t> keys;
-  std::vector<double> acc;
-  for (int64_t e = 0; e < lev.m(); ++e) {
-    const int i = lev.e0[e], j = lev.e1[e];
-    const int I = agg_of[i], J = agg_of[j];
-    if (I < 0 || J < 0 || I == J) continue;
-    const int a = std::min(I, J), b = std::max(I, J);
-    const Sq T = sq_mul(sq_mul(sq_qhalf(lev.xp(i), lev.xp(j), k),
-                               sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k)),
-                        sq_qhalf(&cc[size_t(3) * J], &cc[size_t(3) * I], k));
-    const Sq C = sq_t3(T, lev.Emat(e), T);
-    const int64_t key = int64_t(a) * nc + b;
-    auto it = slot.find(key);
-    if (it == slot.end()) {
-      slot.emplace(key, int64_t(keys.size()));
-      keys.push_back(key);
-      acc.insert(acc.end(), C.a, C.a + kk);
-    } else {
-      double *d = &acc[size_t(it->second) * kk];
-      for (int q = 0; q < kk; ++q) d[q] += C.a[q];
+  });
+  // coarse edge key of every fine edge (-1: dropped); the fine edges of one key are summed in
+  // ascending fine-edge order (stable sort), so the result does not depend on the threads
+  const int64_t m = lev.m();
+  std::vector<int64_t> key(static_cast<size_t>(m), -1);
+  parallel_for(m, [&](int64_t e) {
+    const int I = agg_of[lev.e0[e]], J = agg_of[lev.e1[e]];
+    if (I < 0 || J < 0 || I == J) return;
+    key[e] = int64_t(std::min(I, J)) * nc + std::max(I, J);
+  });
+  std::vector<int64_t> order;
+  order.reserve(static_cast<size_t>(m));
+  for (int64_t e = 0; e < m; ++e)
+    if (key[e] >= 0) order.push_back(e);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+  std::vector<int64_t> start;
+  for (size_t q = 0; q < order.size(); ++q)
+    if (q == 0 || key[order[q]] != key[order[q - 1]]) start.push_back(int64_t(q));
+  const int64_t ne = int64_t(start.size());
+  start.push_back(int64_t(order.size()));
+  out.e0.resize(static_cast<size_t>(ne));
+  out.e1.resize(static_cast<size_t>(ne));
+  out.E.assign(size_t(ne) * kk, 0.0);
+  parallel_for(ne, [&](int64_t g) {
+    Sq acc(k);
+    for (int64_t q = start[g]; q < start[g + 1]; ++q) {
+      const int64_t e = order[q];
+      const int i = lev.e0[e], j = lev.e1[e];
+      const int I = agg_of[i], J = agg_of[j];
+      const Sq T = sq_mul(sq_mul(sq_qhalf(lev.xp(i), lev.xp(j), k),
+                                 sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k)),
+                          sq_qhalf(&cc[size_t(3) * J], &cc[size_t(3) * I], k));
+      sq_axpy(acc, 1.0, sq_t3(T, lev.Emat(e), T));
     }
-  }
-  std::vector<int64_t> order(keys.size());
-  for (size_t q = 0; q < order.size(); ++q) order[q] = int64_t(q);
-  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return keys[x] < keys[y]; });
-  out.e0.resize(order.size());
-  out.e1.resize(order.size());
-  out.E.resize(order.size() * kk);
-  for (size_t q = 0; q < order.size(); ++q) {
-    const int64_t key = keys[order[q]];
-    out.e0[q] = int(key / nc);
-    out.e1[q] = int(key % nc);
-    std::copy(&acc[size_t(order[q]) * kk], &acc[size_t(order[q]) * kk] + kk, &out.E[q * kk]);
-  }
+    const int64_t kk0 = key[order[start[g]]];
+    out.e0[g] = int(kk0 / nc);
+    out.e1[g] = int(kk0 % nc);
+    std::copy(acc.a, acc.a + kk, &out.E[size_t(g) * kk]);
+  });
   out.build_adjacency();
   return out;
 }
@@ -437,11 +455,11 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
 
 void dhat_all(const AuxLevel &lev, std::vector<Sq> &D) {
   D.assign(size_t(lev.n), Sq(lev.k));
-  for (int i = 0; i < lev.n; ++i) {
-    Sq d = lev.Mmat(i);
-    for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) sq_axpy(d, 1.0, pulled(lev, lev.nb_e[p], i));
+  parallel_for(lev.n, [&](int64_t i) {
+    Sq d = lev.Mmat(int(i));
+    for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) sq_axpy(d, 1.0, pulled(lev, lev.nb_e[p], int(i)));
     D[i] = d;
-  }
+  });
 }
 
 void trace_strength(const AuxLevel &lev, std::vector<double> &m) {
@@ -487,27 +505,33 @@ double mu_b(const AuxLevel &lev, int i, int j, const std::vector<Sq> &D, double 
 }
 
 double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<Sq> &D, double tau) {
+  // Block form of Thm thm:mu1 (delta = 1): every matrix below is assembled from k x k blocks.
   const int k = lev.k;
   std::vector<int> mem = Cin;
   std::sort(mem.begin(), mem.end());
   const int nC = int(mem.size());
   double xH[3];
   mean_pos(lev, mem, xH);
-  Mat PC(nC * k, k), DC(nC * k, nC * k), R(nC * k, nC * k);
+  // L = D_C - D_C P_C pinv(P_C^T D_C P_C) P_C^T D_C with P_C = [Q^{H->i}]
+  std::vector<Sq> Y(static_cast<size_t>(nC));
+  Sq Z(k);
+  for (int a = 0; a < nC; ++a) {
+    const Sq Q = sq_qtrans(xH, lev.xp(mem[a]), k);
+    Y[a] = sq_mul(D[mem[a]], Q);              // D_a Q_a
+    sq_axpy(Z, 1.0, sq_mul(sq_t(Q), Y[a]));  // Q_a^T D_a Q_a
+  }
+  const Sq Zp = sq_pinv(Z, tau);
+  Mat L(nC * k, nC * k), R(nC * k, nC * k);
   auto put = [&](Mat &X, int a, int b, const Sq &S, double s) {
     for (int u = 0; u < k; ++u)
       for (int v = 0; v < k; ++v) X(a * k + u, b * k + v) += s * S(u, v);
   };
   for (int a = 0; a < nC; ++a) {
-    const Sq Q = sq_qtrans(xH, lev.xp(mem[a]), k);
-    for (int u = 0; u < k; ++u)
-      for (int v = 0; v < k; ++v) PC(a * k + u, v) = Q(u, v);
-    put(DC, a, a, D[mem[a]], 1.0);
+    const Sq YZ = sq_mul(Y[a], Zp);
+    for (int b = 0; b < nC; ++b) put(L, a, b, sq_mul(YZ, sq_t(Y[b])), -1.0);
+    put(L, a, a, D[mem[a]], 1.0);
     put(R, a, a, lev.Mmat(mem[a]), 1.0);
   }
-  const Mat DP = matmul(DC, PC);
-  Mat L = DC;
-  axpy_mat(L, -1.0, matmul(matmul(DP, pinv_tau(matmul(transpose(PC), DP), tau)), transpose(DP)));
   // edges inside C (eq. auxa) and the outside neighbours
   std::vector<std::pair<int, std::vector<std::pair<int, int>>>> outside;  // l -> (a, e)
   std::unordered_map<int, size_t> opos;
@@ -539,25 +563,39 @@ double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<
   }
   std::sort(outside.begin(), outside.end(),
             [](const auto &x, const auto &y) { return x.first < y.first; });
+  std::vector<Sq> Kcw, Kcc;
+  std::vector<int> am;
   for (const auto &ol : outside) {
     if (ol.second.size() < 2) continue;
     const int l = ol.first;
-    Mat KCC(nC * k, nC * k), KCw(nC * k, k), Kww(k, k);
+    // local assembly of the edges (i, l), i in C, with unknowns (v_C, w); Schur complement on v_C
+    Kcw.clear();
+    Kcc.clear();
+    am.clear();
+    Sq Kww(k);
     for (const auto &ae : ol.second) {
       const int a = ae.first, e = ae.second, i = mem[a];
       const Sq Qil = sq_qhalf(lev.xp(i), lev.xp(l), k), Qli = sq_qhalf(lev.xp(l), lev.xp(i), k);
       const Sq Ee = lev.Emat(e);
-      put(KCC, a, a, sq_t3(Qil, Ee, Qil), 1.0);
-      const Sq X = sq_t3(Qil, Ee, Qli);
-      for (int u = 0; u < k; ++u)
-        for (int v = 0; v < k; ++v) KCw(a * k + u, v) -= X(u, v);
-      const Sq Y = sq_t3(Qli, Ee, Qli);
-      for (int u = 0; u < k; ++u)
-        for (int v = 0; v < k; ++v) Kww(u, v) += Y(u, v);
+      am.push_back(a);
+      Kcc.push_back(sq_t3(Qil, Ee, Qil));
+      Sq X = sq_t3(Qil, Ee, Qli);
+      for (int q = 0; q < k * k; ++q) X.a[q] = -X.a[q];
+      Kcw.push_back(X);
+      sq_axpy(Kww, 1.0, sq_t3(Qli, Ee, Qli));
     }
-    Mat S = KCC;
-    axpy_mat(S, -1.0, matmul(matmul(KCw, pinv_tau(Kww, tau)), transpose(KCw)));
-    axpy_mat(R, 0.5, sym(S));
+    const Sq Wp = sq_pinv(Kww, tau);
+    for (size_t x = 0; x < am.size(); ++x) {
+      const Sq KW = sq_mul(Kcw[x], Wp);
+      for (size_t y = 0; y < am.size(); ++y) {
+        Sq S = sq_mul(KW, sq_t(Kcw[y]));
+        for (int q = 0; q < k * k; ++q) S.a[q] = -S.a[q];
+        if (x == y) sq_axpy(S, 1.0, Kcc[x]);
+        // 1/2 sym(S_l): add half of the block and half of its mirror
+        put(R, am[x], am[y], S, 0.25);
+        put(R, am[y], am[x], sq_t(S), 0.25);
+      }
+    }
   }
   return genmax(sym(L), sym(R), tau);
 }
@@ -613,22 +651,31 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   const int n = lev.n;
   const double sigma = prm.sigma;
   MatchResult res;
+  PhaseTimer tm;
+  double t_mub = 0.0, t_mug = 0.0;
+  long n_mub = 0, n_mug = 0;
   auto note = [&](double mu) {
     if (std::isfinite(mu)) res.min_margin = std::min(res.min_margin, std::fabs(mu - sigma) / sigma);
   };
   std::vector<Sq> Dhat;
   dhat_all(lev, Dhat);
+  tm.mark("dhat");
   res.dmask.assign(static_cast<size_t>(n), 0);
   for (int i = 0; i < n; ++i) res.dmask[i] = vd.empty() ? 0 : vd[i];
+  std::vector<double> md(static_cast<size_t>(n), 0.0);
+  parallel_for(n, [&](int64_t i) {
+    if (!res.dmask[i]) md[i] = mu_D(lev, int(i), Dhat, prm.tau);
+  });
   for (int i = 0; i < n; ++i) {
     if (res.dmask[i]) continue;
-    const double md = mu_D(lev, i, Dhat, prm.tau);
-    note(md);
-    if (md < sigma) res.dmask[i] = 1;
+    note(md[i]);
+    if (md[i] < sigma) res.dmask[i] = 1;
   }
   std::vector<char> in_T(static_cast<size_t>(n));
   for (int i = 0; i < n; ++i) in_T[i] = !res.dmask[i];
+  tm.mark("mu_D");
   std::vector<int> order = cuthill_mckee(lev, in_T);
+  tm.mark("cuthill-mckee");
 
   AuxLevel work_store;
   const AuxLevel *work = &lev;
@@ -669,13 +716,19 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           }
         res.max_tie = std::max(res.max_tie, ntie);
         const int cj = cands[best].first;
+        const auto tb0 = std::chrono::steady_clock::now();
         const double mu = mu_b(*work, ci, cj, *wdhat, prm.tau);
+        t_mub += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb0).count();
+        ++n_mub;
         note(mu);
         bool ok = mu < sigma;
         if (ok && members[ci].size() + members[cj].size() > 2) {
           std::vector<int> u = members[ci];
           u.insert(u.end(), members[cj].begin(), members[cj].end());
+          const auto tg0 = std::chrono::steady_clock::now();
           const double mg = mu_g(lev, u, Dhat, prm.tau);
+          t_mug += std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
+          ++n_mug;
           note(mg);
           ok = mg < sigma;
         }
@@ -692,6 +745,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         singles.push_back(ci);
       }
     }
+    tm.mark("matching pass");
+    if (tm.on)
+      std::fprintf(stderr, "[eamg]   mu_b %ld calls %.3f s, mu_g %ld calls %.3f s\n", n_mub, t_mub, n_mug, t_mug);
+    t_mub = t_mug = 0.0;
+    n_mub = n_mug = 0;
     std::vector<std::vector<int>> groups;
     for (const auto &pq : pairs) groups.push_back({pq.first, pq.second});
     for (int s : singles) groups.push_back({s});
@@ -710,6 +768,7 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       work = &work_store;
       dhat_all(*work, wdhat_store);
       wdhat = &wdhat_store;
+      tm.mark("intermediate weights");
       members = entries;
       in_T.assign(entries.size(), 1);
       order.resize(entries.size());
@@ -721,6 +780,7 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   res.ccoords.resize(res.aggs.size() * 3);
   for (size_t I = 0; I < res.aggs.size(); ++I) mean_pos(lev, res.aggs[I], &res.ccoords[3 * I]);
   res.coarse = coarse_aux(lev, res.aggs, res.dmask, res.ccoords);
+  tm.mark("coarse weights");
   return res;
 }
 

@@ -10,13 +10,37 @@
 //  * successive_matching: Algorithm alg:pwagg.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dense.hpp"
 
 namespace eamg {
+
+// f(i) for i in [0, n) on up to 16 threads (contiguous chunks); f must not throw and must only
+// write data owned by index i, so the result does not depend on the thread count.
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if (n < 2048 || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    const int64_t lo = int64_t(t) * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&f, lo, hi] {
+      for (int64_t i = lo; i < hi; ++i) f(i);
+    });
+  }
+  for (auto &x : th) x.join();
+}
 
 // Small square matrix, k <= 6, row-major.
 struct Sq {

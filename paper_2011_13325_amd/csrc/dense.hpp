@@ -2,8 +2,8 @@
 // coarsest level factorization).  All FP64.  Matrices are row-major std::vector backed.
 //
 // Symmetric eigenproblems use the cyclic Jacobi method (rotations chosen to annihilate one
-// off-diagonal pair at a time, Golub & Van Loan section 8.5), which is accurate to a few ulps
-// of the matrix norm for the small (<= 6 k) matrices met here.
+// off-diagonal pair at a time, Golub & Van Loan section 8.5) up to 8 x 8 and Householder
+// tridiagonalization + implicit QL above; both are accurate to a few ulps of the matrix norm.
 #pragma once
 
 #include <algorithm>
@@ -77,8 +77,126 @@ inline double trace(const Mat &X) {
   return s;
 }
 
-// Symmetric eigen-decomposition: w ascending, V columns are the eigenvectors.
+// Symmetric eigen-decomposition for larger matrices: Householder reduction to tridiagonal form
+// (accumulating the reflections), then the implicit QL iteration with Wilkinson shifts on the
+// tridiagonal matrix (Golub & Van Loan sections 8.3.1 and 8.3.3).  w ascending, V columns are
+// the eigenvectors.
+inline void eigh_tridiag_ql(const Mat &Ain, std::vector<double> &w, Mat &V, bool vectors = true) {
+  const int n = Ain.r;
+  Mat A = Ain;
+  V = vectors ? Mat::eye(n) : Mat();
+  w.assign(n, 0.0);
+  if (n == 0) return;
+  std::vector<double> v(n), p(n), q(n), e(n, 0.0);
+  for (int k = 0; k + 2 < n; ++k) {
+    double alpha2 = 0.0;
+    for (int i = k + 1; i < n; ++i) alpha2 += A(i, k) * A(i, k);
+    const double x0 = A(k + 1, k);
+    double tail2 = alpha2 - x0 * x0;
+    if (tail2 <= 0.0) continue;  // column already tridiagonal
+    const double alpha = std::sqrt(alpha2);
+    const double sub = x0 >= 0.0 ? -alpha : alpha;  // new subdiagonal entry
+    for (int i = 0; i < n; ++i) v[i] = 0.0;
+    v[k + 1] = x0 - sub;
+    for (int i = k + 2; i < n; ++i) v[i] = A(i, k);
+    double vn2 = 0.0;
+    for (int i = k + 1; i < n; ++i) vn2 += v[i] * v[i];
+    if (vn2 == 0.0) continue;
+    const double beta = 2.0 / vn2;
+    // A <- H A H on the trailing block, H = I - beta v v^T
+    double K = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += A(i, j) * v[j];
+      p[i] = beta * s;
+      K += p[i] * v[i];
+    }
+    K *= 0.5 * beta;
+    for (int i = k + 1; i < n; ++i) q[i] = p[i] - K * v[i];
+    for (int i = k + 1; i < n; ++i)
+      for (int j = k + 1; j < n; ++j) A(i, j) -= v[i] * q[j] + q[i] * v[j];
+    A(k + 1, k) = A(k, k + 1) = sub;
+    for (int i = k + 2; i < n; ++i) A(i, k) = A(k, i) = 0.0;
+    // V <- V H
+    for (int r = 0; vectors && r < n; ++r) {
+      double t = 0.0;
+      for (int j = k + 1; j < n; ++j) t += V(r, j) * v[j];
+      t *= beta;
+      for (int j = k + 1; j < n; ++j) V(r, j) -= t * v[j];
+    }
+  }
+  std::vector<double> d(n);
+  for (int i = 0; i < n; ++i) d[i] = A(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = A(i + 1, i);
+  e[n - 1] = 0.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 100; ++iter) {
+      int m = l;
+      for (; m + 1 < n; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m == l) break;
+      // Wilkinson-type shift from the leading 2x2 block
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      int i = m - 1;
+      bool deflated = false;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // premature deflation
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        for (int k = 0; vectors && k < n; ++k) {
+          f = V(k, i + 1);
+          V(k, i + 1) = s * V(k, i) + c * f;
+          V(k, i) = c * V(k, i) - s * f;
+        }
+      }
+      if (deflated) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+  for (int j = 0; j < n; ++j) w[j] = d[idx[j]];
+  if (!vectors) return;
+  Mat Vs(n, n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) Vs(i, j) = V(i, idx[j]);
+  V = Vs;
+}
+
+// Symmetric eigen-decomposition: w ascending, V columns are the eigenvectors.  Cyclic Jacobi for
+// small matrices, tridiagonal QL above 8 x 8.
+inline void eigh_jacobi(const Mat &Ain, std::vector<double> &w, Mat &V);
 inline void eigh(const Mat &Ain, std::vector<double> &w, Mat &V) {
+  if (Ain.r > 8)
+    eigh_tridiag_ql(Ain, w, V);
+  else
+    eigh_jacobi(Ain, w, V);
+}
+
+inline void eigh_jacobi(const Mat &Ain, std::vector<double> &w, Mat &V) {
   const int n = Ain.r;
   Mat A = Ain;
   V = Mat::eye(n);
@@ -204,7 +322,11 @@ inline double genmax(const Mat &Lin, const Mat &Rin, double tau) {
   }
   std::vector<double> g;
   Mat G;
-  eigh(sym(tmul3(W, L, W)), g, G);
+  const Mat S = sym(tmul3(W, L, W));
+  if (S.r > 8)
+    eigh_tridiag_ql(S, g, G, false);
+  else
+    eigh(S, g, G);
   return g.back();
 }
 
