@@ -7,7 +7,8 @@ multicolour block Gauss-Seidel sweep pre / post; PCG to ||r|| <= 1e-8 ||b||.
 
 A step is one PCG solve to 1e-8 (V-cycle + CG kernels) on the hierarchy, with b resident in
 HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerkin / D^+ /
-coarsest factor) is timed separately and reported in the same line.
+coarsest factor) is timed separately and reported in the same line.  The same solve with the
+FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle".
 
 Prints ONE JSON line.
 """
@@ -58,6 +59,45 @@ def cpu_baseline(n):
                       f"same elasticity problem"}
 
 
+def _timed_solves(E, torch, hier, b, x, stream, steps, warmup, precond):
+    for _ in range(warmup):
+        hier.solve(b, x, precond=precond)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        _, info = hier.solve(b, x, precond=precond)
+        infos.append(info)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    assert infos[-1]["status"] == E.EAMG_OK and infos[-1]["rel_res_true"] <= 1e-8, infos[-1]
+    return ms, infos[-1]
+
+
+def _profiled(E, hier, b, x, steps, precond):
+    """Per-kernel durations with events on the solve stream, over the same number of steps."""
+    E.eamg_profile_enable(hier.h, True)
+    for _ in range(steps):
+        hier.solve(b, x, precond=precond)
+    kstats = E.eamg_profile_read(hier.h)
+    E.eamg_profile_enable(hier.h, False)
+    dom = kstats[0]
+    achieved = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": 8000.0,
+            "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+            "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3,
+            "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"]}
+    kern = [{"name": k["name"], "launches_per_step": k["launches"] / steps,
+             "ms_per_step": k["total_ms"] / steps,
+             "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9 if k["total_ms"] else None}
+            for k in kstats[:12]]
+    return roof, kern
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -73,38 +113,25 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hier = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, stream=stream)
+    # FP32 copies of the V-cycle matrices are kept too, so that the same hierarchy serves the
+    # FP64 solve (the headline) and the mixed-precision comparison
+    prm = E.eamg_default_setup_params(vcycle_fp32=1)
+    hier = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, prm,
+                       stream=stream)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     st = hier.stats()
     b = torch.tensor(p.b, device=dev)
     x = torch.zeros_like(b)
-    for _ in range(args.warmup):
-        hier.solve(b, x)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    infos = []
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        _, info = hier.solve(b, x)
-        infos.append(info)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    ms = total_ms / args.steps
-    # per-kernel durations with events on the solve stream, over the same number of steps
-    E.eamg_profile_enable(hier.h, True)
-    for _ in range(args.steps):
-        hier.solve(b, x)
-    kstats = E.eamg_profile_read(hier.h)
-    E.eamg_profile_enable(hier.h, False)
-    dom = kstats[0]
-    achieved = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
-    its = infos[-1]["iterations"]
-    assert infos[-1]["status"] == E.EAMG_OK and infos[-1]["rel_res_true"] <= 1e-8, infos[-1]
-    vbytes, itbytes = E.eamg_traffic_model(hier.h)
+    ms, info = _timed_solves(E, torch, hier, b, x, stream, args.steps, args.warmup,
+                             E.EAMG_PRECOND_VCYCLE)
+    roof, kern = _profiled(E, hier, b, x, args.steps, E.EAMG_PRECOND_VCYCLE)
+    ms32, info32 = _timed_solves(E, torch, hier, b, x, stream, args.steps, args.warmup,
+                                 E.EAMG_PRECOND_VCYCLE_FP32)
+    roof32, kern32 = _profiled(E, hier, b, x, args.steps, E.EAMG_PRECOND_VCYCLE_FP32)
+    its = info["iterations"]
+    vbytes, itbytes = E.eamg_traffic_model(hier.h, E.EAMG_PRECOND_VCYCLE)
+    vbytes32, itbytes32 = E.eamg_traffic_model(hier.h, E.EAMG_PRECOND_VCYCLE_FP32)
     value = p.n_free_dofs / (ms / 1e3)
     out = {
         "metric": "AMG-PCG time to 1e-8 and dofs/s, FP64 vs mixed/batched; V-cycle HBM GB/s",
@@ -114,20 +141,21 @@ def main():
         "config": {"workload": f"elasticity cube {args.n}^3 vertices (Kuhn P1, E=1, nu=0.3, "
                                f"clamped x=0, RHS seed 1), FP64 AMG-PCG to 1e-8",
                    "dofs": p.n_dofs, "free_dofs": p.n_free_dofs, "iterations": its,
-                   "rel_res_true": infos[-1]["rel_res_true"], "levels": st["n_levels"],
+                   "rel_res_true": info["rel_res_true"], "levels": st["n_levels"],
                    "level_vertices": st["n"], "vc": round(st["vc"], 4), "oc": round(st["oc"], 4),
                    "setup_s": round(setup_s, 3),
                    "model_bytes_per_iteration": itbytes,
                    "model_GBps_whole_solve": itbytes * its / (ms / 1e3) / 1e9},
     }
-    out["roofline"] = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": 8000.0,
-                       "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
-                       "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3,
-                       "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"]}
-    out["kernels"] = [{"name": k["name"], "launches_per_step": k["launches"] / args.steps,
-                       "ms_per_step": k["total_ms"] / args.steps,
-                       "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9 if k["total_ms"] else None}
-                      for k in kstats[:12]]
+    out["roofline"] = roof
+    out["kernels"] = kern
+    out["mixed_fp32_vcycle"] = {
+        "value": p.n_free_dofs / (ms32 / 1e3), "unit": "dofs/s", "ms_per_step": ms32,
+        "speedup_vs_fp64": ms / ms32, "iterations": info32["iterations"],
+        "rel_res_true": info32["rel_res_true"], "dtype": "f32 V-cycle in f64 CG",
+        "model_bytes_per_iteration": itbytes32,
+        "model_GBps_whole_solve": itbytes32 * info32["iterations"] / (ms32 / 1e3) / 1e9,
+        "roofline": roof32, "kernels": kern32[:8]}
     levels = []
     for l in range(st["n_levels"]):
         li = E.eamg_level_info_get(hier.h, l)

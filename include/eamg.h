@@ -92,6 +92,9 @@ typedef struct {
  *  cap_std_l0, cap_std columns per real-matrix row of P_s, finest / coarser (defaults 8, 6; 1..16)
  *  pinv_rtol          relative eigenvalue threshold of pseudo-inverses (default 1e-10)
  *  tie_rtol           relative band in which mu_s values tie (default 1e-12)
+ *  vcycle_fp32        0: FP64 V-cycle only (default).  1: also keep FP32 copies of the V-cycle
+ *                     matrices (A_l, P_s, R, D^+) and FP32 level vectors, so that solves and
+ *                     V-cycles may ask for EAMG_PRECOND_VCYCLE_FP32 (about +50% V-cycle memory).
  */
 typedef struct {
   double sigma;
@@ -99,11 +102,23 @@ typedef struct {
   double omega;
   int32_t cap_aux, cap_std_l0, cap_std;
   double pinv_rtol, tie_rtol;
+  int32_t vcycle_fp32;
 } eamg_setup_params;
 
+/* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,
+ * residual, transfers, their matrices, D^+ and level vectors) in FP32 with FP32 accumulation,
+ * except the coarsest level's inverse (FP64 matrix, FP64 accumulation, FP32 vectors); the CG
+ * operator, vectors, inner products and the stopping test stay FP64, with one conversion of r
+ * to FP32 and of z to FP64 per iteration.  It needs a setup with vcycle_fp32 = 1. */
+enum {
+  EAMG_PRECOND_NONE = 0,
+  EAMG_PRECOND_VCYCLE = 1,      /* one FP64 V-cycle (default) */
+  EAMG_PRECOND_VCYCLE_FP32 = 2  /* one FP32 V-cycle           */
+};
+
 /* Solve parameters.  rtol: stop when ||r||_2 <= rtol ||b||_2 (recursive residual, x0 = 0 unless
- * use_x0); max_it: iteration limit (>= 1); use_x0: 1 = start from the given x; precond: 0 none,
- * 1 one V-cycle. */
+ * use_x0); max_it: iteration limit (>= 1); use_x0: 1 = start from the given x; precond: one of
+ * EAMG_PRECOND_* (INVALID_ARG for FP32 without vcycle_fp32 at setup). */
 typedef struct {
   double rtol;
   int32_t max_it;
@@ -155,9 +170,11 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
 
 /*
  * Apply one V-cycle z = B^{-1} r (DEVICE arrays, n*dim doubles, level-0 natural order).
- * Dirichlet dofs of r are treated as 0.
+ * Dirichlet dofs of r are treated as 0.  precision: EAMG_PRECOND_VCYCLE (FP64) or
+ * EAMG_PRECOND_VCYCLE_FP32 (needs vcycle_fp32 = 1 at setup); anything else is INVALID_ARG.
  */
-eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, void *stream);
+eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, int32_t precision,
+                        void *stream);
 
 /* Hierarchy statistics (HOST outputs, any may be NULL).  per_level_n / per_level_nnzb must hold
  * max_levels entries.  vc = sum n_l / n_0, oc = sum nnz_l / nnz_0 counting scalar entries. */
@@ -180,8 +197,9 @@ eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *a
                               int32_t *A_rowptr, int32_t *A_col, double *A_val, int32_t *color);
 
 /* Bytes of one V-cycle's algorithmic HBM traffic and of one PCG iteration (matrix and vector
- * streams counted once per kernel), from the real per-level sizes. */
-eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes,
+ * streams counted once per kernel), from the real per-level sizes, for the V-cycle precision
+ * EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32. */
+eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, double *vcycle_bytes,
                                double *iteration_bytes);
 
 /*

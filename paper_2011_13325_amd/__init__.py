@@ -25,6 +25,10 @@ EAMG_ERR_BREAKDOWN = -4
 EAMG_ERR_HIP = -5
 EAMG_ERR_OOM = -6
 
+EAMG_PRECOND_NONE = 0
+EAMG_PRECOND_VCYCLE = 1
+EAMG_PRECOND_VCYCLE_FP32 = 2
+
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED_KERNEL",
                 -3: "NOT_SPD", -4: "BREAKDOWN", -5: "HIP", -6: "OOM"}
 
@@ -50,7 +54,7 @@ class eamg_setup_params(ctypes.Structure):
                 ("max_levels", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("cap_aux", ctypes.c_int32), ("cap_std_l0", ctypes.c_int32),
                 ("cap_std", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
-                ("tie_rtol", ctypes.c_double)]
+                ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):
@@ -96,7 +100,7 @@ def lib():
     L.eamg_setup.restype = ctypes.c_int
     L.eamg_solve.argtypes = [vp, vp, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve.restype = ctypes.c_int
-    L.eamg_vcycle.argtypes = [vp, vp, vp, vp]
+    L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.eamg_vcycle.restype = ctypes.c_int
     L.eamg_stats.argtypes = [vp, P(i32), vp, vp, P(dp), P(dp)]
     L.eamg_stats.restype = ctypes.c_int
@@ -104,7 +108,7 @@ def lib():
     L.eamg_level_info_get.restype = ctypes.c_int
     L.eamg_export_level.argtypes = [vp, i32] + [vp] * 8
     L.eamg_export_level.restype = ctypes.c_int
-    L.eamg_traffic_model.argtypes = [vp, P(dp), P(dp)]
+    L.eamg_traffic_model.argtypes = [vp, i32, P(dp), P(dp)]
     L.eamg_traffic_model.restype = ctypes.c_int
     L.eamg_destroy.argtypes = [vp]
     L.eamg_destroy.restype = None
@@ -208,8 +212,8 @@ def eamg_solve(h, b, x, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stre
                     rel_res_true=info.rel_res_true, ms=info.ms)
 
 
-def eamg_vcycle(h, r, z, stream=None):
-    st = lib().eamg_vcycle(h, _dptr(r), _dptr(z), _stream(stream))
+def eamg_vcycle(h, r, z, precision=EAMG_PRECOND_VCYCLE, stream=None):
+    st = lib().eamg_vcycle(h, _dptr(r), _dptr(z), int(precision), _stream(stream))
     if st != EAMG_OK:
         raise EamgError(st, "eamg_vcycle")
 
@@ -255,9 +259,9 @@ def eamg_export_level(h, level):
     return out
 
 
-def eamg_traffic_model(h):
+def eamg_traffic_model(h, precision=EAMG_PRECOND_VCYCLE):
     v, it = ctypes.c_double(), ctypes.c_double()
-    st = lib().eamg_traffic_model(h, ctypes.byref(v), ctypes.byref(it))
+    st = lib().eamg_traffic_model(h, int(precision), ctypes.byref(v), ctypes.byref(it))
     if st != EAMG_OK:
         raise EamgError(st, "eamg_traffic_model")
     return v.value, it.value

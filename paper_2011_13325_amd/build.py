@@ -2,6 +2,7 @@
 
 Usage: python -m paper_2011_13325_amd.build   (or call build())
 """
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -33,18 +34,18 @@ def build(verbose=False):
     hipcc = _hipcc()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        _run(cmd, verbose)
-        objs.append(obj)
+        jobs.append(([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
         # host sources include the HIP runtime header: compile with hipcc in host-only mode
-        cmd = [hipcc, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        _run(cmd, verbose)
-        objs.append(obj)
+        jobs.append(([hipcc, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)

@@ -112,7 +112,38 @@ struct Level {
   // algorithmic bytes of every launch (for the traffic model and the profiler)
   std::vector<double> bytes_fwd, bytes_bwd;   // per colour
   double bytes_resid = 0, bytes_R = 0, bytes_P = 0, bytes_spmv = 0;
+  // FP32 V-cycle: values in SoaMat::val32, D^+ and level vectors in float
+  float *Dinv32 = nullptr, *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+  std::vector<double> bytes_fwd32, bytes_bwd32;
+  double bytes_resid32 = 0, bytes_R32 = 0, bytes_P32 = 0;
 };
+
+// Per-precision view of a level's V-cycle buffers.
+template <class T>
+struct LevelBufs {
+  const T *Dinv;
+  T *x, *b, *r;
+};
+template <class T>
+LevelBufs<T> bufs(Level &L);
+template <>
+LevelBufs<double> bufs<double>(Level &L) {
+  return {L.Dinv, L.x, L.b, L.r};
+}
+template <>
+LevelBufs<float> bufs<float>(Level &L) {
+  return {L.Dinv32, L.x32, L.b32, L.r32};
+}
+template <class T>
+const char *type_name();
+template <>
+const char *type_name<double>() {
+  return "double";
+}
+template <>
+const char *type_name<float>() {
+  return "float";
+}
 
 struct ProfRec {
   std::string name;
@@ -142,10 +173,12 @@ struct eamg_hierarchy {
   std::vector<eamg::ProfRec> prof;
   // PCG iteration captured as a graph (V-cycle .. r.r and the scalar copy), replayed per iteration
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t g_iter = nullptr;
-  bool graph_tried = false;
+  // one graph per V-cycle precision: [0] FP64, [1] FP32
+  hipGraphExec_t g_iter[2] = {nullptr, nullptr};
+  bool graph_tried[2] = {false, false};
   ~eamg_hierarchy() {
-    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    for (hipGraphExec_t g : g_iter)
+      if (g) (void)hipGraphExecDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (scal_h) (void)hipHostFree(scal_h);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -169,6 +202,7 @@ eamg_setup_params defaults() {
   p.cap_std = 6;
   p.pinv_rtol = 1e-10;
   p.tie_rtol = 1e-12;
+  p.vcycle_fp32 = 0;
   return p;
 }
 
@@ -186,6 +220,7 @@ void validate_params(const eamg_setup_params &p) {
     fail(EAMG_ERR_INVALID_ARG, "row caps must be in 1..16");
   if (!(p.pinv_rtol > 0.0 && p.pinv_rtol <= 1e-2)) fail(EAMG_ERR_INVALID_ARG, "pinv_rtol must be in (0, 1e-2]");
   if (!(p.tie_rtol >= 0.0 && p.tie_rtol <= 1e-6)) fail(EAMG_ERR_INVALID_ARG, "tie_rtol must be in [0, 1e-6]");
+  if (p.vcycle_fp32 != 0 && p.vcycle_fp32 != 1) fail(EAMG_ERR_INVALID_ARG, "vcycle_fp32 must be 0 or 1");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -303,7 +338,7 @@ std::vector<int> to_i32(const std::vector<int64_t> &v) {
 // Build one solve-phase SoA matrix from natural AoS values with a host permutation map.
 SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br, int bc,
                 const double *aos, hipStream_t s, std::vector<int> *diag_out = nullptr,
-                bool transpose_blocks = false) {
+                bool transpose_blocks = false, bool fp32 = false) {
   SoaMat M;
   M.n_rows = Pp.n_rows;
   M.n_cols = Pp.n_cols;
@@ -315,6 +350,7 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
   M.col = ar.upload(Pp.col, s);
   int64_t *src_d = ar.upload(src, s);
   double *v = ar.alloc<double>(size_t(M.nnz) * br * bc);
+  float *v32 = fp32 ? ar.alloc<float>(size_t(M.nnz) * br * bc) : nullptr;
   if (transpose_blocks) {
     // input blocks are bc x br; transpose into a temporary AoS array, then to planes
     double *tmp = ar.alloc<double>(size_t(M.nnz) * br * bc);
@@ -323,15 +359,18 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
     for (int64_t q = 0; q < M.nnz; ++q) iota[q] = q;
     int64_t *id = ar.upload(iota, s);
     hip_check(launch_gather_soa(M.nnz, br * bc, id, tmp, v, s), "gather_soa");
+    if (fp32) hip_check(launch_gather_soa_f32(M.nnz, br * bc, id, tmp, v32, s), "gather_soa_f32");
     hip_check(hipStreamSynchronize(s), "sync");
     ar.release(tmp);
     ar.release(id);
   } else {
     hip_check(launch_gather_soa(M.nnz, br * bc, src_d, aos, v, s), "gather_soa");
+    if (fp32) hip_check(launch_gather_soa_f32(M.nnz, br * bc, src_d, aos, v32, s), "gather_soa_f32");
     hip_check(hipStreamSynchronize(s), "sync");
   }
   ar.release(src_d);
   M.val = v;
+  M.val32 = v32;
   if (diag_out) {
     std::vector<int> dg(size_t(M.n_rows), -1);
     for (int i = 0; i < M.n_rows; ++i)
@@ -383,7 +422,7 @@ std::string tname(const char *base, int a, int b) {
 // Bytes of a row range [r0, r1) of a colour-major square level: blocks [lo(row), hi(row)) read,
 // plus `per_row` bytes per row and every distinct column of those blocks gathered once.
 double range_bytes(const Pattern &Ap, const std::vector<int> &dg, int bs, int r0, int r1, int part,
-                   double per_row, std::vector<int> &mark, int stamp) {
+                   double per_row, std::vector<int> &mark, int stamp, double vs = 8.0) {
   double blocks = 0.0, uniq = 0.0;
   for (int i = r0; i < r1; ++i) {
     const int64_t lo = part == 2 ? dg[i] + 1 : Ap.rp[i];
@@ -395,10 +434,10 @@ double range_bytes(const Pattern &Ap, const std::vector<int> &dg, int bs, int r0
         uniq += 1.0;
       }
   }
-  return blocks * (bs * bs * 8.0 + 4.0) + double(r1 - r0) * per_row + uniq * bs * 8.0;
+  return blocks * (bs * bs * vs + 4.0) + double(r1 - r0) * per_row + uniq * bs * vs;
 }
 
-double rect_bytes(const Pattern &M, int br, int bc, bool accumulate) {
+double rect_bytes(const Pattern &M, int br, int bc, bool accumulate, double vs = 8.0) {
   std::vector<char> seen(size_t(M.n_cols), 0);
   double uniq = 0.0;
   for (int c : M.col)
@@ -406,8 +445,8 @@ double rect_bytes(const Pattern &M, int br, int bc, bool accumulate) {
       seen[c] = 1;
       uniq += 1.0;
     }
-  return double(M.nnz()) * (br * bc * 8.0 + 4.0) + 4.0 * (M.n_rows + 1) + uniq * bc * 8.0 +
-         double(M.n_rows) * br * 8.0 * (accumulate ? 2.0 : 1.0);
+  return double(M.nnz()) * (br * bc * vs + 4.0) + 4.0 * (M.n_rows + 1) + uniq * bc * vs +
+         double(M.n_rows) * br * vs * (accumulate ? 2.0 : 1.0);
 }
 
 void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
@@ -436,7 +475,8 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   std::vector<int64_t> src;
   const Pattern Ap = permute_pattern(L.A, L.perm, L.inv, src);
   std::vector<int> dg;
-  L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg);
+  const bool f32 = h->prm.vcycle_fp32 != 0;
+  L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
   {
@@ -460,12 +500,22 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
       L.bytes_fwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 0, rowb + 3.0 * bs * 8.0, mark, stamp++));
       // backward: whole rows; b read, x written
       L.bytes_bwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb + 2.0 * bs * 8.0, mark, stamp++));
+      if (f32) {
+        const double rowb32 = 8.0 + bs * bs * 4.0;
+        L.bytes_fwd32.push_back(range_bytes(Ap, dg, bs, r0, r1, 0, rowb32 + 3.0 * bs * 4.0, mark, stamp++, 4.0));
+        L.bytes_bwd32.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb32 + 2.0 * bs * 4.0, mark, stamp++, 4.0));
+      }
     }
     L.bytes_resid = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 8.0, mark, stamp++);
+    if (f32) L.bytes_resid32 = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 4.0, mark, stamp++, 4.0);
   }
   if (coarsest) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
     L.x = ar.alloc<double>(size_t(L.n) * bs);
+    if (f32) {
+      L.b32 = ar.alloc<float>(size_t(L.n) * bs);
+      L.x32 = ar.alloc<float>(size_t(L.n) * bs);
+    }
     return;
   }
   // smoother diagonals (natural), then rows gathered into colour-major order
@@ -473,24 +523,35 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   hip_check(launch_diag_pinv(L.n, bs, L.A_rp, L.A_col, L.A_val, Dn, h->prm.pinv_rtol, s), "diag_pinv");
   L.Dinv = ar.alloc<double>(size_t(L.n) * bs * bs);
   hip_check(launch_gather_rows(L.n, bs * bs, L.perm_d, Dn, L.Dinv, s), "gather_rows");
+  if (f32) {
+    L.Dinv32 = ar.alloc<float>(size_t(L.n) * bs * bs);
+    hip_check(launch_convert(int64_t(L.n) * bs * bs, L.Dinv, L.Dinv32, s), "convert");
+  }
   hip_check(hipStreamSynchronize(s), "sync");
   ar.release(Dn);
   // transfers: fine rows colour-major, coarse columns in the coarse level's colour-major order
   const Level &C = h->lv[l + 1];
   std::vector<int64_t> srcP;
   const Pattern Pp = permute_rect(L.P, L.perm, C.inv, srcP);
-  L.Pm = make_soa(ar, Pp, srcP, bs, L.kc, L.P_val, s);
+  L.Pm = make_soa(ar, Pp, srcP, bs, L.kc, L.P_val, s, nullptr, false, f32);
   std::vector<int64_t> srcT;
   const Pattern Rp = transpose_pattern(Pp, srcT);
   std::vector<int64_t> srcR(srcT.size());
   for (size_t q = 0; q < srcT.size(); ++q) srcR[q] = srcP[size_t(srcT[q])];
-  L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true);
+  L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true, f32);
   L.bytes_R = rect_bytes(Rp, L.kc, bs, false);
   L.bytes_P = rect_bytes(Pp, bs, L.kc, true);
   L.r = ar.alloc<double>(size_t(L.n) * bs);
   if (l > 0) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
     L.x = ar.alloc<double>(size_t(L.n) * bs);
+  }
+  if (f32) {
+    L.bytes_R32 = rect_bytes(Rp, L.kc, bs, false, 4.0);
+    L.bytes_P32 = rect_bytes(Pp, bs, L.kc, true, 4.0);
+    L.r32 = ar.alloc<float>(size_t(L.n) * bs);
+    L.b32 = ar.alloc<float>(size_t(L.n) * bs);
+    L.x32 = ar.alloc<float>(size_t(L.n) * bs);
   }
 }
 
@@ -543,53 +604,75 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
   hip_check(hipStreamSynchronize(s), "sync");
 }
 
-void vcycle(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t s) {
+template <class T>
+void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   Level &L = h->lv[l];
+  const bool f32 = sizeof(T) == 4;
+  const std::string ty = type_name<T>();
   if (l + 1 == h->lv.size()) {
-    const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * 8.0;
-    timed(h, "coarsest", "k_dense_gemv", by, s, [&] { return launch_dense_gemv(h->nL, h->Ainv, b, x, s); });
+    const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * double(sizeof(T));
+    timed(h, "coarsest", "k_dense_gemv<" + ty + ">", by, s,
+          [&] { return launch_dense_gemv<T>(h->nL, h->Ainv, b, x, s); });
     return;
   }
+  const LevelBufs<T> B = bufs<T>(L);
   const int bs = L.bs;
   double fwd_bytes = 0.0, bwd_bytes = 0.0;
   for (int c = 0; c < L.ncolors; ++c) {
-    fwd_bytes += L.bytes_fwd[c];
-    bwd_bytes += L.bytes_bwd[c];
+    fwd_bytes += f32 ? L.bytes_fwd32[c] : L.bytes_fwd[c];
+    bwd_bytes += f32 ? L.bytes_bwd32[c] : L.bytes_bwd[c];
   }
+  const std::string gs = "k_gs_color<" + ty + ", " + std::to_string(bs);
   // the colours of a sweep are back-to-back launches of one kernel: timed as one run
-  timed_n(h, "gs_fwd", tname("k_gs_color", bs, 1), fwd_bytes, L.ncolors, s, [&] {
+  timed_n(h, "gs_fwd", gs + ", true>", fwd_bytes, L.ncolors, s, [&] {
     for (int c = 0; c < L.ncolors; ++c) {
-      const hipError_t e = launch_gs_fwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s);
+      const hipError_t e = launch_gs_fwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
-  timed(h, "resid_upper", tname("k_resid_upper", bs), L.bytes_resid, s,
-        [&] { return launch_resid_upper(L.Am, x, L.r, s); });
+  timed(h, "resid_upper", "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">",
+        f32 ? L.bytes_resid32 : L.bytes_resid, s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
   Level &C = h->lv[l + 1];
-  timed(h, "restrict", tname("k_rect", L.kc, bs), L.bytes_R, s,
-        [&] { return launch_rect(L.Rm, L.r, C.b, false, s); });
-  vcycle(h, l + 1, C.b, C.x, s);
-  timed(h, "prolong", tname("k_rect", bs, L.kc), L.bytes_P, s,
-        [&] { return launch_rect(L.Pm, C.x, x, true, s); });
-  timed_n(h, "gs_bwd", tname("k_gs_color", bs, 0), bwd_bytes, L.ncolors, s, [&] {
+  const LevelBufs<T> CB = bufs<T>(C);
+  timed(h, "restrict", "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">",
+        f32 ? L.bytes_R32 : L.bytes_R, s, [&] { return launch_rect<T>(L.Rm, B.r, CB.b, false, s); });
+  vcycle_t<T>(h, l + 1, CB.b, CB.x, s);
+  timed(h, "prolong", "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">",
+        f32 ? L.bytes_P32 : L.bytes_P, s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
+  timed_n(h, "gs_bwd", gs + ", false>", bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
-      const hipError_t e = launch_gs_bwd(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+      const hipError_t e = launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
 }
 
+// z = V(r) on colour-major level-0 vectors: FP64, or FP32 with conversions at the boundary.
+void vcycle(eamg_hierarchy *h, const double *r, double *z, bool f32, hipStream_t s) {
+  if (f32) {
+    Level &L0 = h->lv[0];
+    const int64_t N = int64_t(L0.n) * L0.bs;
+    timed(h, "convert", "k_convert<double, float>", 12.0 * N, s,
+          [&] { return launch_convert<double, float>(N, r, L0.b32, s); });
+    vcycle_t<float>(h, 0, L0.b32, L0.x32, s);
+    timed(h, "convert", "k_convert<float, double>", 12.0 * N, s,
+          [&] { return launch_convert<float, double>(N, L0.x32, z, s); });
+  } else {
+    vcycle_t<double>(h, 0, r, z, s);
+  }
+}
+
 // One PCG iteration after the stopping test: z = V(r), beta, p = z + beta p, q = A p, alpha,
 // x += alpha p, r -= alpha q, r.r, and the scalars copied to pinned host memory.
-void enqueue_iteration(eamg_hierarchy *h, hipStream_t s) {
+void enqueue_iteration(eamg_hierarchy *h, bool f32, hipStream_t s) {
   const Level &L0 = h->lv[0];
   const SoaMat &A = L0.Am;
   const int64_t N = int64_t(L0.n) * L0.bs;
   const int nd = dot_blocks(N);
   const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
-  vcycle(h, 0, h->r, h->z, s);
+  vcycle(h, h->r, h->z, f32, s);
   hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
   hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
   hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
@@ -602,11 +685,11 @@ void enqueue_iteration(eamg_hierarchy *h, hipStream_t s) {
 }
 
 // Capture enqueue_iteration once; on any failure fall back to eager launches.
-void try_build_graph(eamg_hierarchy *h) {
-  h->graph_tried = true;
+void try_build_graph(eamg_hierarchy *h, bool f32) {
+  h->graph_tried[f32] = true;
   if (const char *e = std::getenv("EAMG_GRAPH"))
     if (std::atoi(e) == 0) return;
-  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     h->cap_stream = nullptr;
     return;
   }
@@ -614,7 +697,7 @@ void try_build_graph(eamg_hierarchy *h) {
   if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return;
   bool ok = true;
   try {
-    enqueue_iteration(h, h->cap_stream);
+    enqueue_iteration(h, f32, h->cap_stream);
   } catch (const Failure &) {
     ok = false;
   }
@@ -624,7 +707,7 @@ void try_build_graph(eamg_hierarchy *h) {
     return;
   }
   hipGraphExec_t ex = nullptr;
-  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) h->g_iter = ex;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) h->g_iter[f32] = ex;
   (void)hipGraphDestroy(g);
   (void)hipGetLastError();
 }
@@ -672,7 +755,7 @@ void eamg_default_solve_params(eamg_solve_params *out) {
   out->rtol = 1e-8;
   out->max_it = 1000;
   out->use_x0 = 0;
-  out->precond = 1;
+  out->precond = EAMG_PRECOND_VCYCLE;
 }
 
 const char *eamg_last_error(void) { return g_last_error.c_str(); }
@@ -835,13 +918,18 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
   });
 }
 
-eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, void *stream) {
+eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, int32_t precision,
+                        void *stream) {
   return guarded([&] {
     if (!h || !r_dev || !z_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    if (precision != EAMG_PRECOND_VCYCLE && precision != EAMG_PRECOND_VCYCLE_FP32)
+      fail(EAMG_ERR_INVALID_ARG, "precision must be EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32");
+    if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
+      fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Level &L0 = h->lv[0];
     hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, r_dev, h->bp, s), "perm_in");
-    vcycle(h, 0, h->bp, h->z, s);
+    vcycle(h, h->bp, h->z, precision == EAMG_PRECOND_VCYCLE_FP32, s);
     hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, h->z, z_dev, s), "perm_out");
     hip_check(hipStreamSynchronize(s), "sync");
   });
@@ -860,6 +948,11 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
     if (params) sp = *params;
     if (sp.max_it < 1) fail(EAMG_ERR_INVALID_ARG, "max_it must be >= 1");
     if (!(sp.rtol >= 0.0)) fail(EAMG_ERR_INVALID_ARG, "rtol must be >= 0");
+    if (sp.precond < EAMG_PRECOND_NONE || sp.precond > EAMG_PRECOND_VCYCLE_FP32)
+      fail(EAMG_ERR_INVALID_ARG, "precond must be 0, 1 or 2");
+    if (sp.precond == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
+      fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
+    const bool f32 = sp.precond == EAMG_PRECOND_VCYCLE_FP32;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Level &L0 = h->lv[0];
     const int64_t N = int64_t(L0.n) * L0.bs;
@@ -893,7 +986,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
     }
     auto precondition = [&]() {
       if (sp.precond)
-        vcycle(h, 0, h->r, h->z, s);
+        vcycle(h, h->r, h->z, f32, s);
       else
         hip_check(launch_copy(N, h->r, h->z, s), "copy");
     };
@@ -931,7 +1024,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
             [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
       fetch_scalars(h, s);
       const bool graphs = sp.precond && !h->prof_on;
-      if (graphs && !h->graph_tried) try_build_graph(h);
+      if (graphs && !h->graph_tried[f32]) try_build_graph(h, f32);
       while (!converged) {
         ++iters;
         if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
@@ -943,8 +1036,8 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
           break;
         }
         if (iters >= sp.max_it) break;
-        if (graphs && h->g_iter) {
-          hip_check(hipGraphLaunch(h->g_iter, s), "graph launch");
+        if (graphs && h->g_iter[f32]) {
+          hip_check(hipGraphLaunch(h->g_iter[f32], s), "graph launch");
           hip_check(hipStreamSynchronize(s), "sync");
         } else {
           precondition();
@@ -1061,19 +1154,26 @@ eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *a
   });
 }
 
-eamg_status eamg_traffic_model(const eamg_hierarchy *h, double *vcycle_bytes, double *iteration_bytes) {
+eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, double *vcycle_bytes,
+                               double *iteration_bytes) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
-    double v = 0.0;
+    if (precision != EAMG_PRECOND_VCYCLE && precision != EAMG_PRECOND_VCYCLE_FP32)
+      fail(EAMG_ERR_INVALID_ARG, "precision must be EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32");
+    if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
+      fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
+    const bool f32 = precision == EAMG_PRECOND_VCYCLE_FP32;
+    // FP32: the two level-0 conversions (read 8 + write 4, read 4 + write 8 bytes per dof)
+    double v = f32 ? 24.0 * double(h->lv[0].n) * h->lv[0].bs : 0.0;
     for (size_t l = 0; l < h->lv.size(); ++l) {
       const Level &L = h->lv[l];
       if (l + 1 == h->lv.size()) {
-        v += double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * 8.0;
+        v += double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * (f32 ? 4.0 : 8.0);
         break;
       }
-      for (double x : L.bytes_fwd) v += x;
-      for (double x : L.bytes_bwd) v += x;
-      v += L.bytes_resid + L.bytes_R + L.bytes_P;
+      for (double x : (f32 ? L.bytes_fwd32 : L.bytes_fwd)) v += x;
+      for (double x : (f32 ? L.bytes_bwd32 : L.bytes_bwd)) v += x;
+      v += f32 ? L.bytes_resid32 + L.bytes_R32 + L.bytes_P32 : L.bytes_resid + L.bytes_R + L.bytes_P;
     }
     const Level &L0 = h->lv[0];
     const double vec0 = double(L0.n) * L0.bs * 8.0;

@@ -308,21 +308,24 @@ __device__ inline double block_sum(double v, double *sh) {
   return sh[0];
 }
 
-template <int BR>
-__device__ inline void group_reduce(double (&acc)[BR], int G) {
+// The solve-phase kernels below are templated on the value type T of the matrices and vectors
+// they stream (double, or float for the FP32 V-cycle); they accumulate in T.
+
+template <class T, int BR>
+__device__ inline void group_reduce(T (&acc)[BR], int G) {
   for (int off = G >> 1; off > 0; off >>= 1)
 #pragma unroll
     for (int r = 0; r < BR; ++r) acc[r] += __shfl_xor(acc[r], off, G);
 }
 
 // acc[r] += sum over blocks p in [p0, p1) (strided by G) of A_p x_col(p)
-template <int BR, int BC>
+template <class T, int BR, int BC>
 __device__ inline void row_accumulate(int p0, int p1, int lane, int G, const int *__restrict__ col,
-                                      const double *__restrict__ val, int64_t nnz,
-                                      const double *x, double (&acc)[BR]) {
+                                      const T *__restrict__ val, int64_t nnz, const T *x,
+                                      T (&acc)[BR]) {
   for (int p = p0 + lane; p < p1; p += G) {
     const int64_t c = col[p];
-    double xv[BC];
+    T xv[BC];
 #pragma unroll
     for (int cc = 0; cc < BC; ++cc) xv[cc] = x[c * BC + cc];
 #pragma unroll
@@ -344,8 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n_rows, int G, const int *_
   double acc[BR];
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = 0.0;
-  if (row < n_rows) row_accumulate<BR, BC>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
-  group_reduce<BR>(acc, G);
+  if (row < n_rows) row_accumulate<double, BR, BC>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
+  group_reduce<double, BR>(acc, G);
   double d = 0.0;
   if (row < n_rows && lane == 0) {
 #pragma unroll
@@ -360,17 +363,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n_rows, int G, const int *_
   }
 }
 
-// Butterfly all-reduce within the group: every lane ends with the group total.
-template <int B>
-__device__ inline void group_allreduce(double (&acc)[B], int G) {
-  for (int off = G >> 1; off > 0; off >>= 1)
-#pragma unroll
-    for (int r = 0; r < B; ++r) acc[r] += __shfl_xor(acc[r], off, G);
-}
-
-template <int B>
-__device__ inline double pick(const double (&v)[B], int i) {
-  double out = 0.0;
+template <class T, int B>
+__device__ inline T pick(const T (&v)[B], int i) {
+  T out = T(0);
 #pragma unroll
   for (int q = 0; q < B; ++q) out = (q == i) ? v[q] : out;
   return out;
@@ -380,13 +375,13 @@ __device__ inline double pick(const double (&v)[B], int i) {
 // FWD: x = 0 before the sweep, so only the blocks left of the diagonal (lower colours) are read;
 // also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row.
 // Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
-// together with the row's blocks, so a row costs one round of row loads plus the x gathers.
-template <int B, bool FWD>
+// together with the row's blocks, so a row costs one round of row loads plus the x gathers;
+// a butterfly all-reduce leaves the row sum on every lane.
+template <class T, int B, bool FWD>
 __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                               const int *__restrict__ col, const int *__restrict__ diag,
-                              const double *__restrict__ val, int64_t nnz,
-                              const double *__restrict__ Dinv, const double *__restrict__ b,
-                              double *x, double *r) {
+                              const T *__restrict__ val, int64_t nnz, const T *__restrict__ Dinv,
+                              const T *__restrict__ b, T *x, T *r) {
   const bool own = valid && lane < B;
   int p0 = 0, p1 = 0;
   int64_t dp = 0;
@@ -395,11 +390,11 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
     dp = diag[row];
     p1 = FWD ? int(dp) : rp[row + 1];
   }
-  double bq = 0.0, Dq[B], Aq[B];
+  T bq = T(0), Dq[B], Aq[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) {
-    Dq[c] = 0.0;
-    Aq[c] = 0.0;
+    Dq[c] = T(0);
+    Aq[c] = T(0);
   }
   if (own) {
     bq = b[int64_t(row) * B + lane];
@@ -409,23 +404,23 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
       if (FWD) Aq[c] = val[int64_t(lane * B + c) * nnz + dp];
     }
   }
-  double acc[B];
+  T acc[B];
 #pragma unroll
-  for (int q = 0; q < B; ++q) acc[q] = 0.0;
-  if (valid) row_accumulate<B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  group_allreduce<B>(acc, G);
-  const double tq = bq - pick<B>(acc, lane);   // t component of this lane (lanes < B)
-  double t[B];
+  for (int q = 0; q < B; ++q) acc[q] = T(0);
+  if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
+  group_reduce<T, B>(acc, G);
+  const T tq = bq - pick<T, B>(acc, lane);   // t component of this lane (lanes < B)
+  T t[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) t[c] = __shfl(tq, c, G);
-  double xq = 0.0;
+  T xq = T(0);
 #pragma unroll
   for (int c = 0; c < B; ++c) xq = fma(Dq[c], t[c], xq);
   if (FWD) {
-    double xi[B];
+    T xi[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) xi[c] = __shfl(xq, c, G);
-    double rq = tq;
+    T rq = tq;
 #pragma unroll
     for (int c = 0; c < B; ++c) rq = fma(-Aq[c], xi[c], rq);
     if (own) {
@@ -438,64 +433,62 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 }
 
 // r_i -= sum_{j > i} A_ij x_j for one row.
-template <int B>
+template <class T, int B>
 __device__ inline void resid_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                                  const int *__restrict__ col, const int *__restrict__ diag,
-                                 const double *__restrict__ val, int64_t nnz, const double *x,
-                                 double *r) {
-  double rq = 0.0;
+                                 const T *__restrict__ val, int64_t nnz, const T *x, T *r) {
+  T rq = T(0);
   int p0 = 0, p1 = 0;
   if (valid) {
     p0 = diag[row] + 1;
     p1 = rp[row + 1];
     if (lane < B) rq = r[int64_t(row) * B + lane];
   }
-  double acc[B];
+  T acc[B];
 #pragma unroll
-  for (int a = 0; a < B; ++a) acc[a] = 0.0;
-  if (valid) row_accumulate<B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  group_allreduce<B>(acc, G);
-  if (valid && lane < B) r[int64_t(row) * B + lane] = rq - pick<B>(acc, lane);
+  for (int a = 0; a < B; ++a) acc[a] = T(0);
+  if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
+  group_reduce<T, B>(acc, G);
+  if (valid && lane < B) r[int64_t(row) * B + lane] = rq - pick<T, B>(acc, lane);
 }
 
 // One colour (rows [r0, r1)) per launch.
-template <int B, bool FWD>
+template <class T, int B, bool FWD>
 __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ diag,
-                                                    const double *__restrict__ val, int64_t nnz,
-                                                    const double *__restrict__ Dinv,
-                                                    const double *__restrict__ b, double *x,
-                                                    double *r) {
+                                                    const T *__restrict__ val, int64_t nnz,
+                                                    const T *__restrict__ Dinv,
+                                                    const T *__restrict__ b, T *x, T *r) {
   const int lane = threadIdx.x & (G - 1);
   const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  gs_row<B, FWD>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r);
+  gs_row<T, B, FWD>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r);
 }
 
-template <int B>
+template <class T, int B>
 __global__ __launch_bounds__(kBlock) void k_resid_upper(int n_rows, int G, const int *__restrict__ rp,
                                                        const int *__restrict__ col,
                                                        const int *__restrict__ diag,
-                                                       const double *__restrict__ val, int64_t nnz,
-                                                       const double *x, double *r) {
+                                                       const T *__restrict__ val, int64_t nnz,
+                                                       const T *x, T *r) {
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  resid_row<B>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r);
+  resid_row<T, B>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r);
 }
 
-template <int BR, int BC>
+template <class T, int BR, int BC>
 __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *__restrict__ rp,
                                                 const int *__restrict__ col,
-                                                const double *__restrict__ val, int64_t nnz,
-                                                const double *__restrict__ x, double *__restrict__ y,
+                                                const T *__restrict__ val, int64_t nnz,
+                                                const T *__restrict__ x, T *__restrict__ y,
                                                 int accumulate) {
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  double acc[BR];
+  T acc[BR];
 #pragma unroll
-  for (int r = 0; r < BR; ++r) acc[r] = 0.0;
-  if (row < n_rows) row_accumulate<BR, BC>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
-  group_reduce<BR>(acc, G);
+  for (int r = 0; r < BR; ++r) acc[r] = T(0);
+  if (row < n_rows) row_accumulate<T, BR, BC>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
+  group_reduce<T, BR>(acc, G);
   if (row < n_rows && lane == 0) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
@@ -507,17 +500,32 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
   }
 }
 
+// y = D x with the dense FP64 coarsest inverse D; vectors of type T, FP64 accumulation.
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double *__restrict__ D,
-                                                      const double *__restrict__ x,
-                                                      double *__restrict__ y) {
+                                                      const T *__restrict__ x, T *__restrict__ y) {
   const int G = 64;
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
   double acc[1] = {0.0};
   if (row < n)
-    for (int c = lane; c < n; c += G) acc[0] = fma(D[int64_t(row) * n + c], x[c], acc[0]);
-  group_reduce<1>(acc, G);
-  if (row < n && lane == 0) y[row] = acc[0];
+    for (int c = lane; c < n; c += G) acc[0] = fma(D[int64_t(row) * n + c], double(x[c]), acc[0]);
+  group_reduce<double, 1>(acc, G);
+  if (row < n && lane == 0) y[row] = T(acc[0]);
+}
+
+template <class S, class D>
+__global__ void k_convert(int64_t n, const S *__restrict__ in, D *__restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = D(in[i]);
+}
+
+__global__ void k_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in, float *out) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gid >= nnz * bsz) return;
+  const int64_t q = gid % nnz;
+  const int e = int(gid / nnz);
+  out[int64_t(e) * nnz + q] = float(in[src[q] * bsz + e]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
@@ -693,52 +701,75 @@ hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part
   EAMG_LAUNCH_CHECK();
 }
 
-#define EAMG_GS_LAUNCH(B_, FWD_, RPTR_)                                                          \
-  hipLaunchKernelGGL((k_gs_color<B_, FWD_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp,     \
-                     A.col, A.diag, A.val, A.nnz, Dinv, b, x, RPTR_)
+template <class T>
+const T *soa_vals(const SoaMat &M);
+template <>
+const double *soa_vals<double>(const SoaMat &M) {
+  return M.val;
+}
+template <>
+const float *soa_vals<float>(const SoaMat &M) {
+  return M.val32;
+}
 
-hipError_t launch_gs_fwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
-                         double *x, double *r, hipStream_t s) {
+template <class T>
+hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
+                         hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
+  const T *val = soa_vals<T>(A);
+  if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   switch (A.br) {
-    case 1: EAMG_GS_LAUNCH(1, true, r); break;
-    case 3: EAMG_GS_LAUNCH(3, true, r); break;
-    case 6: EAMG_GS_LAUNCH(6, true, r); break;
+    case 1: hipLaunchKernelGGL((k_gs_color<T, 1, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
+    case 3: hipLaunchKernelGGL((k_gs_color<T, 3, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
+    case 6: hipLaunchKernelGGL((k_gs_color<T, 6, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
 }
 
-hipError_t launch_resid_upper(const SoaMat &A, const double *x, double *r, hipStream_t s) {
+template <class T>
+hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
+                         hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  const T *val = soa_vals<T>(A);
+  if (!val) return hipErrorInvalidValue;
+  const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
+  T *none = nullptr;
+  switch (A.br) {
+    case 1: hipLaunchKernelGGL((k_gs_color<T, 1, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
+    case 3: hipLaunchKernelGGL((k_gs_color<T, 3, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
+    case 6: hipLaunchKernelGGL((k_gs_color<T, 6, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
+    default: return hipErrorInvalidValue;
+  }
+  EAMG_LAUNCH_CHECK();
+}
+
+template <class T>
+hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
+  const T *val = soa_vals<T>(A);
+  if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(A.n_rows, groups_for(A.group)));
-  EAMG_DISPATCH_SQ(A.br, k_resid_upper, grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col,
-                   A.diag, A.val, A.nnz, x, r);
-  EAMG_LAUNCH_CHECK();
-}
-
-hipError_t launch_gs_bwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
-                         double *x, hipStream_t s) {
-  if (r1 <= r0) return hipSuccess;
-  const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
-  double *none = nullptr;
   switch (A.br) {
-    case 1: EAMG_GS_LAUNCH(1, false, none); break;
-    case 3: EAMG_GS_LAUNCH(3, false, none); break;
-    case 6: EAMG_GS_LAUNCH(6, false, none); break;
+    case 1: hipLaunchKernelGGL((k_resid_upper<T, 1>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
+    case 3: hipLaunchKernelGGL((k_resid_upper<T, 3>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
+    case 6: hipLaunchKernelGGL((k_resid_upper<T, 6>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
 }
 
-hipError_t launch_rect(const SoaMat &M, const double *x, double *y, bool accumulate, hipStream_t s) {
+template <class T>
+hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipStream_t s) {
   if (M.n_rows == 0) return hipSuccess;
+  const T *val = soa_vals<T>(M);
+  if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(M.n_rows, groups_for(M.group)));
   const int accf = accumulate ? 1 : 0;
-#define EAMG_RECT(BR_, BC_)                                                                       \
-  hipLaunchKernelGGL((k_rect<BR_, BC_>), grid, dim3(kBlock), 0, s, M.n_rows, M.group, M.rp, M.col, \
-                     M.val, M.nnz, x, y, accf)
+#define EAMG_RECT(BR_, BC_)                                                                          \
+  hipLaunchKernelGGL((k_rect<T, BR_, BC_>), grid, dim3(kBlock), 0, s, M.n_rows, M.group, M.rp, M.col, \
+                     val, M.nnz, x, y, accf)
   if (M.br == 1 && M.bc == 1) EAMG_RECT(1, 1);
   else if (M.br == 3 && M.bc == 6) EAMG_RECT(3, 6);
   else if (M.br == 6 && M.bc == 3) EAMG_RECT(6, 3);
@@ -748,11 +779,40 @@ hipError_t launch_rect(const SoaMat &M, const double *x, double *y, bool accumul
   EAMG_LAUNCH_CHECK();
 }
 
-hipError_t launch_dense_gemv(int n, const double *D, const double *x, double *y, hipStream_t s) {
+template <class T>
+hipError_t launch_dense_gemv(int n, const double *D, const T *x, T *y, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_gemv, dim3(cdiv64(n, kBlock / 64)), dim3(kBlock), 0, s, n, D, x, y);
+  hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv64(n, kBlock / 64)), dim3(kBlock), 0, s, n, D, x, y);
   EAMG_LAUNCH_CHECK();
 }
+
+template <class S, class D>
+hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_convert<S, D>), dim3(cdiv64(n, 256)), dim3(256), 0, s, n, in, out);
+  EAMG_LAUNCH_CHECK();
+}
+
+hipError_t launch_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
+                                 float *out, hipStream_t s) {
+  if (nnz == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_soa_f32, dim3(cdiv64(nnz * bsz, 256)), dim3(256), 0, s, nnz, bsz, src,
+                     in, out);
+  EAMG_LAUNCH_CHECK();
+}
+
+template hipError_t launch_gs_fwd<double>(const SoaMat &, const double *, int, int, const double *, double *, double *, hipStream_t);
+template hipError_t launch_gs_fwd<float>(const SoaMat &, const float *, int, int, const float *, float *, float *, hipStream_t);
+template hipError_t launch_gs_bwd<double>(const SoaMat &, const double *, int, int, const double *, double *, hipStream_t);
+template hipError_t launch_gs_bwd<float>(const SoaMat &, const float *, int, int, const float *, float *, hipStream_t);
+template hipError_t launch_resid_upper<double>(const SoaMat &, const double *, double *, hipStream_t);
+template hipError_t launch_resid_upper<float>(const SoaMat &, const float *, float *, hipStream_t);
+template hipError_t launch_rect<double>(const SoaMat &, const double *, double *, bool, hipStream_t);
+template hipError_t launch_rect<float>(const SoaMat &, const float *, float *, bool, hipStream_t);
+template hipError_t launch_dense_gemv<double>(int, const double *, const double *, double *, hipStream_t);
+template hipError_t launch_dense_gemv<float>(int, const double *, const float *, float *, hipStream_t);
+template hipError_t launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
+template hipError_t launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
 
 int dot_blocks(int64_t n) {
   const int64_t b = (n + kBlock - 1) / kBlock;

@@ -68,24 +68,38 @@ struct SoaMat {
   const int *rp = nullptr;   // int32 row offsets (nnz < 2^31 for one level)
   const int *col = nullptr;
   const double *val = nullptr;
+  const float *val32 = nullptr;  // FP32 copy of val (FP32 V-cycle), or nullptr
   const int *diag = nullptr; // square matrices only
 };
 
 // y = A x ; if part != nullptr also writes per-workgroup partial sums of x.y (dot_blocks entries)
 hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part, hipStream_t s);
+// The V-cycle kernels are instantiated for T = double (values SoaMat::val) and T = float
+// (values SoaMat::val32); they accumulate in T.
 // Forward colour sweep with x = 0 initially on rows [r0, r1):
 //   t = b_i - sum_{j < i} A_ij x_j ; x_i = Dinv_i t ; r_i = t - A_ii x_i
-hipError_t launch_gs_fwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
-                         double *x, double *r, hipStream_t s);
+template <class T>
+hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
+                         hipStream_t s);
 // r_i -= sum_{j > i} A_ij x_j on all rows (completes r = b - A x after the forward sweep).
-hipError_t launch_resid_upper(const SoaMat &A, const double *x, double *r, hipStream_t s);
+template <class T>
+hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s);
 // Backward colour sweep on rows [r0, r1): x_i += Dinv_i (b_i - sum_j A_ij x_j).
-hipError_t launch_gs_bwd(const SoaMat &A, const double *Dinv, int r0, int r1, const double *b,
-                         double *x, hipStream_t s);
+template <class T>
+hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
+                         hipStream_t s);
 // y = M x (rectangular, overwrite) or y += M x (accumulate = true).
-hipError_t launch_rect(const SoaMat &M, const double *x, double *y, bool accumulate, hipStream_t s);
-// y = D x for a dense n x n row-major matrix.
-hipError_t launch_dense_gemv(int n, const double *D, const double *x, double *y, hipStream_t s);
+template <class T>
+hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipStream_t s);
+// y = D x for the dense n x n row-major FP64 matrix D (FP64 accumulation).
+template <class T>
+hipError_t launch_dense_gemv(int n, const double *D, const T *x, T *y, hipStream_t s);
+// out[i] = D(in[i])
+template <class S, class D>
+hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s);
+// AoS double -> SoA float gather: out[e * nnz + q] = float(in[src[q] * bsz + e]).
+hipError_t launch_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
+                                 float *out, hipStream_t s);
 
 // Vector operations with deterministic reductions; grid size fixed by the length.
 int dot_blocks(int64_t n);

@@ -285,3 +285,124 @@ def test_graph_replay_matches_eager_launches():
         assert torch.equal(hg.solve(b, rtol=0.0, max_it=k)[0], ref)
     he.close()
     hg.close()
+
+
+# --- FP32 V-cycle inside the FP64 CG -------------------------------------------------------
+# The FP32 V-cycle is a different (rounded) preconditioner, so it is compared with the FP64
+# oracle by the error it makes, stated per case:
+#  * one V-cycle z = B^{-1} r: relative error against the oracle's FP64 V-cycle.  Every stored
+#    matrix entry and vector carries a relative rounding error u = 2^-24 ~ 6e-8 and every block
+#    row sum a few u more; the V-cycle is a fixed linear map built from ~2L+1 sweeps of such
+#    rows, so its relative error is a small multiple of u times the growth of the map's
+#    condition with the level count (measured: 0.6e-7 .. 2e-7 on the cases here).
+#    F32_VC_TOL = 1e-5 leaves two orders of margin and still fails a wrong sign, a dropped term
+#    or a skipped level (O(1) errors) and an FP16-like rounding (u = 5e-4).
+#  * the PCG solution: the outer FP64 CG recovers FP64 accuracy, so the same stopping test as
+#    the FP64 solve must hold for the true residual (checked here on the CPU with the assembled
+#    matrix), within at most F32_EXTRA_ITS more iterations than the FP64 V-cycle needs, and the
+#    iterate must be as close to the oracle's converged (rtol 1e-12) solution as the FP64
+#    library's own 1e-8 iterate is, up to a factor 10.
+F32_VC_TOL = 1e-5
+F32_EXTRA_ITS = 3
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def pair32(request):
+    name = request.param
+    p = make_problem(**CASES[name])
+    print(f"\n[case {name} fp32] n={p.n_vertices} dofs={p.n_dofs}", flush=True)
+    ho = _oracle_cached(name, p)
+    hl = _lib(p, vcycle_fp32=1)
+    yield name, p, ho, hl
+    hl.close()
+
+
+def _bound_matrix(p):
+    A = sp.bsr_matrix((p.vals, p.col_idx, p.row_ptr), shape=(p.n_dofs,) * 2).tocsr()
+    dm = np.repeat(p.dirichlet.astype(bool), p.dim)
+    Dm = sp.diags((~dm).astype(float))
+    return Dm @ A @ Dm + sp.diags(dm.astype(float))
+
+
+def test_fp32_vcycle_error(pair32):
+    name, p, ho, hl = pair32
+    r = np.random.default_rng(3).standard_normal(p.n_dofs)
+    r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    zo = oracle.vcycle(ho, r)
+    z32 = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+    z64 = torch.empty_like(z32)
+    E.eamg_vcycle(hl.h, _dev(r), z32, E.EAMG_PRECOND_VCYCLE_FP32)
+    E.eamg_vcycle(hl.h, _dev(r), z64, E.EAMG_PRECOND_VCYCLE)
+    torch.cuda.synchronize()
+    err32 = np.linalg.norm(z32.cpu().numpy() - zo) / np.linalg.norm(zo)
+    err64 = np.linalg.norm(z64.cpu().numpy() - zo) / np.linalg.norm(zo)
+    print(f"[{name}] V-cycle rel err vs FP64 oracle: fp32 {err32:.2e} fp64 {err64:.2e}", flush=True)
+    assert err64 <= X_TOL
+    assert err32 <= F32_VC_TOL
+    # Dirichlet dofs stay exactly zero in both precisions
+    dm = torch.tensor(np.repeat(p.dirichlet.astype(bool), p.dim), device="cuda")
+    assert bool(dm.any()) and float(z32[dm].abs().max()) == 0.0
+
+
+def test_fp32_pcg_error(pair32):
+    name, p, ho, hl = pair32
+    b = _dev(p.b)
+    x64, i64 = hl.solve(b, rtol=1e-8, precond=E.EAMG_PRECOND_VCYCLE)
+    x32, i32 = hl.solve(b, rtol=1e-8, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+    assert i64["status"] == E.EAMG_OK and i32["status"] == E.EAMG_OK
+    Ab = _bound_matrix(p)
+    bn = np.linalg.norm(p.b)
+    res32 = np.linalg.norm(p.b - Ab @ x32.cpu().numpy()) / bn
+    assert res32 <= 1e-8 and abs(res32 - i32["rel_res_true"]) <= 1e-3 * res32 + 1e-15
+    assert i32["iterations"] <= i64["iterations"] + F32_EXTRA_ITS
+    xs, _, _, rel_s, conv_s = oracle.pcg(ho, p.b, rtol=1e-12)
+    assert conv_s
+    e64 = np.linalg.norm(x64.cpu().numpy() - xs) / np.linalg.norm(xs)
+    e32 = np.linalg.norm(x32.cpu().numpy() - xs) / np.linalg.norm(xs)
+    print(f"[{name}] its fp64={i64['iterations']} fp32={i32['iterations']} true res fp32 "
+          f"{res32:.2e}; x rel err vs oracle (rtol 1e-12): fp64 {e64:.2e} fp32 {e32:.2e}",
+          flush=True)
+    assert e32 <= 10.0 * max(e64, 1e-12)
+    # reproducible run to run, graph replay included
+    x32b, _ = hl.solve(b, rtol=1e-8, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+    assert torch.equal(x32, x32b)
+
+
+def test_fp32_requires_setup_flag():
+    p = make_problem(6)
+    hl = _lib(p)
+    b = _dev(p.b)
+    with pytest.raises(E.EamgError) as ei:
+        hl.solve(b, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+    assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+    z = torch.empty_like(b)
+    with pytest.raises(E.EamgError) as ei:
+        E.eamg_vcycle(hl.h, b, z, E.EAMG_PRECOND_VCYCLE_FP32)
+    assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+    with pytest.raises(E.EamgError) as ei:
+        E.eamg_vcycle(hl.h, b, z, 3)
+    assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+    hl.close()
+
+
+def test_fp32_graph_replay_matches_eager():
+    import os
+    p = make_problem(13, seed=6)
+    b = _dev(p.b)
+    old = os.environ.get("EAMG_GRAPH")
+    os.environ["EAMG_GRAPH"] = "0"
+    try:
+        he = _lib(p, vcycle_fp32=1)
+        xe, ie = he.solve(b, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+    finally:
+        if old is None:
+            del os.environ["EAMG_GRAPH"]
+        else:
+            os.environ["EAMG_GRAPH"] = old
+    hg = _lib(p, vcycle_fp32=1)
+    for prec in (E.EAMG_PRECOND_VCYCLE_FP32, E.EAMG_PRECOND_VCYCLE, E.EAMG_PRECOND_VCYCLE_FP32):
+        xg, ig = hg.solve(b, precond=prec)
+        if prec == E.EAMG_PRECOND_VCYCLE_FP32:
+            assert ig["iterations"] == ie["iterations"] and torch.equal(xg, xe)
+    he.close()
+    hg.close()
