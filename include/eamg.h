@@ -126,13 +126,15 @@ typedef struct {
   int32_t precond;
 } eamg_solve_params;
 
-/* Solve report: iterations done, final recursive and true relative residual, and the
- * wall time of the solve in milliseconds measured with events on the stream. */
+/* Solve report: iterations done, final recursive and true relative residual, the wall time of
+ * the solve in milliseconds measured with events on the stream (for a batch: of the whole
+ * batch), and the status of this right-hand side (OK, NOT_CONVERGED or BREAKDOWN). */
 typedef struct {
   int32_t iterations;
   double rel_res;
   double rel_res_true;
   double ms;
+  int32_t status;
 } eamg_solve_info;
 
 /* Per-level sizes, for sizing eamg_export_level buffers. */
@@ -167,6 +169,25 @@ eamg_status eamg_setup(const eamg_problem *problem, const eamg_setup_params *par
  */
 eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
                        const eamg_solve_params *params, void *stream, eamg_solve_info *info);
+
+/*
+ * Solve A X = B for nrhs right-hand sides at once (block panels of up to 64 columns: every
+ * matrix of the V-cycle and the CG operator is streamed once per panel).  Each column runs its
+ * own PCG recurrence (own alpha, beta and stopping test, exactly as eamg_solve) and stops on
+ * its own; converged columns are frozen while the others continue.
+ *   B_dev, X_dev  DEVICE arrays, column-major: column c is the n*dim doubles at offset c*ld;
+ *                 ld >= n*dim; caller-owned; may not overlap.
+ *   infos         HOST array of nrhs reports (may be NULL); infos[c].status is OK,
+ *                 NOT_CONVERGED or BREAKDOWN (non-finite b column, non-positive curvature or
+ *                 preconditioned inner product in that column; its x column is the last
+ *                 iterate, or 0 when it never started).
+ * Returns OK when every column converged, NOT_CONVERGED when at least one did not (iteration
+ * limit or breakdown of that column), INVALID_ARG or HIP.  The first call with a given panel
+ * width allocates the panel workspace (about 7 * n*dim*K doubles plus the V-cycle levels).
+ */
+eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const double *B_dev, int64_t ld,
+                             double *X_dev, const eamg_solve_params *params, void *stream,
+                             eamg_solve_info *infos);
 
 /*
  * Apply one V-cycle z = B^{-1} r (DEVICE arrays, n*dim doubles, level-0 natural order).

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
-            "eamg_profile_enable", "eamg_profile_read"]
+            "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -64,7 +64,8 @@ class eamg_solve_params(ctypes.Structure):
 
 class eamg_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("rel_res", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("ms", ctypes.c_double),
+                ("status", ctypes.c_int32)]
 
 
 class eamg_level_info(ctypes.Structure):
@@ -100,6 +101,8 @@ def lib():
     L.eamg_setup.restype = ctypes.c_int
     L.eamg_solve.argtypes = [vp, vp, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve.restype = ctypes.c_int
+    L.eamg_solve_batch.argtypes = [vp, i32, vp, i64, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
+    L.eamg_solve_batch.restype = ctypes.c_int
     L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.eamg_vcycle.restype = ctypes.c_int
     L.eamg_stats.argtypes = [vp, P(i32), vp, vp, P(dp), P(dp)]
@@ -210,6 +213,21 @@ def eamg_solve(h, b, x, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stre
         raise EamgError(st, "eamg_solve")
     return st, dict(iterations=info.iterations, rel_res=info.rel_res,
                     rel_res_true=info.rel_res_true, ms=info.ms)
+
+
+def eamg_solve_batch(h, B, X, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stream=None):
+    """B, X: float64 device tensors of shape (nrhs, n*dim), rows contiguous (column c of the
+    batch is row c).  Returns (status, [info dict per right-hand side])."""
+    nrhs, ndof = B.shape
+    assert X.shape == B.shape and B.stride(1) == 1 and X.stride(1) == 1 and B.stride(0) == X.stride(0)
+    sp = eamg_solve_params(rtol, max_it, int(use_x0), int(precond))
+    infos = (eamg_solve_info * nrhs)()
+    st = lib().eamg_solve_batch(h, nrhs, _dptr(B), B.stride(0), _dptr(X), ctypes.byref(sp),
+                                _stream(stream), infos)
+    if st < 0:
+        raise EamgError(st, "eamg_solve_batch")
+    return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
+                     ms=i.ms, status=i.status) for i in infos]
 
 
 def eamg_vcycle(h, r, z, precision=EAMG_PRECOND_VCYCLE, stream=None):
@@ -325,6 +343,13 @@ class Hierarchy:
         st, info = eamg_solve(self.h, b, x, **kw)
         info["status"] = st
         return x, info
+
+    def solve_batch(self, B, X=None, **kw):
+        import torch
+        if X is None:
+            X = torch.zeros_like(B)
+        st, infos = eamg_solve_batch(self.h, B, X, **kw)
+        return X, st, infos
 
     def stats(self):
         return eamg_stats(self.h)

@@ -15,177 +15,14 @@
 #include "../../include/eamg.h"
 #include "coarsen.hpp"
 #include "dense.hpp"
+#include "hierarchy.hpp"
 #include "kernels.hpp"
 #include "structure.hpp"
 
 namespace eamg {
 
-namespace {
-
 thread_local std::string g_last_error;
 
-struct Failure {
-  eamg_status code;
-  std::string msg;
-};
-
-[[noreturn]] void fail(eamg_status code, const std::string &msg) { throw Failure{code, msg}; }
-
-void hip_check(hipError_t e, const char *what) {
-  if (e == hipSuccess) return;
-  if (e == hipErrorOutOfMemory) fail(EAMG_ERR_OOM, std::string(what) + ": out of device memory");
-  fail(EAMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-// Device allocations owned by a hierarchy; freed together.
-struct DevArena {
-  std::vector<void *> ptrs;
-  template <class T>
-  T *alloc(size_t count) {
-    void *p = nullptr;
-    if (count == 0) count = 1;
-    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
-    ptrs.push_back(p);
-    return static_cast<T *>(p);
-  }
-  template <class T>
-  T *upload(const std::vector<T> &v, hipStream_t s) {
-    return upload(v.data(), v.size(), s);
-  }
-  template <class T>
-  T *upload(const T *p, size_t count, hipStream_t s) {
-    // setup-time upload from pageable memory: wait so the source may be freed on return
-    T *d = alloc<T>(count);
-    if (count) {
-      hip_check(hipMemcpyAsync(d, p, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
-      hip_check(hipStreamSynchronize(s), "sync");
-    }
-    return d;
-  }
-  void release(void *p) {
-    auto it = std::find(ptrs.begin(), ptrs.end(), p);
-    if (it != ptrs.end()) {
-      (void)hipFree(p);
-      ptrs.erase(it);
-    }
-  }
-  ~DevArena() {
-    for (void *p : ptrs) (void)hipFree(p);
-  }
-};
-
-template <class T>
-std::vector<T> download(const T *d, size_t count, hipStream_t s) {
-  std::vector<T> h(count);
-  if (count) hip_check(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s), "download");
-  hip_check(hipStreamSynchronize(s), "sync");
-  return h;
-}
-
-int pick_group(int64_t nnz, int rows) {
-  const double avg = rows ? double(nnz) / rows : 1.0;
-  int g = 4;
-  while (g < 64 && g < avg) g <<= 1;
-  return g;
-}
-
-struct Level {
-  int n = 0, bs = 0;
-  Pattern A;                 // natural pattern
-  int64_t *A_rp = nullptr;   // natural pattern on the device
-  int *A_col = nullptr;
-  double *A_val = nullptr;   // natural AoS values (n_blocks * bs * bs)
-  // coarsening products (levels above the coarsest)
-  std::vector<int> agg;
-  Pattern P;
-  int kc = 0;
-  double *P_val = nullptr;   // natural AoS values (nnz * bs * kc)
-  std::vector<int> color;    // natural
-  int ncolors = 0;
-  // colour-major solve layout
-  std::vector<int> perm, inv, color_ptr;
-  int *perm_d = nullptr;
-  SoaMat Am, Pm, Rm;
-  double *Dinv = nullptr;
-  int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
-  double *x = nullptr, *b = nullptr, *r = nullptr;
-  // algorithmic bytes of every launch (for the traffic model and the profiler)
-  std::vector<double> bytes_fwd, bytes_bwd;   // per colour
-  double bytes_resid = 0, bytes_R = 0, bytes_P = 0, bytes_spmv = 0;
-  // FP32 V-cycle: values in SoaMat::val32, D^+ and level vectors in float
-  float *Dinv32 = nullptr, *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
-  std::vector<double> bytes_fwd32, bytes_bwd32;
-  double bytes_resid32 = 0, bytes_R32 = 0, bytes_P32 = 0;
-};
-
-// Per-precision view of a level's V-cycle buffers.
-template <class T>
-struct LevelBufs {
-  const T *Dinv;
-  T *x, *b, *r;
-};
-template <class T>
-LevelBufs<T> bufs(Level &L);
-template <>
-LevelBufs<double> bufs<double>(Level &L) {
-  return {L.Dinv, L.x, L.b, L.r};
-}
-template <>
-LevelBufs<float> bufs<float>(Level &L) {
-  return {L.Dinv32, L.x32, L.b32, L.r32};
-}
-template <class T>
-const char *type_name();
-template <>
-const char *type_name<double>() {
-  return "double";
-}
-template <>
-const char *type_name<float>() {
-  return "float";
-}
-
-struct ProfRec {
-  std::string name;
-  double bytes;
-  int launches;
-  hipEvent_t a, b;
-};
-
-}  // namespace
-}  // namespace eamg
-
-struct eamg_hierarchy {
-  int dim = 0, k = 0, n0 = 0;
-  eamg_setup_params prm{};
-  std::vector<eamg::Level> lv;
-  eamg::DevArena arena;
-  double *Ainv = nullptr;
-  int nL = 0;                 // coarsest dofs
-  uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
-  double *part = nullptr, *scal = nullptr;
-  double *scal_h = nullptr;   // pinned
-  // profiler: events around every launch while enabled
-  bool prof_on = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<eamg::ProfRec> prof;
-  // PCG iteration captured as a graph (V-cycle .. r.r and the scalar copy), replayed per iteration
-  hipStream_t cap_stream = nullptr;
-  // one graph per V-cycle precision: [0] FP64, [1] FP32
-  hipGraphExec_t g_iter[2] = {nullptr, nullptr};
-  bool graph_tried[2] = {false, false};
-  ~eamg_hierarchy() {
-    for (hipGraphExec_t g : g_iter)
-      if (g) (void)hipGraphExecDestroy(g);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (scal_h) (void)hipHostFree(scal_h);
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-  }
-};
-
-namespace eamg {
 namespace {
 
 eamg_setup_params defaults() {
@@ -383,70 +220,39 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
 }
 
 
-hipEvent_t next_event(eamg_hierarchy *h) {
-  if (h->ev_used == h->ev_pool.size()) {
-    hipEvent_t e;
-    hip_check(hipEventCreate(&e), "event");
-    h->ev_pool.push_back(e);
-  }
-  return h->ev_pool[h->ev_used++];
-}
-
-// Run `f`, which enqueues `launches` back-to-back launches of one kernel; while profiling,
-// bracket them with one pair of events and record their algorithmic bytes.
-template <class F>
-void timed_n(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
-             int launches, hipStream_t s, F &&f) {
-  if (!h->prof_on) {
-    hip_check(f(), what);
-    return;
-  }
-  ProfRec r{name, bytes, launches, next_event(h), next_event(h)};
-  hip_check(hipEventRecord(r.a, s), "event");
-  hip_check(f(), what);
-  hip_check(hipEventRecord(r.b, s), "event");
-  h->prof.push_back(r);
-}
-
-template <class F>
-void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
-           hipStream_t s, F &&f) {
-  timed_n(h, what, name, bytes, 1, s, std::forward<F>(f));
-}
-
-std::string tname(const char *base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }
-std::string tname(const char *base, int a, int b) {
-  return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
-}
 
 // Bytes of a row range [r0, r1) of a colour-major square level: blocks [lo(row), hi(row)) read,
 // plus `per_row` bytes per row and every distinct column of those blocks gathered once.
-double range_bytes(const Pattern &Ap, const std::vector<int> &dg, int bs, int r0, int r1, int part,
-                   double per_row, std::vector<int> &mark, int stamp, double vs = 8.0) {
-  double blocks = 0.0, uniq = 0.0;
+// Blocks, rows and distinct columns of rows [r0, r1) of the colour-major pattern; part 0: lower
+// blocks and the diagonal, 1: whole rows, 2: blocks right of the diagonal.
+LaunchShape range_shape(const Pattern &Ap, const std::vector<int> &dg, int r0, int r1, int part,
+                        std::vector<int> &mark, int stamp) {
+  LaunchShape sh;
+  sh.rows = r1 - r0;
   for (int i = r0; i < r1; ++i) {
     const int64_t lo = part == 2 ? dg[i] + 1 : Ap.rp[i];
     const int64_t hi = part == 0 ? dg[i] + 1 : Ap.rp[i + 1];
-    blocks += double(hi - lo);
+    sh.blocks += double(hi - lo);
     for (int64_t q = lo; q < hi; ++q)
       if (mark[Ap.col[q]] != stamp) {
         mark[Ap.col[q]] = stamp;
-        uniq += 1.0;
+        sh.uniq += 1.0;
       }
   }
-  return blocks * (bs * bs * vs + 4.0) + double(r1 - r0) * per_row + uniq * bs * vs;
+  return sh;
 }
 
-double rect_bytes(const Pattern &M, int br, int bc, bool accumulate, double vs = 8.0) {
+LaunchShape matrix_shape(const Pattern &M) {
+  LaunchShape sh;
+  sh.rows = M.n_rows;
+  sh.blocks = double(M.nnz());
   std::vector<char> seen(size_t(M.n_cols), 0);
-  double uniq = 0.0;
   for (int c : M.col)
     if (!seen[c]) {
       seen[c] = 1;
-      uniq += 1.0;
+      sh.uniq += 1.0;
     }
-  return double(M.nnz()) * (br * bc * vs + 4.0) + 4.0 * (M.n_rows + 1) + uniq * bc * vs +
-         double(M.n_rows) * br * vs * (accumulate ? 2.0 : 1.0);
+  return sh;
 }
 
 void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
@@ -479,35 +285,16 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
-  {
-    std::vector<int> seen(size_t(L.n), 0);
-    double uniq = 0.0;
-    for (int c : Ap.col)
-      if (!seen[c]) {
-        seen[c] = 1;
-        uniq += 1.0;
-      }
-    L.bytes_spmv = double(Ap.nnz()) * (bs * bs * 8.0 + 4.0) + 4.0 * (L.n + 1) + uniq * bs * 8.0 +
-                   double(L.n) * bs * 8.0;
-  }
+  L.sh_spmv = matrix_shape(Ap);
   if (!coarsest) {
     std::vector<int> mark(size_t(L.n), -1);
     int stamp = 0;
-    const double rowb = 8.0 + bs * bs * 8.0;   // row offset + diagonal index, D^+ block
     for (int c = 0; c < L.ncolors; ++c) {
       const int r0 = L.color_ptr[c], r1 = L.color_ptr[c + 1];
-      // forward: lower blocks + diagonal; b read, x and r written
-      L.bytes_fwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 0, rowb + 3.0 * bs * 8.0, mark, stamp++));
-      // backward: whole rows; b read, x written
-      L.bytes_bwd.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb + 2.0 * bs * 8.0, mark, stamp++));
-      if (f32) {
-        const double rowb32 = 8.0 + bs * bs * 4.0;
-        L.bytes_fwd32.push_back(range_bytes(Ap, dg, bs, r0, r1, 0, rowb32 + 3.0 * bs * 4.0, mark, stamp++, 4.0));
-        L.bytes_bwd32.push_back(range_bytes(Ap, dg, bs, r0, r1, 1, rowb32 + 2.0 * bs * 4.0, mark, stamp++, 4.0));
-      }
+      L.sh_fwd.push_back(range_shape(Ap, dg, r0, r1, 0, mark, stamp++));
+      L.sh_bwd.push_back(range_shape(Ap, dg, r0, r1, 1, mark, stamp++));
     }
-    L.bytes_resid = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 8.0, mark, stamp++);
-    if (f32) L.bytes_resid32 = range_bytes(Ap, dg, bs, 0, L.n, 2, 8.0 + 2.0 * bs * 4.0, mark, stamp++, 4.0);
+    L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, stamp++);
   }
   if (coarsest) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
@@ -539,16 +326,14 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   std::vector<int64_t> srcR(srcT.size());
   for (size_t q = 0; q < srcT.size(); ++q) srcR[q] = srcP[size_t(srcT[q])];
   L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true, f32);
-  L.bytes_R = rect_bytes(Rp, L.kc, bs, false);
-  L.bytes_P = rect_bytes(Pp, bs, L.kc, true);
+  L.sh_R = matrix_shape(Rp);
+  L.sh_P = matrix_shape(Pp);
   L.r = ar.alloc<double>(size_t(L.n) * bs);
   if (l > 0) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
     L.x = ar.alloc<double>(size_t(L.n) * bs);
   }
   if (f32) {
-    L.bytes_R32 = rect_bytes(Rp, L.kc, bs, false, 4.0);
-    L.bytes_P32 = rect_bytes(Pp, bs, L.kc, true, 4.0);
     L.r32 = ar.alloc<float>(size_t(L.n) * bs);
     L.b32 = ar.alloc<float>(size_t(L.n) * bs);
     L.x32 = ar.alloc<float>(size_t(L.n) * bs);
@@ -617,10 +402,11 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   }
   const LevelBufs<T> B = bufs<T>(L);
   const int bs = L.bs;
+  const double vs = sizeof(T);
   double fwd_bytes = 0.0, bwd_bytes = 0.0;
   for (int c = 0; c < L.ncolors; ++c) {
-    fwd_bytes += f32 ? L.bytes_fwd32[c] : L.bytes_fwd[c];
-    bwd_bytes += f32 ? L.bytes_bwd32[c] : L.bytes_bwd[c];
+    fwd_bytes += launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, 1);
+    bwd_bytes += launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, 1);
   }
   const std::string gs = "k_gs_color<" + ty + ", " + std::to_string(bs);
   // the colours of a sweep are back-to-back launches of one kernel: timed as one run
@@ -632,14 +418,14 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
     return hipSuccess;
   });
   timed(h, "resid_upper", "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">",
-        f32 ? L.bytes_resid32 : L.bytes_resid, s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
+        launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
   Level &C = h->lv[l + 1];
   const LevelBufs<T> CB = bufs<T>(C);
   timed(h, "restrict", "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">",
-        f32 ? L.bytes_R32 : L.bytes_R, s, [&] { return launch_rect<T>(L.Rm, B.r, CB.b, false, s); });
+        launch_bytes(L.sh_R, LK_RECT, L.kc, bs, vs, 1), s, [&] { return launch_rect<T>(L.Rm, B.r, CB.b, false, s); });
   vcycle_t<T>(h, l + 1, CB.b, CB.x, s);
   timed(h, "prolong", "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">",
-        f32 ? L.bytes_P32 : L.bytes_P, s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
+        launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1), s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
   timed_n(h, "gs_bwd", gs + ", false>", bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
       const hipError_t e = launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
@@ -712,28 +498,6 @@ void try_build_graph(eamg_hierarchy *h, bool f32) {
   (void)hipGetLastError();
 }
 
-void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
-  hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s), "copy");
-  hip_check(hipStreamSynchronize(s), "sync");
-}
-
-template <class F>
-eamg_status guarded(F &&f) {
-  try {
-    f();
-    g_last_error.clear();
-    return EAMG_OK;
-  } catch (const Failure &e) {
-    g_last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    g_last_error = "host allocation failed";
-    return EAMG_ERR_OOM;
-  } catch (const std::exception &e) {
-    g_last_error = e.what();
-    return EAMG_ERR_INVALID_ARG;
-  }
-}
 
 double bytes_bcsr(int64_t nnzb, int r, int c, int rows) {
   return double(nnzb) * (r * c * 8.0 + 4.0) + 4.0 * (rows + 1);
@@ -1014,7 +778,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
     }
     if (!converged) {
       // first iteration (p = z already set), then z = V(r) ... per further iteration
-      timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
+      timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 8.0 * ns, s,
             [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
       timed(h, "reduce", "k_reduce", 8.0 * ns, s,
             [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
@@ -1047,7 +811,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
                 [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
           timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
                 [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
-          timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), L0.bytes_spmv + 8.0 * ns, s,
+          timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 8.0 * ns, s,
                 [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
           timed(h, "reduce", "k_reduce", 8.0 * ns, s,
                 [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
@@ -1074,17 +838,16 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
     hip_check(hipEventElapsedTime(&fms, e0, e1), "event");
     ms = fms;
   });
+  const eamg_status out = (st == EAMG_OK && !converged) ? EAMG_NOT_CONVERGED : st;
+  if (out == EAMG_NOT_CONVERGED) g_last_error = "iteration limit reached";
   if (info) {
     info->iterations = iters;
     info->rel_res = rel;
     info->rel_res_true = rel_true;
     info->ms = ms;
+    info->status = out;
   }
-  if (st == EAMG_OK && !converged) {
-    g_last_error = "iteration limit reached";
-    return EAMG_NOT_CONVERGED;
-  }
-  return st;
+  return out;
 }
 
 eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,
@@ -1171,14 +934,18 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
         v += double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * (f32 ? 4.0 : 8.0);
         break;
       }
-      for (double x : (f32 ? L.bytes_fwd32 : L.bytes_fwd)) v += x;
-      for (double x : (f32 ? L.bytes_bwd32 : L.bytes_bwd)) v += x;
-      v += f32 ? L.bytes_resid32 + L.bytes_R32 + L.bytes_P32 : L.bytes_resid + L.bytes_R + L.bytes_P;
+      const double vs = f32 ? 4.0 : 8.0;
+      const int bs = L.bs;
+      for (const LaunchShape &sh : L.sh_fwd) v += launch_bytes(sh, LK_GS_FWD, bs, bs, vs, 1);
+      for (const LaunchShape &sh : L.sh_bwd) v += launch_bytes(sh, LK_GS_BWD, bs, bs, vs, 1);
+      v += launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1) +
+           launch_bytes(L.sh_R, LK_RECT, L.kc, bs, vs, 1) +
+           launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1);
     }
     const Level &L0 = h->lv[0];
     const double vec0 = double(L0.n) * L0.bs * 8.0;
     // PCG: SpMV with p.q, x / r update (x rw, r rw, p, q), r.z, p update (z, p rw)
-    const double it = L0.bytes_spmv + 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0;
+    const double it = launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0;
     if (vcycle_bytes) *vcycle_bytes = v;
     if (iteration_bytes) *iteration_bytes = it + v;
   });

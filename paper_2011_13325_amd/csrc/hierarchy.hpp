@@ -1,0 +1,276 @@
+// Device hierarchy of libeamg shared by the setup / PCG driver (api.cpp) and the batched
+// block-panel driver (batch.cpp): levels in colour-major solve layout, device arena, the
+// per-launch profiler and the error plumbing of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/eamg.h"
+#include "kernels.hpp"
+#include "structure.hpp"
+
+namespace eamg {
+
+extern thread_local std::string g_last_error;
+
+struct Failure {
+  eamg_status code;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(eamg_status code, const std::string &msg) { throw Failure{code, msg}; }
+
+inline void hip_check(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) fail(EAMG_ERR_OOM, std::string(what) + ": out of device memory");
+  fail(EAMG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device allocations owned by a hierarchy; freed together.
+struct DevArena {
+  std::vector<void *> ptrs;
+  template <class T>
+  T *alloc(size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hip_check(hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+    ptrs.push_back(p);
+    return static_cast<T *>(p);
+  }
+  template <class T>
+  T *upload(const std::vector<T> &v, hipStream_t s) {
+    return upload(v.data(), v.size(), s);
+  }
+  template <class T>
+  T *upload(const T *p, size_t count, hipStream_t s) {
+    // setup-time upload from pageable memory: wait so the source may be freed on return
+    T *d = alloc<T>(count);
+    if (count) {
+      hip_check(hipMemcpyAsync(d, p, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+      hip_check(hipStreamSynchronize(s), "sync");
+    }
+    return d;
+  }
+  void release(void *p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(p);
+      ptrs.erase(it);
+    }
+  }
+  ~DevArena() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <class T>
+std::vector<T> download(const T *d, size_t count, hipStream_t s) {
+  std::vector<T> h(count);
+  if (count) hip_check(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s), "download");
+  hip_check(hipStreamSynchronize(s), "sync");
+  return h;
+}
+
+inline int pick_group(int64_t nnz, int rows) {
+  const double avg = rows ? double(nnz) / rows : 1.0;
+  int g = 4;
+  while (g < 64 && g < avg) g <<= 1;
+  return g;
+}
+
+// What one solve-phase launch streams: matrix blocks (each with its column index), block rows,
+// and distinct gathered block columns.
+struct LaunchShape {
+  double blocks = 0, rows = 0, uniq = 0;
+};
+
+enum LaunchKind { LK_GS_FWD, LK_GS_BWD, LK_RESID, LK_RECT, LK_RECT_ACC, LK_SPMV };
+
+// Algorithmic HBM bytes of a launch: every matrix block and index read once, every gathered
+// vector block once, row data (offsets, D^+ blocks, own vector entries) once; values of vs
+// bytes, K right-hand sides per vector entry.  br x bc is the block shape.
+//   GS_FWD: lower blocks + diagonal; row offset and diagonal index, D^+; b read, x and r written
+//   GS_BWD: whole rows; row offset and diagonal index, D^+; b read, x written
+//   RESID : blocks right of the diagonal; row offset and diagonal index; r read and written
+//   RECT  : y = M x (RECT_ACC: y += M x, y also read); SPMV: y = A x
+inline double launch_bytes(const LaunchShape &sh, LaunchKind kind, int br, int bc, double vs, int K) {
+  const double mat = sh.blocks * (br * bc * vs + 4.0);
+  const double gat = sh.uniq * bc * K * vs;
+  const double vec = br * K * vs;   // one row's vector entries
+  switch (kind) {
+    case LK_GS_FWD: return mat + gat + sh.rows * (8.0 + br * br * vs + 3.0 * vec);
+    case LK_GS_BWD: return mat + gat + sh.rows * (8.0 + br * br * vs + 2.0 * vec);
+    case LK_RESID: return mat + gat + sh.rows * (8.0 + 2.0 * vec);
+    case LK_RECT: return mat + gat + 4.0 * (sh.rows + 1) + sh.rows * vec;
+    case LK_RECT_ACC: return mat + gat + 4.0 * (sh.rows + 1) + 2.0 * sh.rows * vec;
+    case LK_SPMV: return mat + gat + 4.0 * (sh.rows + 1) + sh.rows * vec;
+  }
+  return 0.0;
+}
+
+struct Level {
+  int n = 0, bs = 0;
+  Pattern A;                 // natural pattern
+  int64_t *A_rp = nullptr;   // natural pattern on the device
+  int *A_col = nullptr;
+  double *A_val = nullptr;   // natural AoS values (n_blocks * bs * bs)
+  // coarsening products (levels above the coarsest)
+  std::vector<int> agg;
+  Pattern P;
+  int kc = 0;
+  double *P_val = nullptr;   // natural AoS values (nnz * bs * kc)
+  std::vector<int> color;    // natural
+  int ncolors = 0;
+  // colour-major solve layout
+  std::vector<int> perm, inv, color_ptr;
+  int *perm_d = nullptr;
+  SoaMat Am, Pm, Rm;
+  double *Dinv = nullptr;
+  int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
+  double *x = nullptr, *b = nullptr, *r = nullptr;
+  // what every launch streams (for the traffic model and the profiler)
+  std::vector<LaunchShape> sh_fwd, sh_bwd;   // per colour
+  LaunchShape sh_resid, sh_R, sh_P, sh_spmv;
+  // FP32 V-cycle: values in SoaMat::val32, D^+ and level vectors in float
+  float *Dinv32 = nullptr, *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
+};
+
+// Per-precision view of a level's V-cycle buffers.
+template <class T>
+struct LevelBufs {
+  const T *Dinv;
+  T *x, *b, *r;
+};
+template <class T>
+LevelBufs<T> bufs(Level &L);
+template <>
+inline LevelBufs<double> bufs<double>(Level &L) {
+  return {L.Dinv, L.x, L.b, L.r};
+}
+template <>
+inline LevelBufs<float> bufs<float>(Level &L) {
+  return {L.Dinv32, L.x32, L.b32, L.r32};
+}
+template <class T>
+const char *type_name();
+template <>
+inline const char *type_name<double>() {
+  return "double";
+}
+template <>
+inline const char *type_name<float>() {
+  return "float";
+}
+
+struct ProfRec {
+  std::string name;
+  double bytes;
+  int launches;
+  hipEvent_t a, b;
+};
+
+struct BatchWork;
+void destroy_batch(BatchWork *w);
+
+}  // namespace eamg
+
+struct eamg_hierarchy {
+  int dim = 0, k = 0, n0 = 0;
+  eamg_setup_params prm{};
+  std::vector<eamg::Level> lv;
+  eamg::DevArena arena;
+  double *Ainv = nullptr;
+  int nL = 0;                 // coarsest dofs
+  uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
+  double *part = nullptr, *scal = nullptr;
+  double *scal_h = nullptr;   // pinned
+  // profiler: events around every launch while enabled
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<eamg::ProfRec> prof;
+  // PCG iteration captured as a graph (V-cycle .. r.r and the scalar copy), replayed per iteration
+  hipStream_t cap_stream = nullptr;
+  // one graph per V-cycle precision: [0] FP64, [1] FP32
+  hipGraphExec_t g_iter[2] = {nullptr, nullptr};
+  bool graph_tried[2] = {false, false};
+  // block-panel (multi right-hand side) workspace, allocated by the first batched call
+  eamg::BatchWork *batch = nullptr;
+  ~eamg_hierarchy() {
+    eamg::destroy_batch(batch);
+    for (hipGraphExec_t g : g_iter)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (scal_h) (void)hipHostFree(scal_h);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace eamg {
+
+inline hipEvent_t next_event(eamg_hierarchy *h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "event");
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Run `f`, which enqueues `launches` back-to-back launches of one kernel; while profiling,
+// bracket them with one pair of events and record their algorithmic bytes.
+template <class F>
+void timed_n(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
+             int launches, hipStream_t s, F &&f) {
+  if (!h->prof_on) {
+    hip_check(f(), what);
+    return;
+  }
+  ProfRec r{name, bytes, launches, next_event(h), next_event(h)};
+  hip_check(hipEventRecord(r.a, s), "event");
+  hip_check(f(), what);
+  hip_check(hipEventRecord(r.b, s), "event");
+  h->prof.push_back(r);
+}
+
+template <class F>
+void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
+           hipStream_t s, F &&f) {
+  timed_n(h, what, name, bytes, 1, s, std::forward<F>(f));
+}
+
+inline std::string tname(const char *base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }
+inline std::string tname(const char *base, int a, int b) {
+  return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
+}
+
+inline void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
+  hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s), "copy");
+  hip_check(hipStreamSynchronize(s), "sync");
+}
+
+template <class F>
+eamg_status guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return EAMG_OK;
+  } catch (const Failure &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return EAMG_ERR_OOM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return EAMG_ERR_INVALID_ARG;
+  }
+}
+
+}  // namespace eamg

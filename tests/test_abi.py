@@ -104,3 +104,19 @@ def test_host_matching_matches_oracle_bit_for_bit(n, kind):
         assert np.array_equal(agg, ao)
         assert np.abs(cc - res.coarse_coords).max() <= 1e-15
         lev, vd = res.coarse_level, np.zeros(res.coarse_level.n, bool)
+
+
+def test_solve_entry_points_reject_null_hierarchy():
+    """Argument checks that run before any device work (no GPU needed)."""
+    import ctypes
+    L = E.lib()
+    sp = E.eamg_solve_params(1e-8, 10, 0, 1)
+    info = (E.eamg_solve_info * 2)()
+    buf = ctypes.c_void_p(16)
+    assert L.eamg_solve_batch(None, 2, buf, 8, buf, ctypes.byref(sp), None, info) == E.EAMG_ERR_INVALID_ARG
+    assert L.eamg_solve(None, buf, buf, ctypes.byref(sp), None, info) == E.EAMG_ERR_INVALID_ARG
+    assert L.eamg_vcycle(None, buf, buf, E.EAMG_PRECOND_VCYCLE, None) == E.EAMG_ERR_INVALID_ARG
+    v, it = ctypes.c_double(), ctypes.c_double()
+    assert L.eamg_traffic_model(None, 1, ctypes.byref(v), ctypes.byref(it)) == E.EAMG_ERR_INVALID_ARG
+    p = E.eamg_default_setup_params()
+    assert p.vcycle_fp32 == 0
