@@ -225,14 +225,15 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
 
 /*
  * Per-kernel timing, for measuring each kernel against its bandwidth roofline.  While enabled,
- * eamg_solve / eamg_vcycle launch eagerly (no graph) and every launch -- or run of back-to-back
- * launches of one kernel, such as the colours of one smoother sweep -- is bracketed by events on
- * the solve stream and its
- * algorithmic HBM bytes (matrix blocks and index arrays read once, vectors read or written
- * once, gathered vector entries counted once per launch) are recorded.  eamg_profile_read
- * synchronizes the device, aggregates the records by kernel name (the template instance, e.g.
- * "k_gs_bwd<6>"), sorts them by total time, copies up to max_entries of them into out,
- * stores the number of kernels in *n_out and clears the records.  Enabling resets them.
+ * eamg_solve / eamg_solve_batch / eamg_vcycle launch eagerly (no graph) and every launch -- or
+ * run of back-to-back launches of one kernel, such as the colours of one smoother sweep -- is
+ * bracketed by events on the solve stream and its algorithmic HBM bytes (matrix blocks and
+ * index arrays read once, vectors read or written once, gathered vector entries counted once
+ * per launch) are recorded.  eamg_profile_read synchronizes the device, aggregates the records
+ * by kernel name (the template instance, e.g. "k_gs_color<double, 6, false>"), sorts them by
+ * total time, copies up to max_entries of them into out, stores the number of kernels in
+ * *n_out and clears the records.  on: 0 off, 1 per kernel, 2 per kernel and level (V-cycle
+ * names prefixed "L<level> ").  Enabling resets the records.
  */
 typedef struct {
   char name[48];

@@ -396,7 +396,7 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   const std::string ty = type_name<T>();
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * double(sizeof(T));
-    timed(h, "coarsest", "k_dense_gemv<" + ty + ">", by, s,
+    timed(h, "coarsest", lvname(h, l, "k_dense_gemv<" + ty + ">"), by, s,
           [&] { return launch_dense_gemv<T>(h->nL, h->Ainv, b, x, s); });
     return;
   }
@@ -410,23 +410,23 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   }
   const std::string gs = "k_gs_color<" + ty + ", " + std::to_string(bs);
   // the colours of a sweep are back-to-back launches of one kernel: timed as one run
-  timed_n(h, "gs_fwd", gs + ", true>", fwd_bytes, L.ncolors, s, [&] {
+  timed_n(h, "gs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
     for (int c = 0; c < L.ncolors; ++c) {
       const hipError_t e = launch_gs_fwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
-  timed(h, "resid_upper", "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">",
+  timed(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
   Level &C = h->lv[l + 1];
   const LevelBufs<T> CB = bufs<T>(C);
-  timed(h, "restrict", "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">",
+  timed(h, "restrict", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_R, LK_RECT, L.kc, bs, vs, 1), s, [&] { return launch_rect<T>(L.Rm, B.r, CB.b, false, s); });
   vcycle_t<T>(h, l + 1, CB.b, CB.x, s);
-  timed(h, "prolong", "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">",
+  timed(h, "prolong", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1), s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
-  timed_n(h, "gs_bwd", gs + ", false>", bwd_bytes, L.ncolors, s, [&] {
+  timed_n(h, "gs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
       const hipError_t e = launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
       if (e != hipSuccess) return e;
@@ -955,6 +955,7 @@ eamg_status eamg_profile_enable(eamg_hierarchy *h, int32_t on) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
     h->prof_on = on != 0;
+    h->prof_levels = on == 2;
     h->prof.clear();
     h->ev_used = 0;
   });

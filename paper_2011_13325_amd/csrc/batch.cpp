@@ -108,7 +108,7 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   Level &L = h->lv[l];
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * K * vs;
-    timed(h, "coarsest", "k_pdense<" + ty + ">", by, s,
+    timed(h, "coarsest", lvname(h, l, "k_pdense<" + ty + ">"), by, s,
           [&] { return launch_pdense<T>(h->nL, K, h->Ainv, b, x, s); });
     return;
   }
@@ -121,26 +121,26 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
     bwd_bytes += launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, K);
   }
   const std::string gs = "k_pgs_color<" + ty + ", " + std::to_string(bs);
-  timed_n(h, "pgs_fwd", gs + ", true>", fwd_bytes, L.ncolors, s, [&] {
+  timed_n(h, "pgs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
     for (int c = 0; c < L.ncolors; ++c) {
       const hipError_t e = launch_pgs_fwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, R, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
-  timed(h, "presid_upper", "k_presid_upper<" + ty + ", " + std::to_string(bs) + ">",
+  timed(h, "presid_upper", lvname(h, l, "k_presid_upper<" + ty + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, K), s,
         [&] { return launch_presid_upper<T>(L.Am, K, x, R, s); });
   T *Cb = vp<T>(w->vb[pi][l + 1]);
   T *Cx = vp<T>(w->vx[pi][l + 1]);
-  timed(h, "prestrict", "k_prect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">",
+  timed(h, "prestrict", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_R, LK_RECT, L.kc, bs, vs, K), s,
         [&] { return launch_prect<T>(L.Rm, K, R, Cb, false, s); });
   pvcycle_t<T>(h, w, l + 1, Cb, Cx, s);
-  timed(h, "pprolong", "k_prect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">",
+  timed(h, "pprolong", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, K), s,
         [&] { return launch_prect<T>(L.Pm, K, Cx, x, true, s); });
-  timed_n(h, "pgs_bwd", gs + ", false>", bwd_bytes, L.ncolors, s, [&] {
+  timed_n(h, "pgs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
       const hipError_t e = launch_pgs_bwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s);
       if (e != hipSuccess) return e;

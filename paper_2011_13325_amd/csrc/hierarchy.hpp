@@ -192,6 +192,7 @@ struct eamg_hierarchy {
   double *scal_h = nullptr;   // pinned
   // profiler: events around every launch while enabled
   bool prof_on = false;
+  bool prof_levels = false;   // V-cycle records per level
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<eamg::ProfRec> prof;
@@ -243,6 +244,11 @@ template <class F>
 void timed(eamg_hierarchy *h, const char *what, const std::string &name, double bytes,
            hipStream_t s, F &&f) {
   timed_n(h, what, name, bytes, 1, s, std::forward<F>(f));
+}
+
+// Profiler name of a V-cycle launch on level l.
+inline std::string lvname(const eamg_hierarchy *h, size_t l, const std::string &name) {
+  return h->prof_levels ? "L" + std::to_string(l) + " " + name : name;
 }
 
 inline std::string tname(const char *base, int a) { return std::string(base) + "<" + std::to_string(a) + ">"; }

@@ -27,126 +27,275 @@ const float *pvals<float>(const SoaMat &M) {
   return M.val32;
 }
 
-// acc[r] += sum over blocks p in [p0, p1) of M_p X_col(p), column k.  The block's entries are
-// the same address for the K lanes of the team; the X loads are K-wide contiguous.
-template <class T, int BR, int BC>
-__device__ inline void pteam_accumulate(int p0, int p1, int k, int K, const int *__restrict__ col,
-                                        const T *__restrict__ val, int64_t nnz,
-                                        const T *__restrict__ x, T (&acc)[BR]) {
-#pragma unroll 2
-  for (int p = p0; p < p1; ++p) {
-    const int64_t c = col[p];
-    T xv[BC];
+// A block row belongs to a team of 64 W lanes (W = 1: one wavefront per row, four rows per
+// workgroup; W = 4: the whole workgroup on one row, for levels of few long rows).  A lane owns C
+// consecutive columns (register blocking: every matrix value it loads serves C columns, and the
+// C values of one dof are one vector load); the K / C lanes covering a panel form a sub-team,
+// and the S = 64 W C / K sub-teams of the team take the row's blocks in turn: sub-team s reads
+// blocks p0 + s, p0 + s + S, ...  At every step the S sub-teams read S consecutive blocks (the
+// same cache lines of every element plane), and the column index of a sub-team's next block is
+// fetched one step ahead, so a step waits for one round of gathers only.  The row sums of
+// column group g end in lane g of the team (sub-team 0).
+constexpr int kWave = 64;
+
+template <class T, int C>
+struct PVec {
+  T v[C];
+};
+
+// X entries of one dof for columns g C .. g C + C - 1 (C-aligned, contiguous).
+template <class T, int C>
+__device__ inline PVec<T, C> pload(const T *p) {
+  PVec<T, C> out;
+  if constexpr (C == 1) {
+    out.v[0] = p[0];
+  } else {
+    typedef T vec_t __attribute__((ext_vector_type(C)));
+    const vec_t w = *reinterpret_cast<const vec_t *>(p);
 #pragma unroll
-    for (int cc = 0; cc < BC; ++cc) xv[cc] = x[(c * BC + cc) * K + k];
+    for (int i = 0; i < C; ++i) out.v[i] = w[i];
+  }
+  return out;
+}
+
+template <class T, int C>
+__device__ inline void pstore(T *p, const T (&v)[C]) {
+  if constexpr (C == 1) {
+    p[0] = v[0];
+  } else {
+    typedef T vec_t __attribute__((ext_vector_type(C)));
+    vec_t w;
 #pragma unroll
-    for (int r = 0; r < BR; ++r)
-#pragma unroll
-      for (int cc = 0; cc < BC; ++cc) acc[r] = fma(val[int64_t(r * BC + cc) * nnz + p], xv[cc], acc[r]);
+    for (int i = 0; i < C; ++i) w[i] = v[i];
+    *reinterpret_cast<vec_t *>(p) = w;
   }
 }
 
+// Where a thread sits in a row team of 64 W lanes for K columns, C per lane.
+template <int C, int W>
+struct PTeam {
+  int row_in_wg;   // which of the kPB / (64 W) rows of the workgroup
+  int t;           // lane within the row team
+  int lg;          // log2(K / C)
+  int g;           // column group (columns g C .. g C + C - 1)
+  int s;           // sub-team
+  int S;           // sub-teams per row
+  __device__ PTeam(int K) {
+    row_in_wg = threadIdx.x / (kWave * W);
+    t = threadIdx.x % (kWave * W);
+    lg = __builtin_ctz(K / C);
+    g = t & ((K / C) - 1);
+    s = t >> lg;
+    S = (kWave * W) >> lg;
+  }
+  __device__ bool lead() const { return t < (1 << lg); }
+};
+
+// Column groups per sub-team are at most 64 / 4 (K <= 64 with C = 4 for K >= 4).
+constexpr int kMaxGroups = 16;
+
+// acc[r][i] = sum over blocks p in [p0, p1) of M_p X_col(p), column g C + i, in the lead lanes.
+// red: W > 1 only, kPB / (64 W) * W * kMaxGroups * BR * C values of LDS.
+template <class T, int BR, int BC, int C, int W>
+__device__ inline void pteam_accumulate(int p0, int p1, int K, const PTeam<C, W> &tm,
+                                        const int *__restrict__ col, const T *__restrict__ val,
+                                        int64_t nnz, const T *__restrict__ x, T (&acc)[BR][C],
+                                        T *red) {
+  int p = p0 + tm.s;
+  int cn = p < p1 ? col[p] : 0;
+  for (; p < p1; p += tm.S) {
+    const int64_t c = cn;
+    const int pn = p + tm.S;
+    cn = pn < p1 ? col[pn] : 0;
+    T a[BR * BC];
+#pragma unroll
+    for (int e = 0; e < BR * BC; ++e) a[e] = val[int64_t(e) * nnz + p];
+    PVec<T, C> xv[BC];
+#pragma unroll
+    for (int cc = 0; cc < BC; ++cc) xv[cc] = pload<T, C>(x + (c * BC + cc) * K + tm.g * C);
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int cc = 0; cc < BC; ++cc)
+#pragma unroll
+        for (int i = 0; i < C; ++i) acc[r][i] = fma(a[r * BC + cc], xv[cc].v[i], acc[r][i]);
+  }
+  // sub-teams of one wavefront: butterfly over the lane bits above the column group
+  for (int off = K / C; off < kWave; off <<= 1)
+#pragma unroll
+    for (int r = 0; r < BR; ++r)
+#pragma unroll
+      for (int i = 0; i < C; ++i) acc[r][i] += __shfl_xor(acc[r][i], off, kWave);
+  if constexpr (W > 1) {
+    // wavefronts of the team: through LDS, summed in wavefront order by the lead lanes
+    const int wv = tm.t / kWave, ln = tm.t % kWave;
+    T *rr = red + tm.row_in_wg * (W * kMaxGroups * BR * C);
+    if (ln < (K / C))
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int i = 0; i < C; ++i) rr[((wv * kMaxGroups + ln) * BR + r) * C + i] = acc[r][i];
+    __syncthreads();
+    if (tm.lead())
+#pragma unroll
+      for (int r = 0; r < BR; ++r)
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+          T v = rr[(tm.t * BR + r) * C + i];
+#pragma unroll
+          for (int w = 1; w < W; ++w) v += rr[((w * kMaxGroups + tm.t) * BR + r) * C + i];
+          acc[r][i] = v;
+        }
+  }
+}
+
+// LDS for the cross-wavefront reduction of a W = 4 team (one row per workgroup).
+template <class T, int BR, int C, int W>
+struct PRed {
+  static constexpr int n = W > 1 ? (kPB / (kWave * W)) * W * kMaxGroups * BR * C : 1;
+};
+
 // One colour of the symmetric block Gauss-Seidel sweep for K columns (see launch_pgs_fwd /
 // launch_pgs_bwd).  The row's D^+ block and right-hand side are loaded before the row's blocks
-// so their latency overlaps the block stream.
-template <class T, int B, bool FWD>
+// so their latency overlaps the block stream; the lead lanes finish the row.
+template <class T, int B, bool FWD, int C, int W>
 __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const int *__restrict__ rp,
                                                    const int *__restrict__ col,
                                                    const int *__restrict__ diag,
                                                    const T *__restrict__ val, int64_t nnz,
                                                    const T *__restrict__ Dinv,
                                                    const T *__restrict__ b, T *x, T *r) {
-  const int k = threadIdx.x & (K - 1);
-  const int row = r0 + blockIdx.x * (kPB / K) + threadIdx.x / K;
-  if (row >= r1) return;
+  __shared__ T red[PRed<T, B, C, W>::n];
+  const PTeam<C, W> tm(K);
+  const int row = r0 + blockIdx.x * (kPB / (kWave * W)) + tm.row_in_wg;
+  if (row >= r1) return;   // W = 4: the whole workgroup leaves together
   const int p0 = rp[row];
   const int dp = diag[row];
   const int p1 = FWD ? dp : rp[row + 1];
-  T bq[B], D[B][B];
+  PVec<T, C> bq[B];
+  T D[B][B];
+  const int64_t rb = int64_t(row) * B;
+  // every lane loads (valid addresses); only the lead lanes use them
 #pragma unroll
   for (int q = 0; q < B; ++q) {
-    bq[q] = b[(int64_t(row) * B + q) * K + k];
+    bq[q] = pload<T, C>(b + (rb + q) * K + tm.g * C);
 #pragma unroll
-    for (int c = 0; c < B; ++c) D[q][c] = Dinv[(int64_t(row) * B + q) * B + c];
+    for (int c = 0; c < B; ++c) D[q][c] = Dinv[(rb + q) * B + c];
   }
-  T acc[B];
+  T acc[B][C];
 #pragma unroll
-  for (int q = 0; q < B; ++q) acc[q] = T(0);
-  pteam_accumulate<T, B, B>(p0, p1, k, K, col, val, nnz, x, acc);
-  T t[B], xi[B];
+  for (int q = 0; q < B; ++q)
 #pragma unroll
-  for (int q = 0; q < B; ++q) t[q] = bq[q] - acc[q];
+    for (int i = 0; i < C; ++i) acc[q][i] = T(0);
+  pteam_accumulate<T, B, B, C, W>(p0, p1, K, tm, col, val, nnz, x, acc, red);
+  if (!tm.lead()) return;
+  // forward: the diagonal block, loaded after the row stream to keep registers for it
+  T Ad[B][B];
 #pragma unroll
-  for (int q = 0; q < B; ++q) {
-    T v = T(0);
+  for (int q = 0; q < B; ++q)
 #pragma unroll
-    for (int c = 0; c < B; ++c) v = fma(D[q][c], t[c], v);
-    xi[q] = v;
-  }
-  if (FWD) {
+    for (int c = 0; c < B; ++c) Ad[q][c] = FWD ? val[int64_t(q * B + c) * nnz + dp] : T(0);
+  T xo[B][C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    T t[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) t[q] = bq[q].v[i] - acc[q][i];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      T v = t[q];
+      T v = T(0);
 #pragma unroll
-      for (int c = 0; c < B; ++c) v = fma(-val[int64_t(q * B + c) * nnz + dp], xi[c], v);
-      x[(int64_t(row) * B + q) * K + k] = xi[q];
-      r[(int64_t(row) * B + q) * K + k] = v;
+      for (int c = 0; c < B; ++c) v = fma(D[q][c], t[c], v);
+      xo[q][i] = v;
     }
-  } else {
+    if (FWD) {
+      // r = t - A_ii x_i, kept in acc
 #pragma unroll
-    for (int q = 0; q < B; ++q) x[(int64_t(row) * B + q) * K + k] += xi[q];
+      for (int q = 0; q < B; ++q) {
+        T v = t[q];
+#pragma unroll
+        for (int c = 0; c < B; ++c) v = fma(-Ad[q][c], xo[c][i], v);
+        acc[q][i] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    T *xq = x + (rb + q) * K + tm.g * C;
+    if (FWD) {
+      pstore<T, C>(xq, xo[q]);
+      pstore<T, C>(r + (rb + q) * K + tm.g * C, acc[q]);
+    } else {
+      const PVec<T, C> old = pload<T, C>(xq);
+      T nv[C];
+#pragma unroll
+      for (int i = 0; i < C; ++i) nv[i] = old.v[i] + xo[q][i];
+      pstore<T, C>(xq, nv);
+    }
   }
 }
 
-template <class T, int B>
+template <class T, int B, int C, int W>
 __global__ __launch_bounds__(kPB) void k_presid_upper(int n_rows, int K, const int *__restrict__ rp,
                                                       const int *__restrict__ col,
                                                       const int *__restrict__ diag,
                                                       const T *__restrict__ val, int64_t nnz,
                                                       const T *__restrict__ x, T *__restrict__ r) {
-  const int k = threadIdx.x & (K - 1);
-  const int row = blockIdx.x * (kPB / K) + threadIdx.x / K;
+  __shared__ T red[PRed<T, B, C, W>::n];
+  const PTeam<C, W> tm(K);
+  const int row = blockIdx.x * (kPB / (kWave * W)) + tm.row_in_wg;
   if (row >= n_rows) return;
-  T rq[B], acc[B];
+  const int64_t rb = int64_t(row) * B;
+  PVec<T, C> rq[B];
+  T acc[B][C];
 #pragma unroll
   for (int q = 0; q < B; ++q) {
-    rq[q] = r[(int64_t(row) * B + q) * K + k];
-    acc[q] = T(0);
-  }
-  pteam_accumulate<T, B, B>(diag[row] + 1, rp[row + 1], k, K, col, val, nnz, x, acc);
+    rq[q] = pload<T, C>(r + (rb + q) * K + tm.g * C);
 #pragma unroll
-  for (int q = 0; q < B; ++q) r[(int64_t(row) * B + q) * K + k] = rq[q] - acc[q];
+    for (int i = 0; i < C; ++i) acc[q][i] = T(0);
+  }
+  pteam_accumulate<T, B, B, C, W>(diag[row] + 1, rp[row + 1], K, tm, col, val, nnz, x, acc, red);
+  if (!tm.lead()) return;
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    T v[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) v[i] = rq[q].v[i] - acc[q][i];
+    pstore<T, C>(r + (rb + q) * K + tm.g * C, v);
+  }
 }
 
-template <class T, int BR, int BC>
+template <class T, int BR, int BC, int C, int W>
 __global__ __launch_bounds__(kPB) void k_prect(int n_rows, int K, const int *__restrict__ rp,
                                                const int *__restrict__ col,
                                                const T *__restrict__ val, int64_t nnz,
                                                const T *__restrict__ x, T *__restrict__ y,
                                                int accumulate) {
-  const int k = threadIdx.x & (K - 1);
-  const int row = blockIdx.x * (kPB / K) + threadIdx.x / K;
+  __shared__ T red[PRed<T, BR, C, W>::n];
+  const PTeam<C, W> tm(K);
+  const int row = blockIdx.x * (kPB / (kWave * W)) + tm.row_in_wg;
   if (row >= n_rows) return;
-  T acc[BR];
+  T acc[BR][C];
 #pragma unroll
-  for (int q = 0; q < BR; ++q) acc[q] = accumulate ? y[(int64_t(row) * BR + q) * K + k] : T(0);
-  pteam_accumulate<T, BR, BC>(rp[row], rp[row + 1], k, K, col, val, nnz, x, acc);
+  for (int q = 0; q < BR; ++q)
 #pragma unroll
-  for (int q = 0; q < BR; ++q) y[(int64_t(row) * BR + q) * K + k] = acc[q];
-}
-
-// Y = D X: team of K lanes per row of D, FP64 accumulation.
-template <class T>
-__global__ __launch_bounds__(kPB) void k_pdense(int n, int K, const double *__restrict__ D,
-                                                const T *__restrict__ x, T *__restrict__ y) {
-  const int k = threadIdx.x & (K - 1);
-  const int row = blockIdx.x * (kPB / K) + threadIdx.x / K;
-  if (row >= n) return;
-  double acc = 0.0;
-  const double *Dr = D + int64_t(row) * n;
-#pragma unroll 4
-  for (int c = 0; c < n; ++c) acc = fma(Dr[c], double(x[int64_t(c) * K + k]), acc);
-  y[int64_t(row) * K + k] = T(acc);
+    for (int i = 0; i < C; ++i) acc[q][i] = T(0);
+  pteam_accumulate<T, BR, BC, C, W>(rp[row], rp[row + 1], K, tm, col, val, nnz, x, acc, red);
+  if (!tm.lead()) return;
+#pragma unroll
+  for (int q = 0; q < BR; ++q) {
+    T *yq = y + (int64_t(row) * BR + q) * K + tm.g * C;
+    T v[C];
+    if (accumulate) {
+      const PVec<T, C> old = pload<T, C>(yq);
+#pragma unroll
+      for (int i = 0; i < C; ++i) v[i] = old.v[i] + acc[q][i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < C; ++i) v[i] = acc[q][i];
+    }
+    pstore<T, C>(yq, v);
+  }
 }
 
 // Reduce v over the threads of a workgroup that share t mod K; the sums end in threads t < K.
@@ -160,31 +309,73 @@ __device__ inline double pcol_sum(double v, int K, double *sh) {
   return sh[threadIdx.x];
 }
 
-template <int B>
+// Y = D X: one workgroup per row of D; thread t = s * K + k sums columns c = s (mod 256 / K)
+// of D row times X column k, FP64 accumulation.
+template <class T>
+__global__ __launch_bounds__(kPB) void k_pdense(int n, int K, const double *__restrict__ D,
+                                                const T *__restrict__ x, T *__restrict__ y) {
+  __shared__ double sh[kPB];
+  const int k = threadIdx.x & (K - 1);
+  const int S = kPB / K;
+  const int row = blockIdx.x;
+  const double *Dr = D + int64_t(row) * n;
+  double acc = 0.0;
+  for (int c = threadIdx.x / K; c < n; c += S) acc = fma(Dr[c], double(x[int64_t(c) * K + k]), acc);
+  const double t = pcol_sum(acc, K, sh);
+  if (int(threadIdx.x) < K) y[int64_t(row) * K + k] = T(t);
+}
+
+// Y = A X (W = 1 teams), the workgroups striding over groups of four rows so that the
+// per-column partial sums of X.Y come in at most kPSpmvMax workgroups.
+constexpr int kPSpmvMax = 2048;
+
+template <int B, int C>
 __global__ __launch_bounds__(kPB) void k_pspmv(int n_rows, int K, const int *__restrict__ rp,
                                                const int *__restrict__ col,
                                                const double *__restrict__ val, int64_t nnz,
                                                const double *__restrict__ x, double *__restrict__ y,
                                                double *part) {
-  __shared__ double sh[kPB];
-  const int k = threadIdx.x & (K - 1);
-  const int row = blockIdx.x * (kPB / K) + threadIdx.x / K;
-  double d = 0.0;
-  if (row < n_rows) {
-    double acc[B];
+  __shared__ double sh[kPB][C];
+  const PTeam<C, 1> tm(K);
+  constexpr int rows_pb = kPB / kWave;
+  double d[C];
 #pragma unroll
-    for (int q = 0; q < B; ++q) acc[q] = 0.0;
-    pteam_accumulate<double, B, B>(rp[row], rp[row + 1], k, K, col, val, nnz, x, acc);
+  for (int i = 0; i < C; ++i) d[i] = 0.0;
+  for (int row0 = blockIdx.x * rows_pb; row0 < n_rows; row0 += gridDim.x * rows_pb) {
+    const int row = row0 + tm.row_in_wg;
+    if (row >= n_rows) continue;   // whole wavefronts; no workgroup barrier inside
+    double acc[B][C];
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-      const int64_t e = (int64_t(row) * B + q) * K + k;
-      y[e] = acc[q];
-      d = fma(x[e], acc[q], d);
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int i = 0; i < C; ++i) acc[q][i] = 0.0;
+    pteam_accumulate<double, B, B, C, 1>(rp[row], rp[row + 1], K, tm, col, val, nnz, x, acc, nullptr);
+    if (tm.lead()) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int64_t e = (int64_t(row) * B + q) * K + tm.g * C;
+        const PVec<double, C> xv = pload<double, C>(x + e);
+        pstore<double, C>(y + e, acc[q]);
+#pragma unroll
+        for (int i = 0; i < C; ++i) d[i] = fma(xv.v[i], acc[q][i], d[i]);
+      }
     }
   }
   if (part) {
-    const double s = pcol_sum(d, K, sh);
-    if (int(threadIdx.x) < K) part[int64_t(blockIdx.x) * K + threadIdx.x] = s;
+    // per-column sums over the workgroup: thread t holds columns (t mod (K / C)) C + i
+#pragma unroll
+    for (int i = 0; i < C; ++i) sh[threadIdx.x][i] = tm.lead() ? d[i] : 0.0;
+    __syncthreads();
+    const int KL = K / C;
+    for (int st = kPB / 2; st >= KL; st >>= 1) {
+      if (int(threadIdx.x) < st)
+#pragma unroll
+        for (int i = 0; i < C; ++i) sh[threadIdx.x][i] += sh[threadIdx.x + st][i];
+      __syncthreads();
+    }
+    if (int(threadIdx.x) < KL)
+#pragma unroll
+      for (int i = 0; i < C; ++i) part[int64_t(blockIdx.x) * K + threadIdx.x * C + i] = sh[threadIdx.x][i];
   }
 }
 
@@ -353,37 +544,59 @@ bool valid_k(int K) { return K >= 1 && K <= 64 && (K & (K - 1)) == 0; }
 
 #define EAMG_PCHECK() return hipGetLastError()
 
-template <class T>
-hipError_t launch_pgs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
-                          T *r, hipStream_t s) {
+// Columns per lane: 4 when the panel is at least 4 wide.
+inline int pcols(int K) { return K >= 4 ? 4 : K; }
+
+// Team width: a whole workgroup per row when its 64 * 4 * C / K sub-teams still find a block
+// each in an average row, else one wavefront per row.
+inline int pwaves(const SoaMat &M, int K) {
+  const double avg = M.n_rows ? double(M.nnz) / M.n_rows : 0.0;
+  return (kWave * 4.0 * pcols(K) / K <= avg) ? 4 : 1;
+}
+
+inline unsigned pteam_grid(int rows, int W) { return pgrid(rows, kPB / (kWave * W)); }
+
+#define EAMG_PCOLS(C_, ...)                                     \
+  switch (pcols(K)) {                                           \
+    case 1: { constexpr int C_ = 1; __VA_ARGS__; } break;       \
+    case 2: { constexpr int C_ = 2; __VA_ARGS__; } break;       \
+    default: { constexpr int C_ = 4; __VA_ARGS__; } break;      \
+  }
+#define EAMG_PTEAM(W_, M_, ...)                                 \
+  if (pwaves(M_, K) == 4) { constexpr int W_ = 4; __VA_ARGS__; } \
+  else { constexpr int W_ = 1; __VA_ARGS__; }
+
+template <class T, bool FWD>
+hipError_t launch_pgs(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x, T *r,
+                      hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
   const T *val = pvals<T>(A);
   if (!val || !valid_k(K) || !A.diag) return hipErrorInvalidValue;
-  const dim3 grid(pgrid(r1 - r0, kPB / K));
+#define EAMG_PGS(B_)                                                                                \
+  EAMG_PTEAM(W, A, EAMG_PCOLS(C, hipLaunchKernelGGL((k_pgs_color<T, B_, FWD, C, W>),               \
+                                                    dim3(pteam_grid(r1 - r0, W)), dim3(kPB), 0, s, \
+                                                    r0, r1, K, A.rp, A.col, A.diag, val, A.nnz,    \
+                                                    Dinv, b, x, r)))
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_pgs_color<T, 1, true>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
-    case 3: hipLaunchKernelGGL((k_pgs_color<T, 3, true>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
-    case 6: hipLaunchKernelGGL((k_pgs_color<T, 6, true>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
+    case 1: EAMG_PGS(1); break;
+    case 3: EAMG_PGS(3); break;
+    case 6: EAMG_PGS(6); break;
     default: return hipErrorInvalidValue;
   }
+#undef EAMG_PGS
   EAMG_PCHECK();
+}
+
+template <class T>
+hipError_t launch_pgs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
+                          T *r, hipStream_t s) {
+  return launch_pgs<T, true>(A, Dinv, r0, r1, K, b, x, r, s);
 }
 
 template <class T>
 hipError_t launch_pgs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
                           hipStream_t s) {
-  if (r1 <= r0) return hipSuccess;
-  const T *val = pvals<T>(A);
-  if (!val || !valid_k(K) || !A.diag) return hipErrorInvalidValue;
-  const dim3 grid(pgrid(r1 - r0, kPB / K));
-  T *none = nullptr;
-  switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_pgs_color<T, 1, false>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
-    case 3: hipLaunchKernelGGL((k_pgs_color<T, 3, false>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
-    case 6: hipLaunchKernelGGL((k_pgs_color<T, 6, false>), grid, dim3(kPB), 0, s, r0, r1, K, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
-    default: return hipErrorInvalidValue;
-  }
-  EAMG_PCHECK();
+  return launch_pgs<T, false>(A, Dinv, r0, r1, K, b, x, nullptr, s);
 }
 
 template <class T>
@@ -391,13 +604,18 @@ hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStre
   if (A.n_rows == 0) return hipSuccess;
   const T *val = pvals<T>(A);
   if (!val || !valid_k(K) || !A.diag) return hipErrorInvalidValue;
-  const dim3 grid(pgrid(A.n_rows, kPB / K));
+#define EAMG_PRES(B_)                                                                             \
+  EAMG_PTEAM(W, A, EAMG_PCOLS(C, hipLaunchKernelGGL((k_presid_upper<T, B_, C, W>),               \
+                                                    dim3(pteam_grid(A.n_rows, W)), dim3(kPB), 0, \
+                                                    s, A.n_rows, K, A.rp, A.col, A.diag, val,    \
+                                                    A.nnz, x, r)))
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_presid_upper<T, 1>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
-    case 3: hipLaunchKernelGGL((k_presid_upper<T, 3>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
-    case 6: hipLaunchKernelGGL((k_presid_upper<T, 6>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
+    case 1: EAMG_PRES(1); break;
+    case 3: EAMG_PRES(3); break;
+    case 6: EAMG_PRES(6); break;
     default: return hipErrorInvalidValue;
   }
+#undef EAMG_PRES
   EAMG_PCHECK();
 }
 
@@ -406,15 +624,16 @@ hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulat
   if (M.n_rows == 0) return hipSuccess;
   const T *val = pvals<T>(M);
   if (!val || !valid_k(K)) return hipErrorInvalidValue;
-  const dim3 grid(pgrid(M.n_rows, kPB / K));
   const int accf = accumulate ? 1 : 0;
-#define EAMG_PRECT(BR_, BC_)                                                                   \
-  hipLaunchKernelGGL((k_prect<T, BR_, BC_>), grid, dim3(kPB), 0, s, M.n_rows, K, M.rp, M.col, \
-                     val, M.nnz, x, y, accf)
-  if (M.br == 1 && M.bc == 1) EAMG_PRECT(1, 1);
-  else if (M.br == 3 && M.bc == 6) EAMG_PRECT(3, 6);
-  else if (M.br == 6 && M.bc == 3) EAMG_PRECT(6, 3);
-  else if (M.br == 6 && M.bc == 6) EAMG_PRECT(6, 6);
+#define EAMG_PRECT(BR_, BC_)                                                                      \
+  EAMG_PTEAM(W, M, EAMG_PCOLS(C, hipLaunchKernelGGL((k_prect<T, BR_, BC_, C, W>),                \
+                                                    dim3(pteam_grid(M.n_rows, W)), dim3(kPB), 0, \
+                                                    s, M.n_rows, K, M.rp, M.col, val, M.nnz, x,  \
+                                                    y, accf)))
+  if (M.br == 1 && M.bc == 1) { EAMG_PRECT(1, 1); }
+  else if (M.br == 3 && M.bc == 6) { EAMG_PRECT(3, 6); }
+  else if (M.br == 6 && M.bc == 3) { EAMG_PRECT(6, 3); }
+  else if (M.br == 6 && M.bc == 6) { EAMG_PRECT(6, 6); }
   else return hipErrorInvalidValue;
 #undef EAMG_PRECT
   EAMG_PCHECK();
@@ -424,21 +643,24 @@ template <class T>
 hipError_t launch_pdense(int n, int K, const double *D, const T *x, T *y, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (!valid_k(K)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pdense<T>, dim3(pgrid(n, kPB / K)), dim3(kPB), 0, s, n, K, D, x, y);
+  hipLaunchKernelGGL(k_pdense<T>, dim3(n), dim3(kPB), 0, s, n, K, D, x, y);
   EAMG_PCHECK();
 }
 
-int pspmv_blocks(const SoaMat &A, int K) { return int(pgrid(A.n_rows, kPB / K)); }
+int pspmv_blocks(const SoaMat &A, int K) {
+  const int g = K > 0 ? int(pgrid(A.n_rows, kPB / kWave)) : 0;
+  return g < kPSpmvMax ? (g < 1 ? 1 : g) : kPSpmvMax;
+}
 
 hipError_t launch_pspmv(const SoaMat &A, int K, const double *x, double *y, double *part,
                         hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
   if (!valid_k(K) || A.br != A.bc) return hipErrorInvalidValue;
-  const dim3 grid(pgrid(A.n_rows, kPB / K));
+  const dim3 grid(pspmv_blocks(A, K));
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_pspmv<1>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part); break;
-    case 3: hipLaunchKernelGGL((k_pspmv<3>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part); break;
-    case 6: hipLaunchKernelGGL((k_pspmv<6>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part); break;
+    case 1: EAMG_PCOLS(C, hipLaunchKernelGGL((k_pspmv<1, C>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part)); break;
+    case 3: EAMG_PCOLS(C, hipLaunchKernelGGL((k_pspmv<3, C>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part)); break;
+    case 6: EAMG_PCOLS(C, hipLaunchKernelGGL((k_pspmv<6, C>), grid, dim3(kPB), 0, s, A.n_rows, K, A.rp, A.col, A.val, A.nnz, x, y, part)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_PCHECK();

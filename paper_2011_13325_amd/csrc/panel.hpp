@@ -1,11 +1,13 @@
 // Launchers of the block-panel (multi right-hand side) kernels (panel.hip).
 //
 // A panel holds K right-hand sides of one level interleaved: entry (dof d, column k) of a panel
-// vector lives at v[d * K + k], so the K values of one dof are contiguous.  Every matrix kernel
-// gives one block row to a team of K lanes, lane k computing column k: the matrix blocks are
-// read once per team (all lanes of a team load the same address) and reused for all K
-// columns, while the gathered vector entries are K-wide coalesced loads.  K is a power of two
-// in [1, 64]; teams never communicate, so the columns stay independent in every kernel.
+// vector lives at v[d * K + k], so the K values of one dof are contiguous.  Every sparse matrix
+// kernel gives one block row to a wavefront: 64 / K sub-teams of K lanes share out the row's
+// blocks, lane k of a sub-team computing column k, and a shuffle reduction adds the sub-teams'
+// sums.  A matrix block is read once per sub-team (its K lanes load the same address) and
+// reused for all K columns; the gathered vector entries are K-wide contiguous loads.  K is a
+// power of two in [1, 64]; lanes of different columns never combine values, so the columns
+// stay independent in every kernel.
 //
 // Matrices are the SoaMat element planes of the single-vector path (kernels.hpp), with rows
 // in the level's colour-major order.  All pointers are device pointers; every launcher
