@@ -8,13 +8,14 @@ multicolour block Gauss-Seidel sweep pre / post; PCG to ||r|| <= 1e-8 ||b||.
 A step is one PCG solve to 1e-8 (V-cycle + CG kernels) on the hierarchy, with b resident in
 HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerkin / D^+ /
 coarsest factor) is timed separately and reported in the same line.  The same solve with the
-FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle".
+FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle", and the
+batched block-panel solve of 32 seeded load cases on the same hierarchy (FP64 and FP32 V-cycle)
+as "batched".
 
 Prints ONE JSON line.
 """
 import argparse
 import json
-import os
 import sys
 import time
 
@@ -29,34 +30,34 @@ def _args():
     ap.add_argument("--n", type=int, default=64, help="vertices per cube side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=17, help="cube side of the oracle sample")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="right-hand sides of the batched block-panel solve (0: skip)")
     return ap.parse_args()
 
 
 def cpu_baseline(n):
-    """The CPU oracle (FP64 NumPy/SciPy, one process) on a bounded sample: setup and PCG solve
-    to 1e-8 on an n^3 cube of the same problem family; the solve is timed."""
+    """The CPU oracle (FP64 NumPy/SciPy, one process, BLAS limited to one thread) on a bounded
+    sample: setup and PCG solve to 1e-8 on an n^3 cube of the same problem family; the solve
+    is timed."""
+    from threadpoolctl import threadpool_limits
+
     import oracle
     from gen import make_problem
     p = make_problem(n, seed=1)
-    t0 = time.perf_counter()
-    h = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
-    t_setup = time.perf_counter() - t0
-    times = []
-    for _ in range(3):
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        x, it, rel, rel_true, conv = oracle.pcg(h, p.b, rtol=1e-8)
-        times.append(time.perf_counter() - t0)
+        h = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
+        t_setup = time.perf_counter() - t0
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            x, it, rel, rel_true, conv = oracle.pcg(h, p.b, rtol=1e-8)
+            times.append(time.perf_counter() - t0)
     t = float(np.median(times))
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": p.n_free_dofs / t, "unit": "dofs/s", "cores": min(cores, threads),
-            "kind": "oracle",
+    return {"value": p.n_free_dofs / t, "unit": "dofs/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle setup ({t_setup:.1f} s) + PCG to 1e-8 ({it} its, median of 3: "
                       f"{t:.2f} s) on the {n}^3-vertex cube ({p.n_free_dofs} free dofs) of the "
-                      f"same elasticity problem"}
+                      f"same elasticity problem, one thread"}
 
 
 def _timed_solves(E, torch, hier, b, x, stream, steps, warmup, precond):
@@ -96,6 +97,47 @@ def _profiled(E, hier, b, x, steps, precond):
              "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9 if k["total_ms"] else None}
             for k in kstats[:12]]
     return roof, kern
+
+
+def _batch_rhs(p, m):
+    """m seeded load cases (case c from default_rng([4, c])), uniform[-1, 1], Dirichlet dofs 0."""
+    B = np.stack([np.random.default_rng([4, c]).uniform(-1.0, 1.0, p.n_dofs) for c in range(m)])
+    B[:, np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    return B
+
+
+def _batched(E, torch, hier, p, m, steps, warmup):
+    """Batched block-panel solves of m right-hand sides, FP64 and FP32 V-cycle."""
+    B = torch.tensor(_batch_rhs(p, m), device="cuda")
+    X = torch.zeros_like(B)
+    out = {"rhs": m}
+    for prec, key in ((E.EAMG_PRECOND_VCYCLE, "fp64_vcycle"), (E.EAMG_PRECOND_VCYCLE_FP32, "fp32_vcycle")):
+        for _ in range(warmup):
+            hier.solve_batch(B, X, precond=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, st, infos = hier.solve_batch(B, X, precond=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        assert st == E.EAMG_OK and max(i["rel_res_true"] for i in infos) <= 1e-8, st
+        E.eamg_profile_enable(hier.h, True)
+        hier.solve_batch(B, X, precond=prec)
+        ks = E.eamg_profile_read(hier.h)
+        E.eamg_profile_enable(hier.h, False)
+        dom = ks[0]
+        ach = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
+        its = [i["iterations"] for i in infos]
+        out[key] = {"ms_per_batch_solve": ms, "value": p.n_free_dofs * m / (ms / 1e3),
+                    "unit": "dofs*rhs/s", "iterations_min_max": [min(its), max(its)],
+                    "max_rel_res_true": max(i["rel_res_true"] for i in infos),
+                    "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
+                                 "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
+                                 "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3},
+                    "kernels": [{"name": k["name"], "ms_per_solve": k["total_ms"],
+                                 "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9}
+                                for k in ks[:6]]}
+    return out
 
 
 def main():
@@ -156,6 +198,10 @@ def main():
         "model_bytes_per_iteration": itbytes32,
         "model_GBps_whole_solve": itbytes32 * info32["iterations"] / (ms32 / 1e3) / 1e9,
         "roofline": roof32, "kernels": kern32[:8]}
+    if args.batch > 0:
+        out["batched"] = _batched(E, torch, hier, p, args.batch, args.steps, args.warmup)
+        out["batched"]["speedup_per_rhs_vs_single_fp64"] = {
+            k: out["batched"][k]["value"] / value for k in ("fp64_vcycle", "fp32_vcycle")}
     levels = []
     for l in range(st["n_levels"]):
         li = E.eamg_level_info_get(hier.h, l)
