@@ -183,6 +183,9 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
   M.bc = bc;
   M.nnz = Pp.nnz();
   M.group = pick_group(M.nnz, M.n_rows);
+  // long rows of a square level matrix: one row per workgroup, so that a row is one round of
+  // loads (at most one block per lane) instead of a loop over its blocks
+  if (diag_out && M.n_rows > 0 && double(M.nnz) / M.n_rows > kWideRowBlocks) M.group = kBlock;
   M.rp = ar.upload(to_i32(Pp.rp), s);
   M.col = ar.upload(Pp.col, s);
   int64_t *src_d = ar.upload(src, s);

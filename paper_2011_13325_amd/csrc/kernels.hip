@@ -12,7 +12,6 @@ namespace eamg {
 
 namespace {
 
-constexpr int kBlock = 256;
 
 inline int cdiv64(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
@@ -318,6 +317,24 @@ __device__ inline void group_reduce(T (&acc)[BR], int G) {
     for (int r = 0; r < BR; ++r) acc[r] += __shfl_xor(acc[r], off, G);
 }
 
+// A row team of a whole workgroup (kBlock lanes, "wide"): butterfly within each wavefront,
+// then the four wavefront sums added in wavefront order through LDS; every lane gets the total.
+template <class T, int BR>
+__device__ inline void wide_reduce(T (&acc)[BR], T *sh) {
+  group_reduce<T, BR>(acc, 64);
+  const int wv = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int r = 0; r < BR; ++r) sh[wv * BR + r] = acc[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < BR; ++r) {
+    T v = sh[r];
+    for (int w = 1; w < kBlock / 64; ++w) v += sh[w * BR + r];
+    acc[r] = v;
+  }
+}
+
 // acc[r] += sum over blocks p in [p0, p1) (strided by G) of A_p x_col(p)
 template <class T, int BR, int BC>
 __device__ inline void row_accumulate(int p0, int p1, int lane, int G, const int *__restrict__ col,
@@ -377,11 +394,11 @@ __device__ inline T pick(const T (&v)[B], int i) {
 // Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
 // together with the row's blocks, so a row costs one round of row loads plus the x gathers;
 // a butterfly all-reduce leaves the row sum on every lane.
-template <class T, int B, bool FWD>
+template <class T, int B, bool FWD, bool WIDE>
 __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                               const int *__restrict__ col, const int *__restrict__ diag,
                               const T *__restrict__ val, int64_t nnz, const T *__restrict__ Dinv,
-                              const T *__restrict__ b, T *x, T *r) {
+                              const T *__restrict__ b, T *x, T *r, T *sh) {
   const bool own = valid && lane < B;
   int p0 = 0, p1 = 0;
   int64_t dp = 0;
@@ -408,18 +425,23 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 #pragma unroll
   for (int q = 0; q < B; ++q) acc[q] = T(0);
   if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  group_reduce<T, B>(acc, G);
+  if (WIDE)
+    wide_reduce<T, B>(acc, sh);
+  else
+    group_reduce<T, B>(acc, G);
+  // wide teams: the owning lanes (< B) are in wavefront 0; shuffles stay within wavefronts
+  const int GS = WIDE ? 64 : G;
   const T tq = bq - pick<T, B>(acc, lane);   // t component of this lane (lanes < B)
   T t[B];
 #pragma unroll
-  for (int c = 0; c < B; ++c) t[c] = __shfl(tq, c, G);
+  for (int c = 0; c < B; ++c) t[c] = __shfl(tq, c, GS);
   T xq = T(0);
 #pragma unroll
   for (int c = 0; c < B; ++c) xq = fma(Dq[c], t[c], xq);
   if (FWD) {
     T xi[B];
 #pragma unroll
-    for (int c = 0; c < B; ++c) xi[c] = __shfl(xq, c, G);
+    for (int c = 0; c < B; ++c) xi[c] = __shfl(xq, c, GS);
     T rq = tq;
 #pragma unroll
     for (int c = 0; c < B; ++c) rq = fma(-Aq[c], xi[c], rq);
@@ -433,10 +455,10 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 }
 
 // r_i -= sum_{j > i} A_ij x_j for one row.
-template <class T, int B>
+template <class T, int B, bool WIDE>
 __device__ inline void resid_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                                  const int *__restrict__ col, const int *__restrict__ diag,
-                                 const T *__restrict__ val, int64_t nnz, const T *x, T *r) {
+                                 const T *__restrict__ val, int64_t nnz, const T *x, T *r, T *sh) {
   T rq = T(0);
   int p0 = 0, p1 = 0;
   if (valid) {
@@ -448,32 +470,38 @@ __device__ inline void resid_row(int row, bool valid, int lane, int G, const int
 #pragma unroll
   for (int a = 0; a < B; ++a) acc[a] = T(0);
   if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  group_reduce<T, B>(acc, G);
+  if (WIDE)
+    wide_reduce<T, B>(acc, sh);
+  else
+    group_reduce<T, B>(acc, G);
   if (valid && lane < B) r[int64_t(row) * B + lane] = rq - pick<T, B>(acc, lane);
 }
 
-// One colour (rows [r0, r1)) per launch.
-template <class T, int B, bool FWD>
+// One colour (rows [r0, r1)) per launch.  G = kBlock: one row per workgroup ("wide"), for
+// levels whose rows are long; else kBlock / G rows per workgroup.
+template <class T, int B, bool FWD, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ diag,
                                                     const T *__restrict__ val, int64_t nnz,
                                                     const T *__restrict__ Dinv,
                                                     const T *__restrict__ b, T *x, T *r) {
+  __shared__ T sh[WIDE ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  gs_row<T, B, FWD>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r);
+  gs_row<T, B, FWD, WIDE>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r, sh);
 }
 
-template <class T, int B>
+template <class T, int B, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_resid_upper(int n_rows, int G, const int *__restrict__ rp,
                                                        const int *__restrict__ col,
                                                        const int *__restrict__ diag,
                                                        const T *__restrict__ val, int64_t nnz,
                                                        const T *x, T *r) {
+  __shared__ T sh[WIDE ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  resid_row<T, B>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r);
+  resid_row<T, B, WIDE>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r, sh);
 }
 
 template <class T, int BR, int BC>
@@ -720,9 +748,9 @@ hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_gs_color<T, 1, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
-    case 3: hipLaunchKernelGGL((k_gs_color<T, 3, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
-    case 6: hipLaunchKernelGGL((k_gs_color<T, 6, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r); break;
+    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 1, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 1, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
+    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 3, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 3, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
+    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 6, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 6, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -737,9 +765,9 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   T *none = nullptr;
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_gs_color<T, 1, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
-    case 3: hipLaunchKernelGGL((k_gs_color<T, 3, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
-    case 6: hipLaunchKernelGGL((k_gs_color<T, 6, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none); break;
+    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 1, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 1, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
+    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 3, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 3, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
+    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 6, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 6, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -752,9 +780,9 @@ hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s) 
   if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(A.n_rows, groups_for(A.group)));
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_resid_upper<T, 1>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
-    case 3: hipLaunchKernelGGL((k_resid_upper<T, 3>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
-    case 6: hipLaunchKernelGGL((k_resid_upper<T, 6>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r); break;
+    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 1, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 1, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
+    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 3, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 3, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
+    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 6, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 6, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();

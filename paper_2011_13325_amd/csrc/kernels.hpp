@@ -62,7 +62,12 @@ hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in,
                               hipStream_t s);
 
 // ---- solve -------------------------------------------------------------------------------
+constexpr int kBlock = 256;          // threads per workgroup of the solve kernels
+constexpr double kWideRowBlocks = 96; // square matrices with longer average rows: group = kBlock
+
 struct SoaMat {
+  // group: lanes per row (a power of two <= 64), or kBlock for one row per workgroup
+  // (square matrices with diag only)
   int n_rows = 0, n_cols = 0, br = 0, bc = 0, group = 16;
   int64_t nnz = 0;
   const int *rp = nullptr;   // int32 row offsets (nnz < 2^31 for one level)
