@@ -3,6 +3,7 @@
 #include "coarsen.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -652,8 +653,6 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   const double sigma = prm.sigma;
   MatchResult res;
   PhaseTimer tm;
-  double t_mub = 0.0, t_mug = 0.0;
-  long n_mub = 0, n_mug = 0;
   auto note = [&](double mu) {
     if (std::isfinite(mu)) res.min_margin = std::min(res.min_margin, std::fabs(mu - sigma) / sigma);
   };
@@ -686,70 +685,110 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   std::vector<std::vector<int>> entries;
   std::vector<double> mtr;
   std::vector<int> pos;
-  std::vector<std::pair<int, double>> cands;
+  // Optimistic parallel walks.  mu_b and mu_g of a pair are functions of this pass's level data
+  // only.  A walk that meets a pair whose criteria are not known yet records it and assumes it
+  // passes; all pairs recorded by a walk are then evaluated in parallel and the walk is repeated,
+  // until one walk needs no unknown pair.  That walk used exact criteria only, so it is the
+  // sequential algorithm's walk, bit for bit.
+  struct Crit {
+    double mub, mug;   // mug NaN when not needed (mub >= sigma or a pair of single vertices)
+  };
+  std::unordered_map<int64_t, Crit> known;
   for (int p = 1; p <= prm.rounds; ++p) {
     pos.assign(size_t(work->n), 0);
     for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
     trace_strength(*work, mtr);
+    known.clear();
+    const int64_t nw = work->n;
+    auto key = [nw](int ci, int cj) { return int64_t(ci) * nw + cj; };
     std::vector<std::pair<int, int>> pairs;
     std::vector<int> singles;
-    for (int ci : order) {
-      if (!in_T[ci]) continue;
-      in_T[ci] = 0;
-      cands.clear();
-      for (int64_t q = work->nb_ptr[ci]; q < work->nb_ptr[ci + 1]; ++q) {
-        const int cj = work->nb[q];
-        if (!in_T[cj]) continue;
-        const double ms = mu_s(*work, ci, cj, mtr);
-        note(ms);
-        if (ms < sigma) cands.emplace_back(cj, ms);
-      }
-      int matched = -1;
-      while (!cands.empty()) {
-        double mmin = cands[0].second;
-        for (const auto &c : cands) mmin = std::min(mmin, c.second);
-        int best = -1, ntie = 0;
-        for (size_t c = 0; c < cands.size(); ++c)
-          if (cands[c].second <= mmin * (1.0 + prm.tie_rtol)) {
-            ++ntie;
-            if (best < 0 || pos[cands[c].first] < pos[cands[best].first]) best = int(c);
+    std::vector<std::pair<int, int>> unknown;
+    int walks = 0;
+    long n_eval = 0;
+    for (;;) {
+      ++walks;
+      pairs.clear();
+      singles.clear();
+      unknown.clear();
+      MatchResult notes;   // margins and ties of this walk
+      auto note_w = [&](double mu) {
+        if (std::isfinite(mu)) notes.min_margin = std::min(notes.min_margin, std::fabs(mu - sigma) / sigma);
+      };
+      std::vector<char> inT = in_T;
+      std::vector<std::pair<int, double>> cands;
+      for (int ci : order) {
+        if (!inT[ci]) continue;
+        inT[ci] = 0;
+        cands.clear();
+        for (int64_t q = work->nb_ptr[ci]; q < work->nb_ptr[ci + 1]; ++q) {
+          const int cj = work->nb[q];
+          if (!inT[cj]) continue;
+          const double ms = mu_s(*work, ci, cj, mtr);
+          note_w(ms);
+          if (ms < sigma) cands.emplace_back(cj, ms);
+        }
+        int matched = -1;
+        while (!cands.empty()) {
+          double mmin = cands[0].second;
+          for (const auto &c : cands) mmin = std::min(mmin, c.second);
+          int best = -1, ntie = 0;
+          for (size_t c = 0; c < cands.size(); ++c)
+            if (cands[c].second <= mmin * (1.0 + prm.tie_rtol)) {
+              ++ntie;
+              if (best < 0 || pos[cands[c].first] < pos[cands[best].first]) best = int(c);
+            }
+          notes.max_tie = std::max(notes.max_tie, ntie);
+          const int cj = cands[best].first;
+          const auto it = known.find(key(ci, cj));
+          bool ok;
+          if (it == known.end()) {
+            unknown.emplace_back(ci, cj);
+            ok = true;   // optimistic
+          } else {
+            const Crit &c = it->second;
+            note_w(c.mub);
+            ok = c.mub < sigma;
+            if (ok && !std::isnan(c.mug)) {
+              note_w(c.mug);
+              ok = c.mug < sigma;
+            }
           }
-        res.max_tie = std::max(res.max_tie, ntie);
-        const int cj = cands[best].first;
-        const auto tb0 = std::chrono::steady_clock::now();
-        const double mu = mu_b(*work, ci, cj, *wdhat, prm.tau);
-        t_mub += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb0).count();
-        ++n_mub;
-        note(mu);
-        bool ok = mu < sigma;
-        if (ok && members[ci].size() + members[cj].size() > 2) {
-          std::vector<int> u = members[ci];
-          u.insert(u.end(), members[cj].begin(), members[cj].end());
-          const auto tg0 = std::chrono::steady_clock::now();
-          const double mg = mu_g(lev, u, Dhat, prm.tau);
-          t_mug += std::chrono::duration<double>(std::chrono::steady_clock::now() - tg0).count();
-          ++n_mug;
-          note(mg);
-          ok = mg < sigma;
+          if (ok) {
+            matched = cj;
+            break;
+          }
+          cands.erase(cands.begin() + best);
         }
-        if (ok) {
-          matched = cj;
-          break;
+        if (matched >= 0) {
+          pairs.emplace_back(ci, matched);
+          inT[matched] = 0;
+        } else {
+          singles.push_back(ci);
         }
-        cands.erase(cands.begin() + best);
       }
-      if (matched >= 0) {
-        pairs.emplace_back(ci, matched);
-        in_T[matched] = 0;
-      } else {
-        singles.push_back(ci);
+      if (unknown.empty()) {
+        res.min_margin = std::min(res.min_margin, notes.min_margin);
+        res.max_tie = std::max(res.max_tie, notes.max_tie);
+        in_T = inT;
+        break;
       }
+      std::vector<Crit> val(unknown.size());
+      parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
+        const int ci = unknown[u].first, cj = unknown[u].second;
+        Crit c{mu_b(*work, ci, cj, *wdhat, prm.tau), std::numeric_limits<double>::quiet_NaN()};
+        if (c.mub < sigma && members[ci].size() + members[cj].size() > 2) {
+          std::vector<int> un = members[ci];
+          un.insert(un.end(), members[cj].begin(), members[cj].end());
+          c.mug = mu_g(lev, un, Dhat, prm.tau);
+        }
+        val[u] = c;
+      }, 16);
+      for (size_t u = 0; u < unknown.size(); ++u) known.emplace(key(unknown[u].first, unknown[u].second), val[u]);
+      n_eval += long(unknown.size());
     }
+    if (tm.on) std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel\n", walks, n_eval);
     tm.mark("matching pass");
-    if (tm.on)
-      std::fprintf(stderr, "[eamg]   mu_b %ld calls %.3f s, mu_g %ld calls %.3f s\n", n_mub, t_mub, n_mug, t_mug);
-    t_mub = t_mug = 0.0;
-    n_mub = n_mug = 0;
     std::vector<std::vector<int>> groups;
     for (const auto &pq : pairs) groups.push_back({pq.first, pq.second});
     for (int s : singles) groups.push_back({s});

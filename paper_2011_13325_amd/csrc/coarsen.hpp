@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <string>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -53,6 +54,25 @@ struct Sq {
   double &operator()(int i, int j) { return a[i * k + j]; }
   double operator()(int i, int j) const { return a[i * k + j]; }
 };
+
+// Parallel loop with dynamic chunks, for iterations of uneven cost.
+template <class F>
+void parallel_for_dynamic(int64_t n, F &&f, int64_t chunk = 64) {
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min(nt, 16u));
+  if (n < 2 * chunk || nt == 1) {
+    for (int64_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t)
+    th.emplace_back([&] {
+      for (int64_t lo = next.fetch_add(chunk); lo < n; lo = next.fetch_add(chunk))
+        for (int64_t i = lo; i < std::min(n, lo + chunk); ++i) f(i);
+    });
+  for (auto &x : th) x.join();
+}
 
 struct MatchParams {
   double sigma = 20.0;
