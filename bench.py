@@ -10,7 +10,7 @@ HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerki
 coarsest factor) is timed separately and reported in the same line.  The same solve with the
 FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle", and the
 batched block-panel solve of 32 seeded load cases on the same hierarchy (FP64 and FP32 V-cycle)
-as "batched".
+as "batched", and 16 independent cubes of uneven size solved together as "multi_mesh".
 
 Prints ONE JSON line.
 """
@@ -32,6 +32,8 @@ def _args():
     ap.add_argument("--cpu-n", type=int, default=17, help="cube side of the oracle sample")
     ap.add_argument("--batch", type=int, default=32,
                     help="right-hand sides of the batched block-panel solve (0: skip)")
+    ap.add_argument("--multi", type=int, default=16,
+                    help="independent meshes of the multi-system solve (0: skip)")
     return ap.parse_args()
 
 
@@ -140,6 +142,53 @@ def _batched(E, torch, hier, p, m, steps, warmup):
     return out
 
 
+def _multi_mesh(E, torch, steps, count=16, seed=4):
+    """Independent meshes of uneven size solved together (eamg_solve_multi): count cubes with
+    sides uniform in [8, 48] and Poisson ratios uniform in [0.2, 0.45], FP32 V-cycle in FP64 CG;
+    against the same systems solved one after another."""
+    from gen import make_problem
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(8, 49, size=count)
+    nus = rng.uniform(0.2, 0.45, size=count)
+    t0 = time.perf_counter()
+    sysm = []
+    for c, (n, nu) in enumerate(zip(sides, nus)):
+        p = make_problem(int(n), nu=float(nu), seed=100 + c)
+        h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                        E.eamg_default_setup_params(vcycle_fp32=1))
+        sysm.append((p, h))
+    setup_s = time.perf_counter() - t0
+    bs = [torch.tensor(p.b, device="cuda") for p, _ in sysm]
+    xs = [torch.zeros_like(b) for b in bs]
+    hs = [h.h for _, h in sysm]
+    prec = E.EAMG_PRECOND_VCYCLE_FP32
+    for (p, h), b, x in zip(sysm, bs, xs):
+        h.solve(b, x, precond=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for (p, h), b, x in zip(sysm, bs, xs):
+            h.solve(b, x, precond=prec)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3 / steps
+    E.eamg_solve_multi(hs, bs, xs, precond=prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, infos = E.eamg_solve_multi(hs, bs, xs, precond=prec)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert st == E.EAMG_OK and max(i["rel_res_true"] for i in infos) <= 1e-8
+    dofs = sum(p.n_free_dofs for p, _ in sysm)
+    for _, h in sysm:
+        h.close()
+    return {"meshes": [int(n) for n in sides], "free_dofs": dofs, "setup_s": round(setup_s, 3),
+            "dtype": "f32 V-cycle in f64 CG", "ms_per_solve_all": ms,
+            "value": dofs / (ms / 1e3), "unit": "dofs/s",
+            "ms_one_after_another": seq_ms, "speedup_vs_one_after_another": seq_ms / ms,
+            "iterations": [i["iterations"] for i in infos]}
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -202,6 +251,8 @@ def main():
         out["batched"] = _batched(E, torch, hier, p, args.batch, args.steps, args.warmup)
         out["batched"]["speedup_per_rhs_vs_single_fp64"] = {
             k: out["batched"][k]["value"] / value for k in ("fp64_vcycle", "fp32_vcycle")}
+    if args.multi > 0:
+        out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi)
     levels = []
     for l in range(st["n_levels"]):
         li = E.eamg_level_info_get(hier.h, l)

@@ -190,6 +190,24 @@ eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const double *B_de
                              eamg_solve_info *infos);
 
 /*
+ * Solve nsys independent systems (each with its own hierarchy, e.g. meshes of different sizes)
+ * together: each PCG iteration replays the captured iteration graph of every system that is
+ * still iterating, each on a stream of its own, so the small launches of different systems can
+ * overlap; the host then applies every system's stopping test.
+ * Each system follows exactly the eamg_solve recurrence (same kernels in the same order, so its
+ * result is eamg_solve's bit for bit) and stops on its own test.
+ *   hs[nsys]          distinct hierarchies (a hierarchy may appear only once)
+ *   b_dev[m], x_dev[m] DEVICE arrays of system m (n_m * dim doubles, natural order)
+ *   params            shared by all systems (precond FP32 needs vcycle_fp32 on every hierarchy)
+ *   infos             HOST array of nsys reports (may be NULL); infos[m].status is OK,
+ *                     NOT_CONVERGED or BREAKDOWN (that system's x is not written on BREAKDOWN)
+ * Returns OK when every system converged, NOT_CONVERGED otherwise, INVALID_ARG or HIP.
+ */
+eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const double *const *b_dev,
+                             double *const *x_dev, const eamg_solve_params *params, void *stream,
+                             eamg_solve_info *infos);
+
+/*
  * Apply one V-cycle z = B^{-1} r (DEVICE arrays, n*dim doubles, level-0 natural order).
  * Dirichlet dofs of r are treated as 0.  precision: EAMG_PRECOND_VCYCLE (FP64) or
  * EAMG_PRECOND_VCYCLE_FP32 (needs vcycle_fp32 = 1 at setup); anything else is INVALID_ARG.

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
-            "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch"]
+            "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -103,6 +103,8 @@ def lib():
     L.eamg_solve.restype = ctypes.c_int
     L.eamg_solve_batch.argtypes = [vp, i32, vp, i64, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve_batch.restype = ctypes.c_int
+    L.eamg_solve_multi.argtypes = [i32, P(vp), P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
+    L.eamg_solve_multi.restype = ctypes.c_int
     L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.eamg_vcycle.restype = ctypes.c_int
     L.eamg_stats.argtypes = [vp, P(i32), vp, vp, P(dp), P(dp)]
@@ -226,6 +228,23 @@ def eamg_solve_batch(h, B, X, rtol=1e-8, max_it=1000, use_x0=False, precond=True
                                 _stream(stream), infos)
     if st < 0:
         raise EamgError(st, "eamg_solve_batch")
+    return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
+                     ms=i.ms, status=i.status) for i in infos]
+
+
+def eamg_solve_multi(hs, bs, xs, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stream=None):
+    """hs: hierarchy handles; bs, xs: float64 device tensors, one per system.
+    Returns (status, [info dict per system])."""
+    n = len(hs)
+    assert len(bs) == n and len(xs) == n
+    H = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h) if not isinstance(h, ctypes.c_void_p) else h for h in hs])
+    Bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+    Xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    sp = eamg_solve_params(rtol, max_it, int(use_x0), int(precond))
+    infos = (eamg_solve_info * n)()
+    st = lib().eamg_solve_multi(n, H, Bp, Xp, ctypes.byref(sp), _stream(stream), infos)
+    if st < 0:
+        raise EamgError(st, "eamg_solve_multi")
     return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
                      ms=i.ms, status=i.status) for i in infos]
 

@@ -460,7 +460,7 @@ void enqueue_iteration(eamg_hierarchy *h, bool f32, hipStream_t s) {
   const SoaMat &A = L0.Am;
   const int64_t N = int64_t(L0.n) * L0.bs;
   const int nd = dot_blocks(N);
-  const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
+  const int ns = spmv_blocks(A);
   vcycle(h, h->r, h->z, f32, s);
   hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
   hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
@@ -505,6 +505,249 @@ void try_build_graph(eamg_hierarchy *h, bool f32) {
 double bytes_bcsr(int64_t nnzb, int r, int c, int rows) {
   return double(nnzb) * (r * c * 8.0 + 4.0) + 4.0 * (rows + 1);
 }
+
+// One PCG solve on one hierarchy, in phases, so that several solves can be interleaved
+// (eamg_solve_multi): init, start (b in, x0, z = V(r), p = z, first iteration), next (the
+// stopping test; true while an iteration is due), the iteration itself (graph replay,
+// enqueue_iteration or eager_iteration), finish (true residual, x out) and report.
+struct SolveRun {
+  eamg_hierarchy *h = nullptr;
+  eamg_solve_params sp{};
+  bool f32 = false;
+  hipStream_t s = nullptr;
+  int64_t N = 0;
+  int nd = 0, ns = 0;
+  double vecb = 0.0, bnorm = 0.0;
+  int iters = 0;
+  double rel = 0.0, rel_true = 0.0, ms = 0.0;
+  bool converged = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~SolveRun() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+
+  void init(eamg_hierarchy *hh, const eamg_solve_params *params, hipStream_t st) {
+    h = hh;
+    s = st;
+    eamg_default_solve_params(&sp);
+    if (params) sp = *params;
+    if (sp.max_it < 1) fail(EAMG_ERR_INVALID_ARG, "max_it must be >= 1");
+    if (!(sp.rtol >= 0.0)) fail(EAMG_ERR_INVALID_ARG, "rtol must be >= 0");
+    if (sp.precond < EAMG_PRECOND_NONE || sp.precond > EAMG_PRECOND_VCYCLE_FP32)
+      fail(EAMG_ERR_INVALID_ARG, "precond must be 0, 1 or 2");
+    if (sp.precond == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
+      fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
+    f32 = sp.precond == EAMG_PRECOND_VCYCLE_FP32;
+    const Level &L0 = h->lv[0];
+    N = int64_t(L0.n) * L0.bs;
+    nd = dot_blocks(N);
+    ns = spmv_blocks(L0.Am);
+    vecb = double(N) * 8.0;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+  }
+
+  void precondition() {
+    if (sp.precond)
+      vcycle(h, h->r, h->z, f32, s);
+    else
+      hip_check(launch_copy(N, h->r, h->z, s), "copy");
+  }
+
+  double spmv_bytes() const {
+    const Level &L0 = h->lv[0];
+    return launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 8.0 * ns;
+  }
+
+  void copy_scalars() {
+    hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s),
+              "copy");
+  }
+  void wait() { hip_check(hipStreamSynchronize(s), "sync"); }
+
+  // start() in phases: each enqueue_* ends with the scalars copied to the host, each complete_*
+  // (after the stream has been synchronised) reads them.  Interleaving the phases of several
+  // systems lets their start-up launches overlap.
+  bool active_start = true;   // false once start() has settled the solve
+
+  void enqueue_start_a(const double *b_dev, const double *x_dev) {
+    const Level &L0 = h->lv[0];
+    const SoaMat &A = L0.Am;
+    hip_check(hipEventRecord(e0, s), "event");
+    hip_check(launch_fill(SC_COUNT, 0.0, h->scal, s), "fill");
+    hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, b_dev, h->bp, s), "perm_in");
+    hip_check(launch_finite_check(N, h->bp, h->scal, SC_NONFINITE, s), "finite");
+    hip_check(launch_dot(N, h->bp, h->bp, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_BB, RED_STORE, s), "reduce");
+    if (sp.use_x0) {
+      hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, x_dev, h->x, s), "perm_in");
+      hip_check(launch_spmv(A, h->x, h->q, nullptr, s), "spmv");
+      hip_check(launch_sub(N, h->bp, h->q, h->r, s), "sub");
+    } else {
+      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
+      hip_check(launch_copy(N, h->bp, h->r, s), "copy");
+    }
+    copy_scalars();
+  }
+  void complete_start_a() {
+    if (h->scal_h[SC_NONFINITE] != 0.0) fail(EAMG_ERR_BREAKDOWN, "right-hand side is not finite");
+    bnorm = std::sqrt(h->scal_h[SC_BB]);
+    if (bnorm == 0.0) {
+      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
+      converged = true;
+      active_start = false;
+    }
+  }
+  void enqueue_start_b() {
+    precondition();
+    hip_check(launch_copy(N, h->z, h->p, s), "copy");
+    hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_RHO, RED_STORE, s), "reduce");
+    copy_scalars();
+  }
+  void complete_start_b() {
+    const double rho0 = h->scal_h[SC_RHO];
+    if (!(rho0 > 0.0) || !std::isfinite(rho0)) {
+      // r = b - A x0 may already be zero (exact x0); otherwise the preconditioner is not SPD
+      hip_check(launch_dot(N, h->r, h->r, h->part, s), "dot");
+      hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+      fetch_scalars(h, s);
+      if (h->scal_h[SC_RR] != 0.0) fail(EAMG_ERR_BREAKDOWN, "r.z <= 0 at the start (preconditioner not SPD)");
+      converged = true;
+      active_start = false;
+    }
+  }
+  // first iteration (p = z already set)
+  void enqueue_start_c() {
+    const Level &L0 = h->lv[0];
+    const SoaMat &A = L0.Am;
+    timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), spmv_bytes(), s,
+          [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
+    timed(h, "reduce", "k_reduce", 8.0 * ns, s,
+          [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
+    timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
+          [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+    timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+          [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
+    copy_scalars();
+  }
+
+  void start(const double *b_dev, const double *x_dev) {
+    enqueue_start_a(b_dev, x_dev);
+    wait();
+    complete_start_a();
+    if (!active_start) return;
+    enqueue_start_b();
+    wait();
+    complete_start_b();
+    if (!active_start) return;
+    enqueue_start_c();
+    wait();
+  }
+
+  // The stopping test on the scalars of the last iteration (in h->scal_h); true when another
+  // iteration is due.
+  bool next() {
+    if (converged) return false;
+    ++iters;
+    if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
+    const double rr = h->scal_h[SC_RR];
+    if (!std::isfinite(rr)) fail(EAMG_ERR_BREAKDOWN, "residual is not finite");
+    rel = std::sqrt(rr) / bnorm;
+    if (std::sqrt(rr) <= sp.rtol * bnorm) {
+      converged = true;
+      return false;
+    }
+    return iters < sp.max_it;
+  }
+
+  void eager_iteration() {
+    const Level &L0 = h->lv[0];
+    const SoaMat &A = L0.Am;
+    precondition();
+    timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
+          [&] { return launch_dot(N, h->r, h->z, h->part, s); });
+    timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+          [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
+    timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
+          [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
+    timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), spmv_bytes(), s,
+          [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
+    timed(h, "reduce", "k_reduce", 8.0 * ns, s,
+          [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
+    timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
+          [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+    timed(h, "reduce", "k_reduce", 8.0 * nd, s,
+          [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
+    fetch_scalars(h, s);
+  }
+
+  void enqueue_finish(double *x_dev) {
+    const Level &L0 = h->lv[0];
+    hip_check(launch_spmv(L0.Am, h->x, h->q, nullptr, s), "spmv");
+    hip_check(launch_sub(N, h->bp, h->q, h->z, s), "sub");
+    hip_check(launch_dot(N, h->z, h->z, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
+    hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, h->x, x_dev, s), "perm_out");
+    hip_check(hipEventRecord(e1, s), "event");
+    copy_scalars();
+  }
+  void complete_finish() {
+    const double bn = std::sqrt(h->scal_h[SC_BB]);
+    rel_true = bn > 0.0 ? std::sqrt(h->scal_h[SC_RR]) / bn : 0.0;
+    if (bn == 0.0) rel = 0.0;
+    float fms = 0.0f;
+    hip_check(hipEventElapsedTime(&fms, e0, e1), "event");
+    ms = fms;
+  }
+  void finish(double *x_dev) {
+    enqueue_finish(x_dev);
+    wait();
+    complete_finish();
+  }
+
+  eamg_status report(eamg_status st, eamg_solve_info *info) const {
+    const eamg_status out = (st == EAMG_OK && !converged) ? EAMG_NOT_CONVERGED : st;
+    if (out == EAMG_NOT_CONVERGED) g_last_error = "iteration limit reached";
+    if (info) {
+      info->iterations = iters;
+      info->rel_res = rel;
+      info->rel_res_true = rel_true;
+      info->ms = ms;
+      info->status = out;
+    }
+    return out;
+  }
+};
+
+// Streams of eamg_solve_multi: as many as the runtime's default hardware queues per process;
+// more streams than queues only adds queue switching (measured slower).
+constexpr int kMultiStreams = 4;
+
+// Streams for the systems of eamg_solve_multi: each iteration forks from the solve stream,
+// replays every active system's own iteration graph on a stream of its own, and joins.
+struct MultiStreams {
+  std::vector<hipStream_t> st;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t fork = nullptr;
+  ~MultiStreams() {
+    for (hipStream_t x : st) (void)hipStreamDestroy(x);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+  }
+  void ensure(size_t n) {
+    if (!fork) hip_check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "event");
+    while (st.size() < n) {
+      hipStream_t x = nullptr;
+      hip_check(hipStreamCreateWithFlags(&x, hipStreamNonBlocking), "stream");
+      st.push_back(x);
+      hipEvent_t e = nullptr;
+      hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+      ev.push_back(e);
+    }
+  }
+};
 
 }  // namespace
 }  // namespace eamg
@@ -674,8 +917,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     h->q = ar.alloc<double>(size_t(N0));
     h->bp = ar.alloc<double>(size_t(N0));
     const SoaMat &A0 = h->lv[0].Am;
-    const int spmv_blocks = (A0.n_rows + (256 / A0.group) - 1) / (256 / A0.group);
-    h->part = ar.alloc<double>(size_t(std::max(dot_blocks(N0), spmv_blocks)));
+    h->part = ar.alloc<double>(size_t(std::max(dot_blocks(N0), spmv_blocks(A0))));
     h->scal = ar.alloc<double>(SC_COUNT);
 
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&h->scal_h), sizeof(double) * SC_COUNT, 0),
@@ -683,6 +925,130 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     hip_check(hipStreamSynchronize(s), "sync");
     *out = h.release();
   });
+}
+
+eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const double *const *b_dev,
+                             double *const *x_dev, const eamg_solve_params *params, void *stream,
+                             eamg_solve_info *infos) {
+  bool all = true;
+  const eamg_status st = guarded([&] {
+    if (nsys < 1 || !hs || !b_dev || !x_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument or nsys < 1");
+    for (int m = 0; m < nsys; ++m) {
+      if (!hs[m] || !b_dev[m] || !x_dev[m]) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy or vector");
+      if (b_dev[m] == x_dev[m]) fail(EAMG_ERR_INVALID_ARG, "b and x may not alias");
+      for (int l = 0; l < m; ++l)
+        if (hs[l] == hs[m]) fail(EAMG_ERR_INVALID_ARG, "a hierarchy may appear only once");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<std::unique_ptr<SolveRun>> runs;
+    for (int m = 0; m < nsys; ++m) {
+      runs.emplace_back(std::make_unique<SolveRun>());
+      runs[m]->init(hs[m], params, s);
+    }
+    // a system that breaks down stops with its status; the others go on
+    std::vector<eamg_status> sst(size_t(nsys), EAMG_OK);
+    std::vector<char> live(size_t(nsys), 1);
+    auto guard_sys = [&](int m, auto &&f) {
+      try {
+        f();
+      } catch (const Failure &e) {
+        if (e.code != EAMG_ERR_BREAKDOWN) throw;
+        sst[m] = e.code;
+        live[m] = 0;
+      }
+    };
+    // start-up and finish of all systems in interleaved phases on the streams
+    MultiStreams ms;
+    ms.ensure(size_t(std::min(nsys, kMultiStreams)));
+    for (int m = 0; m < nsys; ++m) runs[m]->s = ms.st[size_t(m) % ms.st.size()];
+    auto phase = [&](auto &&enq, auto &&done) {
+      for (int m = 0; m < nsys; ++m)
+        if (live[m]) guard_sys(m, [&] { enq(m); });
+      for (hipStream_t x : ms.st) hip_check(hipStreamSynchronize(x), "sync");
+      for (int m = 0; m < nsys; ++m)
+        if (live[m]) guard_sys(m, [&] {
+            done(m);
+            if (!runs[m]->active_start) live[m] = 2;   // settled: no iterations, but finish
+          });
+    };
+    phase([&](int m) { runs[m]->enqueue_start_a(b_dev[m], x_dev[m]); },
+          [&](int m) { runs[m]->complete_start_a(); });
+    for (int m = 0; m < nsys; ++m) live[m] = live[m] == 1;
+    phase([&](int m) { runs[m]->enqueue_start_b(); }, [&](int m) { runs[m]->complete_start_b(); });
+    for (int m = 0; m < nsys; ++m) live[m] = live[m] == 1;
+    phase([&](int m) { runs[m]->enqueue_start_c(); }, [](int) {});
+    for (int m = 0; m < nsys; ++m) runs[m]->s = s;
+    bool graphs = runs[0]->sp.precond != EAMG_PRECOND_NONE;
+    for (int m = 0; m < nsys; ++m) graphs = graphs && !hs[m]->prof_on;
+    if (const char *e = std::getenv("EAMG_GRAPH"))
+      if (std::atoi(e) == 0) graphs = false;
+    const bool f32 = runs[0]->f32;
+    for (int m = 0; m < nsys && graphs; ++m) {
+      if (!hs[m]->graph_tried[f32]) try_build_graph(hs[m], f32);
+      graphs = hs[m]->g_iter[f32] != nullptr;
+    }
+    // estimated time of one iteration of each system: its launches (the colour sweeps dominate
+    // the small systems) plus its bytes at a fraction of the HBM rate
+    std::vector<double> cost(size_t(nsys), 0.0);
+    for (int m = 0; m < nsys; ++m) {
+      double launches = 8.0, bytes = 0.0;
+      for (const Level &L : hs[m]->lv) {
+        launches += 2.0 * L.ncolors + 4.0;
+        bytes += double(L.A.nnz()) * L.bs * L.bs * (f32 ? 4.0 : 8.0) * 2.0;
+      }
+      cost[m] = launches * 6e-6 + bytes / 2e12;
+    }
+    std::vector<int> active;
+    for (;;) {
+      active.clear();
+      for (int m = 0; m < nsys; ++m) {
+        if (!live[m]) continue;
+        bool more = false;
+        guard_sys(m, [&] { more = runs[m]->next(); });
+        if (more)
+          active.push_back(m);
+        else
+          live[m] = 0;
+      }
+      if (active.empty()) break;
+      if (graphs) {
+        // largest first onto the least loaded of the streams
+        std::vector<int> ord = active;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        const size_t nst = std::min(ord.size(), ms.st.size());
+        std::vector<double> load(nst, 0.0);
+        hip_check(hipEventRecord(ms.fork, s), "event");
+        for (size_t i = 0; i < nst; ++i) hip_check(hipStreamWaitEvent(ms.st[i], ms.fork, 0), "wait");
+        for (int m : ord) {
+          const size_t i = size_t(std::min_element(load.begin(), load.end()) - load.begin());
+          load[i] += cost[m];
+          hip_check(hipGraphLaunch(hs[m]->g_iter[f32], ms.st[i]), "graph launch");
+        }
+        for (size_t i = 0; i < nst; ++i) {
+          hip_check(hipEventRecord(ms.ev[i], ms.st[i]), "event");
+          hip_check(hipStreamWaitEvent(s, ms.ev[i], 0), "wait");
+        }
+        hip_check(hipStreamSynchronize(s), "sync");
+      } else {
+        for (int m : active) runs[m]->eager_iteration();
+      }
+    }
+    for (int m = 0; m < nsys; ++m) {
+      runs[m]->s = ms.st[size_t(m) % ms.st.size()];
+      if (sst[m] == EAMG_OK) runs[m]->enqueue_finish(x_dev[m]);
+    }
+    for (hipStream_t x : ms.st) hip_check(hipStreamSynchronize(x), "sync");
+    for (int m = 0; m < nsys; ++m) {
+      if (sst[m] == EAMG_OK) runs[m]->complete_finish();
+      const eamg_status o = runs[m]->report(sst[m], infos ? infos + m : nullptr);
+      all = all && o == EAMG_OK;
+    }
+  });
+  if (st == EAMG_OK && !all) {
+    g_last_error = "some systems did not converge";
+    return EAMG_NOT_CONVERGED;
+  }
+  return st;
 }
 
 eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, int32_t precision,
@@ -704,153 +1070,26 @@ eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, i
 
 eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
                        const eamg_solve_params *params, void *stream, eamg_solve_info *info) {
-  int iters = 0;
-  double rel = 0.0, rel_true = 0.0, ms = 0.0;
-  bool converged = false;
+  SolveRun run;
   const eamg_status st = guarded([&] {
     if (!h || !b_dev || !x_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
-    if (b_dev == x_dev) fail(EAMG_ERR_INVALID_ARG, "b and x may not alias");
-    eamg_solve_params sp;
-    eamg_default_solve_params(&sp);
-    if (params) sp = *params;
-    if (sp.max_it < 1) fail(EAMG_ERR_INVALID_ARG, "max_it must be >= 1");
-    if (!(sp.rtol >= 0.0)) fail(EAMG_ERR_INVALID_ARG, "rtol must be >= 0");
-    if (sp.precond < EAMG_PRECOND_NONE || sp.precond > EAMG_PRECOND_VCYCLE_FP32)
-      fail(EAMG_ERR_INVALID_ARG, "precond must be 0, 1 or 2");
-    if (sp.precond == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
-      fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
-    const bool f32 = sp.precond == EAMG_PRECOND_VCYCLE_FP32;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Level &L0 = h->lv[0];
-    const int64_t N = int64_t(L0.n) * L0.bs;
-    const int nd = dot_blocks(N);
-    const SoaMat &A = L0.Am;
-    const int ns = (A.n_rows + (256 / A.group) - 1) / (256 / A.group);
-    const double vecb = double(N) * 8.0;
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "event");
-    hip_check(hipEventCreate(&e1), "event");
-    struct EvGuard {
-      hipEvent_t a, b;
-      ~EvGuard() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-      }
-    } eg{e0, e1};
-    hip_check(hipEventRecord(e0, s), "event");
-    hip_check(launch_fill(SC_COUNT, 0.0, h->scal, s), "fill");
-    hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, b_dev, h->bp, s), "perm_in");
-    hip_check(launch_finite_check(N, h->bp, h->scal, SC_NONFINITE, s), "finite");
-    hip_check(launch_dot(N, h->bp, h->bp, h->part, s), "dot");
-    hip_check(launch_reduce(nd, h->part, h->scal, SC_BB, RED_STORE, s), "reduce");
-    if (sp.use_x0) {
-      hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, x_dev, h->x, s), "perm_in");
-      hip_check(launch_spmv(A, h->x, h->q, nullptr, s), "spmv");
-      hip_check(launch_sub(N, h->bp, h->q, h->r, s), "sub");
-    } else {
-      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
-      hip_check(launch_copy(N, h->bp, h->r, s), "copy");
-    }
-    auto precondition = [&]() {
-      if (sp.precond)
-        vcycle(h, h->r, h->z, f32, s);
-      else
-        hip_check(launch_copy(N, h->r, h->z, s), "copy");
-    };
-    fetch_scalars(h, s);
-    if (h->scal_h[SC_NONFINITE] != 0.0) fail(EAMG_ERR_BREAKDOWN, "right-hand side is not finite");
-    const double bnorm = std::sqrt(h->scal_h[SC_BB]);
-    if (bnorm == 0.0) {
-      hip_check(launch_fill(N, 0.0, h->x, s), "fill");
-      converged = true;
-    } else {
-      precondition();
-      hip_check(launch_copy(N, h->z, h->p, s), "copy");
-      hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
-      hip_check(launch_reduce(nd, h->part, h->scal, SC_RHO, RED_STORE, s), "reduce");
-      fetch_scalars(h, s);
-      const double rho0 = h->scal_h[SC_RHO];
-      if (!(rho0 > 0.0) || !std::isfinite(rho0)) {
-        // r = b - A x0 may already be zero (exact x0); otherwise the preconditioner is not SPD
-        hip_check(launch_dot(N, h->r, h->r, h->part, s), "dot");
-        hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
-        fetch_scalars(h, s);
-        if (h->scal_h[SC_RR] != 0.0) fail(EAMG_ERR_BREAKDOWN, "r.z <= 0 at the start (preconditioner not SPD)");
-        converged = true;
-      }
-    }
-    if (!converged) {
-      // first iteration (p = z already set), then z = V(r) ... per further iteration
-      timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 8.0 * ns, s,
-            [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
-      timed(h, "reduce", "k_reduce", 8.0 * ns, s,
-            [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
-      timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
-            [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
-      timed(h, "reduce", "k_reduce", 8.0 * nd, s,
-            [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
-      fetch_scalars(h, s);
-      const bool graphs = sp.precond && !h->prof_on;
-      if (graphs && !h->graph_tried[f32]) try_build_graph(h, f32);
-      while (!converged) {
-        ++iters;
-        if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
-        const double rr = h->scal_h[SC_RR];
-        if (!std::isfinite(rr)) fail(EAMG_ERR_BREAKDOWN, "residual is not finite");
-        rel = std::sqrt(rr) / bnorm;
-        if (std::sqrt(rr) <= sp.rtol * bnorm) {
-          converged = true;
-          break;
-        }
-        if (iters >= sp.max_it) break;
-        if (graphs && h->g_iter[f32]) {
-          hip_check(hipGraphLaunch(h->g_iter[f32], s), "graph launch");
-          hip_check(hipStreamSynchronize(s), "sync");
+    run.init(h, params, static_cast<hipStream_t>(stream));
+    run.start(b_dev, x_dev);
+    if (!run.converged) {
+      const bool graphs = run.sp.precond && !h->prof_on;
+      if (graphs && !h->graph_tried[run.f32]) try_build_graph(h, run.f32);
+      while (run.next()) {
+        if (graphs && h->g_iter[run.f32]) {
+          hip_check(hipGraphLaunch(h->g_iter[run.f32], run.s), "graph launch");
+          hip_check(hipStreamSynchronize(run.s), "sync");
         } else {
-          precondition();
-          timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
-                [&] { return launch_dot(N, h->r, h->z, h->part, s); });
-          timed(h, "reduce", "k_reduce", 8.0 * nd, s,
-                [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
-          timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
-                [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
-          timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 8.0 * ns, s,
-                [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
-          timed(h, "reduce", "k_reduce", 8.0 * ns, s,
-                [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
-          timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
-                [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
-          timed(h, "reduce", "k_reduce", 8.0 * nd, s,
-                [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
-          fetch_scalars(h, s);
+          run.eager_iteration();
         }
       }
     }
-    // true residual
-    hip_check(launch_spmv(A, h->x, h->q, nullptr, s), "spmv");
-    hip_check(launch_sub(N, h->bp, h->q, h->z, s), "sub");
-    hip_check(launch_dot(N, h->z, h->z, h->part, s), "dot");
-    hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
-    hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, h->x, x_dev, s), "perm_out");
-    hip_check(hipEventRecord(e1, s), "event");
-    fetch_scalars(h, s);
-    const double bn = std::sqrt(h->scal_h[SC_BB]);
-    rel_true = bn > 0.0 ? std::sqrt(h->scal_h[SC_RR]) / bn : 0.0;
-    if (bn == 0.0) rel = 0.0;
-    float fms = 0.0f;
-    hip_check(hipEventElapsedTime(&fms, e0, e1), "event");
-    ms = fms;
+    run.finish(x_dev);
   });
-  const eamg_status out = (st == EAMG_OK && !converged) ? EAMG_NOT_CONVERGED : st;
-  if (out == EAMG_NOT_CONVERGED) g_last_error = "iteration limit reached";
-  if (info) {
-    info->iterations = iters;
-    info->rel_res = rel;
-    info->rel_res_true = rel_true;
-    info->ms = ms;
-    info->status = out;
-  }
-  return out;
+  return run.report(st, info);
 }
 
 eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,

@@ -716,14 +716,21 @@ hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in,
     default: return hipErrorInvalidValue;                                                       \
   }
 
+// k_spmv reduces within wavefronts: a matrix with one row per workgroup runs it with 64 lanes
+// per row.
+inline int spmv_group(const SoaMat &A) { return A.group == kBlock ? 64 : A.group; }
+
+int spmv_blocks(const SoaMat &A) { return int(cdiv64(A.n_rows, groups_for(spmv_group(A)))); }
+
 hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part, hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
-  const dim3 grid(cdiv64(A.n_rows, groups_for(A.group)));
+  const int G = spmv_group(A);
+  const dim3 grid(spmv_blocks(A));
   if (A.br != A.bc) return hipErrorInvalidValue;
   switch (A.br) {
-    case 1: hipLaunchKernelGGL((k_spmv<1, 1>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.val, A.nnz, x, y, part); break;
-    case 3: hipLaunchKernelGGL((k_spmv<3, 3>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.val, A.nnz, x, y, part); break;
-    case 6: hipLaunchKernelGGL((k_spmv<6, 6>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.val, A.nnz, x, y, part); break;
+    case 1: hipLaunchKernelGGL((k_spmv<1, 1>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.val, A.nnz, x, y, part); break;
+    case 3: hipLaunchKernelGGL((k_spmv<3, 3>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.val, A.nnz, x, y, part); break;
+    case 6: hipLaunchKernelGGL((k_spmv<6, 6>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.val, A.nnz, x, y, part); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();

@@ -77,8 +77,10 @@ struct SoaMat {
   const int *diag = nullptr; // square matrices only
 };
 
-// y = A x ; if part != nullptr also writes per-workgroup partial sums of x.y (dot_blocks entries)
+// y = A x ; if part != nullptr also writes per-workgroup partial sums of x.y (spmv_blocks(A)
+// entries)
 hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part, hipStream_t s);
+int spmv_blocks(const SoaMat &A);
 // The V-cycle kernels are instantiated for T = double (values SoaMat::val) and T = float
 // (values SoaMat::val32); they accumulate in T.
 // Forward colour sweep with x = 0 initially on rows [r0, r1):
