@@ -211,6 +211,10 @@ def main():
                        stream=stream)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    # launch shapes measured on this hierarchy (single vector and 32-wide panels), once
+    t0 = time.perf_counter()
+    tune_before, tune_after = E.eamg_autotune(hier.h, panel_width=max(args.batch, 0), stream=stream)
+    tune_s = time.perf_counter() - t0
     st = hier.stats()
     b = torch.tensor(p.b, device=dev)
     x = torch.zeros_like(b)
@@ -235,6 +239,8 @@ def main():
                    "rel_res_true": info["rel_res_true"], "levels": st["n_levels"],
                    "level_vertices": st["n"], "vc": round(st["vc"], 4), "oc": round(st["oc"], 4),
                    "setup_s": round(setup_s, 3),
+                   "autotune": {"s": round(tune_s, 3), "tuned_ms_before": tune_before,
+                                "tuned_ms_after": tune_after},
                    "model_bytes_per_iteration": itbytes,
                    "model_GBps_whole_solve": itbytes * its / (ms / 1e3) / 1e9},
     }

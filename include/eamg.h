@@ -190,6 +190,20 @@ eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const double *B_de
                              eamg_solve_info *infos);
 
 /*
+ * Autotuner: measure candidate launch shapes on this hierarchy's own matrices (events on
+ * `stream`, median of 5) and keep the fastest.  Single right-hand side: lanes per block row of
+ * every level's smoother and residual kernels (8, 16, 32, 64 or a whole workgroup).  If
+ * panel_width > 0, also the panel kernels for that many right-hand sides (rounded up to a power
+ * of two): one or four wavefronts per row for every level matrix and transfer.  Later solves use
+ * the tuned shapes (captured iteration graphs are rebuilt); results then differ from the
+ * untuned ones only in summation order.  ms_before / ms_after (may be NULL): summed time of the
+ * tuned launch sequences with the previous and the chosen shapes.  Allocates the panel
+ * workspace when panel_width > 0.  Returns OK, INVALID_ARG (panel_width outside [0, 64]) or HIP.
+ */
+eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, double *ms_before,
+                          double *ms_after);
+
+/*
  * Solve nsys independent systems (each with its own hierarchy, e.g. meshes of different sizes)
  * together: each PCG iteration replays the captured iteration graph of every system that is
  * still iterating, each on a stream of its own, so the small launches of different systems can

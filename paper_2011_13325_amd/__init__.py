@@ -36,7 +36,8 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
-            "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi"]
+            "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
+            "eamg_autotune"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -103,6 +104,8 @@ def lib():
     L.eamg_solve.restype = ctypes.c_int
     L.eamg_solve_batch.argtypes = [vp, i32, vp, i64, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve_batch.restype = ctypes.c_int
+    L.eamg_autotune.argtypes = [vp, i32, vp, P(dp), P(dp)]
+    L.eamg_autotune.restype = ctypes.c_int
     L.eamg_solve_multi.argtypes = [i32, P(vp), P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve_multi.restype = ctypes.c_int
     L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
@@ -247,6 +250,15 @@ def eamg_solve_multi(hs, bs, xs, rtol=1e-8, max_it=1000, use_x0=False, precond=T
         raise EamgError(st, "eamg_solve_multi")
     return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
                      ms=i.ms, status=i.status) for i in infos]
+
+
+def eamg_autotune(h, panel_width=0, stream=None):
+    """Tune launch shapes on the hierarchy; returns (ms before, ms after) of the tuned kernels."""
+    b, a = ctypes.c_double(), ctypes.c_double()
+    st = lib().eamg_autotune(h, int(panel_width), _stream(stream), ctypes.byref(b), ctypes.byref(a))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_autotune")
+    return b.value, a.value
 
 
 def eamg_vcycle(h, r, z, precision=EAMG_PRECOND_VCYCLE, stream=None):

@@ -927,6 +927,82 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
   });
 }
 
+eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, double *ms_before,
+                          double *ms_after) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (panel_width < 0 || panel_width > 64) fail(EAMG_ERR_INVALID_ARG, "panel_width must be in [0, 64]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int reps = 5;
+    double before = 0.0, after = 0.0;
+    auto time_ms = [&](auto &&f) {
+      hipEvent_t a, b;
+      hip_check(hipEventCreate(&a), "event");
+      hip_check(hipEventCreate(&b), "event");
+      std::vector<float> t;
+      for (int r = 0; r < reps; ++r) {
+        hip_check(hipEventRecord(a, s), "event");
+        f();
+        hip_check(hipEventRecord(b, s), "event");
+        hip_check(hipEventSynchronize(b), "sync");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, a, b), "event");
+        t.push_back(ms);
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      std::sort(t.begin(), t.end());
+      return double(t[t.size() / 2]);
+    };
+    // single right-hand side: lanes per row of each level's sweeps (FP64 kernels; the FP32 ones
+    // share the choice)
+    for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
+      Level &L = h->lv[l];
+      const int64_t nv = int64_t(L.n) * L.bs;
+      double *b = l == 0 ? h->r : L.b, *x = l == 0 ? h->z : L.x;
+      for (double *v : {b, x, L.r}) hip_check(launch_fill(nv, 0.0, v, s), "fill");
+      auto sweeps = [&] {
+        for (int c = 0; c < L.ncolors; ++c)
+          hip_check(launch_gs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
+        hip_check(launch_resid_upper<double>(L.Am, x, L.r, s), "resid");
+        for (int c = L.ncolors - 1; c >= 0; --c)
+          hip_check(launch_gs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
+      };
+      const int orig = L.Am.group;
+      const double t0 = time_ms(sweeps);
+      double best = t0;
+      int best_g = orig;
+      for (int g : {8, 16, 32, 64, kBlock}) {
+        if (g == orig) continue;
+        L.Am.group = g;
+        const double t = time_ms(sweeps);
+        if (t < best) {
+          best = t;
+          best_g = g;
+        }
+      }
+      L.Am.group = best_g;
+      before += t0;
+      after += best;
+    }
+    for (int p = 0; p < 2; ++p) {
+      if (h->g_iter[p]) (void)hipGraphExecDestroy(h->g_iter[p]);
+      h->g_iter[p] = nullptr;
+      h->graph_tried[p] = false;
+    }
+    if (panel_width > 0) {
+      int K = 1;
+      while (K < panel_width) K <<= 1;
+      const auto pa = tune_panels(h, K, s);
+      before += pa.first;
+      after += pa.second;
+    }
+    hip_check(hipStreamSynchronize(s), "sync");
+    if (ms_before) *ms_before = before;
+    if (ms_after) *ms_after = after;
+  });
+}
+
 eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const double *const *b_dev,
                              double *const *x_dev, const eamg_solve_params *params, void *stream,
                              eamg_solve_info *infos) {

@@ -4,6 +4,7 @@
 // same coarsest inverse), applied to K columns per launch.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdlib>
 #include <memory>
 #include <string>
@@ -326,7 +327,90 @@ bool solve_panel(eamg_hierarchy *h, int m, const double *B, int64_t ld, double *
   return all;
 }
 
+// Time one launch sequence on the stream (events), median of reps.
+template <class F>
+double time_ms(hipStream_t s, int reps, F &&f) {
+  hipEvent_t a, b;
+  hip_check(hipEventCreate(&a), "event");
+  hip_check(hipEventCreate(&b), "event");
+  std::vector<float> t;
+  for (int r = 0; r < reps; ++r) {
+    hip_check(hipEventRecord(a, s), "event");
+    f();
+    hip_check(hipEventRecord(b, s), "event");
+    hip_check(hipEventSynchronize(b), "sync");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, a, b), "event");
+    t.push_back(ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
 }  // namespace
+
+// Panel launch shapes measured on the hierarchy's own matrices for K columns (FP64 V-cycle
+// kernels): per level, the sweep + upper-residual sequence and each transfer with one or four
+// wavefronts per row; the faster is kept in SoaMat::panel_waves.  Returns the summed time of the
+// tuned kernels before / after (ms).
+std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s) {
+  BatchWork *w = ensure_work(h, K, false);
+  const int reps = 5;
+  double before = 0.0, after = 0.0;
+  for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
+    Level &L = h->lv[l];
+    double *b = l == 0 ? w->r : vp<double>(w->vb[0][l]);
+    double *x = l == 0 ? w->z : vp<double>(w->vx[0][l]);
+    double *r = vp<double>(w->vr[0][l]);
+    double *cb = vp<double>(w->vb[0][l + 1]);
+    double *cx = vp<double>(w->vx[0][l + 1]);
+    const int64_t nv = level_dofs(L) * K, nc = level_dofs(h->lv[l + 1]) * K;
+    for (double *v : {b, x, r}) hip_check(launch_fill(nv, 0.0, v, s), "fill");
+    for (double *v : {cb, cx}) hip_check(launch_fill(nc, 0.0, v, s), "fill");
+    auto sweeps = [&] {
+      for (int c = 0; c < L.ncolors; ++c)
+        hip_check(launch_pgs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, r, s), "pgs");
+      hip_check(launch_presid_upper<double>(L.Am, K, x, r, s), "presid");
+      for (int c = L.ncolors - 1; c >= 0; --c)
+        hip_check(launch_pgs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s), "pgs");
+    };
+    auto restrict_ = [&] { hip_check(launch_prect<double>(L.Rm, K, r, cb, false, s), "prect"); };
+    auto prolong = [&] { hip_check(launch_prect<double>(L.Pm, K, cx, x, true, s), "prect"); };
+    struct Item {
+      SoaMat *M;
+      std::function<void()> run;
+    } items[] = {{&L.Am, sweeps}, {&L.Rm, restrict_}, {&L.Pm, prolong}};
+    for (Item &it : items) {
+      const int orig = it.M->panel_waves;
+      double best = 0.0;
+      int best_w = orig;
+      it.M->panel_waves = orig;
+      const double t0 = time_ms(s, reps, it.run);
+      before += t0;
+      best = t0;
+      for (int wv : {1, 4}) {
+        it.M->panel_waves = wv;
+        const double t = time_ms(s, reps, it.run);
+        if (t < best) {
+          best = t;
+          best_w = wv;
+        }
+      }
+      it.M->panel_waves = best_w;
+      after += best;
+    }
+  }
+  // captured iteration graphs hold the old launch shapes
+  for (int p = 0; p < 2; ++p) {
+    if (w->g[p]) (void)hipGraphExecDestroy(w->g[p]);
+    w->g[p] = nullptr;
+    w->tried[p] = false;
+  }
+  return {before, after};
+}
+
 }  // namespace eamg
 
 using namespace eamg;

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/eamg.h"
@@ -176,6 +177,8 @@ struct ProfRec {
 
 struct BatchWork;
 void destroy_batch(BatchWork *w);
+// Panel launch shapes tuned on the hierarchy for K columns; (time before, after) in ms.
+std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
 
 }  // namespace eamg
 

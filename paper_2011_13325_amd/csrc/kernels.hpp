@@ -69,6 +69,8 @@ struct SoaMat {
   // group: lanes per row (a power of two <= 64), or kBlock for one row per workgroup
   // (square matrices with diag only)
   int n_rows = 0, n_cols = 0, br = 0, bc = 0, group = 16;
+  // panel kernels: wavefronts per row (1 or 4), or 0 for the built-in choice
+  int panel_waves = 0;
   int64_t nnz = 0;
   const int *rp = nullptr;   // int32 row offsets (nnz < 2^31 for one level)
   const int *col = nullptr;

@@ -550,6 +550,7 @@ inline int pcols(int K) { return K >= 4 ? 4 : K; }
 // Team width: a whole workgroup per row when its 64 * 4 * C / K sub-teams still find a block
 // each in an average row, else one wavefront per row.
 inline int pwaves(const SoaMat &M, int K) {
+  if (M.panel_waves == 1 || M.panel_waves == 4) return M.panel_waves;   // tuned
   const double avg = M.n_rows ? double(M.nnz) / M.n_rows : 0.0;
   return (kWave * 4.0 * pcols(K) / K <= avg) ? 4 : 1;
 }

@@ -406,3 +406,31 @@ def test_fp32_graph_replay_matches_eager():
             assert ig["iterations"] == ie["iterations"] and torch.equal(xg, xe)
     he.close()
     hg.close()
+
+
+def test_autotuned_hierarchy_keeps_parity():
+    """Launch shapes chosen by eamg_autotune change summation order only: the V-cycle, the PCG
+    iterate and a batched panel solve stay within the FP64 bars against the oracle."""
+    p = make_problem(**CASES["cube17"])
+    ho = _oracle_cached("cube17", p)
+    hl = _lib(p)
+    before, after = E.eamg_autotune(hl.h, panel_width=8)
+    print(f"\n[autotune] tuned launch sequences {before:.3f} ms -> {after:.3f} ms", flush=True)
+    assert 0.0 < after <= before
+    r = np.random.default_rng(3).standard_normal(p.n_dofs)
+    r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    zo = oracle.vcycle(ho, r)
+    z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+    E.eamg_vcycle(hl.h, _dev(r), z)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) <= X_TOL
+    xo, it, _, _, _ = oracle.pcg(ho, p.b, rtol=1e-8)
+    xk, info = hl.solve(_dev(p.b), rtol=0.0, max_it=it)
+    assert np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo) <= X_TOL
+    B = np.stack([p.b, -0.5 * p.b, np.roll(p.b, 3 * 17)])
+    B[:, np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    X, st, infos = hl.solve_batch(_dev(B), rtol=0.0, max_it=it)
+    for c in range(3):
+        xc, _, _, _, _ = oracle.pcg(ho, B[c], rtol=0.0, max_it=it)
+        assert np.linalg.norm(X[c].cpu().numpy() - xc) / np.linalg.norm(xc) <= X_TOL
+    hl.close()
