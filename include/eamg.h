@@ -189,6 +189,48 @@ eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const double *B_de
                              double *X_dev, const eamg_solve_params *params, void *stream,
                              eamg_solve_info *infos);
 
+/* ---- learned coarsening: edge-scoring network ---------------------------------------------
+ *
+ * A three-layer graph network scores the candidate pairs of a matching pass (Algorithm
+ * alg:pwagg) with the logit of "the exact criterion (mu_b, and mu_g for larger unions;
+ * Thm thm:mu1, Lemma thm:mu2) accepts this pair".  Per pair it reads EAMG_GNN_FEATURES inputs
+ * built from the quantities of the criteria (log mu_s; the spectrum of E^{ij} / tr E^{ij}; the
+ * traces of D-hat and M at both ends; the aggregate sizes; the trace-strength ratio):
+ *   a1 = W1 x + b1, h1 = relu(a1); m_i = mean of h1 over the candidate pairs at node i;
+ *   a2 = W2a h1 + W2b (m_u + m_v) + b2, h2 = relu(a2); z = w3 . h2 + b3.
+ * Hidden width 64; W1, W2a, W2b, w3 are used rounded to bfloat16, all sums are FP32.
+ * Parameters are EAMG_GNN_PARAMS floats packed as W1 (64 x 12, row-major), b1 (64),
+ * W2a (64 x 64), W2b (64 x 64), b2 (64), w3 (64), b3 (1).
+ * Graph arguments are HOST arrays: X (m x 12 floats), edges (m x 2 int32 node ids in [0, n),
+ * distinct ends), labels y and weights w (m floats; weight 0 = unlabelled).  The network and all
+ * its arithmetic run on the GPU; parameters live on the device.
+ */
+#define EAMG_GNN_FEATURES 12
+#define EAMG_GNN_PARAMS 9153
+typedef struct eamg_gnn eamg_gnn;
+
+/* New network from params (HOST, EAMG_GNN_PARAMS floats) or, if params is NULL, from a seeded
+ * He-uniform initialisation (biases 0).  INVALID_ARG for non-finite parameters. */
+eamg_status eamg_gnn_create(const float *params, uint64_t seed, eamg_gnn **out);
+/* Copy the current FP32 parameters to params (HOST, EAMG_GNN_PARAMS floats). */
+eamg_status eamg_gnn_params(const eamg_gnn *g, float *params);
+/* Logits of the m pairs (HOST output, m floats). */
+eamg_status eamg_gnn_forward(eamg_gnn *g, int64_t m, int32_t n, const float *X,
+                             const int32_t *edges, float *logits);
+/* Weighted mean binary cross-entropy of the logits against y and its gradient with respect to
+ * the parameters (as used: the gradient of the bfloat16-rounded weights is applied to the FP32
+ * masters).  loss, grad (HOST, EAMG_GNN_PARAMS) may be NULL. */
+eamg_status eamg_gnn_loss_grad(eamg_gnn *g, int64_t m, int32_t n, const float *X,
+                               const int32_t *edges, const float *y, const float *w, double *loss,
+                               float *grad);
+/* Adam (beta 0.9 / 0.999, eps 1e-8, step lr) over `epochs` passes of the ngraphs graphs, one
+ * step per graph.  loss_history (HOST, epochs floats, may be NULL): mean loss per epoch. */
+eamg_status eamg_gnn_train(eamg_gnn *g, int32_t ngraphs, const int64_t *m, const int32_t *n,
+                           const float *const *X, const int32_t *const *edges,
+                           const float *const *y, const float *const *w, int32_t epochs, float lr,
+                           float *loss_history);
+void eamg_gnn_destroy(eamg_gnn *g);
+
 /*
  * Autotuner: measure candidate launch shapes on this hierarchy's own matrices (events on
  * `stream`, median of 5) and keep the fastest.  Single right-hand side: lanes per block row of

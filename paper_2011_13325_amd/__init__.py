@@ -37,7 +37,8 @@ EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setu
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
             "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
-            "eamg_autotune"]
+            "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
+            "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -104,6 +105,19 @@ def lib():
     L.eamg_solve.restype = ctypes.c_int
     L.eamg_solve_batch.argtypes = [vp, i32, vp, i64, vp, P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve_batch.restype = ctypes.c_int
+    fp = P(ctypes.c_float)
+    L.eamg_gnn_create.argtypes = [vp, ctypes.c_uint64, P(vp)]
+    L.eamg_gnn_create.restype = ctypes.c_int
+    L.eamg_gnn_params.argtypes = [vp, vp]
+    L.eamg_gnn_params.restype = ctypes.c_int
+    L.eamg_gnn_forward.argtypes = [vp, i64, i32, vp, vp, vp]
+    L.eamg_gnn_forward.restype = ctypes.c_int
+    L.eamg_gnn_loss_grad.argtypes = [vp, i64, i32, vp, vp, vp, vp, P(dp), vp]
+    L.eamg_gnn_loss_grad.restype = ctypes.c_int
+    L.eamg_gnn_train.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, i32, ctypes.c_float, vp]
+    L.eamg_gnn_train.restype = ctypes.c_int
+    L.eamg_gnn_destroy.argtypes = [vp]
+    L.eamg_gnn_destroy.restype = None
     L.eamg_autotune.argtypes = [vp, i32, vp, P(dp), P(dp)]
     L.eamg_autotune.restype = ctypes.c_int
     L.eamg_solve_multi.argtypes = [i32, P(vp), P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
@@ -250,6 +264,89 @@ def eamg_solve_multi(hs, bs, xs, rtol=1e-8, max_it=1000, use_x0=False, precond=T
         raise EamgError(st, "eamg_solve_multi")
     return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
                      ms=i.ms, status=i.status) for i in infos]
+
+
+GNN_FEATURES = 12
+GNN_PARAMS = 9153
+
+
+class EdgeNet:
+    """The edge-scoring network (eamg_gnn_*): parameters on the device, host arrays in/out."""
+
+    def __init__(self, params=None, seed=0):
+        h = ctypes.c_void_p()
+        pp = None
+        if params is not None:
+            self._p = np.ascontiguousarray(params, dtype=np.float32)
+            assert self._p.size == GNN_PARAMS
+            pp = _ptr(self._p)
+        st = lib().eamg_gnn_create(pp, int(seed), ctypes.byref(h))
+        if st != EAMG_OK:
+            raise EamgError(st, "eamg_gnn_create")
+        self.h = h
+
+    @staticmethod
+    def _graph(X, edges):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        edges = np.ascontiguousarray(edges, dtype=np.int32)
+        assert X.ndim == 2 and X.shape[1] == GNN_FEATURES and edges.shape == (X.shape[0], 2)
+        return X, edges
+
+    def params(self):
+        out = np.zeros(GNN_PARAMS, dtype=np.float32)
+        st = lib().eamg_gnn_params(self.h, _ptr(out))
+        if st != EAMG_OK:
+            raise EamgError(st, "eamg_gnn_params")
+        return out
+
+    def forward(self, X, edges, n):
+        X, edges = self._graph(X, edges)
+        z = np.zeros(X.shape[0], dtype=np.float32)
+        st = lib().eamg_gnn_forward(self.h, X.shape[0], int(n), _ptr(X), _ptr(edges), _ptr(z))
+        if st != EAMG_OK:
+            raise EamgError(st, "eamg_gnn_forward")
+        return z
+
+    def loss_grad(self, X, edges, n, y, w):
+        X, edges = self._graph(X, edges)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        loss = ctypes.c_double()
+        g = np.zeros(GNN_PARAMS, dtype=np.float32)
+        st = lib().eamg_gnn_loss_grad(self.h, X.shape[0], int(n), _ptr(X), _ptr(edges), _ptr(y),
+                                      _ptr(w), ctypes.byref(loss), _ptr(g))
+        if st != EAMG_OK:
+            raise EamgError(st, "eamg_gnn_loss_grad")
+        return loss.value, g
+
+    def train(self, graphs, epochs, lr=3e-3):
+        """graphs: list of (X, edges, n, y, w).  Returns the mean loss per epoch."""
+        keep = []
+        for X, edges, n, y, w in graphs:
+            X, edges = self._graph(X, edges)
+            keep.append((X, edges, int(n), np.ascontiguousarray(y, dtype=np.float32),
+                         np.ascontiguousarray(w, dtype=np.float32)))
+        k = len(keep)
+        ms = np.array([g[0].shape[0] for g in keep], dtype=np.int64)
+        ns = np.array([g[2] for g in keep], dtype=np.int32)
+        arr = lambda i: (ctypes.c_void_p * k)(*[g[i].ctypes.data for g in keep])
+        hist = np.zeros(epochs, dtype=np.float32)
+        st = lib().eamg_gnn_train(self.h, k, _ptr(ms), _ptr(ns), arr(0), arr(1), arr(3), arr(4),
+                                  int(epochs), float(lr), _ptr(hist))
+        if st != EAMG_OK:
+            raise EamgError(st, "eamg_gnn_train")
+        return hist
+
+    def close(self):
+        if self.h is not None:
+            lib().eamg_gnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def eamg_autotune(h, panel_width=0, stream=None):

@@ -787,7 +787,9 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       for (size_t u = 0; u < unknown.size(); ++u) known.emplace(key(unknown[u].first, unknown[u].second), val[u]);
       n_eval += long(unknown.size());
     }
-    if (tm.on) std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel\n", walks, n_eval);
+    if (tm.on)
+      std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel, %zu pairs formed, %zu singles\n",
+                   walks, n_eval, pairs.size(), singles.size());
     tm.mark("matching pass");
     std::vector<std::vector<int>> groups;
     for (const auto &pq : pairs) groups.push_back({pq.first, pq.second});
