@@ -95,7 +95,17 @@ typedef struct {
  *  vcycle_fp32        0: FP64 V-cycle only (default).  1: also keep FP32 copies of the V-cycle
  *                     matrices (A_l, P_s, R, D^+) and FP32 level vectors, so that solves and
  *                     V-cycles may ask for EAMG_PRECOND_VCYCLE_FP32 (about +50% V-cycle memory).
+ *  gnn, gnn_skip      learned walk (NULL / 0: the exact walk, default).  With a network (see
+ *                     eamg_gnn_*) and gnn_skip in (0, 1): in every matching pass the candidate
+ *                     pairs are scored once on the GPU; the walk passes over candidates whose
+ *                     predicted acceptance is below gnn_skip without evaluating mu_b / mu_g, and
+ *                     a vertex whose candidates were all passed over evaluates its best scored
+ *                     one.  Every pair formed is accepted by the exact criteria.  The network
+ *                     is borrowed for the call only.
+ *  gnn_record         1: keep every pass's candidate pairs with features and exact labels
+ *                     (eamg_gnn_samples), for training.  Default 0.
  */
+typedef struct eamg_gnn eamg_gnn;
 typedef struct {
   double sigma;
   int32_t delta, R, rounds, coarsest_max_dofs, max_levels;
@@ -103,6 +113,9 @@ typedef struct {
   int32_t cap_aux, cap_std_l0, cap_std;
   double pinv_rtol, tie_rtol;
   int32_t vcycle_fp32;
+  const eamg_gnn *gnn;
+  double gnn_skip;
+  int32_t gnn_record;
 } eamg_setup_params;
 
 /* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,
@@ -207,7 +220,6 @@ eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const double *B_de
  */
 #define EAMG_GNN_FEATURES 12
 #define EAMG_GNN_PARAMS 9153
-typedef struct eamg_gnn eamg_gnn;
 
 /* New network from params (HOST, EAMG_GNN_PARAMS floats) or, if params is NULL, from a seeded
  * He-uniform initialisation (biases 0).  INVALID_ARG for non-finite parameters. */
@@ -230,6 +242,17 @@ eamg_status eamg_gnn_train(eamg_gnn *g, int32_t ngraphs, const int64_t *m, const
                            const float *const *y, const float *const *w, int32_t epochs, float lr,
                            float *loss_history);
 void eamg_gnn_destroy(eamg_gnn *g);
+
+/* Coarsening statistics of a hierarchy (HOST outputs, any may be NULL): criteria evaluations of
+ * the matching walks (mu_b; evaluated_g of them also mu_g), candidates the learned walk passed
+ * over, and the number of recorded passes (gnn_record). */
+eamg_status eamg_coarsening_stats(const eamg_hierarchy *h, int64_t *evaluated, int64_t *evaluated_g,
+                                  int64_t *skipped, int32_t *sample_passes);
+/* Recorded pass `pass` (gnn_record = 1): m candidate pairs over n working-level vertices, their
+ * features X (m x 12), ends (m x 2), labels y (1: the exact criteria accept) and weights w (1:
+ * evaluated by the walk, 0: unlabelled).  HOST arrays sized from a first call with NULLs. */
+eamg_status eamg_gnn_samples(const eamg_hierarchy *h, int32_t pass, int64_t *m, int32_t *n, float *X,
+                             int32_t *edges, float *y, float *w);
 
 /*
  * Autotuner: measure candidate launch shapes on this hierarchy's own matrices (events on

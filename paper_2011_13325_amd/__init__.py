@@ -38,7 +38,8 @@ EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setu
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
             "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
             "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
-            "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy"]
+            "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy", "eamg_coarsening_stats",
+            "eamg_gnn_samples"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -56,7 +57,9 @@ class eamg_setup_params(ctypes.Structure):
                 ("max_levels", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("cap_aux", ctypes.c_int32), ("cap_std_l0", ctypes.c_int32),
                 ("cap_std", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
-                ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32)]
+                ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32),
+                ("gnn", ctypes.c_void_p), ("gnn_skip", ctypes.c_double),
+                ("gnn_record", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):
@@ -118,6 +121,10 @@ def lib():
     L.eamg_gnn_train.restype = ctypes.c_int
     L.eamg_gnn_destroy.argtypes = [vp]
     L.eamg_gnn_destroy.restype = None
+    L.eamg_coarsening_stats.argtypes = [vp, P(i64), P(i64), P(i64), P(i32)]
+    L.eamg_coarsening_stats.restype = ctypes.c_int
+    L.eamg_gnn_samples.argtypes = [vp, i32, P(i64), P(i32), vp, vp, vp, vp]
+    L.eamg_gnn_samples.restype = ctypes.c_int
     L.eamg_autotune.argtypes = [vp, i32, vp, P(dp), P(dp)]
     L.eamg_autotune.restype = ctypes.c_int
     L.eamg_solve_multi.argtypes = [i32, P(vp), P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
@@ -347,6 +354,33 @@ class EdgeNet:
             self.close()
         except Exception:
             pass
+
+
+def eamg_coarsening_stats(h):
+    ev, eg, sk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    npass = ctypes.c_int32()
+    st = lib().eamg_coarsening_stats(h, ctypes.byref(ev), ctypes.byref(eg), ctypes.byref(sk),
+                                     ctypes.byref(npass))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_coarsening_stats")
+    return dict(evaluated=ev.value, evaluated_g=eg.value, skipped=sk.value, sample_passes=npass.value)
+
+
+def eamg_gnn_samples(h, k):
+    """Recorded pass k: (X, edges, n, y, w)."""
+    m, n = ctypes.c_int64(), ctypes.c_int32()
+    st = lib().eamg_gnn_samples(h, int(k), ctypes.byref(m), ctypes.byref(n), None, None, None, None)
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_gnn_samples")
+    X = np.zeros((m.value, GNN_FEATURES), dtype=np.float32)
+    edges = np.zeros((m.value, 2), dtype=np.int32)
+    y = np.zeros(m.value, dtype=np.float32)
+    w = np.zeros(m.value, dtype=np.float32)
+    st = lib().eamg_gnn_samples(h, int(k), ctypes.byref(m), ctypes.byref(n), _ptr(X), _ptr(edges),
+                                _ptr(y), _ptr(w))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_gnn_samples")
+    return X, edges, n.value, y, w
 
 
 def eamg_autotune(h, panel_width=0, stream=None):

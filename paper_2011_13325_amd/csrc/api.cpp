@@ -15,6 +15,7 @@
 #include "../../include/eamg.h"
 #include "coarsen.hpp"
 #include "dense.hpp"
+#include "gnn_host.hpp"
 #include "hierarchy.hpp"
 #include "kernels.hpp"
 #include "structure.hpp"
@@ -40,6 +41,9 @@ eamg_setup_params defaults() {
   p.pinv_rtol = 1e-10;
   p.tie_rtol = 1e-12;
   p.vcycle_fp32 = 0;
+  p.gnn = nullptr;
+  p.gnn_skip = 0.0;
+  p.gnn_record = 0;
   return p;
 }
 
@@ -58,6 +62,8 @@ void validate_params(const eamg_setup_params &p) {
   if (!(p.pinv_rtol > 0.0 && p.pinv_rtol <= 1e-2)) fail(EAMG_ERR_INVALID_ARG, "pinv_rtol must be in (0, 1e-2]");
   if (!(p.tie_rtol >= 0.0 && p.tie_rtol <= 1e-6)) fail(EAMG_ERR_INVALID_ARG, "tie_rtol must be in [0, 1e-6]");
   if (p.vcycle_fp32 != 0 && p.vcycle_fp32 != 1) fail(EAMG_ERR_INVALID_ARG, "vcycle_fp32 must be 0 or 1");
+  if (!(p.gnn_skip >= 0.0 && p.gnn_skip < 1.0)) fail(EAMG_ERR_INVALID_ARG, "gnn_skip must be in [0, 1)");
+  if (p.gnn_record != 0 && p.gnn_record != 1) fail(EAMG_ERR_INVALID_ARG, "gnn_record must be 0 or 1");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -817,6 +823,16 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     mp.rounds = prm.rounds;
     mp.tie_rtol = prm.tie_rtol;
     mp.tau = prm.pinv_rtol;
+    mp.record = prm.gnn_record != 0;
+    if (prm.gnn && prm.gnn_skip > 0.0) {
+      eamg_gnn *net = const_cast<eamg_gnn *>(prm.gnn);
+      mp.skip = prm.gnn_skip;
+      mp.scorer = [net, s](const PassSamples &ps, std::vector<float> &z) {
+        DeviceGraph dg(int64_t(ps.edges.size() / 2), ps.n, ps.X.data(), ps.edges.data(), nullptr,
+                       nullptr, s);
+        gnn_logits(net, dg, s, z);
+      };
+    }
     while (true) {
       const size_t l = h->lv.size() - 1;
       {
@@ -824,6 +840,10 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
         if (int64_t(L.bs) * L.n < prm.coarsest_max_dofs || int(h->lv.size()) >= prm.max_levels) break;
       }
       MatchResult mr = successive_matching(aux, l == 0 ? vd : std::vector<char>(), mp);
+      h->crit_evaluated += mr.evaluated;
+      h->crit_evaluated_g += mr.evaluated_g;
+      h->crit_skipped += mr.skipped;
+      for (auto &smp : mr.samples) h->samples.push_back(std::move(smp));
       const int nc = int(mr.aggs.size());
       if (nc == 0 || double(nc) > 0.9 * h->lv[l].n) break;
       Level &L = h->lv[l];
@@ -924,6 +944,33 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
               "hipHostMalloc");
     hip_check(hipStreamSynchronize(s), "sync");
     *out = h.release();
+  });
+}
+
+eamg_status eamg_coarsening_stats(const eamg_hierarchy *h, int64_t *evaluated, int64_t *evaluated_g,
+                                  int64_t *skipped, int32_t *sample_passes) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (evaluated) *evaluated = h->crit_evaluated;
+    if (evaluated_g) *evaluated_g = h->crit_evaluated_g;
+    if (skipped) *skipped = h->crit_skipped;
+    if (sample_passes) *sample_passes = int32_t(h->samples.size());
+  });
+}
+
+eamg_status eamg_gnn_samples(const eamg_hierarchy *h, int32_t pass, int64_t *m, int32_t *n, float *X,
+                             int32_t *edges, float *y, float *w) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (pass < 0 || pass >= int(h->samples.size())) fail(EAMG_ERR_INVALID_ARG, "pass out of range");
+    const PassSamples &ps = h->samples[size_t(pass)];
+    const size_t np = ps.edges.size() / 2;
+    if (m) *m = int64_t(np);
+    if (n) *n = ps.n;
+    if (X) std::copy(ps.X.begin(), ps.X.end(), X);
+    if (edges) std::copy(ps.edges.begin(), ps.edges.end(), edges);
+    if (y) std::copy(ps.y.begin(), ps.y.end(), y);
+    if (w) std::copy(ps.w.begin(), ps.w.end(), w);
   });
 }
 

@@ -484,6 +484,27 @@ double mu_s(const AuxLevel &lev, int i, int j, const std::vector<double> &mtr) {
   return std::sqrt(mtr[i] * mtr[j]) / t;
 }
 
+// Features of candidate pair (i, j) (edge e): log mu_s, the spectrum of sym(E^{ij}) / tr E^{ij}
+// (descending, padded), log of the smaller and larger tr D-hat over tr E^{ij}, log(1 + sum of
+// tr M / tr D-hat at both ends), the aggregate sizes / 4, |log| of the trace-strength ratio.
+void pair_features(const AuxLevel &lev, int i, int j, int e, const std::vector<Sq> &D,
+                   const std::vector<double> &mtr, int nmem_i, int nmem_j, float *f) {
+  const Sq Ee = lev.Emat(e);
+  const double t = sq_trace(Ee);
+  double w[6] = {0, 0, 0, 0, 0, 0};
+  Sq V;
+  sq_eigh(sq_sym(Ee), w, V);
+  for (int q = 0; q < kPairFeatures; ++q) f[q] = 0.0f;
+  f[0] = float(std::log(std::sqrt(mtr[i] * mtr[j]) / t));
+  for (int q = 0; q < lev.k && q < 6; ++q) f[1 + q] = float(w[lev.k - 1 - q] / t);
+  const double di = sq_trace(D[i]), dj = sq_trace(D[j]);
+  f[7] = float(std::log(std::min(di, dj) / t));
+  f[8] = float(std::log(std::max(di, dj) / t));
+  f[9] = float(std::log1p(sq_trace(lev.Mmat(i)) / di + sq_trace(lev.Mmat(j)) / dj));
+  f[10] = float(double(nmem_i + nmem_j) / 4.0);
+  f[11] = float(std::fabs(std::log(mtr[i] / mtr[j])));
+}
+
 double mu_b(const AuxLevel &lev, int i, int j, const std::vector<Sq> &D, double tau) {
   const int k = lev.k;
   const double *xi = lev.xp(i), *xj = lev.xp(j);
@@ -701,6 +722,41 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
     known.clear();
     const int64_t nw = work->n;
     auto key = [nw](int ci, int cj) { return int64_t(ci) * nw + cj; };
+    // candidate pairs of the pass (both ends free, mu_s < sigma), scored by the learned model
+    const bool learned = bool(prm.scorer) && prm.skip > 0.0;
+    PassSamples ps;
+    std::unordered_map<int64_t, float> prob;
+    if (learned || prm.record) {
+      ps.n = work->n;
+      for (int i = 0; i < work->n; ++i) {
+        if (!in_T[i]) continue;
+        for (int64_t q = work->nb_ptr[i]; q < work->nb_ptr[i + 1]; ++q) {
+          const int j = work->nb[q];
+          if (j <= i || !in_T[j]) continue;
+          if (!(mu_s(*work, i, j, mtr) < sigma)) continue;
+          ps.edges.push_back(i);
+          ps.edges.push_back(j);
+        }
+      }
+      const size_t np = ps.edges.size() / 2;
+      ps.X.assign(np * kPairFeatures, 0.0f);
+      parallel_for(int64_t(np), [&](int64_t q) {
+        const int i = ps.edges[2 * q], j = ps.edges[2 * q + 1];
+        pair_features(*work, i, j, work->edge_id(i, j), *wdhat, mtr, int(members[i].size()),
+                      int(members[j].size()), &ps.X[size_t(q) * kPairFeatures]);
+      });
+      if (learned && np > 0) {
+        std::vector<float> z;
+        prm.scorer(ps, z);
+        for (size_t q = 0; q < np; ++q) {
+          const float pr = 1.0f / (1.0f + std::exp(-z[q]));
+          prob[key(ps.edges[2 * q], ps.edges[2 * q + 1])] = pr;
+          prob[key(ps.edges[2 * q + 1], ps.edges[2 * q])] = pr;
+        }
+      }
+    }
+    tm.mark("candidate scores");
+    int64_t w_eval = 0, w_eval_g = 0, w_skip = 0;
     std::vector<std::pair<int, int>> pairs;
     std::vector<int> singles;
     std::vector<std::pair<int, int>> unknown;
@@ -712,6 +768,7 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       singles.clear();
       unknown.clear();
       MatchResult notes;   // margins and ties of this walk
+      w_eval = w_eval_g = w_skip = 0;
       auto note_w = [&](double mu) {
         if (std::isfinite(mu)) notes.min_margin = std::min(notes.min_margin, std::fabs(mu - sigma) / sigma);
       };
@@ -729,6 +786,27 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           if (ms < sigma) cands.emplace_back(cj, ms);
         }
         int matched = -1;
+        // the exact criteria for (ci, cj), or an optimistic pass when not known yet
+        auto check = [&](int cj) {
+          ++w_eval;
+          const auto it = known.find(key(ci, cj));
+          if (it == known.end()) {
+            unknown.emplace_back(ci, cj);
+            return true;   // optimistic
+          }
+          const Crit &c = it->second;
+          note_w(c.mub);
+          bool ok = c.mub < sigma;
+          if (ok && !std::isnan(c.mug)) {
+            ++w_eval_g;
+            note_w(c.mug);
+            ok = c.mug < sigma;
+          }
+          return ok;
+        };
+        bool any_checked = false;
+        int pass_over = -1;       // best scored candidate passed over
+        float pass_over_p = -1.0f;
         while (!cands.empty()) {
           double mmin = cands[0].second;
           for (const auto &c : cands) mmin = std::min(mmin, c.second);
@@ -740,26 +818,28 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
             }
           notes.max_tie = std::max(notes.max_tie, ntie);
           const int cj = cands[best].first;
-          const auto it = known.find(key(ci, cj));
-          bool ok;
-          if (it == known.end()) {
-            unknown.emplace_back(ci, cj);
-            ok = true;   // optimistic
-          } else {
-            const Crit &c = it->second;
-            note_w(c.mub);
-            ok = c.mub < sigma;
-            if (ok && !std::isnan(c.mug)) {
-              note_w(c.mug);
-              ok = c.mug < sigma;
+          if (learned) {
+            const auto pit = prob.find(key(ci, cj));
+            const float pr = pit == prob.end() ? 1.0f : pit->second;
+            if (pr < prm.skip) {
+              ++w_skip;
+              if (pr > pass_over_p) {
+                pass_over_p = pr;
+                pass_over = cj;
+              }
+              cands.erase(cands.begin() + best);
+              continue;
             }
           }
-          if (ok) {
+          any_checked = true;
+          if (check(cj)) {
             matched = cj;
             break;
           }
           cands.erase(cands.begin() + best);
         }
+        // fallback: every candidate was passed over -> the exact criteria decide the best scored
+        if (matched < 0 && !any_checked && pass_over >= 0 && check(pass_over)) matched = pass_over;
         if (matched >= 0) {
           pairs.emplace_back(ci, matched);
           inT[matched] = 0;
@@ -770,6 +850,9 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       if (unknown.empty()) {
         res.min_margin = std::min(res.min_margin, notes.min_margin);
         res.max_tie = std::max(res.max_tie, notes.max_tie);
+        res.evaluated += w_eval;
+        res.evaluated_g += w_eval_g;
+        res.skipped += w_skip;
         in_T = inT;
         break;
       }
@@ -788,8 +871,26 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       n_eval += long(unknown.size());
     }
     if (tm.on)
-      std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel, %zu pairs formed, %zu singles\n",
-                   walks, n_eval, pairs.size(), singles.size());
+      std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel, %zu pairs formed, %zu singles; "
+                   "walk: %lld evaluations (%lld with mu_g), %lld passed over\n",
+                   walks, n_eval, pairs.size(), singles.size(), (long long)w_eval, (long long)w_eval_g,
+                   (long long)w_skip);
+    if (prm.record) {
+      const size_t np = ps.edges.size() / 2;
+      ps.y.assign(np, 0.0f);
+      ps.w.assign(np, 0.0f);
+      for (size_t q = 0; q < np; ++q) {
+        const int i = ps.edges[2 * q], j = ps.edges[2 * q + 1];
+        auto it = known.find(key(i, j));
+        if (it == known.end()) it = known.find(key(j, i));
+        if (it == known.end()) continue;
+        const Crit &c = it->second;
+        const bool acc = c.mub < sigma && (std::isnan(c.mug) || c.mug < sigma);
+        ps.y[q] = acc ? 1.0f : 0.0f;
+        ps.w[q] = 1.0f;
+      }
+      res.samples.push_back(std::move(ps));
+    }
     tm.mark("matching pass");
     std::vector<std::vector<int>> groups;
     for (const auto &pq : pairs) groups.push_back({pq.first, pq.second});

@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <string>
 #include <atomic>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -74,11 +75,31 @@ void parallel_for_dynamic(int64_t n, F &&f, int64_t chunk = 64) {
   for (auto &x : th) x.join();
 }
 
+// Features of the candidate pairs of one matching pass (kPairFeatures per pair), for the
+// learned walk and for training: pairs (i, j) of working-level vertices, the graph's node count,
+// labels y (1: the exact criterion accepts) and weights w (1: the pair was evaluated).
+constexpr int kPairFeatures = 12;
+struct PassSamples {
+  int n = 0;
+  std::vector<int32_t> edges;   // 2 per pair
+  std::vector<float> X;         // kPairFeatures per pair
+  std::vector<float> y, w;
+};
+
+// Scores the candidate pairs of a pass: logits (one per pair) of "the exact criterion accepts".
+using PairScorer = std::function<void(const PassSamples &, std::vector<float> &)>;
+
 struct MatchParams {
   double sigma = 20.0;
   int rounds = 2;
   double tie_rtol = 1e-12;
   double tau = 1e-10;
+  // learned walk: candidates scored below `skip` (probability) are passed over without
+  // evaluating the criteria; a vertex whose candidates were all passed over evaluates its best
+  // scored one.  Every pair formed is accepted by the exact criteria.
+  PairScorer scorer;
+  double skip = 0.0;
+  bool record = false;   // keep every pass's candidate pairs, features and labels
 };
 
 struct AuxLevel {
@@ -105,6 +126,9 @@ struct MatchResult {
   AuxLevel coarse;
   double min_margin = 1e300;
   int max_tie = 0;
+  // criteria evaluations the walk made (mu_b; mu_g among them) and candidates it passed over
+  int64_t evaluated = 0, evaluated_g = 0, skipped = 0;
+  std::vector<PassSamples> samples;
 };
 
 // Build the finest level.  Returns false with err set on malformed input.

@@ -13,6 +13,7 @@
 
 #include "../../include/eamg.h"
 #include "kernels.hpp"
+#include "coarsen.hpp"
 #include "structure.hpp"
 
 namespace eamg {
@@ -206,6 +207,10 @@ struct eamg_hierarchy {
   bool graph_tried[2] = {false, false};
   // block-panel (multi right-hand side) workspace, allocated by the first batched call
   eamg::BatchWork *batch = nullptr;
+  // coarsening: criteria evaluations of the matching walks, candidates passed over by the
+  // learned walk, and (when asked for) every pass's candidate pairs with features and labels
+  int64_t crit_evaluated = 0, crit_evaluated_g = 0, crit_skipped = 0;
+  std::vector<eamg::PassSamples> samples;
   ~eamg_hierarchy() {
     eamg::destroy_batch(batch);
     for (hipGraphExec_t g : g_iter)
