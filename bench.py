@@ -10,7 +10,8 @@ HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerki
 coarsest factor) is timed separately and reported in the same line.  The same solve with the
 FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle", and the
 batched block-panel solve of 32 seeded load cases on the same hierarchy (FP64 and FP32 V-cycle)
-as "batched", and 16 independent cubes of uneven size solved together as "multi_mesh".
+as "batched", 16 independent cubes of uneven size solved together as "multi_mesh", and the
+learned coarsening against the exact one on a heterogeneous cube as "learned_coarsening".
 
 Prints ONE JSON line.
 """
@@ -32,6 +33,7 @@ def _args():
     ap.add_argument("--cpu-n", type=int, default=17, help="cube side of the oracle sample")
     ap.add_argument("--batch", type=int, default=32,
                     help="right-hand sides of the batched block-panel solve (0: skip)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarsening section")
     ap.add_argument("--multi", type=int, default=16,
                     help="independent meshes of the multi-system solve (0: skip)")
     return ap.parse_args()
@@ -189,6 +191,53 @@ def _multi_mesh(E, torch, steps, count=16, seed=4):
             "iterations": [i["iterations"] for i in infos]}
 
 
+def _learned(E, torch, n=40, inclusions=60):
+    """Learned coarsening on a heterogeneous cube (stiff spherical inclusions, E = 1e4): the
+    edge network is trained on the GPU on small meshes of the same kind (their exact
+    criterion decisions), then the exact and the learned walk build hierarchies of the n^3
+    mesh; criteria evaluations, setup time and PCG iterations are compared."""
+    from gen import make_problem
+
+    def hier(p, **kw):
+        return E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                           E.eamg_default_setup_params(**kw))
+
+    t0 = time.perf_counter()
+    graphs = []
+    for c, (m, inc, nu) in enumerate([(12, 8, 0.3), (14, 12, 0.4), (16, 16, 0.35), (13, 10, 0.45)]):
+        p = make_problem(m, inclusions=inc, nu=nu, geometry_seed=10 + c, seed=c)
+        h = hier(p, gnn_record=1)
+        for k in range(E.eamg_coarsening_stats(h.h)["sample_passes"]):
+            X, edges, nn, y, w = E.eamg_gnn_samples(h.h, k)
+            if len(y) and w.sum() > 0:
+                graphs.append((X, edges, nn, y, w))
+        h.close()
+    net = E.EdgeNet(seed=3)
+    hist = net.train(graphs, epochs=200, lr=3e-3)
+    train_s = time.perf_counter() - t0
+    p = make_problem(n, inclusions=inclusions, nu=0.35, geometry_seed=96, seed=5)
+    b = torch.tensor(p.b, device="cuda")
+    out = {"workload": f"elasticity cube {n}^3, {inclusions} stiff spherical inclusions (E=1e4), "
+                       f"nu=0.35; network trained on 4 meshes of 12^3..16^3",
+           "train_s": round(train_s, 3), "train_loss": [float(hist[0]), float(hist[-1])]}
+    for key, kw in (("exact", {}), ("learned", {"gnn": net.h.value, "gnn_skip": 0.2})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = hier(p, **kw)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        st = E.eamg_coarsening_stats(h.h)
+        _, info = h.solve(b)
+        out[key] = {"setup_s": round(setup_s, 3), "criteria_evaluations": st["evaluated"],
+                    "mu_g_evaluations": st["evaluated_g"], "passed_over": st["skipped"],
+                    "pcg_iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+                    "oc": round(h.stats()["oc"], 4)}
+        h.close()
+    net.close()
+    out["evaluations_saved"] = 1.0 - out["learned"]["criteria_evaluations"] / out["exact"]["criteria_evaluations"]
+    return out
+
+
 def main():
     args = _args()
     if args.gpus != 1:
@@ -259,6 +308,8 @@ def main():
             k: out["batched"][k]["value"] / value for k in ("fp64_vcycle", "fp32_vcycle")}
     if args.multi > 0:
         out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi)
+    if not args.no_learned:
+        out["learned_coarsening"] = _learned(E, torch)
     levels = []
     for l in range(st["n_levels"]):
         li = E.eamg_level_info_get(hier.h, l)
