@@ -17,6 +17,7 @@ Prints ONE JSON line.
 """
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -34,6 +35,8 @@ def _args():
     ap.add_argument("--batch", type=int, default=32,
                     help="right-hand sides of the batched block-panel solve (0: skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarsening section")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="run only the workload of the rocprofv3 counter passes (no JSON line)")
     ap.add_argument("--multi", type=int, default=16,
                     help="independent meshes of the multi-system solve (0: skip)")
     return ap.parse_args()
@@ -93,7 +96,8 @@ def _profiled(E, hier, b, x, steps, precond):
     dom = kstats[0]
     achieved = dom["bytes"] / (dom["total_ms"] / 1e3) / 1e9
     roof = {"bound": "hbm", "kernel": dom["name"], "achieved": achieved, "peak": 8000.0,
-            "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+            "unit": "GB/s", "frac": achieved / 8000.0, "traffic": _traffic(dom["name"]),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3,
             "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"]}
     kern = [{"name": k["name"], "launches_per_step": k["launches"] / steps,
@@ -238,8 +242,55 @@ def _learned(E, torch, n=40, inclusions=60):
     return out
 
 
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None if
+    the summary is for another kernel or kernels.hip has changed since it was measured."""
+    import hashlib
+    import re
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        txt = open(os.path.join(root, "profiles", "traffic_k_gs_color_cube64.md")).read()
+        src = open(os.path.join(root, "paper_2011_13325_amd", "csrc", "kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    k = re.search(r"^traffic_kernel: (.+)$", txt, re.M)
+    v = re.search(r"^traffic_bytes_per_launch: (\d+)$", txt, re.M)
+    h = re.search(r"^kernels_hip_sha256: ([0-9a-f]+)$", txt, re.M)
+    if not (k and v and h) or k.group(1).strip() != kernel:
+        return None
+    if hashlib.sha256(src).hexdigest() != h.group(1):
+        return None
+    return float(v.group(1))
+
+
+def _counter_pass():
+    """Workload of the rocprofv3 counter passes (profiles/traffic_*.md): a calibration copy of
+    64 MiB, then one FP64 solve of the bench problem with eager launches."""
+    os.environ["EAMG_GRAPH"] = "0"
+    import torch
+    import paper_2011_13325_amd as E
+    from gen import make_problem
+    torch.cuda.set_device(0)
+    n = 8 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    p = make_problem(64, seed=1)
+    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
+    E.eamg_autotune(h.h, 0)
+    x, info = h.solve(torch.tensor(p.b, device="cuda"))
+    torch.cuda.synchronize()
+    print(f"counter pass: copy of {8 * n} bytes; solve {info['iterations']} iterations", flush=True)
+    h.close()
+
+
 def main():
     args = _args()
+    if args.counter_pass:
+        _counter_pass()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
