@@ -278,7 +278,9 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
     L.color.assign(size_t(L.n), -1);
     L.color_ptr = {0, L.n};
   } else {
+    PhaseTimer tc;
     L.color = greedy_coloring(L.A, L.ncolors);
+    tc.mark("layout: colouring");
     L.color_ptr.assign(size_t(L.ncolors) + 1, 0);
     for (int c : L.color) L.color_ptr[c + 1]++;
     for (int c = 0; c < L.ncolors; ++c) L.color_ptr[c + 1] += L.color_ptr[c];
@@ -286,12 +288,15 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
     for (int i = 0; i < L.n; ++i) L.perm[fill[L.color[i]]++] = i;
     for (int r = 0; r < L.n; ++r) L.inv[L.perm[r]] = r;
   }
+  PhaseTimer tl;
   L.perm_d = ar.upload(L.perm, s);
   std::vector<int64_t> src;
   const Pattern Ap = permute_pattern(L.A, L.perm, L.inv, src);
+  tl.mark("layout: permute");
   std::vector<int> dg;
   const bool f32 = h->prm.vcycle_fp32 != 0;
   L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
+  tl.mark("layout: A planes");
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
   L.sh_spmv = matrix_shape(Ap);
@@ -305,6 +310,7 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
     }
     L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, stamp++);
   }
+  tl.mark("layout: launch shapes");
   if (coarsest) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
     L.x = ar.alloc<double>(size_t(L.n) * bs);
@@ -337,6 +343,7 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true, f32);
   L.sh_R = matrix_shape(Rp);
   L.sh_P = matrix_shape(Pp);
+  tl.mark("layout: D+ and transfers");
   L.r = ar.alloc<double>(size_t(L.n) * bs);
   if (l > 0) {
     L.b = ar.alloc<double>(size_t(L.n) * bs);
@@ -793,11 +800,13 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     h->k = pb->k_kernel;
     h->n0 = n;
     h->prm = prm;
+    PhaseTimer tm;
     AuxLevel aux;
     std::string err;
     if (!finest_aux(dim, n, pb->coords, pb->row_ptr, pb->col_idx, pb->vals, pb->edges, pb->n_edges,
                     aux, err))
       fail(EAMG_ERR_INVALID_ARG, err);
+    tm.mark("setup: finest weights");
     DevArena &ar = h->arena;
     {
       Level L0;
@@ -839,7 +848,9 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
         const Level &L = h->lv[l];
         if (int64_t(L.bs) * L.n < prm.coarsest_max_dofs || int(h->lv.size()) >= prm.max_levels) break;
       }
+      tm.mark("setup: level upload");
       MatchResult mr = successive_matching(aux, l == 0 ? vd : std::vector<char>(), mp);
+      tm.mark("setup: matching");
       h->crit_evaluated += mr.evaluated;
       h->crit_evaluated_g += mr.evaluated_g;
       h->crit_skipped += mr.skipped;
@@ -856,6 +867,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
                                                prm.tie_rtol);
       L.P = pl.P;
       L.kc = kc;
+      tm.mark("setup: P_s plan");
       const int64_t nP = L.P.nnz();
       // auxiliary smoothed prolongation, numeric (device)
       int *type_d = ar.upload(pl.type, s);
@@ -895,6 +907,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
       std::vector<int64_t> srcT;
       const Pattern Rt = transpose_pattern(L.P, srcT);
       Pattern Ac = spgemm_symbolic(Rt, AP);
+      tm.mark("setup: Galerkin symbolic");
       int *APcrow = ar.upload(crow_of(AP), s);
       int *APcol = ar.upload(AP.col, s);
       int64_t *APrp = ar.upload(AP.rp, s);
@@ -924,11 +937,14 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
                       (void *)APcrow, (void *)APcol, (void *)APrp, (void *)Rrp, (void *)Rcol,
                       (void *)srcT_d, (void *)Accrow, (void *)R_val, (void *)AP_val})
         ar.release(p);
+      tm.mark("setup: P_s / Galerkin numeric");
       aux = std::move(mr.coarse);
       h->lv.push_back(std::move(C));
     }
     coarsest_factor(h.get(), s);
+    tm.mark("setup: coarsest factor");
     for (size_t l = h->lv.size(); l-- > 0;) build_level_layout(h.get(), l, s);
+    tm.mark("setup: solve layout");
     const int64_t N0 = int64_t(n) * dim;
     h->x = ar.alloc<double>(size_t(N0));
     h->r = ar.alloc<double>(size_t(N0));

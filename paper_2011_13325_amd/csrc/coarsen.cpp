@@ -18,18 +18,6 @@ namespace {
 
 const double kInf = std::numeric_limits<double>::infinity();
 
-// Phase timing on stderr when EAMG_VERBOSE is set.
-struct PhaseTimer {
-  bool on;
-  std::chrono::steady_clock::time_point t0;
-  PhaseTimer() : on(std::getenv("EAMG_VERBOSE") != nullptr), t0(std::chrono::steady_clock::now()) {}
-  void mark(const char *what) {
-    if (!on) return;
-    const auto t1 = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "[eamg] %-28s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
-    t0 = t1;
-  }
-};
 
 // ---- small square matrices --------------------------------------------------------------
 
@@ -762,20 +750,47 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
     std::vector<std::pair<int, int>> unknown;
     int walks = 0;
     long n_eval = 0;
+    double t_walk = 0.0, t_eval = 0.0;
+    // Walk state; a walk resumes from the state just before the first vertex at which the
+    // previous walk used an unknown pair (everything before it was already exact).
+    struct WalkState {
+      size_t a = 0;                  // position in `order`
+      std::vector<char> inT;
+      size_t npairs = 0, nsingles = 0;
+      double min_margin = 1e300;
+      int max_tie = 0;
+      int64_t ev = 0, evg = 0, sk = 0;
+    };
+    WalkState ck;
+    ck.inT = in_T;
+    pairs.clear();
+    singles.clear();
     for (;;) {
       ++walks;
-      pairs.clear();
-      singles.clear();
+      const auto tw0 = std::chrono::steady_clock::now();
+      std::vector<char> inT = ck.inT;
+      pairs.resize(ck.npairs);
+      singles.resize(ck.nsingles);
+      double min_margin = ck.min_margin;
+      int max_tie = ck.max_tie;
+      w_eval = ck.ev;
+      w_eval_g = ck.evg;
+      w_skip = ck.sk;
       unknown.clear();
-      MatchResult notes;   // margins and ties of this walk
-      w_eval = w_eval_g = w_skip = 0;
+      WalkState next;
+      bool have_next = false;
       auto note_w = [&](double mu) {
-        if (std::isfinite(mu)) notes.min_margin = std::min(notes.min_margin, std::fabs(mu - sigma) / sigma);
+        if (std::isfinite(mu)) min_margin = std::min(min_margin, std::fabs(mu - sigma) / sigma);
       };
-      std::vector<char> inT = in_T;
       std::vector<std::pair<int, double>> cands;
-      for (int ci : order) {
+      for (size_t a = ck.a; a < order.size(); ++a) {
+        const int ci = order[a];
         if (!inT[ci]) continue;
+        // state before this vertex (scalars; inT is copied only if it becomes the next start)
+        const size_t np0 = pairs.size(), ns0 = singles.size();
+        const double mm0 = min_margin;
+        const int mt0 = max_tie;
+        const int64_t ev0 = w_eval, evg0 = w_eval_g, sk0 = w_skip;
         inT[ci] = 0;
         cands.clear();
         for (int64_t q = work->nb_ptr[ci]; q < work->nb_ptr[ci + 1]; ++q) {
@@ -791,6 +806,19 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           ++w_eval;
           const auto it = known.find(key(ci, cj));
           if (it == known.end()) {
+            if (!have_next) {
+              have_next = true;
+              next.a = a;
+              next.inT = inT;
+              next.inT[ci] = 1;
+              next.npairs = np0;
+              next.nsingles = ns0;
+              next.min_margin = mm0;
+              next.max_tie = mt0;
+              next.ev = ev0;
+              next.evg = evg0;
+              next.sk = sk0;
+            }
             unknown.emplace_back(ci, cj);
             return true;   // optimistic
           }
@@ -816,7 +844,7 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
               ++ntie;
               if (best < 0 || pos[cands[c].first] < pos[cands[best].first]) best = int(c);
             }
-          notes.max_tie = std::max(notes.max_tie, ntie);
+          max_tie = std::max(max_tie, ntie);
           const int cj = cands[best].first;
           if (learned) {
             const auto pit = prob.find(key(ci, cj));
@@ -847,15 +875,18 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           singles.push_back(ci);
         }
       }
+      t_walk += std::chrono::duration<double>(std::chrono::steady_clock::now() - tw0).count();
       if (unknown.empty()) {
-        res.min_margin = std::min(res.min_margin, notes.min_margin);
-        res.max_tie = std::max(res.max_tie, notes.max_tie);
+        res.min_margin = std::min(res.min_margin, min_margin);
+        res.max_tie = std::max(res.max_tie, max_tie);
         res.evaluated += w_eval;
         res.evaluated_g += w_eval_g;
         res.skipped += w_skip;
         in_T = inT;
         break;
       }
+      ck = std::move(next);
+      const auto te0 = std::chrono::steady_clock::now();
       std::vector<Crit> val(unknown.size());
       parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
         const int ci = unknown[u].first, cj = unknown[u].second;
@@ -869,12 +900,14 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       }, 16);
       for (size_t u = 0; u < unknown.size(); ++u) known.emplace(key(unknown[u].first, unknown[u].second), val[u]);
       n_eval += long(unknown.size());
+      t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - te0).count();
     }
     if (tm.on)
       std::fprintf(stderr, "[eamg]   %d walks, %ld pairs evaluated in parallel, %zu pairs formed, %zu singles; "
-                   "walk: %lld evaluations (%lld with mu_g), %lld passed over\n",
+                   "walk: %lld evaluations (%lld with mu_g), %lld passed over; walks %.3f s, "
+                   "parallel criteria %.3f s\n",
                    walks, n_eval, pairs.size(), singles.size(), (long long)w_eval, (long long)w_eval_g,
-                   (long long)w_skip);
+                   (long long)w_skip, t_walk, t_eval);
     if (prm.record) {
       const size_t np = ps.edges.size() / 2;
       ps.y.assign(np, 0.0f);

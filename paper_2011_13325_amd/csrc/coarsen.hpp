@@ -13,6 +13,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <string>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <atomic>
 #include <functional>
 #include <thread>
@@ -54,6 +57,19 @@ struct Sq {
   }
   double &operator()(int i, int j) { return a[i * k + j]; }
   double operator()(int i, int j) const { return a[i * k + j]; }
+};
+
+// Phase timing on stderr when EAMG_VERBOSE is set.
+struct PhaseTimer {
+  bool on;
+  std::chrono::steady_clock::time_point t0;
+  PhaseTimer() : on(std::getenv("EAMG_VERBOSE") != nullptr), t0(std::chrono::steady_clock::now()) {}
+  void mark(const char *what) {
+    if (!on) return;
+    const auto t1 = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[eamg] %-28s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+    t0 = t1;
+  }
 };
 
 // Parallel loop with dynamic chunks, for iterations of uneven cost.

@@ -130,25 +130,59 @@ Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src) {
 
 std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
   const int n = A.n_rows;
-  // smallest-last order: remove a vertex of minimum remaining degree (lowest id on ties)
-  std::vector<int> deg(static_cast<size_t>(n), 0);
-  for (int i = 0; i < n; ++i)
+  // smallest-last order: remove a vertex of minimum remaining degree (lowest id on ties).
+  // Indexed binary min-heap on the key (degree, id), one entry per vertex; a removal lowers
+  // its neighbours' keys in place.
+  std::vector<int64_t> key(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) {
+    int64_t d = 0;
     for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
-      if (A.col[p] != i) ++deg[i];
+      if (A.col[p] != i) ++d;
+    key[i] = (d << 32) | int64_t(i);
+  }
+  std::vector<int> heap(static_cast<size_t>(n)), where(static_cast<size_t>(n));
+  for (int i = 0; i < n; ++i) heap[i] = where[i] = i;
+  int size = n;
+  auto swap_at = [&](int a, int b) {
+    std::swap(heap[a], heap[b]);
+    where[heap[a]] = a;
+    where[heap[b]] = b;
+  };
+  auto sift_up = [&](int a) {
+    while (a > 0) {
+      const int par = (a - 1) / 2;
+      if (key[heap[par]] <= key[heap[a]]) break;
+      swap_at(a, par);
+      a = par;
+    }
+  };
+  auto sift_down = [&](int a) {
+    for (;;) {
+      const int l = 2 * a + 1, r = l + 1;
+      int m = a;
+      if (l < size && key[heap[l]] < key[heap[m]]) m = l;
+      if (r < size && key[heap[r]] < key[heap[m]]) m = r;
+      if (m == a) break;
+      swap_at(a, m);
+      a = m;
+    }
+  };
+  for (int a = n / 2 - 1; a >= 0; --a) sift_down(a);
   std::vector<char> removed(static_cast<size_t>(n), 0);
-  std::priority_queue<std::pair<int, int>, std::vector<std::pair<int, int>>, std::greater<>> heap;
-  for (int v = 0; v < n; ++v) heap.emplace(deg[v], v);
   std::vector<int> seq;
   seq.reserve(static_cast<size_t>(n));
-  while (!heap.empty()) {
-    const auto [d, v] = heap.top();
-    heap.pop();
-    if (removed[v] || d != deg[v]) continue;
+  while (size > 0) {
+    const int v = heap[0];
+    swap_at(0, size - 1);
+    --size;
+    sift_down(0);
     removed[v] = 1;
     seq.push_back(v);
     for (int64_t p = A.rp[v]; p < A.rp[v + 1]; ++p) {
       const int u = A.col[p];
-      if (u != v && !removed[u]) heap.emplace(--deg[u], u);
+      if (u == v || removed[u]) continue;
+      key[u] -= int64_t(1) << 32;
+      sift_up(where[u]);
     }
   }
   std::vector<int> color(static_cast<size_t>(n), -1);
