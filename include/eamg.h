@@ -37,7 +37,7 @@ typedef enum {
   EAMG_NOT_CONVERGED = 1,          /* warning: max_it reached, x holds the last iterate       */
   EAMG_ERR_INVALID_ARG = -1,       /* malformed input (message says which)                    */
   EAMG_ERR_UNSUPPORTED_KERNEL = -2,/* dim / k_kernel / kernel vectors not supported           */
-  EAMG_ERR_NOT_SPD = -3,           /* coarsest Cholesky met a non-positive pivot              */
+  EAMG_ERR_NOT_SPD = -3,           /* coarsest inversion met a non-positive pivot             */
   EAMG_ERR_BREAKDOWN = -4,         /* non-finite value, p.Ap <= 0 or r.z <= 0 in PCG          */
   EAMG_ERR_HIP = -5,               /* a HIP runtime call failed                               */
   EAMG_ERR_OOM = -6                /* device or host allocation failed                        */
@@ -85,7 +85,12 @@ typedef struct {
  *  delta              1 (neighbour term in mu_g / mu_b; only 1 is supported)
  *  R                  1 (candidate chosen by mu_s; only 1 is supported)
  *  rounds             matching passes per level N (default 2, 1..4)
- *  coarsest_max_dofs  level l is the coarsest once bs_l * n_l < this (default 500, <= 4000)
+ *  coarsest_max_dofs  level l is the coarsest once bs_l * n_l < this (default 500, <= 16384).
+ *                     The coarsest matrix, regularized (section on singular coarse levels), is
+ *                     inverted on the GPU at setup (dense, FP64, ld^2 doubles with ld = dofs
+ *                     rounded up to 128) and applied by one dense product per V-cycle: on one
+ *                     GPU a coarsest level of several thousand dofs replaces the many colour
+ *                     launches of the small levels below it.
  *  max_levels         maximum number of levels (default 25)
  *  omega              prolongation smoothing damping (default 2/3)
  *  cap_aux            columns per edge-matrix row of P_s (default 4, 1..16)

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libeamg.so")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp"]
-HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip"]
+HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip"]
 
 # Packed FP32 instructions are kept out of the device code (-packed-fp32-ops).
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

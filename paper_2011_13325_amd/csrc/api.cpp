@@ -52,8 +52,8 @@ void validate_params(const eamg_setup_params &p) {
   if (p.delta != 1) fail(EAMG_ERR_INVALID_ARG, "only delta = 1 is supported");
   if (p.R != 1) fail(EAMG_ERR_INVALID_ARG, "only R = 1 (mu_s candidate choice) is supported");
   if (p.rounds < 1 || p.rounds > 4) fail(EAMG_ERR_INVALID_ARG, "rounds must be in 1..4");
-  if (p.coarsest_max_dofs < 1 || p.coarsest_max_dofs > 4000)
-    fail(EAMG_ERR_INVALID_ARG, "coarsest_max_dofs must be in 1..4000");
+  if (p.coarsest_max_dofs < 1 || p.coarsest_max_dofs > kMaxCoarsestDofs)
+    fail(EAMG_ERR_INVALID_ARG, "coarsest_max_dofs must be in 1.." + std::to_string(kMaxCoarsestDofs));
   if (p.max_levels < 1 || p.max_levels > 64) fail(EAMG_ERR_INVALID_ARG, "max_levels must be in 1..64");
   if (!std::isfinite(p.omega)) fail(EAMG_ERR_INVALID_ARG, "omega must be finite");
   if (p.cap_aux < 1 || p.cap_aux > 16 || p.cap_std_l0 < 1 || p.cap_std_l0 > 16 || p.cap_std < 1 ||
@@ -360,49 +360,45 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
   Level &L = h->lv.back();
   const int bs = L.bs;
   const int N = L.n * bs;
-  if (N > 4000)
-    fail(EAMG_ERR_INVALID_ARG, "coarsening stalled: coarsest level has " + std::to_string(N) + " dofs");
+  if (N > kMaxCoarsestDofs)
+    fail(EAMG_ERR_INVALID_ARG, "coarsening stalled: coarsest level has " + std::to_string(N) +
+                                   " dofs (the direct solve takes at most " +
+                                   std::to_string(kMaxCoarsestDofs) + ")");
+  // regularization: the projector onto the kernel of every diagonal block
   const std::vector<double> vals = download(L.A_val, size_t(L.A.nnz()) * bs * bs, s);
-  Mat Ad(N, N);
-  for (int i = 0; i < L.n; ++i)
-    for (int64_t q = L.A.rp[i]; q < L.A.rp[i + 1]; ++q) {
-      const int j = L.A.col[q];
-      for (int a = 0; a < bs; ++a)
-        for (int c = 0; c < bs; ++c) Ad(i * bs + a, j * bs + c) = vals[size_t(q) * bs * bs + a * bs + c];
-    }
-  // regularization: add the projector onto the kernel of every diagonal block
+  std::vector<double> reg(size_t(L.n) * bs * bs, 0.0);
   for (int i = 0; i < L.n; ++i) {
+    int64_t qd = -1;
+    for (int64_t q = L.A.rp[i]; q < L.A.rp[i + 1]; ++q)
+      if (L.A.col[q] == i) qd = q;
     Mat blk(bs, bs);
-    for (int a = 0; a < bs; ++a)
-      for (int c = 0; c < bs; ++c) blk(a, c) = Ad(i * bs + a, i * bs + c);
+    if (qd >= 0)
+      for (int a = 0; a < bs; ++a)
+        for (int c = 0; c < bs; ++c) blk(a, c) = vals[size_t(qd) * bs * bs + a * bs + c];
     const Mat U0 = kernel_basis(blk, h->prm.pinv_rtol);
     for (int a = 0; a < bs; ++a)
       for (int c = 0; c < bs; ++c) {
         double v = 0.0;
         for (int t = 0; t < U0.c; ++t) v += U0(a, t) * U0(c, t);
-        Ad(i * bs + a, i * bs + c) += v;
+        reg[size_t(i) * bs * bs + a * bs + c] = v;
       }
   }
-  if (!cholesky(Ad)) fail(EAMG_ERR_NOT_SPD, "coarsest level matrix is not positive definite");
-  // Y = L^{-1} (forward substitution on the identity), A^{-1} = Y^T Y
-  Mat Y(N, N);
-  for (int c = 0; c < N; ++c)
-    for (int i = c; i < N; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int t = c; t < i; ++t) v -= Ad(i, t) * Y(t, c);
-      Y(i, c) = v / Ad(i, i);
-    }
-  std::vector<double> inv(size_t(N) * N, 0.0);
-  for (int i = 0; i < N; ++i)
-    for (int j = i; j < N; ++j) {
-      double v = 0.0;
-      for (int t = std::max(i, j); t < N; ++t) v += Y(t, i) * Y(t, j);
-      inv[size_t(i) * N + j] = v;
-      inv[size_t(j) * N + i] = v;
-    }
+  // dense assembly and in-place inversion on the device
+  const int ld = dense_ld(N);
   h->nL = N;
-  h->Ainv = h->arena.upload(inv, s);
-  hip_check(hipStreamSynchronize(s), "sync");
+  h->ldL = ld;
+  h->Ainv = h->arena.alloc<double>(size_t(ld) * ld);
+  double *reg_d = h->arena.upload(reg, s);
+  double *work = h->arena.alloc<double>(gj_work_doubles(ld));
+  int *flag = h->arena.alloc<int>(1);
+  hip_check(hipMemsetAsync(flag, 0, sizeof(int), s), "memset");
+  hip_check(launch_dense_assemble(L.n, bs, L.A_rp, L.A_col, L.A_val, reg_d, ld, h->Ainv, s), "dense_assemble");
+  hip_check(launch_gj_invert(ld, h->Ainv, work, flag, s), "gj_invert");
+  const int bad = download(flag, 1, s)[0];
+  h->arena.release(flag);
+  h->arena.release(work);
+  h->arena.release(reg_d);
+  if (bad) fail(EAMG_ERR_NOT_SPD, "coarsest level matrix is not positive definite");
 }
 
 template <class T>
@@ -413,7 +409,7 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * double(sizeof(T));
     timed(h, "coarsest", lvname(h, l, "k_dense_gemv<" + ty + ">"), by, s,
-          [&] { return launch_dense_gemv<T>(h->nL, h->Ainv, b, x, s); });
+          [&] { return launch_dense_gemv<T>(h->nL, h->ldL, h->Ainv, b, x, s); });
     return;
   }
   const LevelBufs<T> B = bufs<T>(L);

@@ -109,8 +109,8 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   Level &L = h->lv[l];
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * K * vs;
-    timed(h, "coarsest", lvname(h, l, "k_pdense<" + ty + ">"), by, s,
-          [&] { return launch_pdense<T>(h->nL, K, h->Ainv, b, x, s); });
+    timed(h, "coarsest", lvname(h, l, "k_dense_panel<" + ty + ">"), by, s,
+          [&] { return launch_dense_panel<T>(h->nL, h->ldL, K, h->Ainv, b, x, s); });
     return;
   }
   const int bs = L.bs;

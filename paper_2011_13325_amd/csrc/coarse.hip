@@ -1,0 +1,336 @@
+// Coarsest-level direct solve: device assembly of the dense regularized matrix, its in-place
+// blocked Gauss-Jordan inversion, and the dense products that apply the inverse (coarse.hpp).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "coarse.hpp"
+
+namespace eamg {
+
+namespace {
+
+constexpr int T64 = kDenseTile;
+constexpr int kThreads = 256;
+
+inline int cdiv(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+// ---- assembly ------------------------------------------------------------------------------
+
+// One thread per dof row (i, a): row i * bs + a of D gets the blocks of block row i of the
+// block CSR matrix (AoS bs x bs blocks), plus reg_i on the diagonal block.  D is zero on entry.
+__global__ void k_dense_assemble(int n, int bs, const int64_t *__restrict__ rp,
+                                 const int *__restrict__ col, const double *__restrict__ val,
+                                 const double *__restrict__ reg, int ld, double *__restrict__ D) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * bs) return;
+  const int i = int(t / bs), a = int(t % bs);
+  double *Dr = D + size_t(t) * ld;
+  for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
+    const int j = col[q];
+    for (int c = 0; c < bs; ++c) {
+      double v = val[size_t(q) * bs * bs + a * bs + c];
+      if (j == i) v += reg[size_t(i) * bs * bs + a * bs + c];
+      Dr[size_t(j) * bs + c] = v;
+    }
+  }
+}
+
+__global__ void k_dense_pad_identity(int N, int ld, double *D) {
+  const int i = N + int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < ld) D[size_t(i) * ld + i] = 1.0;
+}
+
+// ---- Gauss-Jordan inversion ----------------------------------------------------------------
+// Block step K with P = A_KK^{-1}:  A_KJ := P A_KJ (J != K),  A_IK := -A_IK P (I != K),
+// A_IJ := A_IJ - A_IK P A_KJ (I, J != K),  A_KK := P.  Without pivoting this needs every pivot
+// block (a Schur complement of A) to be invertible, which holds for SPD A.
+
+// P = A_KK^{-1} by unblocked Gauss-Jordan on the tile in LDS (the same step with scalars).
+__global__ __launch_bounds__(kThreads) void k_gj_pivot(int ld, int K, const double *__restrict__ A,
+                                                      double *__restrict__ P, int *flag) {
+  __shared__ double M[T64][T64 + 1];
+  __shared__ double rowk[T64], colk[T64];
+  const int t = threadIdx.x;
+  const double *Akk = A + size_t(K) * T64 * ld + size_t(K) * T64;
+  for (int e = t; e < T64 * T64; e += kThreads) M[e / T64][e % T64] = Akk[size_t(e / T64) * ld + e % T64];
+  __syncthreads();
+  bool bad = false;
+  for (int k = 0; k < T64; ++k) {
+    double piv = M[k][k];
+    if (!(piv > 0.0) || !isfinite(piv)) {   // the same value on every thread: a uniform branch
+      bad = true;
+      piv = 1.0;
+    }
+    if (t < T64) {
+      rowk[t] = (t == k ? 1.0 : M[k][t]) / piv;
+      colk[t] = M[t][k];
+    }
+    __syncthreads();
+    // rows i != k only: row k and column k are read from rowk / colk
+    for (int e = t; e < T64 * T64; e += kThreads) {
+      const int i = e / T64, j = e % T64;
+      if (i != k) M[i][j] = (j == k ? 0.0 : M[i][j]) - colk[i] * rowk[j];
+    }
+    if (t < T64) M[k][t] = rowk[t];
+    __syncthreads();
+  }
+  for (int e = t; e < T64 * T64; e += kThreads) P[e] = M[e / T64][e % T64];
+  if (bad && t == 0) *flag = 1;
+}
+
+// Row panel R_J = P A_KJ (J != K), R_K = P; saved column panel C_J = A_JK (J != K).
+// One workgroup per tile J; thread (ty, tx) computes rows 4 ty + p, columns tx + 16 q.
+__global__ __launch_bounds__(kThreads) void k_gj_panels(int ld, int K, const double *__restrict__ A,
+                                                       const double *__restrict__ P,
+                                                       double *__restrict__ R,
+                                                       double *__restrict__ C) {
+  __shared__ double Ps[T64][T64 + 1], Bs[T64][T64 + 1];
+  const int J = blockIdx.x, t = threadIdx.x;
+  double *Rj = R + size_t(J) * T64 * T64;
+  if (J == K) {
+    for (int e = t; e < T64 * T64; e += kThreads) Rj[e] = P[e];
+    return;
+  }
+  const double *Akj = A + size_t(K) * T64 * ld + size_t(J) * T64;
+  const double *Ajk = A + size_t(J) * T64 * ld + size_t(K) * T64;
+  double *Cj = C + size_t(J) * T64 * T64;
+  for (int e = t; e < T64 * T64; e += kThreads) {
+    const int i = e / T64, j = e % T64;
+    Ps[i][j] = P[e];
+    Bs[i][j] = Akj[size_t(i) * ld + j];
+    Cj[e] = Ajk[size_t(i) * ld + j];
+  }
+  __syncthreads();
+  const int ty = t / 16, tx = t % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+  for (int k = 0; k < T64; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] = Ps[ty * 4 + p][k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = Bs[k][tx + 16 * q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] = fma(a[p], b[q], acc[p][q]);
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Rj[(ty * 4 + p) * T64 + tx + 16 * q] = acc[p][q];
+}
+
+// Tile (I, J): I == K: A_KJ := R_J; else A_IJ := [J != K] A_IJ - C_I R_J.
+__global__ __launch_bounds__(kThreads) void k_gj_update(int ld, int K, double *__restrict__ A,
+                                                       const double *__restrict__ R,
+                                                       const double *__restrict__ C) {
+  __shared__ double Cs[T64][T64 + 1], Rs[T64][T64 + 1];
+  const int J = blockIdx.x, I = blockIdx.y, t = threadIdx.x;
+  double *Aij = A + size_t(I) * T64 * ld + size_t(J) * T64;
+  const double *Rj = R + size_t(J) * T64 * T64;
+  if (I == K) {
+    for (int e = t; e < T64 * T64; e += kThreads) Aij[size_t(e / T64) * ld + e % T64] = Rj[e];
+    return;
+  }
+  const double *Ci = C + size_t(I) * T64 * T64;
+  for (int e = t; e < T64 * T64; e += kThreads) {
+    Cs[e / T64][e % T64] = Ci[e];
+    Rs[e / T64][e % T64] = Rj[e];
+  }
+  const int ty = t / 16, tx = t % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      acc[p][q] = (J == K) ? 0.0 : Aij[size_t(ty * 4 + p) * ld + tx + 16 * q];
+  __syncthreads();
+  for (int k = 0; k < T64; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] = Cs[ty * 4 + p][k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = Rs[k][tx + 16 * q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] = fma(-a[p], b[q], acc[p][q]);
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Aij[size_t(ty * 4 + p) * ld + tx + 16 * q] = acc[p][q];
+}
+
+// A := (A + A^T) / 2; each unordered pair {i, j} belongs to one thread.
+__global__ void k_symmetrize(int ld, double *A) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(ld) * ld) return;
+  const int i = int(e / ld), j = int(e % ld);
+  if (i >= j) return;
+  const double v = 0.5 * (A[size_t(i) * ld + j] + A[size_t(j) * ld + i]);
+  A[size_t(i) * ld + j] = v;
+  A[size_t(j) * ld + i] = v;
+}
+
+// ---- application -----------------------------------------------------------------------------
+
+// y = D x: one wavefront per row; lane l reads columns 128 c + 2 l, 128 c + 1 + 2 l (one 16-byte
+// load) for every chunk c, four chunks in flight; the padding columns (>= n) are zero in D and
+// read as zero from x.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_dense_gemv(int n, int ld, const double *__restrict__ D,
+                                                        const T *__restrict__ x, T *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64;
+  if (row >= n) return;   // whole wavefronts
+  const double2 *Dr = reinterpret_cast<const double2 *>(D + size_t(row) * ld);
+  const int nc = ld / 128;
+  double acc0 = 0.0, acc1 = 0.0;
+  int c = 0;
+  for (; c + 4 <= nc; c += 4) {
+    double2 d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[u] = Dr[(c + u) * 64 + lane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = (c + u) * 128 + 2 * lane;
+      const double x0 = j < n ? double(x[j]) : 0.0;
+      const double x1 = j + 1 < n ? double(x[j + 1]) : 0.0;
+      acc0 = fma(d[u].x, x0, acc0);
+      acc1 = fma(d[u].y, x1, acc1);
+    }
+  }
+  for (; c < nc; ++c) {
+    const double2 d = Dr[c * 64 + lane];
+    const int j = c * 128 + 2 * lane;
+    const double x0 = j < n ? double(x[j]) : 0.0;
+    const double x1 = j + 1 < n ? double(x[j + 1]) : 0.0;
+    acc0 = fma(d.x, x0, acc0);
+    acc1 = fma(d.y, x1, acc1);
+  }
+  double acc = acc0 + acc1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = T(acc);
+}
+
+// Y = D X, K columns: a workgroup owns 16 rows and walks the columns in chunks of 64, the chunk
+// of D (16 x 64) and of X (64 x K) staged in LDS while the next chunk is loaded into registers.
+// Thread t computes column t mod K of rows t / K + a (256 / K).
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_dense_panel(int n, int ld, int K,
+                                                         const double *__restrict__ D,
+                                                         const T *__restrict__ X, T *__restrict__ Y) {
+  constexpr int RT = 16, CH = 64;
+  __shared__ double Ds[RT][CH + 1];
+  __shared__ double Xs[CH * 64];
+  const int t = threadIdx.x;
+  const int row0 = int(blockIdx.x) * RT;
+  const int k = t & (K - 1);
+  const int i0 = t / K;
+  const int rstep = kThreads / K;
+  const int nxe = CH * K;   // X entries of a chunk
+  double dreg[RT * CH / kThreads], xreg[CH * 64 / kThreads];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int q = 0; q < RT * CH / kThreads; ++q) {
+      const int e = t + kThreads * q, i = e / CH, c = e % CH;
+      dreg[q] = row0 + i < n ? D[size_t(row0 + i) * ld + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CH * 64 / kThreads; ++q) {
+      const int e = t + kThreads * q;
+      const int c = e / K, kk = e % K;
+      xreg[q] = (e < nxe && c0 + c < n) ? double(X[size_t(c0 + c) * K + kk]) : 0.0;
+    }
+  };
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  load(0);
+  for (int c0 = 0; c0 < ld; c0 += CH) {
+#pragma unroll
+    for (int q = 0; q < RT * CH / kThreads; ++q) {
+      const int e = t + kThreads * q;
+      Ds[e / CH][e % CH] = dreg[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CH * 64 / kThreads; ++q) {
+      const int e = t + kThreads * q;
+      if (e < nxe) Xs[e] = xreg[q];
+    }
+    __syncthreads();
+    if (c0 + CH < ld) load(c0 + CH);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + a * rstep;
+      if (i < RT)
+        for (int c = 0; c < CH; ++c) acc[a] = fma(Ds[i][c], Xs[c * K + k], acc[a]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + a * rstep;
+    if (i < RT && row0 + i < n) Y[size_t(row0 + i) * K + k] = T(acc[a]);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_dense_assemble(int n, int bs, const int64_t *rp, const int *col,
+                                 const double *val, const double *reg, int ld, double *D,
+                                 hipStream_t s) {
+  const int N = n * bs;
+  if (N > ld) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(D, 0, sizeof(double) * size_t(ld) * ld, s);
+  if (e != hipSuccess) return e;
+  if (N > 0) hipLaunchKernelGGL(k_dense_assemble, dim3(cdiv(N, 256)), dim3(256), 0, s, n, bs, rp, col, val, reg, ld, D);
+  if (ld > N) hipLaunchKernelGGL(k_dense_pad_identity, dim3(cdiv(ld - N, 256)), dim3(256), 0, s, N, ld, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_invert(int ld, double *A, double *work, int *flag, hipStream_t s) {
+  if (ld <= 0 || ld % 128 != 0) return hipErrorInvalidValue;
+  const int nt = ld / T64;
+  double *P = work;
+  double *R = P + T64 * T64;
+  double *C = R + size_t(nt) * T64 * T64;
+  for (int K = 0; K < nt; ++K) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kThreads), 0, s, ld, K, A, P, flag);
+    hipLaunchKernelGGL(k_gj_panels, dim3(nt), dim3(kThreads), 0, s, ld, K, A, P, R, C);
+    hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(kThreads), 0, s, ld, K, A, R, C);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv(int64_t(ld) * ld, 256)), dim3(256), 0, s, ld, A);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ld < n || ld % 128 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, s, n, ld, D, x, y);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_dense_panel(int n, int ld, int K, const double *D, const T *X, T *Y,
+                              hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ld < n || ld % 128 != 0 || K < 1 || K > 64 || (K & (K - 1))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_panel<T>, dim3(cdiv(n, 16)), dim3(kThreads), 0, s, n, ld, K, D, X, Y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_dense_gemv<double>(int, int, const double *, const double *, double *, hipStream_t);
+template hipError_t launch_dense_gemv<float>(int, int, const double *, const float *, float *, hipStream_t);
+template hipError_t launch_dense_panel<double>(int, int, int, const double *, const double *, double *, hipStream_t);
+template hipError_t launch_dense_panel<float>(int, int, int, const double *, const float *, float *, hipStream_t);
+
+}  // namespace eamg

@@ -1,0 +1,55 @@
+// Coarsest-level direct solve on the device (coarse.hip).
+//
+// The regularized coarsest matrix A_L + sum_i Pi_ker(A_L,ii) (section on singular coarse
+// levels: SPD by construction) is inverted once at setup, in place, by blocked Gauss-Jordan
+// elimination without pivoting; every V-cycle then applies the inverse as one dense
+// matrix-vector (or matrix-panel) product, a stream of n^2 doubles at HBM bandwidth.  On one
+// GPU this makes a coarsest level of thousands of dofs cheaper than the many colour launches of
+// the small levels it replaces.
+//
+// Storage: row-major with a leading dimension ld = n rounded up to a multiple of 128; before the
+// inversion the padding rows and columns hold the identity, so the padded matrix is diag(A, I)
+// and its inverse diag(A^{-1}, I): every kernel works on whole 64 x 64 tiles, and the columns
+// n..ld-1 of the first n rows of the inverse are exactly zero.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace eamg {
+
+constexpr int kDenseTile = 64;            // Gauss-Jordan block size
+constexpr int kMaxCoarsestDofs = 16384;   // inverse <= 2 GiB of FP64
+
+inline int dense_ld(int n) { return (n + 127) / 128 * 128; }
+
+// Scratch of launch_gj_invert: the inverted pivot block, the row panel and the saved column
+// panel of one block step.
+inline size_t gj_work_doubles(int ld) {
+  return size_t(kDenseTile) * kDenseTile + 2 * size_t(ld) * kDenseTile;
+}
+
+// D (ld x ld) := the n x n block CSR matrix (rp, col on the device; AoS bs x bs blocks in val)
+// with reg (n blocks of bs x bs, device) added to its diagonal blocks, zero elsewhere, and the
+// identity on the padding rows n * bs .. ld - 1.
+hipError_t launch_dense_assemble(int n, int bs, const int64_t *rp, const int *col,
+                                 const double *val, const double *reg, int ld, double *D,
+                                 hipStream_t s);
+
+// A (ld x ld, ld a multiple of 128, SPD) := A^{-1}, then symmetrized as (A + A^T) / 2.  *flag
+// (device int, zeroed by the caller) becomes 1 if a pivot is not positive and finite, i.e. A is
+// not positive definite (the result is then meaningless).  Deterministic.
+hipError_t launch_gj_invert(int ld, double *A, double *work, int *flag, hipStream_t s);
+
+// y = D x for the first n rows of D (leading dimension ld); x, y of length n; FP64 accumulation.
+template <class T>
+hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, hipStream_t s);
+
+// Y = D X for a panel of K columns (K a power of two in [1, 64]; entry (dof, k) at dof * K + k).
+template <class T>
+hipError_t launch_dense_panel(int n, int ld, int K, const double *D, const T *X, T *Y,
+                              hipStream_t s);
+
+}  // namespace eamg

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/eamg.h"
+#include "coarse.hpp"
 #include "kernels.hpp"
 #include "coarsen.hpp"
 #include "structure.hpp"
@@ -190,6 +191,7 @@ struct eamg_hierarchy {
   eamg::DevArena arena;
   double *Ainv = nullptr;
   int nL = 0;                 // coarsest dofs
+  int ldL = 0;                // leading dimension of Ainv (nL rounded up to 128)
   uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;

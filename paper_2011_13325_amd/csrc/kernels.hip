@@ -528,20 +528,6 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
   }
 }
 
-// y = D x with the dense FP64 coarsest inverse D; vectors of type T, FP64 accumulation.
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_dense_gemv(int n, const double *__restrict__ D,
-                                                      const T *__restrict__ x, T *__restrict__ y) {
-  const int G = 64;
-  const int lane = threadIdx.x & (G - 1);
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  double acc[1] = {0.0};
-  if (row < n)
-    for (int c = lane; c < n; c += G) acc[0] = fma(D[int64_t(row) * n + c], double(x[c]), acc[0]);
-  group_reduce<double, 1>(acc, G);
-  if (row < n && lane == 0) y[row] = T(acc[0]);
-}
-
 template <class S, class D>
 __global__ void k_convert(int64_t n, const S *__restrict__ in, D *__restrict__ out) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -814,13 +800,6 @@ hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipSt
   EAMG_LAUNCH_CHECK();
 }
 
-template <class T>
-hipError_t launch_dense_gemv(int n, const double *D, const T *x, T *y, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv64(n, kBlock / 64)), dim3(kBlock), 0, s, n, D, x, y);
-  EAMG_LAUNCH_CHECK();
-}
-
 template <class S, class D>
 hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -844,8 +823,6 @@ template hipError_t launch_resid_upper<double>(const SoaMat &, const double *, d
 template hipError_t launch_resid_upper<float>(const SoaMat &, const float *, float *, hipStream_t);
 template hipError_t launch_rect<double>(const SoaMat &, const double *, double *, bool, hipStream_t);
 template hipError_t launch_rect<float>(const SoaMat &, const float *, float *, bool, hipStream_t);
-template hipError_t launch_dense_gemv<double>(int, const double *, const double *, double *, hipStream_t);
-template hipError_t launch_dense_gemv<float>(int, const double *, const float *, float *, hipStream_t);
 template hipError_t launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
 template hipError_t launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
 

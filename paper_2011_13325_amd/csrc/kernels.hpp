@@ -100,9 +100,6 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
 // y = M x (rectangular, overwrite) or y += M x (accumulate = true).
 template <class T>
 hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipStream_t s);
-// y = D x for the dense n x n row-major FP64 matrix D (FP64 accumulation).
-template <class T>
-hipError_t launch_dense_gemv(int n, const double *D, const T *x, T *y, hipStream_t s);
 // out[i] = D(in[i])
 template <class S, class D>
 hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s);

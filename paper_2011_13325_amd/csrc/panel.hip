@@ -309,22 +309,6 @@ __device__ inline double pcol_sum(double v, int K, double *sh) {
   return sh[threadIdx.x];
 }
 
-// Y = D X: one workgroup per row of D; thread t = s * K + k sums columns c = s (mod 256 / K)
-// of D row times X column k, FP64 accumulation.
-template <class T>
-__global__ __launch_bounds__(kPB) void k_pdense(int n, int K, const double *__restrict__ D,
-                                                const T *__restrict__ x, T *__restrict__ y) {
-  __shared__ double sh[kPB];
-  const int k = threadIdx.x & (K - 1);
-  const int S = kPB / K;
-  const int row = blockIdx.x;
-  const double *Dr = D + int64_t(row) * n;
-  double acc = 0.0;
-  for (int c = threadIdx.x / K; c < n; c += S) acc = fma(Dr[c], double(x[int64_t(c) * K + k]), acc);
-  const double t = pcol_sum(acc, K, sh);
-  if (int(threadIdx.x) < K) y[int64_t(row) * K + k] = T(t);
-}
-
 // Y = A X (W = 1 teams), the workgroups striding over groups of four rows so that the
 // per-column partial sums of X.Y come in at most kPSpmvMax workgroups.
 constexpr int kPSpmvMax = 2048;
@@ -640,14 +624,6 @@ hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulat
   EAMG_PCHECK();
 }
 
-template <class T>
-hipError_t launch_pdense(int n, int K, const double *D, const T *x, T *y, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (!valid_k(K)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pdense<T>, dim3(n), dim3(kPB), 0, s, n, K, D, x, y);
-  EAMG_PCHECK();
-}
-
 int pspmv_blocks(const SoaMat &A, int K) {
   const int g = K > 0 ? int(pgrid(A.n_rows, kPB / kWave)) : 0;
   return g < kPSpmvMax ? (g < 1 ? 1 : g) : kPSpmvMax;
@@ -745,7 +721,5 @@ template hipError_t launch_presid_upper<double>(const SoaMat &, int, const doubl
 template hipError_t launch_presid_upper<float>(const SoaMat &, int, const float *, float *, hipStream_t);
 template hipError_t launch_prect<double>(const SoaMat &, int, const double *, double *, bool, hipStream_t);
 template hipError_t launch_prect<float>(const SoaMat &, int, const float *, float *, bool, hipStream_t);
-template hipError_t launch_pdense<double>(int, int, const double *, const double *, double *, hipStream_t);
-template hipError_t launch_pdense<float>(int, int, const double *, const float *, float *, hipStream_t);
 
 }  // namespace eamg

@@ -37,9 +37,6 @@ hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStre
 // Y = M X or Y += M X (rectangular transfer).
 template <class T>
 hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulate, hipStream_t s);
-// Y = D X with the dense n x n row-major FP64 coarsest inverse (FP64 accumulation).
-template <class T>
-hipError_t launch_pdense(int n, int K, const double *D, const T *x, T *y, hipStream_t s);
 // FP64 CG operator: Y = A X; if part != nullptr also per-workgroup, per-column partial sums of
 // X.Y into part[wg * K + k] (pspmv_blocks(A, K) workgroups).
 hipError_t launch_pspmv(const SoaMat &A, int K, const double *x, double *y, double *part,
