@@ -2,8 +2,11 @@
 
 Workload: 3D linear elasticity on the unit cube, 64^3 vertices (786,432 dofs, 774,144 free),
 P1 Kuhn tetrahedra, E = 1, nu = 0.3, clamped at x = 0, seeded uniform RHS (seed 1); FP64
-hierarchy and V-cycle; two matching passes per level, coarsest < 500 dofs, one symmetric
-multicolour block Gauss-Seidel sweep pre / post; PCG to ||r|| <= 1e-8 ||b||.
+hierarchy and V-cycle; two matching passes per level, coarsening stopped below 8192 dofs
+(the coarsest level, 1051 vertices here, is inverted on the GPU at setup and applied as one dense
+product), one symmetric multicolour block Gauss-Seidel sweep pre / post; PCG to
+||r|| <= 1e-8 ||b||.  The same problem with coarsening stopped below 500 dofs (seven levels) is
+reported beside it as "coarsest_500".
 
 A step is one PCG solve to 1e-8 (V-cycle + CG kernels) on the hierarchy, with b resident in
 HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerkin / D^+ /
@@ -24,6 +27,12 @@ import time
 import numpy as np
 
 
+# Coarsening stops below this many dofs: on one GPU the dense inverse of a coarsest level of a
+# few thousand dofs (one HBM-bound product per V-cycle) is cheaper than the launch-bound colour
+# sweeps of the small levels it replaces.
+COARSEST_DOFS = 8192
+
+
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +48,10 @@ def _args():
                     help="run only the workload of the rocprofv3 counter passes (no JSON line)")
     ap.add_argument("--multi", type=int, default=16,
                     help="independent meshes of the multi-system solve (0: skip)")
+    ap.add_argument("--coarsest", type=int, default=COARSEST_DOFS,
+                    help="coarsening stops once a level has fewer dofs than this")
+    ap.add_argument("--no-coarsest-500", action="store_true",
+                    help="skip the comparison with coarsening stopped below 500 dofs")
     return ap.parse_args()
 
 
@@ -107,6 +120,27 @@ def _profiled(E, hier, b, x, steps, precond):
     return roof, kern
 
 
+def _coarsest_500(E, torch, p, stream, steps, warmup, ms_headline):
+    """The headline problem with coarsening stopped below 500 dofs (the small-problem setting):
+    setup, autotune and the FP64 solve timed the same way."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                    E.eamg_default_setup_params(coarsest_max_dofs=500), stream=stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    E.eamg_autotune(h.h, 0, stream=stream)
+    b = torch.tensor(p.b, device="cuda")
+    x = torch.zeros_like(b)
+    ms, info = _timed_solves(E, torch, h, b, x, stream, steps, warmup, E.EAMG_PRECOND_VCYCLE)
+    st = h.stats()
+    h.close()
+    return {"value": p.n_free_dofs / (ms / 1e3), "unit": "dofs/s", "ms_per_step": ms,
+            "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
+            "levels": st["n_levels"], "level_vertices": st["n"], "setup_s": round(setup_s, 3),
+            "headline_speedup": ms / ms_headline}
+
+
 def _batch_rhs(p, m):
     """m seeded load cases (case c from default_rng([4, c])), uniform[-1, 1], Dirichlet dofs 0."""
     B = np.stack([np.random.default_rng([4, c]).uniform(-1.0, 1.0, p.n_dofs) for c in range(m)])
@@ -148,7 +182,7 @@ def _batched(E, torch, hier, p, m, steps, warmup):
     return out
 
 
-def _multi_mesh(E, torch, steps, count=16, seed=4):
+def _multi_mesh(E, torch, steps, count=16, seed=4, coarsest=COARSEST_DOFS):
     """Independent meshes of uneven size solved together (eamg_solve_multi): count cubes with
     sides uniform in [8, 48] and Poisson ratios uniform in [0.2, 0.45], FP32 V-cycle in FP64 CG;
     against the same systems solved one after another."""
@@ -161,7 +195,7 @@ def _multi_mesh(E, torch, steps, count=16, seed=4):
     for c, (n, nu) in enumerate(zip(sides, nus)):
         p = make_problem(int(n), nu=float(nu), seed=100 + c)
         h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                        E.eamg_default_setup_params(vcycle_fp32=1))
+                        E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=coarsest))
         sysm.append((p, h))
     setup_s = time.perf_counter() - t0
     bs = [torch.tensor(p.b, device="cuda") for p, _ in sysm]
@@ -189,6 +223,7 @@ def _multi_mesh(E, torch, steps, count=16, seed=4):
     for _, h in sysm:
         h.close()
     return {"meshes": [int(n) for n in sides], "free_dofs": dofs, "setup_s": round(setup_s, 3),
+            "coarsest_max_dofs": coarsest,
             "dtype": "f32 V-cycle in f64 CG", "ms_per_solve_all": ms,
             "value": dofs / (ms / 1e3), "unit": "dofs/s",
             "ms_one_after_another": seq_ms, "speedup_vs_one_after_another": seq_ms / ms,
@@ -278,7 +313,8 @@ def _counter_pass():
         b.copy_(a)
     torch.cuda.synchronize()
     p = make_problem(64, seed=1)
-    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
+    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                    E.eamg_default_setup_params(coarsest_max_dofs=COARSEST_DOFS))
     E.eamg_autotune(h.h, 0)
     x, info = h.solve(torch.tensor(p.b, device="cuda"))
     torch.cuda.synchronize()
@@ -306,7 +342,7 @@ def main():
     t0 = time.perf_counter()
     # FP32 copies of the V-cycle matrices are kept too, so that the same hierarchy serves the
     # FP64 solve (the headline) and the mixed-precision comparison
-    prm = E.eamg_default_setup_params(vcycle_fp32=1)
+    prm = E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=args.coarsest)
     hier = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, prm,
                        stream=stream)
     torch.cuda.synchronize()
@@ -334,7 +370,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"elasticity cube {args.n}^3 vertices (Kuhn P1, E=1, nu=0.3, "
-                               f"clamped x=0, RHS seed 1), FP64 AMG-PCG to 1e-8",
+                               f"clamped x=0, RHS seed 1), FP64 AMG-PCG to 1e-8, coarsening "
+                               f"stopped below {args.coarsest} dofs",
+                   "coarsest_max_dofs": args.coarsest,
                    "dofs": p.n_dofs, "free_dofs": p.n_free_dofs, "iterations": its,
                    "rel_res_true": info["rel_res_true"], "levels": st["n_levels"],
                    "level_vertices": st["n"], "vc": round(st["vc"], 4), "oc": round(st["oc"], 4),
@@ -357,8 +395,11 @@ def main():
         out["batched"] = _batched(E, torch, hier, p, args.batch, args.steps, args.warmup)
         out["batched"]["speedup_per_rhs_vs_single_fp64"] = {
             k: out["batched"][k]["value"] / value for k in ("fp64_vcycle", "fp32_vcycle")}
+    if not args.no_coarsest_500 and args.coarsest != 500:
+        out["coarsest_500"] = _coarsest_500(E, torch, p, stream, args.steps, args.warmup, ms)
     if args.multi > 0:
-        out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi)
+        out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi,
+                                        coarsest=args.coarsest)
     if not args.no_learned:
         out["learned_coarsening"] = _learned(E, torch)
     levels = []
