@@ -342,13 +342,18 @@ __device__ inline void row_accumulate(int p0, int p1, int lane, int G, const int
                                       T (&acc)[BR]) {
   for (int p = p0 + lane; p < p1; p += G) {
     const int64_t c = col[p];
+    T v[BR * BC];
+#pragma unroll
+    for (int e = 0; e < BR * BC; ++e) v[e] = val[int64_t(e) * nnz + p];
+    // every value load is issued before the gathers of x, which wait for the column index
+    __builtin_amdgcn_sched_barrier(0);
     T xv[BC];
 #pragma unroll
     for (int cc = 0; cc < BC; ++cc) xv[cc] = x[c * BC + cc];
 #pragma unroll
     for (int r = 0; r < BR; ++r)
 #pragma unroll
-      for (int cc = 0; cc < BC; ++cc) acc[r] = fma(val[int64_t(r * BC + cc) * nnz + p], xv[cc], acc[r]);
+      for (int cc = 0; cc < BC; ++cc) acc[r] = fma(v[r * BC + cc], xv[cc], acc[r]);
   }
 }
 
