@@ -1014,11 +1014,20 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
         for (int c = L.ncolors - 1; c >= 0; --c)
           hip_check(launch_gs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
       };
+      // EAMG_FORCE_GROUP = 8, 16, 32, 64, 128 or 256 sets every level's lanes per row without
+      // timing (tests use it to run each row-team shape)
+      if (const char *fg = std::getenv("EAMG_FORCE_GROUP")) {
+        const int g = std::atoi(fg);
+        if (g != 8 && g != 16 && g != 32 && g != 64 && g != 128 && g != kBlock)
+          fail(EAMG_ERR_INVALID_ARG, "EAMG_FORCE_GROUP must be 8, 16, 32, 64, 128 or 256");
+        L.Am.group = g;
+        continue;
+      }
       const int orig = L.Am.group;
       const double t0 = time_ms(sweeps);
       double best = t0;
       int best_g = orig;
-      for (int g : {8, 16, 32, 64, kBlock}) {
+      for (int g : {8, 16, 32, 64, 128, kBlock}) {
         if (g == orig) continue;
         L.Am.group = g;
         const double t = time_ms(sweeps);

@@ -317,9 +317,10 @@ __device__ inline void group_reduce(T (&acc)[BR], int G) {
     for (int r = 0; r < BR; ++r) acc[r] += __shfl_xor(acc[r], off, G);
 }
 
-// A row team of a whole workgroup (kBlock lanes, "wide"): butterfly within each wavefront,
-// then the four wavefront sums added in wavefront order through LDS; every lane gets the total.
-template <class T, int BR>
+// A row team of W wavefronts (64 W lanes, "wide"; kBlock / (64 W) rows per workgroup):
+// butterfly within each wavefront, then the W wavefront sums of the row added in wavefront order
+// through LDS; every lane of the row gets the total.  sh: kBlock / 64 * BR values.
+template <class T, int BR, int W>
 __device__ inline void wide_reduce(T (&acc)[BR], T *sh) {
   group_reduce<T, BR>(acc, 64);
   const int wv = threadIdx.x / 64;
@@ -327,10 +328,11 @@ __device__ inline void wide_reduce(T (&acc)[BR], T *sh) {
 #pragma unroll
     for (int r = 0; r < BR; ++r) sh[wv * BR + r] = acc[r];
   __syncthreads();
+  const int w0 = wv - wv % W;   // first wavefront of this row
 #pragma unroll
   for (int r = 0; r < BR; ++r) {
-    T v = sh[r];
-    for (int w = 1; w < kBlock / 64; ++w) v += sh[w * BR + r];
+    T v = sh[w0 * BR + r];
+    for (int w = 1; w < W; ++w) v += sh[(w0 + w) * BR + r];
     acc[r] = v;
   }
 }
@@ -399,7 +401,7 @@ __device__ inline T pick(const T (&v)[B], int i) {
 // Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
 // together with the row's blocks, so a row costs one round of row loads plus the x gathers;
 // a butterfly all-reduce leaves the row sum on every lane.
-template <class T, int B, bool FWD, bool WIDE>
+template <class T, int B, bool FWD, int W>
 __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                               const int *__restrict__ col, const int *__restrict__ diag,
                               const T *__restrict__ val, int64_t nnz, const T *__restrict__ Dinv,
@@ -430,12 +432,13 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 #pragma unroll
   for (int q = 0; q < B; ++q) acc[q] = T(0);
   if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  if (WIDE)
-    wide_reduce<T, B>(acc, sh);
+  if (W > 1)
+    wide_reduce<T, B, W>(acc, sh);
   else
     group_reduce<T, B>(acc, G);
-  // wide teams: the owning lanes (< B) are in wavefront 0; shuffles stay within wavefronts
-  const int GS = WIDE ? 64 : G;
+  // wide teams: the owning lanes (< B) are in the row's first wavefront; shuffles stay within
+  // wavefronts
+  const int GS = W > 1 ? 64 : G;
   const T tq = bq - pick<T, B>(acc, lane);   // t component of this lane (lanes < B)
   T t[B];
 #pragma unroll
@@ -460,7 +463,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 }
 
 // r_i -= sum_{j > i} A_ij x_j for one row.
-template <class T, int B, bool WIDE>
+template <class T, int B, int W>
 __device__ inline void resid_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                                  const int *__restrict__ col, const int *__restrict__ diag,
                                  const T *__restrict__ val, int64_t nnz, const T *x, T *r, T *sh) {
@@ -475,38 +478,39 @@ __device__ inline void resid_row(int row, bool valid, int lane, int G, const int
 #pragma unroll
   for (int a = 0; a < B; ++a) acc[a] = T(0);
   if (valid) row_accumulate<T, B, B>(p0, p1, lane, G, col, val, nnz, x, acc);
-  if (WIDE)
-    wide_reduce<T, B>(acc, sh);
+  if (W > 1)
+    wide_reduce<T, B, W>(acc, sh);
   else
     group_reduce<T, B>(acc, G);
   if (valid && lane < B) r[int64_t(row) * B + lane] = rq - pick<T, B>(acc, lane);
 }
 
-// One colour (rows [r0, r1)) per launch.  G = kBlock: one row per workgroup ("wide"), for
-// levels whose rows are long; else kBlock / G rows per workgroup.
-template <class T, int B, bool FWD, bool WIDE>
+// One colour (rows [r0, r1)) per launch, kBlock / G rows per workgroup.  G = 64 W lanes per
+// row with W = 2 or 4 wavefronts ("wide", W = 4: one row per workgroup) for levels whose rows
+// are long; else G <= 64 (W = 1).
+template <class T, int B, bool FWD, int W>
 __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ diag,
                                                     const T *__restrict__ val, int64_t nnz,
                                                     const T *__restrict__ Dinv,
                                                     const T *__restrict__ b, T *x, T *r) {
-  __shared__ T sh[WIDE ? (kBlock / 64) * B : 1];
+  __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  gs_row<T, B, FWD, WIDE>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r, sh);
+  gs_row<T, B, FWD, W>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r, sh);
 }
 
-template <class T, int B, bool WIDE>
+template <class T, int B, int W>
 __global__ __launch_bounds__(kBlock) void k_resid_upper(int n_rows, int G, const int *__restrict__ rp,
                                                        const int *__restrict__ col,
                                                        const int *__restrict__ diag,
                                                        const T *__restrict__ val, int64_t nnz,
                                                        const T *x, T *r) {
-  __shared__ T sh[WIDE ? (kBlock / 64) * B : 1];
+  __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  resid_row<T, B, WIDE>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r, sh);
+  resid_row<T, B, W>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r, sh);
 }
 
 template <class T, int BR, int BC>
@@ -709,7 +713,7 @@ hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in,
 
 // k_spmv reduces within wavefronts: a matrix with one row per workgroup runs it with 64 lanes
 // per row.
-inline int spmv_group(const SoaMat &A) { return A.group == kBlock ? 64 : A.group; }
+inline int spmv_group(const SoaMat &A) { return A.group > 64 ? 64 : A.group; }
 
 int spmv_blocks(const SoaMat &A) { return int(cdiv64(A.n_rows, groups_for(spmv_group(A)))); }
 
@@ -738,6 +742,12 @@ const float *soa_vals<float>(const SoaMat &M) {
   return M.val32;
 }
 
+// Wavefronts per row team for a level's lanes per row: 4 (kBlock), 2 (128) or 1 (<= 64).
+#define EAMG_GS_W(W_, ...)                                                                       \
+  if (A.group == kBlock) { constexpr int W_ = 4; __VA_ARGS__; }                                 \
+  else if (A.group == 128) { constexpr int W_ = 2; __VA_ARGS__; }                               \
+  else { constexpr int W_ = 1; __VA_ARGS__; }
+
 template <class T>
 hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
                          hipStream_t s) {
@@ -746,9 +756,9 @@ hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   switch (A.br) {
-    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 1, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 1, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
-    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 3, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 3, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
-    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 6, true, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  else hipLaunchKernelGGL((k_gs_color<T, 6, true, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r);  break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -763,9 +773,9 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
   T *none = nullptr;
   switch (A.br) {
-    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 1, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 1, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
-    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 3, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 3, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
-    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_gs_color<T, 6, false, true>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  else hipLaunchKernelGGL((k_gs_color<T, 6, false, false>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none);  break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -778,9 +788,9 @@ hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s) 
   if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(A.n_rows, groups_for(A.group)));
   switch (A.br) {
-    case 1: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 1, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 1, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
-    case 3: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 3, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 3, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
-    case 6: if (A.group == kBlock) hipLaunchKernelGGL((k_resid_upper<T, 6, true>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  else hipLaunchKernelGGL((k_resid_upper<T, 6, false>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r);  break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();

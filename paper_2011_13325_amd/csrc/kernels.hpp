@@ -66,8 +66,8 @@ constexpr int kBlock = 256;          // threads per workgroup of the solve kerne
 constexpr double kWideRowBlocks = 96; // square matrices with longer average rows: group = kBlock
 
 struct SoaMat {
-  // group: lanes per row (a power of two <= 64), or kBlock for one row per workgroup
-  // (square matrices with diag only)
+  // group: lanes per row (a power of two <= 64), or 128 / kBlock for two wavefronts / a whole
+  // workgroup per row (square matrices with diag only)
   int n_rows = 0, n_cols = 0, br = 0, bc = 0, group = 16;
   // panel kernels: wavefronts per row (1 or 4), or 0 for the built-in choice
   int panel_waves = 0;

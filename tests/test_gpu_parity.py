@@ -434,3 +434,35 @@ def test_autotuned_hierarchy_keeps_parity():
         xc, _, _, _, _ = oracle.pcg(ho, B[c], rtol=0.0, max_it=it)
         assert np.linalg.norm(X[c].cpu().numpy() - xc) / np.linalg.norm(xc) <= X_TOL
     hl.close()
+
+
+@pytest.mark.parametrize("group", [8, 16, 32, 64, 128, 256])
+def test_every_row_team_shape_keeps_parity(group):
+    """Each lanes-per-row choice of the sweep kernels (8..64 lanes, two wavefronts, a whole
+    workgroup), forced on every level, changes summation order only: V-cycle (FP64 and FP32
+    V-cycle kernels) and PCG iterate within the FP64 bar against the oracle."""
+    import os
+    p = make_problem(**CASES["cube17"])
+    ho = _oracle_cached("cube17", p)
+    hl = _lib(p, vcycle_fp32=1)
+    os.environ["EAMG_FORCE_GROUP"] = str(group)
+    try:
+        E.eamg_autotune(hl.h, panel_width=0)
+    finally:
+        os.environ.pop("EAMG_FORCE_GROUP", None)
+    r = np.random.default_rng(3).standard_normal(p.n_dofs)
+    r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+    zo = oracle.vcycle(ho, r)
+    z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+    E.eamg_vcycle(hl.h, _dev(r), z)
+    z32 = torch.empty_like(z)
+    E.eamg_vcycle(hl.h, _dev(r), z32, precision=E.EAMG_PRECOND_VCYCLE_FP32)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
+    err32 = np.linalg.norm(z32.cpu().numpy() - zo) / np.linalg.norm(zo)
+    xo, it, _, _, _ = oracle.pcg(ho, p.b, rtol=1e-8)
+    xk, info = hl.solve(_dev(p.b), rtol=0.0, max_it=it)
+    xerr = np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"\n[group {group}] V-cycle {err:.2e} (FP32 kernels {err32:.2e}), x at k* {xerr:.2e}", flush=True)
+    assert err <= X_TOL and xerr <= X_TOL and err32 <= F32_VC_TOL
+    hl.close()
