@@ -1007,10 +1007,12 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       const int64_t nv = int64_t(L.n) * L.bs;
       double *b = l == 0 ? h->r : L.b, *x = l == 0 ? h->z : L.x;
       for (double *v : {b, x, L.r}) hip_check(launch_fill(nv, 0.0, v, s), "fill");
-      auto sweeps = [&] {
+      auto fwd_part = [&] {
         for (int c = 0; c < L.ncolors; ++c)
           hip_check(launch_gs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
         hip_check(launch_resid_upper<double>(L.Am, x, L.r, s), "resid");
+      };
+      auto bwd_part = [&] {
         for (int c = L.ncolors - 1; c >= 0; --c)
           hip_check(launch_gs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
       };
@@ -1021,24 +1023,34 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
         if (g != 8 && g != 16 && g != 32 && g != 64 && g != 128 && g != kBlock)
           fail(EAMG_ERR_INVALID_ARG, "EAMG_FORCE_GROUP must be 8, 16, 32, 64, 128 or 256");
         L.Am.group = g;
+        L.Am.group_bwd = 0;
         continue;
       }
+      // forward sweep + residual update, then the backward sweep: lanes per row chosen apart
+      const int cand[] = {8, 16, 32, 64, 128, kBlock};
+      L.Am.group_bwd = 0;
       const int orig = L.Am.group;
-      const double t0 = time_ms(sweeps);
-      double best = t0;
-      int best_g = orig;
-      for (int g : {8, 16, 32, 64, 128, kBlock}) {
+      const double f0 = time_ms(fwd_part), b0 = time_ms(bwd_part);
+      double bf = f0, bb = b0;
+      int gf = orig, gb = orig;
+      for (int g : cand) {
         if (g == orig) continue;
         L.Am.group = g;
-        const double t = time_ms(sweeps);
-        if (t < best) {
-          best = t;
-          best_g = g;
+        L.Am.group_bwd = g;
+        const double tf = time_ms(fwd_part), tb = time_ms(bwd_part);
+        if (tf < bf) {
+          bf = tf;
+          gf = g;
+        }
+        if (tb < bb) {
+          bb = tb;
+          gb = g;
         }
       }
-      L.Am.group = best_g;
-      before += t0;
-      after += best;
+      L.Am.group = gf;
+      L.Am.group_bwd = gb == gf ? 0 : gb;
+      before += f0 + b0;
+      after += bf + bb;
     }
     for (int p = 0; p < 2; ++p) {
       if (h->g_iter[p]) (void)hipGraphExecDestroy(h->g_iter[p]);

@@ -742,10 +742,10 @@ const float *soa_vals<float>(const SoaMat &M) {
   return M.val32;
 }
 
-// Wavefronts per row team for a level's lanes per row: 4 (kBlock), 2 (128) or 1 (<= 64).
+// Wavefronts per row team for G lanes per row: 4 (kBlock), 2 (128) or 1 (<= 64).
 #define EAMG_GS_W(W_, ...)                                                                       \
-  if (A.group == kBlock) { constexpr int W_ = 4; __VA_ARGS__; }                                 \
-  else if (A.group == 128) { constexpr int W_ = 2; __VA_ARGS__; }                               \
+  if (G == kBlock) { constexpr int W_ = 4; __VA_ARGS__; }                                       \
+  else if (G == 128) { constexpr int W_ = 2; __VA_ARGS__; }                                     \
   else { constexpr int W_ = 1; __VA_ARGS__; }
 
 template <class T>
@@ -754,11 +754,12 @@ hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   if (r1 <= r0) return hipSuccess;
   const T *val = soa_vals<T>(A);
   if (!val) return hipErrorInvalidValue;
-  const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
+  const int G = A.group;
+  const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -770,12 +771,13 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   if (r1 <= r0) return hipSuccess;
   const T *val = soa_vals<T>(A);
   if (!val) return hipErrorInvalidValue;
-  const dim3 grid(cdiv64(r1 - r0, groups_for(A.group)));
+  const int G = A.group_bwd ? A.group_bwd : A.group;
+  const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
   T *none = nullptr;
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, A.group, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -786,11 +788,12 @@ hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s) 
   if (A.n_rows == 0) return hipSuccess;
   const T *val = soa_vals<T>(A);
   if (!val) return hipErrorInvalidValue;
-  const dim3 grid(cdiv64(A.n_rows, groups_for(A.group)));
+  const int G = A.group;
+  const dim3 grid(cdiv64(A.n_rows, groups_for(G)));
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, A.n_rows, A.group, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();

@@ -69,6 +69,9 @@ struct SoaMat {
   // group: lanes per row (a power of two <= 64), or 128 / kBlock for two wavefronts / a whole
   // workgroup per row (square matrices with diag only)
   int n_rows = 0, n_cols = 0, br = 0, bc = 0, group = 16;
+  // lanes per row of the backward sweep (whole rows), or 0 for `group` (forward sweep and the
+  // residual update read about half of each row)
+  int group_bwd = 0;
   // panel kernels: wavefronts per row (1 or 4), or 0 for the built-in choice
   int panel_waves = 0;
   int64_t nnz = 0;
