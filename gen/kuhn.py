@@ -228,6 +228,23 @@ def sphere_inclusions(mesh: KuhnMesh, count: int, seed: int, E_host=1.0, nu_host
     return mu, lam
 
 
+def eleven_boxes(mesh: KuhnMesh, contrast=1.0e4, lam_over_mu=1.0):
+    """Per-(tet type, cell) (mu_L, lambda) of the paper's difficult vector problem: a soft
+    material (paper mu = lambda = 1) on the unit cube except the eleven diagonal boxes
+    [(i-1)/11, i/11]^3, i = 1..11, which touch at their corners and are `contrast` times stiffer.
+    The paper's mu is read as 2 mu_L (Hooke's law), so paper mu = lambda = c gives mu_L = c / 2,
+    lambda = c.  A tetrahedron takes the material of the box containing its centroid."""
+    mu = np.full((6,) + mesh.cell_shape, 0.5)
+    lam = np.full((6,) + mesh.cell_shape, lam_over_mu)
+    for t in range(6):
+        cen = mesh.tet_centroids(t)
+        box = np.floor(cen * 11.0).astype(np.int64)
+        inside = (box[..., 0] == box[..., 1]) & (box[..., 1] == box[..., 2]) & (box[..., 0] >= 0) & (box[..., 0] < 11)
+        mu[t][inside] = 0.5 * contrast
+        lam[t][inside] = lam_over_mu * contrast
+    return mu, lam
+
+
 @dataclasses.dataclass
 class KuhnProblem:
     """A generated problem: BC-free block matrix A_N, coordinates, Dirichlet mask, RHS."""
@@ -264,6 +281,7 @@ def random_rhs(n_dofs: int, dim: int, dirichlet: np.ndarray, seed) -> np.ndarray
 
 def make_problem(n: int, *, kind: str = "elasticity", E: float = 1.0, nu: float = 0.3,
                  seed=0, clamp: str = "x0", inclusions: int = 0, geometry_seed: int = 5,
+                 boxes: bool = False,
                  ny: Optional[int] = None, nz: Optional[int] = None, h: Optional[float] = None,
                  name: Optional[str] = None) -> KuhnProblem:
     """Generate a Kuhn box problem.
@@ -271,11 +289,14 @@ def make_problem(n: int, *, kind: str = "elasticity", E: float = 1.0, nu: float 
     kind: "elasticity" (dim 3) or "poisson" (dim 1).
     clamp: "x0" clamps the vertices with x = 0; "all" clamps the whole boundary; "none"
     gives a pure Neumann problem (singular A_N; only meaningful for setup checks).
+    boxes: the eleven-box material of the paper's difficult vector problem (E, nu ignored).
     """
     mesh = kuhn_mesh(n, ny, nz, h)
     if kind == "elasticity":
         dim = 3
-        if inclusions:
+        if boxes:
+            mu, lam = eleven_boxes(mesh)
+        elif inclusions:
             mu, lam = sphere_inclusions(mesh, inclusions, geometry_seed, E_host=E, nu_host=nu)
         else:
             mu, lam = lame_from_young(E, nu)
@@ -298,7 +319,7 @@ def make_problem(n: int, *, kind: str = "elasticity", E: float = 1.0, nu: float 
         raise ValueError(clamp)
     b = random_rhs(nv * dim, dim, dirichlet, seed)
     meta = dict(kind=kind, n=n, ny=mesh.ny, nz=mesh.nz, h=mesh.h, E=E, nu=nu, seed=seed,
-                clamp=clamp, inclusions=inclusions)
+                clamp=clamp, inclusions=inclusions, boxes=boxes)
     return KuhnProblem(name or f"{kind}{n}", dim, nv, coords, row_ptr, col, vals, dirichlet, b,
                        meta)
 

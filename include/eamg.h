@@ -109,6 +109,11 @@ typedef struct {
  *                     is borrowed for the call only.
  *  gnn_record         1: keep every pass's candidate pairs with features and exact labels
  *                     (eamg_gnn_samples), for training.  Default 0.
+ *  mu_s_only          0: the robust criteria, a pair is formed only if mu_b < sigma and (unions
+ *                     of more than two vertices) mu_g < sigma (Alg. alg:pwagg; default).  1: the
+ *                     candidate of smallest mu_s is paired without evaluating mu_b / mu_g, the
+ *                     scalar-only coarsening the paper contrasts with in its coefficient-jump
+ *                     example (figures fig:2dc_rob / fig:2dc_norob); for comparisons only.
  */
 typedef struct eamg_gnn eamg_gnn;
 typedef struct {
@@ -121,6 +126,7 @@ typedef struct {
   const eamg_gnn *gnn;
   double gnn_skip;
   int32_t gnn_record;
+  int32_t mu_s_only;
 } eamg_setup_params;
 
 /* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,

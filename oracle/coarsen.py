@@ -80,7 +80,10 @@ def _mean_pos(coords, members):
 
 
 def successive_matching(level: AuxLevel, vd_mask, sigma=20.0, rounds=2, tie_rtol=1e-12,
-                        tau=1e-10) -> MatchingResult:
+                        tau=1e-10, mu_s_only=False) -> MatchingResult:
+    """mu_s_only: pair the candidate of smallest mu_s without the robust tests (mu_b, mu_g), the
+    scalar-only coarsening of the paper's coefficient-jump comparison (Figs. fig:2dc_rob /
+    fig:2dc_norob)."""
     n = level.n
     margin = [float("inf")]
     max_tie = [0]
@@ -129,6 +132,9 @@ def successive_matching(level: AuxLevel, vd_mask, sigma=20.0, rounds=2, tie_rtol
                 tied = [c for c, v in cands.items() if v <= mmin * (1.0 + tie_rtol)]
                 max_tie[0] = max(max_tie[0], len(tied))
                 cj = min(tied, key=pos.__getitem__)
+                if mu_s_only:
+                    matched = cj
+                    break
                 mu = mu_b(work, ci, cj, work_dhat, tau)
                 note(mu)
                 ok = mu < sigma

@@ -43,6 +43,7 @@ class SetupParams:
     cap_std: int = 6
     pinv_rtol: float = 1e-10
     tie_rtol: float = 1e-12
+    mu_s_only: bool = False    # scalar-only pairing (no mu_b / mu_g), for comparisons
 
 
 @dataclasses.dataclass
@@ -192,7 +193,8 @@ def setup(dim, coords, row_ptr, col, vals, dirichlet, params: Optional[SetupPara
         if A.r * A.n_rows < params.coarsest_max_dofs or len(levels) >= params.max_levels:
             break
         vd = np.asarray(dirichlet).astype(bool) if lidx == 0 else np.zeros(A.n_rows, bool)
-        res = successive_matching(aux, vd, params.sigma, params.rounds, params.tie_rtol, tau)
+        res = successive_matching(aux, vd, params.sigma, params.rounds, params.tie_rtol, tau,
+                                  params.mu_s_only)
         nc = len(res.aggs)
         if nc == 0 or nc > 0.9 * A.n_rows:
             break

@@ -59,7 +59,7 @@ class eamg_setup_params(ctypes.Structure):
                 ("cap_std", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
                 ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32),
                 ("gnn", ctypes.c_void_p), ("gnn_skip", ctypes.c_double),
-                ("gnn_record", ctypes.c_int32)]
+                ("gnn_record", ctypes.c_int32), ("mu_s_only", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):

@@ -44,6 +44,7 @@ eamg_setup_params defaults() {
   p.gnn = nullptr;
   p.gnn_skip = 0.0;
   p.gnn_record = 0;
+  p.mu_s_only = 0;
   return p;
 }
 
@@ -64,6 +65,7 @@ void validate_params(const eamg_setup_params &p) {
   if (p.vcycle_fp32 != 0 && p.vcycle_fp32 != 1) fail(EAMG_ERR_INVALID_ARG, "vcycle_fp32 must be 0 or 1");
   if (!(p.gnn_skip >= 0.0 && p.gnn_skip < 1.0)) fail(EAMG_ERR_INVALID_ARG, "gnn_skip must be in [0, 1)");
   if (p.gnn_record != 0 && p.gnn_record != 1) fail(EAMG_ERR_INVALID_ARG, "gnn_record must be 0 or 1");
+  if (p.mu_s_only != 0 && p.mu_s_only != 1) fail(EAMG_ERR_INVALID_ARG, "mu_s_only must be 0 or 1");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -813,6 +815,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     MatchParams mp;
     mp.sigma = prm.sigma;
     mp.rounds = prm.rounds;
+    mp.mu_s_only = prm.mu_s_only != 0;
     mp.tie_rtol = prm.tie_rtol;
     mp.tau = prm.pinv_rtol;
     mp.record = prm.gnn_record != 0;
@@ -1409,6 +1412,7 @@ eamg_status eamg_host_match(int32_t k, int32_t n, const double *coords, int64_t 
     MatchParams mp;
     mp.sigma = prm.sigma;
     mp.rounds = prm.rounds;
+    mp.mu_s_only = prm.mu_s_only != 0;
     mp.tie_rtol = prm.tie_rtol;
     mp.tau = prm.pinv_rtol;
     const MatchResult mr = successive_matching(lev, vdm, mp);

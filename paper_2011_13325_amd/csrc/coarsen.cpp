@@ -803,6 +803,7 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         int matched = -1;
         // the exact criteria for (ci, cj), or an optimistic pass when not known yet
         auto check = [&](int cj) {
+          if (prm.mu_s_only) return true;
           ++w_eval;
           const auto it = known.find(key(ci, cj));
           if (it == known.end()) {

@@ -116,6 +116,9 @@ struct MatchParams {
   PairScorer scorer;
   double skip = 0.0;
   bool record = false;   // keep every pass's candidate pairs, features and labels
+  // pair the candidate of smallest mu_s without evaluating mu_b / mu_g (the scalar-only
+  // coarsening the paper contrasts the robust criteria with)
+  bool mu_s_only = false;
 };
 
 struct AuxLevel {

@@ -120,3 +120,22 @@ def test_solve_entry_points_reject_null_hierarchy():
     assert L.eamg_traffic_model(None, 1, ctypes.byref(v), ctypes.byref(it)) == E.EAMG_ERR_INVALID_ARG
     p = E.eamg_default_setup_params()
     assert p.vcycle_fp32 == 0
+
+
+@pytest.mark.parametrize("mu_s_only", [0, 1])
+def test_host_matching_on_eleven_boxes_matches_oracle(mu_s_only):
+    """The coefficient-jump geometry, robust and scalar-only pairing: the library's host matching
+    equals the oracle's agglomerates bit for bit (two passes, two levels)."""
+    p = make_problem(12, boxes=True, seed=14)
+    lev = finest_aux(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals)
+    vd = p.dirichlet.astype(bool)
+    prm = E.eamg_default_setup_params(mu_s_only=mu_s_only)
+    for level in range(2):
+        res = successive_matching(lev, vd, mu_s_only=bool(mu_s_only))
+        agg, nc, cc, margin = E.eamg_host_match(lev.k, lev.coords, lev.edges, lev.E, lev.M, vd, prm)
+        ao = np.full(lev.n, -1)
+        for I, m in enumerate(res.aggs):
+            ao[m] = I
+        assert nc == len(res.aggs)
+        assert np.array_equal(agg, ao)
+        lev, vd = res.coarse_level, np.zeros(res.coarse_level.n, bool)
