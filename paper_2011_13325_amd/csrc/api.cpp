@@ -417,11 +417,21 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   const LevelBufs<T> B = bufs<T>(L);
   const int bs = L.bs;
   const double vs = sizeof(T);
+  double fwd_bytes = 0.0, bwd_bytes = 0.0;
+  for (int c = 0; c < L.ncolors; ++c) {
+    fwd_bytes += launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, 1);
+    bwd_bytes += launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, 1);
+  }
   const std::string gs = "k_gs_color<" + ty + ", " + std::to_string(bs);
-  // one profiler record per colour launch, so that launch gaps stay out of kernel times
-  for (int c = 0; c < L.ncolors; ++c)
-    timed(h, "gs_fwd", lvname(h, l, gs + ", true>"), launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, 1), s,
-          [&] { return launch_gs_fwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s); });
+  // the colours of a sweep are back-to-back launches of one kernel: one profiler record (events
+  // per launch would add their own dispatch to every launch)
+  timed_n(h, "gs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
+    for (int c = 0; c < L.ncolors; ++c) {
+      const hipError_t e = launch_gs_fwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
   timed(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
   Level &C = h->lv[l + 1];
@@ -431,9 +441,13 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   vcycle_t<T>(h, l + 1, CB.b, CB.x, s);
   timed(h, "prolong", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1), s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
-  for (int c = L.ncolors - 1; c >= 0; --c)
-    timed(h, "gs_bwd", lvname(h, l, gs + ", false>"), launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, 1), s,
-          [&] { return launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s); });
+  timed_n(h, "gs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
+    for (int c = L.ncolors - 1; c >= 0; --c) {
+      const hipError_t e = launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
 }
 
 // z = V(r) on colour-major level-0 vectors: FP64, or FP32 with conversions at the boundary.

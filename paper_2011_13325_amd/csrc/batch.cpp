@@ -116,11 +116,19 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   const int bs = L.bs;
   const T *Dinv = bufs<T>(L).Dinv;
   T *R = vp<T>(w->vr[pi][l]);
+  double fwd_bytes = 0.0, bwd_bytes = 0.0;
+  for (int c = 0; c < L.ncolors; ++c) {
+    fwd_bytes += launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, K);
+    bwd_bytes += launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, K);
+  }
   const std::string gs = "k_pgs_color<" + ty + ", " + std::to_string(bs);
-  // one profiler record per colour launch, so that launch gaps stay out of kernel times
-  for (int c = 0; c < L.ncolors; ++c)
-    timed(h, "pgs_fwd", lvname(h, l, gs + ", true>"), launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, K), s,
-          [&] { return launch_pgs_fwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, R, s); });
+  timed_n(h, "pgs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
+    for (int c = 0; c < L.ncolors; ++c) {
+      const hipError_t e = launch_pgs_fwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, R, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
   timed(h, "presid_upper", lvname(h, l, "k_presid_upper<" + ty + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, K), s,
         [&] { return launch_presid_upper<T>(L.Am, K, x, R, s); });
@@ -133,9 +141,13 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   timed(h, "pprolong", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, K), s,
         [&] { return launch_prect<T>(L.Pm, K, Cx, x, true, s); });
-  for (int c = L.ncolors - 1; c >= 0; --c)
-    timed(h, "pgs_bwd", lvname(h, l, gs + ", false>"), launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, K), s,
-          [&] { return launch_pgs_bwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s); });
+  timed_n(h, "pgs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
+    for (int c = L.ncolors - 1; c >= 0; --c) {
+      const hipError_t e = launch_pgs_bwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
 }
 
 // Z = V(R) for the K columns of the level-0 CG panels.
