@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <deque>
 #include <limits>
+#include <memory>
 #include <unordered_map>
 
 namespace eamg {
@@ -19,199 +20,21 @@ namespace {
 const double kInf = std::numeric_limits<double>::infinity();
 
 
-// ---- small square matrices --------------------------------------------------------------
+// ---- small square matrices (crit_core.hpp, shared with the device criteria) ---------------
 
-Sq sq_mul(const Sq &A, const Sq &B) {
-  const int k = A.k;
-  Sq C(k);
-  for (int i = 0; i < k; ++i)
-    for (int l = 0; l < k; ++l) {
-      const double ail = A(i, l);
-      if (ail == 0.0) continue;
-      for (int j = 0; j < k; ++j) C(i, j) += ail * B(l, j);
-    }
-  return C;
-}
-
-Sq sq_t(const Sq &A) {
-  Sq T(A.k);
-  for (int i = 0; i < A.k; ++i)
-    for (int j = 0; j < A.k; ++j) T(j, i) = A(i, j);
-  return T;
-}
-
-// A^T B C
-Sq sq_t3(const Sq &A, const Sq &B, const Sq &C) { return sq_mul(sq_mul(sq_t(A), B), C); }
-
-void sq_axpy(Sq &Y, double s, const Sq &X) {
-  for (int i = 0; i < Y.k * Y.k; ++i) Y.a[i] += s * X.a[i];
-}
-
-Sq sq_sym(const Sq &X) {
-  Sq S(X.k);
-  for (int i = 0; i < X.k; ++i)
-    for (int j = 0; j < X.k; ++j) S(i, j) = 0.5 * (X(i, j) + X(j, i));
-  return S;
-}
-
-double sq_frob(const Sq &X) {
-  double s = 0.0;
-  for (int i = 0; i < X.k * X.k; ++i) s += X.a[i] * X.a[i];
-  return std::sqrt(s);
-}
-
-double sq_trace(const Sq &X) {
-  double s = 0.0;
-  for (int i = 0; i < X.k; ++i) s += X(i, i);
-  return s;
-}
-
-// Cyclic Jacobi, eigenvalues ascending in w, eigenvectors as columns of V.
-void sq_eigh(const Sq &Ain, double *w, Sq &V) {
-  const int n = Ain.k;
-  Sq A = Ain;
-  V = Sq(n);
-  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
-  double fro2 = 0.0;
-  for (int i = 0; i < n * n; ++i) fro2 += A.a[i] * A.a[i];
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) off += A(p, q) * A(p, q);
-    if (off <= 1e-40 * fro2 || off == 0.0) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A(p, q);
-        if (apq == 0.0) continue;
-        const double theta = (A(q, q) - A(p, p)) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A(k, p), akq = A(k, q);
-          A(k, p) = cs * akp - sn * akq;
-          A(k, q) = sn * akp + cs * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A(p, k), aqk = A(q, k);
-          A(p, k) = cs * apk - sn * aqk;
-          A(q, k) = sn * apk + cs * aqk;
-        }
-        A(p, q) = 0.0;
-        A(q, p) = 0.0;
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V(k, p), vkq = V(k, q);
-          V(k, p) = cs * vkp - sn * vkq;
-          V(k, q) = sn * vkp + cs * vkq;
-        }
-      }
-  }
-  int idx[6];
-  for (int i = 0; i < n; ++i) idx[i] = i;
-  std::sort(idx, idx + n, [&](int x, int y) { return A(x, x) < A(y, y); });
-  Sq Vs(n);
-  for (int j = 0; j < n; ++j) {
-    w[j] = A(idx[j], idx[j]);
-    for (int i = 0; i < n; ++i) Vs(i, j) = V(i, idx[j]);
-  }
-  V = Vs;
-}
-
-Sq sq_pinv(const Sq &X, double tau) {
-  const int n = X.k;
-  double w[6];
-  Sq V;
-  sq_eigh(sq_sym(X), w, V);
-  Sq P(n);
-  const double lmax = w[n - 1];
-  if (lmax <= 0.0) return P;
-  for (int k = 0; k < n; ++k) {
-    if (!(w[k] > tau * lmax)) continue;
-    const double inv = 1.0 / w[k];
-    for (int i = 0; i < n; ++i) {
-      const double vi = V(i, k) * inv;
-      for (int j = 0; j < n; ++j) P(i, j) += vi * V(j, k);
-    }
-  }
-  return P;
-}
-
-Sq sq_harmonic(const Sq &A, const Sq &B, double tau) {
-  Sq S = A;
-  sq_axpy(S, 1.0, B);
-  return sq_sym(sq_mul(sq_mul(A, sq_pinv(S, tau)), B));
-}
-
-double sq_genmax(const Sq &Lin, const Sq &Rin, double tau) {
-  const Sq L = sq_sym(Lin), R = sq_sym(Rin);
-  const int n = L.k;
-  const double nL = sq_frob(L);
-  if (nL == 0.0) return 0.0;
-  double w[6];
-  Sq U;
-  sq_eigh(R, w, U);
-  const double lmax = w[n - 1];
-  int keep[6], drop[6], nk = 0, nd = 0;
-  for (int k = 0; k < n; ++k) {
-    if (lmax > 0.0 && w[k] > tau * lmax)
-      keep[nk++] = k;
-    else
-      drop[nd++] = k;
-  }
-  if (nd) {
-    // || U0^T L U0 ||_F
-    double s = 0.0;
-    for (int a = 0; a < nd; ++a)
-      for (int b = 0; b < nd; ++b) {
-        double v = 0.0;
-        for (int i = 0; i < n; ++i) {
-          double li = 0.0;
-          for (int j = 0; j < n; ++j) li += L(i, j) * U(j, drop[b]);
-          v += U(i, drop[a]) * li;
-        }
-        s += v * v;
-      }
-    if (std::sqrt(s) > tau * nL) return kInf;
-  }
-  if (!nk) return 0.0;
-  // W = U_keep / sqrt(w_keep); G = W^T L W
-  Sq G(nk);
-  for (int a = 0; a < nk; ++a)
-    for (int b = 0; b < nk; ++b) {
-      double v = 0.0;
-      for (int i = 0; i < n; ++i) {
-        double li = 0.0;
-        for (int j = 0; j < n; ++j) li += L(i, j) * U(j, keep[b]);
-        v += U(i, keep[a]) * li;
-      }
-      G(a, b) = v / (std::sqrt(w[keep[a]]) * std::sqrt(w[keep[b]]));
-    }
-  double g[6];
-  Sq Gv;
-  sq_eigh(sq_sym(G), g, Gv);
-  return g[nk - 1];
-}
-
-Sq sq_q(const double *t, int k) {
-  Sq Q(k);
-  for (int i = 0; i < k; ++i) Q(i, i) = 1.0;
-  if (k == 6) {
-    double S[9];
-    skew3(t, S);
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) Q(i, 3 + j) = S[3 * i + j];
-  }
-  return Q;
-}
-
-Sq sq_qtrans(const double *xa, const double *xb, int k) {
-  const double t[3] = {xb[0] - xa[0], xb[1] - xa[1], xb[2] - xa[2]};
-  return sq_q(t, k);
-}
-
-Sq sq_qhalf(const double *xa, const double *xb, int k) {
-  const double t[3] = {0.5 * (xb[0] - xa[0]), 0.5 * (xb[1] - xa[1]), 0.5 * (xb[2] - xa[2])};
-  return sq_q(t, k);
-}
+Sq sq_mul(const Sq &A, const Sq &B) { return crit::mul(A, B); }
+Sq sq_t(const Sq &A) { return crit::tr(A); }
+Sq sq_t3(const Sq &A, const Sq &B, const Sq &C) { return crit::t3(A, B, C); }
+void sq_axpy(Sq &Y, double s, const Sq &X) { crit::axpy(Y, s, X); }
+Sq sq_sym(const Sq &X) { return crit::sym(X); }
+double sq_frob(const Sq &X) { return crit::frob(X); }
+double sq_trace(const Sq &X) { return crit::trace(X); }
+void sq_eigh(const Sq &A, double *w, Sq &V) { crit::eigh(A, w, V); }
+Sq sq_pinv(const Sq &X, double tau) { return crit::pinv(X, tau); }
+Sq sq_harmonic(const Sq &A, const Sq &B, double tau) { return crit::harmonic(A, B, tau); }
+double sq_genmax(const Sq &L, const Sq &R, double tau) { return crit::genmax(L, R, tau); }
+Sq sq_qtrans(const double *xa, const double *xb, int k) { return crit::qtrans(xa, xb, k); }
+Sq sq_qhalf(const double *xa, const double *xb, int k) { return crit::qhalf(xa, xb, k); }
 
 void mean_pos(const AuxLevel &lev, const std::vector<int> &members, double *out) {
   std::vector<int> s = members;
@@ -494,24 +317,7 @@ void pair_features(const AuxLevel &lev, int i, int j, int e, const std::vector<S
 }
 
 double mu_b(const AuxLevel &lev, int i, int j, const std::vector<Sq> &D, double tau) {
-  const int k = lev.k;
-  const double *xi = lev.xp(i), *xj = lev.xp(j);
-  const Sq Qij = sq_qhalf(xi, xj, k), Qji = sq_qhalf(xj, xi, k);
-  const Sq L = sq_harmonic(sq_t3(Qji, D[i], Qji), sq_t3(Qij, D[j], Qij), tau);
-  Sq R = lev.Emat(lev.edge_id(i, j));
-  for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) {
-    const int l = lev.nb[p];
-    if (l == j) continue;
-    const int ejl = lev.edge_id(j, l);
-    if (ejl < 0) continue;
-    const int eil = lev.nb_e[p];
-    const double *xl = lev.xp(l);
-    const Sq Qli = sq_qhalf(xl, xi, k), Qlj = sq_qhalf(xl, xj, k);
-    const Sq Hl = sq_harmonic(sq_t3(Qli, lev.Emat(eil), Qli), sq_t3(Qlj, lev.Emat(ejl), Qlj), tau);
-    const Sq T = sq_mul(sq_qtrans(xi, xl, k), Qji);
-    sq_axpy(R, 0.5, sq_t3(T, Hl, T));
-  }
-  return sq_genmax(L, R, tau);
+  return crit::mu_b(lev.view(), D.data(), i, j, tau);
 }
 
 double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<Sq> &D, double tau) {
@@ -520,6 +326,12 @@ double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<
   std::vector<int> mem = Cin;
   std::sort(mem.begin(), mem.end());
   const int nC = int(mem.size());
+  // unions of up to four vertices: the fixed-capacity form shared with the device criteria
+  if (nC <= crit::kMaxUnion && k <= 6) {
+    auto g = std::make_unique<crit::GScratch>();
+    const double v = crit::mu_g(lev.view(), D.data(), mem.data(), nC, tau, *g);
+    if (!std::isnan(v)) return v;
+  }
   double xH[3];
   mean_pos(lev, mem, xH);
   // L = D_C - D_C P_C pinv(P_C^T D_C P_C) P_C^T D_C with P_C = [Q^{H->i}]

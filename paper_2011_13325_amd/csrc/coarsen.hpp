@@ -21,6 +21,8 @@
 #include <thread>
 #include <vector>
 
+#include "crit_core.hpp"
+
 #include "dense.hpp"
 
 namespace eamg {
@@ -47,17 +49,6 @@ void parallel_for(int64_t n, F &&f) {
   for (auto &x : th) x.join();
 }
 
-// Small square matrix, k <= 6, row-major.
-struct Sq {
-  int k = 0;
-  double a[36];
-  Sq() {}
-  explicit Sq(int k_) : k(k_) {
-    for (int i = 0; i < 36; ++i) a[i] = 0.0;
-  }
-  double &operator()(int i, int j) { return a[i * k + j]; }
-  double operator()(int i, int j) const { return a[i * k + j]; }
-};
 
 // Phase timing on stderr when EAMG_VERBOSE is set.
 struct PhaseTimer {
@@ -131,6 +122,18 @@ struct AuxLevel {
   std::vector<int> nb, nb_e;
 
   int64_t m() const { return int64_t(e0.size()); }
+  LevelView view() const {
+    LevelView v;
+    v.n = n;
+    v.k = k;
+    v.x = x.data();
+    v.E = E.data();
+    v.M = M.data();
+    v.nb_ptr = nb_ptr.data();
+    v.nb = nb.data();
+    v.nb_e = nb_e.data();
+    return v;
+  }
   void build_adjacency();
   int edge_id(int i, int j) const;   // -1 if absent
   Sq Emat(int64_t e) const;
