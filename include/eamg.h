@@ -7,8 +7,8 @@
  * topology ("edge matrix") AMG (section "res"): coarsening by successive matching on edge and
  * vertex weight matrices (Algorithm alg:pwagg; Thms thm:deng_elast and thm:cemats), auxiliary
  * smoothed prolongation (Def. def:aux_sp), Galerkin coarse operators, a symmetric multicolour
- * block Gauss-Seidel smoother with pseudo-inverted diagonal blocks and a regularized dense
- * Cholesky coarsest level (section "sing2").
+ * block Gauss-Seidel smoother with pseudo-inverted diagonal blocks and a regularized coarsest
+ * level inverted densely on the GPU (section "sing2").
  *
  * Conventions shared by every entry point:
  *  - Plain C types only.  Integers are int32_t unless stated, reals are IEEE double.
@@ -114,6 +114,11 @@ typedef struct {
  *                     candidate of smallest mu_s is paired without evaluating mu_b / mu_g, the
  *                     scalar-only coarsening the paper contrasts with in its coefficient-jump
  *                     example (figures fig:2dc_rob / fig:2dc_norob); for comparisons only.
+ *  gpu_criteria       1: the matching walks hand the pairs whose criteria they need to GPU
+ *                     kernels in batches (mu_b per pair, mu_g per union of up to four vertices;
+ *                     bit-identical to the host code, so the same hierarchy; default); batches
+ *                     too small to gain from a launch (under 4096 pairs, 128 unions) stay on host
+ *                     threads.  2: every batch on the GPU.  0: host threads only.
  */
 typedef struct eamg_gnn eamg_gnn;
 typedef struct {
@@ -127,6 +132,7 @@ typedef struct {
   double gnn_skip;
   int32_t gnn_record;
   int32_t mu_s_only;
+  int32_t gpu_criteria;
 } eamg_setup_params;
 
 /* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,
@@ -359,6 +365,26 @@ void eamg_destroy(eamg_hierarchy *h);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *eamg_last_error(void);
+
+/*
+ * The exact coarsening criteria of given pairs and unions of one auxiliary level, evaluated by the
+ * GPU kernels the setup uses (use_device = 1, on `stream`) or by the host code (use_device = 0):
+ * for checking the two against each other and against an independent evaluation.  HOST arrays;
+ * the level as in eamg_host_match (D-hat blocks computed from it).
+ *  n_pairs, pairs     2 per pair: vertices i, j joined by an edge -> out_mub[n_pairs], mu_b of
+ *                     Lemma thm:mu2 (delta = 1)
+ *  n_unions, unions   4 per union: distinct ascending vertex ids, padded with -1 at the end ->
+ *                     out_mug[n_unions], mu_g of Thm thm:mu1 for C = the union (delta = 1); a
+ *                     union the device cannot hold (more than 384 edges leaving it) is
+ *                     evaluated on the host
+ *  tau                relative eigenvalue cut of the pseudo-inverses (pinv_rtol)
+ * Pairs that are not edges and malformed unions give EAMG_ERR_INVALID_ARG; nothing is written.
+ */
+eamg_status eamg_criteria_eval(int32_t k, int32_t n, const double *coords, int64_t n_edges,
+                               const int32_t *edges, const double *E, const double *M,
+                               int64_t n_pairs, const int32_t *pairs, int64_t n_unions,
+                               const int32_t *unions, double tau, int32_t use_device,
+                               void *stream, double *out_mub, double *out_mug);
 
 /*
  * Host-only successive matching of one level (Algorithm alg:pwagg), exposed so the coarsening

@@ -36,6 +36,7 @@ STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "INVALID_ARG", -2: "UNSUPPORTED
 EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setup", "eamg_solve",
             "eamg_vcycle", "eamg_stats", "eamg_level_info_get", "eamg_export_level",
             "eamg_traffic_model", "eamg_destroy", "eamg_last_error", "eamg_host_match",
+            "eamg_criteria_eval",
             "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
             "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
             "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy", "eamg_coarsening_stats",
@@ -59,7 +60,8 @@ class eamg_setup_params(ctypes.Structure):
                 ("cap_std", ctypes.c_int32), ("pinv_rtol", ctypes.c_double),
                 ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32),
                 ("gnn", ctypes.c_void_p), ("gnn_skip", ctypes.c_double),
-                ("gnn_record", ctypes.c_int32), ("mu_s_only", ctypes.c_int32)]
+                ("gnn_record", ctypes.c_int32), ("mu_s_only", ctypes.c_int32),
+                ("gpu_criteria", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):
@@ -146,6 +148,9 @@ def lib():
     L.eamg_host_match.argtypes = [i32, i32, vp, i64, vp, vp, vp, vp, P(eamg_setup_params), vp,
                                   P(i32), vp, P(dp)]
     L.eamg_host_match.restype = ctypes.c_int
+    L.eamg_criteria_eval.argtypes = [i32, i32, vp, i64, vp, vp, vp, i64, vp, i64, vp, dp, i32, vp,
+                                     vp, vp]
+    L.eamg_criteria_eval.restype = ctypes.c_int
     L.eamg_profile_enable.argtypes = [vp, i32]
     L.eamg_profile_enable.restype = ctypes.c_int
     L.eamg_profile_read.argtypes = [vp, i32, P(eamg_kernel_stat), P(i32)]
@@ -487,6 +492,28 @@ def eamg_host_match(k, coords, edges, E, M, vd=None, params=None):
     if st != EAMG_OK:
         raise EamgError(st, "eamg_host_match")
     return agg, nc.value, cc[:nc.value], margin.value
+
+
+def eamg_criteria_eval(k, coords, edges, E, M, pairs, unions, tau=1e-10, use_device=True,
+                       stream=None):
+    """mu_b of each pair (m x 2) and mu_g of each union (u x 4, ascending, -1 padded) of one
+    auxiliary level, by the GPU kernels (use_device) or the host code; returns (mub, mug)."""
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    n = coords.shape[0]
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    unions = np.ascontiguousarray(unions, dtype=np.int32).reshape(-1, 4)
+    mub = np.zeros(pairs.shape[0])
+    mug = np.zeros(unions.shape[0])
+    st = lib().eamg_criteria_eval(k, n, _ptr(coords), edges.shape[0], _ptr(edges), _ptr(E), _ptr(M),
+                                  pairs.shape[0], _ptr(pairs), unions.shape[0], _ptr(unions),
+                                  float(tau), int(bool(use_device)),
+                                  _stream(stream) if use_device else None, _ptr(mub), _ptr(mug))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_criteria_eval")
+    return mub, mug
 
 
 class Hierarchy:

@@ -14,7 +14,9 @@ LIB = os.path.join(HERE, "libeamg.so")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp"]
-HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip"]
+HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip"]
+# the criteria must round like the host code (no fused multiply-add)
+FILE_FLAGS = {"criteria.hip": ["-ffp-contract=off"]}
 
 # Packed FP32 instructions are kept out of the device code (-packed-fp32-ops).
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -37,7 +39,8 @@ def build(verbose=False):
     jobs = []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        jobs.append(([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+        jobs.append(([hipcc, *HIP_FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj],
+                     obj))
     for src in HOST_SOURCES:
         obj = os.path.join(objdir, src + ".o")
         # host sources include the HIP runtime header: compile with hipcc in host-only mode

@@ -14,6 +14,7 @@
 
 #include "../../include/eamg.h"
 #include "coarsen.hpp"
+#include "criteria.hpp"
 #include "dense.hpp"
 #include "gnn_host.hpp"
 #include "hierarchy.hpp"
@@ -45,6 +46,7 @@ eamg_setup_params defaults() {
   p.gnn_skip = 0.0;
   p.gnn_record = 0;
   p.mu_s_only = 0;
+  p.gpu_criteria = 1;
   return p;
 }
 
@@ -66,6 +68,8 @@ void validate_params(const eamg_setup_params &p) {
   if (!(p.gnn_skip >= 0.0 && p.gnn_skip < 1.0)) fail(EAMG_ERR_INVALID_ARG, "gnn_skip must be in [0, 1)");
   if (p.gnn_record != 0 && p.gnn_record != 1) fail(EAMG_ERR_INVALID_ARG, "gnn_record must be 0 or 1");
   if (p.mu_s_only != 0 && p.mu_s_only != 1) fail(EAMG_ERR_INVALID_ARG, "mu_s_only must be 0 or 1");
+  if (p.gpu_criteria < 0 || p.gpu_criteria > 2)
+    fail(EAMG_ERR_INVALID_ARG, "gpu_criteria must be 0, 1 or 2");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -833,6 +837,15 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     mp.tie_rtol = prm.tie_rtol;
     mp.tau = prm.pinv_rtol;
     mp.record = prm.gnn_record != 0;
+    std::unique_ptr<CritBatch> crit_dev;
+    if (prm.gpu_criteria) {
+      crit_dev = make_device_criteria(s);
+      mp.batch = crit_dev.get();
+      if (prm.gpu_criteria == 1) {
+        mp.batch_min_pairs = kGpuCritMinPairs;
+        mp.batch_min_unions = kGpuCritMinUnions;
+      }
+    }
     if (prm.gnn && prm.gnn_skip > 0.0) {
       eamg_gnn *net = const_cast<eamg_gnn *>(prm.gnn);
       mp.skip = prm.gnn_skip;
@@ -1393,33 +1406,100 @@ eamg_status eamg_profile_read(eamg_hierarchy *h, int32_t max_entries, eamg_kerne
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// An auxiliary level from host arrays (eamg_host_match / eamg_criteria_eval arguments).
+AuxLevel host_level(int32_t k, int32_t n, const double *coords, int64_t n_edges,
+                    const int32_t *edges, const double *E, const double *M) {
+  if (k != 1 && k != 6) fail(EAMG_ERR_UNSUPPORTED_KERNEL, "k must be 1 or 6");
+  if (n < 0 || n_edges < 0 || !coords || !M || (n_edges && (!edges || !E)))
+    fail(EAMG_ERR_INVALID_ARG, "bad arguments");
+  AuxLevel lev;
+  lev.n = n;
+  lev.k = k;
+  lev.x.assign(coords, coords + size_t(3) * n);
+  lev.e0.resize(size_t(n_edges));
+  lev.e1.resize(size_t(n_edges));
+  for (int64_t e = 0; e < n_edges; ++e) {
+    lev.e0[e] = edges[2 * e];
+    lev.e1[e] = edges[2 * e + 1];
+    if (lev.e0[e] < 0 || lev.e1[e] >= n || lev.e0[e] >= lev.e1[e])
+      fail(EAMG_ERR_INVALID_ARG, "edges must satisfy 0 <= i < j < n");
+    if (e && (lev.e0[e - 1] > lev.e0[e] || (lev.e0[e - 1] == lev.e0[e] && lev.e1[e - 1] >= lev.e1[e])))
+      fail(EAMG_ERR_INVALID_ARG, "edges must be strictly ascending");
+  }
+  lev.E.assign(E, E + size_t(n_edges) * k * k);
+  lev.M.assign(M, M + size_t(n) * k * k);
+  lev.build_adjacency();
+  return lev;
+}
+
+}  // namespace
+
+extern "C" {
+
+eamg_status eamg_criteria_eval(int32_t k, int32_t n, const double *coords, int64_t n_edges,
+                               const int32_t *edges, const double *E, const double *M,
+                               int64_t n_pairs, const int32_t *pairs, int64_t n_unions,
+                               const int32_t *unions, double tau, int32_t use_device,
+                               void *stream, double *out_mub, double *out_mug) {
+  return guarded([&] {
+    if (n_pairs < 0 || n_unions < 0 || (n_pairs && (!pairs || !out_mub)) ||
+        (n_unions && (!unions || !out_mug)) || !(tau >= 0.0) || (use_device != 0 && use_device != 1))
+      fail(EAMG_ERR_INVALID_ARG, "bad arguments");
+    if (n_pairs > INT32_MAX / 2 || n_unions > INT32_MAX / crit::kMaxUnion)
+      fail(EAMG_ERR_INVALID_ARG, "too many pairs or unions");
+    const AuxLevel lev = host_level(k, n, coords, n_edges, edges, E, M);
+    for (int64_t u = 0; u < n_pairs; ++u) {
+      const int i = pairs[2 * u], j = pairs[2 * u + 1];
+      if (i < 0 || i >= n || j < 0 || j >= n || lev.edge_id(i, j) < 0)
+        fail(EAMG_ERR_INVALID_ARG, "every pair must be an edge of the level");
+    }
+    for (int64_t u = 0; u < n_unions; ++u) {
+      const int32_t *m = unions + crit::kMaxUnion * u;
+      if (m[0] < 0 || m[0] >= n) fail(EAMG_ERR_INVALID_ARG, "malformed union");
+      for (int a = 1; a < crit::kMaxUnion; ++a)
+        if (m[a] >= n || (m[a] >= 0 && !(m[a - 1] >= 0 && m[a - 1] < m[a])))
+          fail(EAMG_ERR_INVALID_ARG, "union members must be distinct, ascending, -1 padded");
+    }
+    std::vector<Sq> D;
+    dhat_all(lev, D);
+    std::vector<int32_t> pv(pairs, pairs + 2 * n_pairs), uv(unions, unions + crit::kMaxUnion * n_unions);
+    std::vector<double> mub(static_cast<size_t>(n_pairs)), mug(static_cast<size_t>(n_unions));
+    auto host_g = [&](int64_t u) {
+      std::vector<int> C;
+      for (int a = 0; a < crit::kMaxUnion; ++a)
+        if (uv[crit::kMaxUnion * u + a] >= 0) C.push_back(uv[crit::kMaxUnion * u + a]);
+      mug[u] = mu_g(lev, C, D, tau);
+    };
+    if (use_device) {
+      std::unique_ptr<CritBatch> cb = make_device_criteria(static_cast<hipStream_t>(stream));
+      cb->level(lev, D);
+      cb->work(lev, D);
+      cb->mu_b(pv, tau, mub);
+      cb->mu_g(uv, tau, mug);
+      for (int64_t u = 0; u < n_unions; ++u)
+        if (std::isnan(mug[u])) host_g(u);
+    } else {
+      parallel_for_dynamic(n_pairs, [&](int64_t u) { mub[u] = mu_b(lev, pv[2 * u], pv[2 * u + 1], D, tau); }, 16);
+      parallel_for_dynamic(n_unions, host_g, 4);
+    }
+    if (n_pairs) std::copy(mub.begin(), mub.end(), out_mub);
+    if (n_unions) std::copy(mug.begin(), mug.end(), out_mug);
+  });
+}
+
 eamg_status eamg_host_match(int32_t k, int32_t n, const double *coords, int64_t n_edges,
                             const int32_t *edges, const double *E, const double *M,
                             const uint8_t *vd, const eamg_setup_params *params, int32_t *out_agg,
                             int32_t *out_nc, double *out_ccoords, double *out_margin) {
   return guarded([&] {
-    if (k != 1 && k != 6) fail(EAMG_ERR_UNSUPPORTED_KERNEL, "k must be 1 or 6");
-    if (n < 0 || n_edges < 0 || !coords || !M || !out_agg || !out_nc || (n_edges && (!edges || !E)))
-      fail(EAMG_ERR_INVALID_ARG, "bad arguments");
+    if (!out_agg || !out_nc) fail(EAMG_ERR_INVALID_ARG, "bad arguments");
     const eamg_setup_params prm = params ? *params : defaults();
     validate_params(prm);
-    AuxLevel lev;
-    lev.n = n;
-    lev.k = k;
-    lev.x.assign(coords, coords + size_t(3) * n);
-    lev.e0.resize(size_t(n_edges));
-    lev.e1.resize(size_t(n_edges));
-    for (int64_t e = 0; e < n_edges; ++e) {
-      lev.e0[e] = edges[2 * e];
-      lev.e1[e] = edges[2 * e + 1];
-      if (lev.e0[e] < 0 || lev.e1[e] >= n || lev.e0[e] >= lev.e1[e])
-        fail(EAMG_ERR_INVALID_ARG, "edges must satisfy 0 <= i < j < n");
-      if (e && (lev.e0[e - 1] > lev.e0[e] || (lev.e0[e - 1] == lev.e0[e] && lev.e1[e - 1] >= lev.e1[e])))
-        fail(EAMG_ERR_INVALID_ARG, "edges must be strictly ascending");
-    }
-    lev.E.assign(E, E + size_t(n_edges) * k * k);
-    lev.M.assign(M, M + size_t(n) * k * k);
-    lev.build_adjacency();
+    const AuxLevel lev = host_level(k, n, coords, n_edges, edges, E, M);
     std::vector<char> vdm(static_cast<size_t>(n), 0);
     if (vd)
       for (int i = 0; i < n; ++i) vdm[i] = vd[i] ? 1 : 0;

@@ -515,7 +515,9 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
     double mub, mug;   // mug NaN when not needed (mub >= sigma or a pair of single vertices)
   };
   std::unordered_map<int64_t, Crit> known;
+  bool batch_level = false;
   for (int p = 1; p <= prm.rounds; ++p) {
+    bool batch_work = false;
     pos.assign(size_t(work->n), 0);
     for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
     trace_strength(*work, mtr);
@@ -701,16 +703,72 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       ck = std::move(next);
       const auto te0 = std::chrono::steady_clock::now();
       std::vector<Crit> val(unknown.size());
-      parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
-        const int ci = unknown[u].first, cj = unknown[u].second;
-        Crit c{mu_b(*work, ci, cj, *wdhat, prm.tau), std::numeric_limits<double>::quiet_NaN()};
-        if (c.mub < sigma && members[ci].size() + members[cj].size() > 2) {
+      if (prm.batch && unknown.size() >= size_t(std::max(1, prm.batch_min_pairs))) {
+        // the batch evaluator: mu_b of every unknown pair, then mu_g of the unions of up to
+        // crit::kMaxUnion vertices whose mu_b passes; larger unions and unions it could not
+        // evaluate on the host
+        if (!batch_level) {
+          prm.batch->level(lev, Dhat);
+          batch_level = true;
+        }
+        if (!batch_work) {
+          prm.batch->work(*work, *wdhat);
+          batch_work = true;
+        }
+        std::vector<int32_t> pr(2 * unknown.size());
+        for (size_t u = 0; u < unknown.size(); ++u) {
+          pr[2 * u] = unknown[u].first;
+          pr[2 * u + 1] = unknown[u].second;
+        }
+        std::vector<double> mub, mug;
+        prm.batch->mu_b(pr, prm.tau, mub);
+        std::vector<int32_t> un4;
+        std::vector<size_t> on_dev, on_host;
+        for (size_t u = 0; u < unknown.size(); ++u) {
+          const int ci = unknown[u].first, cj = unknown[u].second;
+          val[u] = Crit{mub[u], std::numeric_limits<double>::quiet_NaN()};
+          const size_t nC = members[ci].size() + members[cj].size();
+          if (!(mub[u] < sigma) || nC <= 2) continue;
+          if (nC > size_t(crit::kMaxUnion) || lev.k > 6) {
+            on_host.push_back(u);
+            continue;
+          }
           std::vector<int> un = members[ci];
           un.insert(un.end(), members[cj].begin(), members[cj].end());
-          c.mug = mu_g(lev, un, Dhat, prm.tau);
+          std::sort(un.begin(), un.end());
+          for (int a = 0; a < crit::kMaxUnion; ++a) un4.push_back(a < int(nC) ? un[a] : -1);
+          on_dev.push_back(u);
         }
-        val[u] = c;
-      }, 16);
+        if (on_dev.size() >= size_t(std::max(1, prm.batch_min_unions))) {
+          prm.batch->mu_g(un4, prm.tau, mug);
+          for (size_t q = 0; q < on_dev.size(); ++q) {
+            if (std::isnan(mug[q]))
+              on_host.push_back(on_dev[q]);
+            else
+              val[on_dev[q]].mug = mug[q];
+          }
+        } else {
+          on_host.insert(on_host.end(), on_dev.begin(), on_dev.end());
+        }
+        parallel_for_dynamic(int64_t(on_host.size()), [&](int64_t q) {
+          const size_t u = on_host[size_t(q)];
+          const int ci = unknown[u].first, cj = unknown[u].second;
+          std::vector<int> un = members[ci];
+          un.insert(un.end(), members[cj].begin(), members[cj].end());
+          val[u].mug = mu_g(lev, un, Dhat, prm.tau);
+        }, 4);
+      } else {
+        parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
+          const int ci = unknown[u].first, cj = unknown[u].second;
+          Crit c{mu_b(*work, ci, cj, *wdhat, prm.tau), std::numeric_limits<double>::quiet_NaN()};
+          if (c.mub < sigma && members[ci].size() + members[cj].size() > 2) {
+            std::vector<int> un = members[ci];
+            un.insert(un.end(), members[cj].begin(), members[cj].end());
+            c.mug = mu_g(lev, un, Dhat, prm.tau);
+          }
+          val[u] = c;
+        }, 16);
+      }
       for (size_t u = 0; u < unknown.size(); ++u) known.emplace(key(unknown[u].first, unknown[u].second), val[u]);
       n_eval += long(unknown.size());
       t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - te0).count();

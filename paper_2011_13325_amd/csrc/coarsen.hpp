@@ -96,6 +96,24 @@ struct PassSamples {
 // Scores the candidate pairs of a pass: logits (one per pair) of "the exact criterion accepts".
 using PairScorer = std::function<void(const PassSamples &, std::vector<float> &)>;
 
+struct AuxLevel;
+
+// Batched evaluation of the exact criteria of a matching pass on another processor (the device
+// implementation is in criteria.hip).  level(): the level being coarsened and its D-hat blocks
+// (the data of mu_g); work(): the working level of the current pass and its D-hat blocks (the
+// data of mu_b; may be the same objects as level()).  Both stay referenced until the next call.
+// mu_b(): one value per pair (i, j) of working-level vertices (2 ints per pair).  mu_g(): one
+// value per union of up to crit::kMaxUnion level vertices (ascending, padded with -1); NaN where
+// the union could not be evaluated there (the caller evaluates it itself).  Values are those of
+// the host criteria bit for bit.
+struct CritBatch {
+  virtual ~CritBatch() = default;
+  virtual void level(const AuxLevel &lev, const std::vector<Sq> &D) = 0;
+  virtual void work(const AuxLevel &w, const std::vector<Sq> &D) = 0;
+  virtual void mu_b(const std::vector<int32_t> &pairs, double tau, std::vector<double> &out) = 0;
+  virtual void mu_g(const std::vector<int32_t> &unions, double tau, std::vector<double> &out) = 0;
+};
+
 struct MatchParams {
   double sigma = 20.0;
   int rounds = 2;
@@ -110,6 +128,11 @@ struct MatchParams {
   // pair the candidate of smallest mu_s without evaluating mu_b / mu_g (the scalar-only
   // coarsening the paper contrasts the robust criteria with)
   bool mu_s_only = false;
+  // evaluate the walks' unknown pairs through this batch evaluator instead of host threads:
+  // batches of at least batch_min_pairs pairs (mu_b) and batch_min_unions unions (mu_g); smaller
+  // ones, whose cost is the evaluator's latency rather than its throughput, stay on host threads
+  CritBatch *batch = nullptr;
+  int batch_min_pairs = 1, batch_min_unions = 1;
 };
 
 struct AuxLevel {

@@ -402,6 +402,7 @@ EAMG_HD inline double mu_g(const LevelView &lev, const Sq *D, const int *mem, in
     int s1 = s0 + 1;
     while (s1 < no && g.ol[s1] == g.ol[s0]) ++s1;
     const int cnt = s1 - s0;
+    if (cnt > kMaxUnion) return __builtin_nan("");   // repeated adjacency entries
     if (cnt >= 2) {
       // local assembly of the edges (i, l), i in C, with unknowns (v_C, w); Schur complement on
       // v_C.  An outside neighbour meets at most kMaxUnion members (one edge each).

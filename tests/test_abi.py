@@ -139,3 +139,33 @@ def test_host_matching_on_eleven_boxes_matches_oracle(mu_s_only):
         assert nc == len(res.aggs)
         assert np.array_equal(agg, ao)
         lev, vd = res.coarse_level, np.zeros(res.coarse_level.n, bool)
+
+
+@pytest.mark.parametrize("kind", ["elasticity", "poisson"])
+def test_host_criteria_match_oracle(kind):
+    """mu_b (Lemma thm:mu2) and mu_g (Thm thm:mu1) of the library's host code against the oracle's
+    numpy evaluation, on the finest level and on a coarse level (vertex weights M != 0)."""
+    from oracle.auxtop import dhat_all
+    from oracle.criteria import mu_b as o_mu_b, mu_g as o_mu_g
+    p = make_problem(8, kind=kind, clamp="x0" if kind == "elasticity" else "all")
+    lev = finest_aux(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals)
+    rng = np.random.default_rng(5)
+    for level in range(2):
+        pairs = np.asarray(lev.edges, np.int32)[rng.choice(len(lev.edges), 80, replace=False)]
+        unions = []
+        for i, j in pairs[:30]:
+            nb = [int(v) for v in lev.neighbors(int(j))[0] if v != i]
+            if nb:
+                mem = sorted({int(i), int(j), nb[0]} | ({nb[-1]} if len(nb) > 1 else set()))
+                unions.append(mem + [-1] * (4 - len(mem)))
+        mub, mug = E.eamg_criteria_eval(lev.k, lev.coords, lev.edges, lev.E, lev.M, pairs,
+                                        np.asarray(unions), use_device=False)
+        D = dhat_all(lev)
+        bo = np.array([o_mu_b(lev, int(i), int(j), D) for i, j in pairs])
+        go = np.array([o_mu_g(lev, [v for v in u if v >= 0], D) for u in unions])
+        for got, ref in ((mub, bo), (mug, go)):
+            fin = np.isfinite(ref)
+            assert np.array_equal(np.isfinite(got), fin)
+            assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-7 * np.abs(ref[fin]))
+        res = successive_matching(lev, p.dirichlet.astype(bool) if level == 0 else np.zeros(lev.n, bool))
+        lev = res.coarse_level
