@@ -44,6 +44,10 @@ def _args():
     ap.add_argument("--batch", type=int, default=32,
                     help="right-hand sides of the batched block-panel solve (0: skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarsening section")
+    ap.add_argument("--learned-n", type=int, default=40,
+                    help="cube side of the learned-coarsening comparison (96: the full configuration)")
+    ap.add_argument("--learned-inclusions", type=int, default=60,
+                    help="stiff spherical inclusions of that cube (200 at 96^3)")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run only the workload of the rocprofv3 counter passes (no JSON line)")
     ap.add_argument("--multi", type=int, default=16,
@@ -401,7 +405,7 @@ def main():
         out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi,
                                         coarsest=args.coarsest)
     if not args.no_learned:
-        out["learned_coarsening"] = _learned(E, torch)
+        out["learned_coarsening"] = _learned(E, torch, args.learned_n, args.learned_inclusions)
     levels = []
     for l in range(st["n_levels"]):
         li = E.eamg_level_info_get(hier.h, l)
