@@ -288,11 +288,20 @@ double mu_D(const AuxLevel &lev, int i, const std::vector<Sq> &D, double tau) {
   return sq_genmax(D[i], lev.Mmat(i), tau);
 }
 
-double mu_s(const AuxLevel &lev, int i, int j, const std::vector<double> &mtr) {
-  const int e = lev.edge_id(i, j);
-  const double t = e >= 0 ? sq_trace(lev.Emat(e)) : 0.0;
+// mu_s of the pair (i, j) joined by edge e (-1: no edge)
+static double mu_s_edge(const AuxLevel &lev, int i, int j, int64_t e, const std::vector<double> &mtr) {
+  double t = 0.0;
+  if (e >= 0) {
+    const int k = lev.k;
+    const double *E = &lev.E[size_t(e) * k * k];
+    for (int d = 0; d < k; ++d) t += E[d * k + d];   // the trace, summed as sq_trace does
+  }
   if (t == 0.0) return kInf;
   return std::sqrt(mtr[i] * mtr[j]) / t;
+}
+
+double mu_s(const AuxLevel &lev, int i, int j, const std::vector<double> &mtr) {
+  return mu_s_edge(lev, i, j, lev.edge_id(i, j), mtr);
 }
 
 // Features of candidate pair (i, j) (edge e): log mu_s, the spectrum of sym(E^{ij}) / tr E^{ij}
@@ -514,20 +523,37 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   struct Crit {
     double mub, mug;   // mug NaN when not needed (mub >= sigma or a pair of single vertices)
   };
-  std::unordered_map<int64_t, Crit> known;
+  // per working-level adjacency entry q (the pair (i, nb[q]), i the walking vertex): mu_s, the
+  // criteria once evaluated, the learned acceptance probability
+  std::vector<double> ms_q;
+  std::vector<Crit> crit_q;
+  std::vector<char> has_q;
+  std::vector<float> prob_q;
   bool batch_level = false;
   for (int p = 1; p <= prm.rounds; ++p) {
     bool batch_work = false;
     pos.assign(size_t(work->n), 0);
     for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
     trace_strength(*work, mtr);
-    known.clear();
-    const int64_t nw = work->n;
-    auto key = [nw](int ci, int cj) { return int64_t(ci) * nw + cj; };
+    const size_t nq = work->nb.size();
+    ms_q.assign(nq, 0.0);
+    parallel_for(work->n, [&](int64_t i) {
+      for (int64_t q = work->nb_ptr[i]; q < work->nb_ptr[i + 1]; ++q)
+        ms_q[q] = mu_s_edge(*work, int(i), work->nb[q], work->nb_e[q], mtr);
+    });
+    crit_q.assign(nq, Crit{0.0, 0.0});
+    has_q.assign(nq, 0);
+    // adjacency entry of j in the list of i (-1: not adjacent)
+    auto qpos = [&](int i, int j) -> int64_t {
+      const auto b = work->nb.begin() + work->nb_ptr[i], e = work->nb.begin() + work->nb_ptr[i + 1];
+      const auto it = std::lower_bound(b, e, j);
+      return (it != e && *it == j) ? int64_t(it - work->nb.begin()) : -1;
+    };
     // candidate pairs of the pass (both ends free, mu_s < sigma), scored by the learned model
     const bool learned = bool(prm.scorer) && prm.skip > 0.0;
     PassSamples ps;
-    std::unordered_map<int64_t, float> prob;
+    std::vector<int64_t> ps_q;   // adjacency entries (i -> j, j -> i) of each candidate pair
+    if (learned) prob_q.assign(nq, 1.0f);
     if (learned || prm.record) {
       ps.n = work->n;
       for (int i = 0; i < work->n; ++i) {
@@ -535,9 +561,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         for (int64_t q = work->nb_ptr[i]; q < work->nb_ptr[i + 1]; ++q) {
           const int j = work->nb[q];
           if (j <= i || !in_T[j]) continue;
-          if (!(mu_s(*work, i, j, mtr) < sigma)) continue;
+          if (!(ms_q[q] < sigma)) continue;
           ps.edges.push_back(i);
           ps.edges.push_back(j);
+          ps_q.push_back(q);
+          ps_q.push_back(qpos(j, i));
         }
       }
       const size_t np = ps.edges.size() / 2;
@@ -552,8 +580,8 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         prm.scorer(ps, z);
         for (size_t q = 0; q < np; ++q) {
           const float pr = 1.0f / (1.0f + std::exp(-z[q]));
-          prob[key(ps.edges[2 * q], ps.edges[2 * q + 1])] = pr;
-          prob[key(ps.edges[2 * q + 1], ps.edges[2 * q])] = pr;
+          prob_q[ps_q[2 * q]] = pr;
+          if (ps_q[2 * q + 1] >= 0) prob_q[ps_q[2 * q + 1]] = pr;
         }
       }
     }
@@ -561,7 +589,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
     int64_t w_eval = 0, w_eval_g = 0, w_skip = 0;
     std::vector<std::pair<int, int>> pairs;
     std::vector<int> singles;
-    std::vector<std::pair<int, int>> unknown;
+    struct Unknown {
+      int ci, cj;
+      int64_t q;   // adjacency entry of (ci, cj)
+    };
+    std::vector<Unknown> unknown;
     int walks = 0;
     long n_eval = 0;
     double t_walk = 0.0, t_eval = 0.0;
@@ -596,7 +628,12 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       auto note_w = [&](double mu) {
         if (std::isfinite(mu)) min_margin = std::min(min_margin, std::fabs(mu - sigma) / sigma);
       };
-      std::vector<std::pair<int, double>> cands;
+      struct Cand {
+        int cj;
+        double ms;
+        int64_t q;
+      };
+      std::vector<Cand> cands;
       for (size_t a = ck.a; a < order.size(); ++a) {
         const int ci = order[a];
         if (!inT[ci]) continue;
@@ -610,17 +647,16 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         for (int64_t q = work->nb_ptr[ci]; q < work->nb_ptr[ci + 1]; ++q) {
           const int cj = work->nb[q];
           if (!inT[cj]) continue;
-          const double ms = mu_s(*work, ci, cj, mtr);
+          const double ms = ms_q[q];
           note_w(ms);
-          if (ms < sigma) cands.emplace_back(cj, ms);
+          if (ms < sigma) cands.push_back(Cand{cj, ms, q});
         }
         int matched = -1;
         // the exact criteria for (ci, cj), or an optimistic pass when not known yet
-        auto check = [&](int cj) {
+        auto check = [&](int cj, int64_t q) {
           if (prm.mu_s_only) return true;
           ++w_eval;
-          const auto it = known.find(key(ci, cj));
-          if (it == known.end()) {
+          if (!has_q[q]) {
             if (!have_next) {
               have_next = true;
               next.a = a;
@@ -634,10 +670,10 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
               next.evg = evg0;
               next.sk = sk0;
             }
-            unknown.emplace_back(ci, cj);
+            unknown.push_back(Unknown{ci, cj, q});
             return true;   // optimistic
           }
-          const Crit &c = it->second;
+          const Crit &c = crit_q[q];
           note_w(c.mub);
           bool ok = c.mub < sigma;
           if (ok && !std::isnan(c.mug)) {
@@ -649,40 +685,43 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         };
         bool any_checked = false;
         int pass_over = -1;       // best scored candidate passed over
+        int64_t pass_over_q = -1;
         float pass_over_p = -1.0f;
         while (!cands.empty()) {
-          double mmin = cands[0].second;
-          for (const auto &c : cands) mmin = std::min(mmin, c.second);
+          double mmin = cands[0].ms;
+          for (const auto &c : cands) mmin = std::min(mmin, c.ms);
           int best = -1, ntie = 0;
           for (size_t c = 0; c < cands.size(); ++c)
-            if (cands[c].second <= mmin * (1.0 + prm.tie_rtol)) {
+            if (cands[c].ms <= mmin * (1.0 + prm.tie_rtol)) {
               ++ntie;
-              if (best < 0 || pos[cands[c].first] < pos[cands[best].first]) best = int(c);
+              if (best < 0 || pos[cands[c].cj] < pos[cands[best].cj]) best = int(c);
             }
           max_tie = std::max(max_tie, ntie);
-          const int cj = cands[best].first;
+          const int cj = cands[best].cj;
+          const int64_t cq = cands[best].q;
           if (learned) {
-            const auto pit = prob.find(key(ci, cj));
-            const float pr = pit == prob.end() ? 1.0f : pit->second;
+            const float pr = prob_q[cq];
             if (pr < prm.skip) {
               ++w_skip;
               if (pr > pass_over_p) {
                 pass_over_p = pr;
                 pass_over = cj;
+                pass_over_q = cq;
               }
               cands.erase(cands.begin() + best);
               continue;
             }
           }
           any_checked = true;
-          if (check(cj)) {
+          if (check(cj, cq)) {
             matched = cj;
             break;
           }
           cands.erase(cands.begin() + best);
         }
         // fallback: every candidate was passed over -> the exact criteria decide the best scored
-        if (matched < 0 && !any_checked && pass_over >= 0 && check(pass_over)) matched = pass_over;
+        if (matched < 0 && !any_checked && pass_over >= 0 && check(pass_over, pass_over_q))
+          matched = pass_over;
         if (matched >= 0) {
           pairs.emplace_back(ci, matched);
           inT[matched] = 0;
@@ -717,15 +756,15 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         }
         std::vector<int32_t> pr(2 * unknown.size());
         for (size_t u = 0; u < unknown.size(); ++u) {
-          pr[2 * u] = unknown[u].first;
-          pr[2 * u + 1] = unknown[u].second;
+          pr[2 * u] = unknown[u].ci;
+          pr[2 * u + 1] = unknown[u].cj;
         }
         std::vector<double> mub, mug;
         prm.batch->mu_b(pr, prm.tau, mub);
         std::vector<int32_t> un4;
         std::vector<size_t> on_dev, on_host;
         for (size_t u = 0; u < unknown.size(); ++u) {
-          const int ci = unknown[u].first, cj = unknown[u].second;
+          const int ci = unknown[u].ci, cj = unknown[u].cj;
           val[u] = Crit{mub[u], std::numeric_limits<double>::quiet_NaN()};
           const size_t nC = members[ci].size() + members[cj].size();
           if (!(mub[u] < sigma) || nC <= 2) continue;
@@ -752,14 +791,14 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
         }
         parallel_for_dynamic(int64_t(on_host.size()), [&](int64_t q) {
           const size_t u = on_host[size_t(q)];
-          const int ci = unknown[u].first, cj = unknown[u].second;
+          const int ci = unknown[u].ci, cj = unknown[u].cj;
           std::vector<int> un = members[ci];
           un.insert(un.end(), members[cj].begin(), members[cj].end());
           val[u].mug = mu_g(lev, un, Dhat, prm.tau);
         }, 4);
       } else {
         parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
-          const int ci = unknown[u].first, cj = unknown[u].second;
+          const int ci = unknown[u].ci, cj = unknown[u].cj;
           Crit c{mu_b(*work, ci, cj, *wdhat, prm.tau), std::numeric_limits<double>::quiet_NaN()};
           if (c.mub < sigma && members[ci].size() + members[cj].size() > 2) {
             std::vector<int> un = members[ci];
@@ -769,7 +808,10 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           val[u] = c;
         }, 16);
       }
-      for (size_t u = 0; u < unknown.size(); ++u) known.emplace(key(unknown[u].first, unknown[u].second), val[u]);
+      for (size_t u = 0; u < unknown.size(); ++u) {
+        crit_q[unknown[u].q] = val[u];
+        has_q[unknown[u].q] = 1;
+      }
       n_eval += long(unknown.size());
       t_eval += std::chrono::duration<double>(std::chrono::steady_clock::now() - te0).count();
     }
@@ -784,11 +826,10 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       ps.y.assign(np, 0.0f);
       ps.w.assign(np, 0.0f);
       for (size_t q = 0; q < np; ++q) {
-        const int i = ps.edges[2 * q], j = ps.edges[2 * q + 1];
-        auto it = known.find(key(i, j));
-        if (it == known.end()) it = known.find(key(j, i));
-        if (it == known.end()) continue;
-        const Crit &c = it->second;
+        int64_t at = ps_q[2 * q];
+        if (!has_q[at]) at = ps_q[2 * q + 1];
+        if (at < 0 || !has_q[at]) continue;
+        const Crit &c = crit_q[at];
         const bool acc = c.mub < sigma && (std::isnan(c.mug) || c.mug < sigma);
         ps.y[q] = acc ? 1.0f : 0.0f;
         ps.w[q] = 1.0f;
