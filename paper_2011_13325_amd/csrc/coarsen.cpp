@@ -230,11 +230,23 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
     if (I < 0 || J < 0 || I == J) return;
     key[e] = int64_t(std::min(I, J)) * nc + std::max(I, J);
   });
-  std::vector<int64_t> order;
-  order.reserve(static_cast<size_t>(m));
+  // stable sort by key = (I, J): counting sort by I keeps ascending e within an I bucket, then a
+  // stable insertion sort by J inside each (small) bucket
+  std::vector<int64_t> bucket(static_cast<size_t>(nc) + 1, 0);
   for (int64_t e = 0; e < m; ++e)
-    if (key[e] >= 0) order.push_back(e);
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    if (key[e] >= 0) ++bucket[size_t(key[e] / nc) + 1];
+  for (int I = 0; I < nc; ++I) bucket[I + 1] += bucket[I];
+  std::vector<int64_t> order(static_cast<size_t>(bucket[nc]));
+  {
+    std::vector<int64_t> fill(bucket.begin(), bucket.end() - 1);
+    for (int64_t e = 0; e < m; ++e)
+      if (key[e] >= 0) order[size_t(fill[size_t(key[e] / nc)]++)] = e;
+  }
+  parallel_for(nc, [&](int64_t I) {
+    for (int64_t a = bucket[I] + 1; a < bucket[I + 1]; ++a)
+      for (int64_t b = a; b > bucket[I] && key[order[b]] < key[order[b - 1]]; --b)
+        std::swap(order[b], order[b - 1]);
+  });
   std::vector<int64_t> start;
   for (size_t q = 0; q < order.size(); ++q)
     if (q == 0 || key[order[q]] != key[order[q - 1]]) start.push_back(int64_t(q));
