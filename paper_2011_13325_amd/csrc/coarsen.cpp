@@ -73,7 +73,7 @@ void AuxLevel::build_adjacency() {
     nb[fill[e1[e]]] = e0[e];
     nb_e[fill[e1[e]]++] = int(e);
   }
-  for (int i = 0; i < n; ++i) {
+  parallel_for(n, [&](int64_t i) {
     const int64_t s = nb_ptr[i], t = nb_ptr[i + 1];
     std::vector<std::pair<int, int>> tmp;
     tmp.reserve(size_t(t - s));
@@ -83,7 +83,7 @@ void AuxLevel::build_adjacency() {
       nb[p] = tmp[p - s].first;
       nb_e[p] = tmp[p - s].second;
     }
-  }
+  });
 }
 
 int AuxLevel::edge_id(int i, int j) const {
