@@ -324,8 +324,8 @@ void pair_features(const AuxLevel &lev, int i, int j, int e, const std::vector<S
   const Sq Ee = lev.Emat(e);
   const double t = sq_trace(Ee);
   double w[6] = {0, 0, 0, 0, 0, 0};
-  Sq V;
-  sq_eigh(sq_sym(Ee), w, V);
+  Sq S = sq_sym(Ee);   // eigenvalues only: the rotations do not depend on the eigenvectors
+  crit::jacobi(S.a, S.k, S.k, w, nullptr);
   for (int q = 0; q < kPairFeatures; ++q) f[q] = 0.0f;
   f[0] = float(std::log(std::sqrt(mtr[i] * mtr[j]) / t));
   for (int q = 0; q < lev.k && q < 6; ++q) f[1 + q] = float(w[lev.k - 1 - q] / t);
