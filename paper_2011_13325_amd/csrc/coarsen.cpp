@@ -197,7 +197,7 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
 // ---- coarse level (Thm thm:cemats) -------------------------------------------------------------
 
 AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &aggs,
-                    const std::vector<char> &dmask, const std::vector<double> &cc) {
+                    const std::vector<char> &dmask, const std::vector<double> &cc, CritBatch *dev) {
   const int k = lev.k, kk = k * k;
   const int nc = int(aggs.size());
   std::vector<int> agg_of(static_cast<size_t>(lev.n), -1);
@@ -207,20 +207,6 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
   out.n = nc;
   out.k = k;
   out.x = cc;
-  out.M.assign(size_t(nc) * kk, 0.0);
-  parallel_for(nc, [&](int64_t I) {
-    std::vector<int> mem = aggs[I];
-    std::sort(mem.begin(), mem.end());
-    Sq acc(k);
-    for (int i : mem) {
-      Sq W = lev.Mmat(i);
-      for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p)
-        if (dmask[lev.nb[p]]) sq_axpy(W, 1.0, pulled(lev, lev.nb_e[p], i));
-      const Sq Q = sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k);
-      sq_axpy(acc, 1.0, sq_t3(Q, W, Q));
-    }
-    std::copy(acc.a, acc.a + kk, &out.M[size_t(I) * kk]);
-  });
   // coarse edge key of every fine edge (-1: dropped); the fine edges of one key are summed in
   // ascending fine-edge order (stable sort), so the result does not depend on the threads
   const int64_t m = lev.m();
@@ -254,6 +240,33 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
   start.push_back(int64_t(order.size()));
   out.e0.resize(static_cast<size_t>(ne));
   out.e1.resize(static_cast<size_t>(ne));
+  for (int64_t g = 0; g < ne; ++g) {
+    const int64_t kk0 = key[order[start[g]]];
+    out.e0[g] = int(kk0 / nc);
+    out.e1[g] = int(kk0 % nc);
+  }
+  if (dev && k <= 6) {
+    std::vector<std::vector<int>> sorted(aggs);
+    for (auto &mem : sorted) std::sort(mem.begin(), mem.end());
+    if (dev->coarse_weights(lev, sorted, agg_of, dmask, cc, order, start, out.M, out.E)) {
+      out.build_adjacency();
+      return out;
+    }
+  }
+  out.M.assign(size_t(nc) * kk, 0.0);
+  parallel_for(nc, [&](int64_t I) {
+    std::vector<int> mem = aggs[I];
+    std::sort(mem.begin(), mem.end());
+    Sq acc(k);
+    for (int i : mem) {
+      Sq W = lev.Mmat(i);
+      for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p)
+        if (dmask[lev.nb[p]]) sq_axpy(W, 1.0, pulled(lev, lev.nb_e[p], i));
+      const Sq Q = sq_qtrans(&cc[size_t(3) * I], lev.xp(i), k);
+      sq_axpy(acc, 1.0, sq_t3(Q, W, Q));
+    }
+    std::copy(acc.a, acc.a + kk, &out.M[size_t(I) * kk]);
+  });
   out.E.assign(size_t(ne) * kk, 0.0);
   parallel_for(ne, [&](int64_t g) {
     Sq acc(k);
@@ -266,9 +279,6 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
                           sq_qhalf(&cc[size_t(3) * J], &cc[size_t(3) * I], k));
       sq_axpy(acc, 1.0, sq_t3(T, lev.Emat(e), T));
     }
-    const int64_t kk0 = key[order[start[g]]];
-    out.e0[g] = int(kk0 / nc);
-    out.e1[g] = int(kk0 % nc);
     std::copy(acc.a, acc.a + kk, &out.E[size_t(g) * kk]);
   });
   out.build_adjacency();
@@ -754,25 +764,35 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       ck = std::move(next);
       const auto te0 = std::chrono::steady_clock::now();
       std::vector<Crit> val(unknown.size());
-      if (prm.batch && unknown.size() >= size_t(std::max(1, prm.batch_min_pairs))) {
-        // the batch evaluator: mu_b of every unknown pair, then mu_g of the unions of up to
-        // crit::kMaxUnion vertices whose mu_b passes; larger unions and unions it could not
-        // evaluate on the host
-        if (!batch_level) {
-          prm.batch->level(lev, Dhat);
-          batch_level = true;
+      if (prm.batch) {
+        // the batch evaluator takes mu_b of the unknown pairs when there are batch_min_pairs of
+        // them, and mu_g of the unions of up to crit::kMaxUnion vertices whose mu_b passes when
+        // there are batch_min_unions of them; host threads take the rest, larger unions and
+        // unions the evaluator could not hold
+        auto ensure_levels = [&] {
+          if (!batch_level) {
+            prm.batch->level(lev, Dhat);
+            batch_level = true;
+          }
+          if (!batch_work) {
+            prm.batch->work(*work, *wdhat);
+            batch_work = true;
+          }
+        };
+        std::vector<double> mub(unknown.size()), mug;
+        if (unknown.size() >= size_t(std::max(1, prm.batch_min_pairs))) {
+          ensure_levels();
+          std::vector<int32_t> pr(2 * unknown.size());
+          for (size_t u = 0; u < unknown.size(); ++u) {
+            pr[2 * u] = unknown[u].ci;
+            pr[2 * u + 1] = unknown[u].cj;
+          }
+          prm.batch->mu_b(pr, prm.tau, mub);
+        } else {
+          parallel_for_dynamic(int64_t(unknown.size()), [&](int64_t u) {
+            mub[u] = mu_b(*work, unknown[u].ci, unknown[u].cj, *wdhat, prm.tau);
+          }, 16);
         }
-        if (!batch_work) {
-          prm.batch->work(*work, *wdhat);
-          batch_work = true;
-        }
-        std::vector<int32_t> pr(2 * unknown.size());
-        for (size_t u = 0; u < unknown.size(); ++u) {
-          pr[2 * u] = unknown[u].ci;
-          pr[2 * u + 1] = unknown[u].cj;
-        }
-        std::vector<double> mub, mug;
-        prm.batch->mu_b(pr, prm.tau, mub);
         std::vector<int32_t> un4;
         std::vector<size_t> on_dev, on_host;
         for (size_t u = 0; u < unknown.size(); ++u) {
@@ -787,10 +807,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
           std::vector<int> un = members[ci];
           un.insert(un.end(), members[cj].begin(), members[cj].end());
           std::sort(un.begin(), un.end());
-          for (int a = 0; a < crit::kMaxUnion; ++a) un4.push_back(a < int(nC) ? un[a] : -1);
+          for (int a2 = 0; a2 < crit::kMaxUnion; ++a2) un4.push_back(a2 < int(nC) ? un[a2] : -1);
           on_dev.push_back(u);
         }
         if (on_dev.size() >= size_t(std::max(1, prm.batch_min_unions))) {
+          ensure_levels();
           prm.batch->mu_g(un4, prm.tau, mug);
           for (size_t q = 0; q < on_dev.size(); ++q) {
             if (std::isnan(mug[q]))
@@ -862,7 +883,17 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       std::vector<double> ic(entries.size() * 3);
       for (size_t I = 0; I < entries.size(); ++I) mean_pos(lev, entries[I], &ic[3 * I]);
       std::vector<char> wmask = p == 1 ? res.dmask : std::vector<char>(size_t(work->n), 0);
-      AuxLevel next = coarse_aux(*work, groups, wmask, ic);
+      if (prm.batch) {
+        if (!batch_level) {
+          prm.batch->level(lev, Dhat);
+          batch_level = true;
+        }
+        if (!batch_work) {
+          prm.batch->work(*work, *wdhat);
+          batch_work = true;
+        }
+      }
+      AuxLevel next = coarse_aux(*work, groups, wmask, ic, prm.batch);
       work_store = std::move(next);
       work = &work_store;
       dhat_all(*work, wdhat_store);
@@ -878,7 +909,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   for (auto &a : res.aggs) std::sort(a.begin(), a.end());
   res.ccoords.resize(res.aggs.size() * 3);
   for (size_t I = 0; I < res.aggs.size(); ++I) mean_pos(lev, res.aggs[I], &res.ccoords[3 * I]);
-  res.coarse = coarse_aux(lev, res.aggs, res.dmask, res.ccoords);
+  if (prm.batch && !batch_level) {
+    prm.batch->level(lev, Dhat);
+    batch_level = true;
+  }
+  res.coarse = coarse_aux(lev, res.aggs, res.dmask, res.ccoords, prm.batch);
   tm.mark("coarse weights");
   return res;
 }

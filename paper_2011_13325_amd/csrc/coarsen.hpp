@@ -112,6 +112,15 @@ struct CritBatch {
   virtual void work(const AuxLevel &w, const std::vector<Sq> &D) = 0;
   virtual void mu_b(const std::vector<int32_t> &pairs, double tau, std::vector<double> &out) = 0;
   virtual void mu_g(const std::vector<int32_t> &unions, double tau, std::vector<double> &out) = 0;
+  // Weights of the coarse level (Thm thm:cemats) from the fine level `fine`, which must be the
+  // object last handed to level() or work(); else false and nothing is computed.  aggs: sorted
+  // members per aggregate; order / start: the fine edges of coarse edge g are order[start[g] ..
+  // start[g + 1]) (ascending), summed in that order.  M: nc*k*k, E: (start.size() - 1)*k*k.
+  virtual bool coarse_weights(const AuxLevel &fine, const std::vector<std::vector<int>> &aggs,
+                              const std::vector<int> &agg_of, const std::vector<char> &dmask,
+                              const std::vector<double> &cc, const std::vector<int64_t> &order,
+                              const std::vector<int64_t> &start, std::vector<double> &M,
+                              std::vector<double> &E) = 0;
 };
 
 struct MatchParams {
@@ -181,8 +190,10 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
                 const double *vals, const int32_t *edges, int64_t n_edges, AuxLevel &out,
                 std::string &err);
 
+// dev: optional evaluator holding `lev` on the device, which then computes the weights
 AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &aggs,
-                    const std::vector<char> &dmask, const std::vector<double> &ccoords);
+                    const std::vector<char> &dmask, const std::vector<double> &ccoords,
+                    CritBatch *dev = nullptr);
 
 void dhat_all(const AuxLevel &lev, std::vector<Sq> &D);
 void trace_strength(const AuxLevel &lev, std::vector<double> &m);

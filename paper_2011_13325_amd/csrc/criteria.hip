@@ -500,6 +500,56 @@ __global__ __launch_bounds__(kCritBlock) void k_mu_g_wave(LevelView lev, const S
   }
 }
 
+// ---- coarse level weights (Thm thm:cemats), one thread per aggregate / coarse edge ------------
+
+// M^I = sum over members i (ascending) of Q^T W_i Q, Q = Q^{I->i}, W_i = M^i + the edges from i
+// to dropped vertices pulled to i
+__global__ __launch_bounds__(kCritBlock) void k_coarse_M(LevelView f, int nc, const int *mptr,
+                                                         const int *mem,
+                                                         const unsigned char *dmask,
+                                                         const double *cc, double *Mout) {
+  const int k = f.k;
+  const int stride = gridDim.x * kCritBlock;
+  for (int I = blockIdx.x * kCritBlock + threadIdx.x; I < nc; I += stride) {
+    Sq acc(k);
+    for (int a = mptr[I]; a < mptr[I + 1]; ++a) {
+      const int i = mem[a];
+      Sq W = f.Mmat(i);
+      for (int64_t p = f.nb_ptr[i]; p < f.nb_ptr[i + 1]; ++p)
+        if (dmask[f.nb[p]]) {
+          const Sq Q = crit::qhalf(f.xp(i), f.xp(f.nb[p]), k);
+          crit::axpy(W, 1.0, crit::t3(Q, f.Emat(f.nb_e[p]), Q));
+        }
+      const Sq Q = crit::qtrans(cc + int64_t(3) * I, f.xp(i), k);
+      crit::axpy(acc, 1.0, crit::t3(Q, W, Q));
+    }
+    for (int t = 0; t < k * k; ++t) Mout[int64_t(I) * k * k + t] = acc.a[t];
+  }
+}
+
+// E^{IJ} = sum over the fine edges (i, j) of the group, in order, of T^T E^{ij} T with
+// T = Q^{ij} Q^{I->i} Q^{JI}
+__global__ __launch_bounds__(kCritBlock) void k_coarse_E(LevelView f, const int *e0, const int *e1,
+                                                         const int *agg_of, const double *cc,
+                                                         int64_t ne, const int64_t *start,
+                                                         const int64_t *order, double *Eout) {
+  const int k = f.k;
+  const int64_t stride = int64_t(gridDim.x) * kCritBlock;
+  for (int64_t g = int64_t(blockIdx.x) * kCritBlock + threadIdx.x; g < ne; g += stride) {
+    Sq acc(k);
+    for (int64_t q = start[g]; q < start[g + 1]; ++q) {
+      const int64_t e = order[q];
+      const int i = e0[e], j = e1[e];
+      const int I = agg_of[i], J = agg_of[j];
+      const double *cI = cc + int64_t(3) * I, *cJ = cc + int64_t(3) * J;
+      const Sq T = crit::mul(crit::mul(crit::qhalf(f.xp(i), f.xp(j), k), crit::qtrans(cI, f.xp(i), k)),
+                             crit::qhalf(cJ, cI, k));
+      crit::axpy(acc, 1.0, crit::t3(T, f.Emat(e), T));
+    }
+    for (int t = 0; t < k * k; ++t) Eout[g * k * k + t] = acc.a[t];
+  }
+}
+
 // Device buffer that only grows.
 struct DBuf {
   void *p = nullptr;
@@ -531,9 +581,11 @@ struct DBuf {
 
 // Device copy of one auxiliary level and its D-hat blocks.
 struct DevLevel {
-  DBuf x, E, M, nb_ptr, nb, nb_e, D;
+  DBuf x, E, M, nb_ptr, nb, nb_e, D, e0b, e1b;
   LevelView v;
   const Sq *d = nullptr;
+  const int *e0 = nullptr, *e1 = nullptr;
+  int64_t m = 0;
   void upload(const AuxLevel &l, const std::vector<Sq> &Dh, hipStream_t s) {
     if (l.n > 0 && Dh.size() != size_t(l.n)) fail(EAMG_ERR_INVALID_ARG, "criteria: D-hat size");
     v.n = l.n;
@@ -545,6 +597,9 @@ struct DevLevel {
     v.nb = nb.put(l.nb.data(), l.nb.size(), s);
     v.nb_e = nb_e.put(l.nb_e.data(), l.nb_e.size(), s);
     d = D.put(Dh.data(), Dh.size(), s);
+    e0 = e0b.put(l.e0.data(), l.e0.size(), s);
+    e1 = e1b.put(l.e1.data(), l.e1.size(), s);
+    m = l.m();
     // the sources may change once this returns
     hip_check(hipStreamSynchronize(s), "sync");
   }
@@ -558,6 +613,7 @@ class DeviceCriteria final : public CritBatch {
     lev_.upload(lev, D, s_);
     lev_src_ = &lev;
     work_ = &lev_;
+    wrk_src_ = nullptr;
   }
   void work(const AuxLevel &w, const std::vector<Sq> &D) override {
     if (&w == lev_src_) {
@@ -566,6 +622,73 @@ class DeviceCriteria final : public CritBatch {
     }
     wrk_.upload(w, D, s_);
     work_ = &wrk_;
+    wrk_src_ = &w;
+  }
+  bool coarse_weights(const AuxLevel &fine, const std::vector<std::vector<int>> &aggs,
+                      const std::vector<int> &agg_of, const std::vector<char> &dmask,
+                      const std::vector<double> &cc, const std::vector<int64_t> &order,
+                      const std::vector<int64_t> &start, std::vector<double> &M,
+                      std::vector<double> &E) override {
+    const DevLevel *dl = nullptr;
+    if (&fine == lev_src_)
+      dl = &lev_;
+    else if (&fine == wrk_src_ && work_ == &wrk_)
+      dl = &wrk_;
+    if (!dl || dl->v.n != fine.n || dl->m != fine.m() || dl->v.k != fine.k || fine.k > 6) return false;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int k = fine.k, kk = k * k, nc = int(aggs.size());
+    const int64_t ne = int64_t(start.size()) - 1;
+    // host checks of everything the kernels index with
+    if (int64_t(agg_of.size()) != fine.n || int64_t(dmask.size()) != fine.n ||
+        int64_t(cc.size()) != int64_t(3) * nc || ne < 0 || start.front() != 0 ||
+        start.back() != int64_t(order.size()))
+      fail(EAMG_ERR_INVALID_ARG, "coarse weights: sizes");
+    std::vector<int> mptr(size_t(nc) + 1, 0), mem;
+    for (int I = 0; I < nc; ++I) {
+      for (int i : aggs[I]) {
+        if (i < 0 || i >= fine.n || agg_of[i] != I) fail(EAMG_ERR_INVALID_ARG, "coarse weights: member");
+        mem.push_back(i);
+      }
+      mptr[I + 1] = int(mem.size());
+    }
+    for (int64_t e : order)
+      if (e < 0 || e >= fine.m() || agg_of[fine.e0[e]] < 0 || agg_of[fine.e1[e]] < 0)
+        fail(EAMG_ERR_INVALID_ARG, "coarse weights: edge");
+    for (int64_t g = 0; g < ne; ++g)
+      if (start[g] > start[g + 1]) fail(EAMG_ERR_INVALID_ARG, "coarse weights: groups");
+    std::vector<unsigned char> dm(dmask.begin(), dmask.end());
+    const int *d_mptr = cw_mptr_.put(mptr.data(), mptr.size(), s_);
+    const int *d_mem = cw_mem_.put(mem.data(), mem.size(), s_);
+    const unsigned char *d_dm = cw_dm_.put(dm.data(), dm.size(), s_);
+    const double *d_cc = cw_cc_.put(cc.data(), cc.size(), s_);
+    const int *d_agg = cw_agg_.put(agg_of.data(), agg_of.size(), s_);
+    const int64_t *d_start = cw_start_.put(start.data(), start.size(), s_);
+    const int64_t *d_order = cw_order_.put(order.data(), order.size(), s_);
+    double *d_M = static_cast<double *>(cw_M_.reserve(size_t(nc) * kk * sizeof(double)));
+    double *d_E = static_cast<double *>(cw_E_.reserve(size_t(ne) * kk * sizeof(double)));
+    if (nc > 0) {
+      const int grid = std::min((nc + kCritBlock - 1) / kCritBlock, 8192);
+      hipLaunchKernelGGL(k_coarse_M, dim3(grid), dim3(kCritBlock), 0, s_, dl->v, nc, d_mptr, d_mem,
+                         d_dm, d_cc, d_M);
+      hip_check(hipGetLastError(), "k_coarse_M");
+    }
+    if (ne > 0) {
+      const int grid = int(std::min<int64_t>((ne + kCritBlock - 1) / kCritBlock, 16384));
+      hipLaunchKernelGGL(k_coarse_E, dim3(grid), dim3(kCritBlock), 0, s_, dl->v, dl->e0, dl->e1,
+                         d_agg, d_cc, ne, d_start, d_order, d_E);
+      hip_check(hipGetLastError(), "k_coarse_E");
+    }
+    M.assign(size_t(nc) * kk, 0.0);
+    E.assign(size_t(ne) * kk, 0.0);
+    if (nc > 0)
+      hip_check(hipMemcpyAsync(M.data(), d_M, M.size() * sizeof(double), hipMemcpyDeviceToHost, s_),
+                "download");
+    if (ne > 0)
+      hip_check(hipMemcpyAsync(E.data(), d_E, E.size() * sizeof(double), hipMemcpyDeviceToHost, s_),
+                "download");
+    hip_check(hipStreamSynchronize(s_), "sync");
+    note("coarse weights", int(ne), t0);
+    return true;
   }
   void mu_b(const std::vector<int32_t> &pairs, double tau, std::vector<double> &out) override {
     const int np = int(pairs.size() / 2);
@@ -624,9 +747,10 @@ class DeviceCriteria final : public CritBatch {
   const bool verbose_ = std::getenv("EAMG_VERBOSE") != nullptr;
   hipStream_t s_;
   DevLevel lev_, wrk_;
-  const AuxLevel *lev_src_ = nullptr;
+  const AuxLevel *lev_src_ = nullptr, *wrk_src_ = nullptr;
   const DevLevel *work_ = nullptr;
   DBuf idx_, res_;
+  DBuf cw_mptr_, cw_mem_, cw_dm_, cw_cc_, cw_agg_, cw_start_, cw_order_, cw_M_, cw_E_;
 };
 
 }  // namespace
