@@ -3,6 +3,7 @@
 #include "coarsen.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -154,7 +155,8 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
   out.e1.resize(size_t(m));
   out.E.assign(size_t(m) * k * k, 0.0);
   out.M.assign(size_t(n) * k * k, 0.0);
-  for (int64_t e = 0; e < m; ++e) {
+  std::atomic<bool> same_pos{false};
+  parallel_for(m, [&](int64_t e) {
     const int i = el[e].first, j = el[e].second;
     out.e0[e] = i;
     out.e1[e] = j;
@@ -168,8 +170,8 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
                      coords[3 * j + 2] - coords[3 * i + 2]};
       const double nt = std::sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
       if (!(nt > 0.0)) {
-        err = "two vertices joined by an edge have the same position";
-        return false;
+        same_pos = true;
+        return;
       }
       for (double &v : t) v /= nt;
       for (int a = 0; a < 3; ++a)
@@ -177,6 +179,10 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
     } else {
       Ee[0] = std::fabs(blk[0]);
     }
+  });
+  if (same_pos) {
+    err = "two vertices joined by an edge have the same position";
+    return false;
   }
   if (dim == 1) {
     for (int i = 0; i < n; ++i) {
@@ -297,13 +303,20 @@ void dhat_all(const AuxLevel &lev, std::vector<Sq> &D) {
 }
 
 void trace_strength(const AuxLevel &lev, std::vector<double> &m) {
+  // m_i = max(tr M^i, tr E^il over the edges at i), raised only by a strictly larger trace: the
+  // value does not depend on the order the edges are visited in
   m.assign(size_t(lev.n), 0.0);
-  for (int i = 0; i < lev.n; ++i) m[i] = sq_trace(lev.Mmat(i));
-  for (int64_t e = 0; e < lev.m(); ++e) {
-    const double t = sq_trace(lev.Emat(e));
-    if (t > m[lev.e0[e]]) m[lev.e0[e]] = t;
-    if (t > m[lev.e1[e]]) m[lev.e1[e]] = t;
-  }
+  const int k = lev.k;
+  parallel_for(lev.n, [&](int64_t i) {
+    double v = sq_trace(lev.Mmat(int(i)));
+    for (int64_t p = lev.nb_ptr[i]; p < lev.nb_ptr[i + 1]; ++p) {
+      const double *E = &lev.E[size_t(lev.nb_e[p]) * k * k];
+      double t = 0.0;
+      for (int d = 0; d < k; ++d) t += E[d * k + d];   // summed as sq_trace does
+      if (t > v) v = t;
+    }
+    m[i] = v;
+  });
 }
 
 double mu_D(const AuxLevel &lev, int i, const std::vector<Sq> &D, double tau) {
