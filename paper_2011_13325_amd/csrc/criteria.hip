@@ -18,6 +18,7 @@
 #include "hierarchy.hpp"
 
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -735,6 +736,11 @@ class DeviceCriteria final : public CritBatch {
     hip_check(hipMemcpyAsync(out.data(), dout, size_t(nu) * sizeof(double), hipMemcpyDeviceToHost,
                              s_), "download");
     hip_check(hipStreamSynchronize(s_), "sync");
+    if (verbose_) {
+      int nan = 0;
+      for (double v : out) nan += std::isnan(v) ? 1 : 0;
+      if (nan) std::fprintf(stderr, "[eamg]     device mu_g: %d unions beyond the device capacity\n", nan);
+    }
     note("mu_g", nu, t0);
   }
 
