@@ -76,6 +76,10 @@ def test_malformed_inputs_are_rejected_before_device_work():
     p = _base()
     p["params"] = E.eamg_default_setup_params(rounds=9)
     assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
+    for bad in (-1, 3):
+        p = _base()
+        p["params"] = E.eamg_default_setup_params(gpu_criteria=bad)
+        assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
 
 
 def test_kernel_vectors_must_span_rigid_body_modes():
@@ -120,6 +124,7 @@ def test_solve_entry_points_reject_null_hierarchy():
     assert L.eamg_traffic_model(None, 1, ctypes.byref(v), ctypes.byref(it)) == E.EAMG_ERR_INVALID_ARG
     p = E.eamg_default_setup_params()
     assert p.vcycle_fp32 == 0
+    assert p.gpu_criteria == 1
 
 
 @pytest.mark.parametrize("mu_s_only", [0, 1])
@@ -169,3 +174,19 @@ def test_host_criteria_match_oracle(kind):
             assert np.all(np.abs(got[fin] - ref[fin]) <= 1e-7 * np.abs(ref[fin]))
         res = successive_matching(lev, p.dirichlet.astype(bool) if level == 0 else np.zeros(lev.n, bool))
         lev = res.coarse_level
+
+
+def test_criteria_eval_argument_checks_on_the_host():
+    p = make_problem(5, kind="poisson", clamp="all")
+    lev = finest_aux(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals)
+    i, j = (int(v) for v in lev.edges[0])
+    far = int(np.setdiff1d(np.arange(lev.n), lev.neighbors(i)[0])[-1])
+    for pairs, unions in (([[i, far]], np.zeros((0, 4))), ([[i, j]], [[j, i, -1, -1]]),
+                          ([[i, j]], [[i, lev.n, -1, -1]])):
+        with pytest.raises(E.EamgError) as ei:
+            E.eamg_criteria_eval(lev.k, lev.coords, lev.edges, lev.E, lev.M, np.asarray(pairs),
+                                 np.asarray(unions), use_device=False)
+        assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+    b, g = E.eamg_criteria_eval(lev.k, lev.coords, lev.edges, lev.E, lev.M, np.zeros((0, 2)),
+                                np.zeros((0, 4)), use_device=False)
+    assert b.size == 0 and g.size == 0
