@@ -696,8 +696,13 @@ class DeviceCriteria final : public CritBatch {
     out.assign(size_t(np), 0.0);
     if (np == 0) return;
     if (!work_) fail(EAMG_ERR_INVALID_ARG, "criteria: no working level");
-    for (int32_t v : pairs)
-      if (v < 0 || v >= work_->v.n) fail(EAMG_ERR_INVALID_ARG, "criteria: pair out of range");
+    // every pair must be an edge of the working level (the kernel reads its edge matrix)
+    const AuxLevel *hw = work_ == &lev_ ? lev_src_ : wrk_src_;
+    for (int u = 0; u < np; ++u) {
+      const int i = pairs[2 * size_t(u)], j = pairs[2 * size_t(u) + 1];
+      if (i < 0 || i >= work_->v.n || j < 0 || j >= work_->v.n || !hw || hw->edge_id(i, j) < 0)
+        fail(EAMG_ERR_INVALID_ARG, "criteria: pair is not an edge of the working level");
+    }
     const auto t0 = std::chrono::steady_clock::now();
     const int *dp = idx_.put(pairs.data(), pairs.size(), s_);
     double *dout = static_cast<double *>(res_.reserve(size_t(np) * sizeof(double)));
