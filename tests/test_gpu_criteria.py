@@ -6,9 +6,10 @@ The matching walks hand every pair whose criteria they need to GPU kernels in ba
   code through the C ABI, bit for bit (same arithmetic, no contraction), on the finest elasticity
   level (M = 0), on a coarse elasticity level (M != 0, from the oracle's matching) and on a scalar
   level (k = 1); and both against the oracle's independent numpy evaluation (relative 1e-7);
-* setups with the criteria on the GPU and on host threads give the same hierarchy: agglomerates of
-  every level, the walk's evaluation counts and the matrices bit for bit; with the oracle's
-  agglomerates too (parity cases), and on the eleven-box coefficient jump.
+* setups with the criteria (and the coarse weights) on the GPU and on host threads give the same
+  hierarchy: agglomerates of every level, the walk's evaluation counts and the matrices bit for
+  bit, also with three and four passes per level; with the oracle's agglomerates too (parity
+  cases), and on the eleven-box coefficient jump.
 """
 import time
 
@@ -151,17 +152,24 @@ def _same_hierarchy(ha, hb):
                 np.testing.assert_array_equal(xa[key], xb[key], err_msg=f"level {l} {key}")
 
 
-@pytest.mark.parametrize("case", ["cube20", "boxes16", "poisson24"])
+@pytest.mark.parametrize("case", ["cube20", "boxes16", "poisson24", "cube14_rounds3",
+                                  "cube14_rounds4"])
 def test_setup_with_gpu_criteria_equals_host_criteria(case):
+    extra = {}
     if case == "cube20":
         p = make_problem(20)
     elif case == "boxes16":
         p = make_problem(16, boxes=True)
-    else:
+    elif case == "poisson24":
         p = make_problem(24, kind="poisson", clamp="all")
-    hd, td = _setup(p, gpu_criteria=2)              # every batch on the GPU
-    hh, th = _setup(p, gpu_criteria=0)              # host threads only
-    hm, tm = _setup(p, gpu_criteria=1)              # default: large batches on the GPU
+    else:
+        # three and four passes per level: the working level of later passes goes to the device,
+        # and unions of more than four vertices are evaluated on the host
+        p = make_problem(14)
+        extra = dict(rounds=int(case[-1]))
+    hd, td = _setup(p, gpu_criteria=2, **extra)     # every batch on the GPU
+    hh, th = _setup(p, gpu_criteria=0, **extra)     # host threads only
+    hm, tm = _setup(p, gpu_criteria=1, **extra)     # default: large batches on the GPU
     ev = E.eamg_coarsening_stats(hd.h)
     print(f"\n[setup {case}] setup with criteria on the GPU {td:.2f} s, on host threads "
           f"{th:.2f} s, default split {tm:.2f} s; levels {hd.stats()['n_levels']}; "
