@@ -437,7 +437,8 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
     return hipSuccess;
   });
   timed(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
-        launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s, [&] { return launch_resid_upper<T>(L.Am, x, B.r, s); });
+        launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s,
+        [&] { return launch_resid_upper<T>(L.resid_mat(), x, B.r, s); });
   Level &C = h->lv[l + 1];
   const LevelBufs<T> CB = bufs<T>(C);
   timed(h, "restrict", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">"),
@@ -477,6 +478,7 @@ void enqueue_iteration(eamg_hierarchy *h, bool f32, hipStream_t s) {
   const int64_t N = int64_t(L0.n) * L0.bs;
   const int nd = dot_blocks(N);
   const int ns = spmv_blocks(A);
+  if (nd > h->part_cap || ns > h->part_cap) fail(EAMG_ERR_INVALID_ARG, "partial-sum buffer too small");
   vcycle(h, h->r, h->z, f32, s);
   hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
   hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
@@ -559,6 +561,7 @@ struct SolveRun {
     N = int64_t(L0.n) * L0.bs;
     nd = dot_blocks(N);
     ns = spmv_blocks(L0.Am);
+    if (nd > h->part_cap || ns > h->part_cap) fail(EAMG_ERR_INVALID_ARG, "partial-sum buffer too small");
     vecb = double(N) * 8.0;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
@@ -965,8 +968,13 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     h->p = ar.alloc<double>(size_t(N0));
     h->q = ar.alloc<double>(size_t(N0));
     h->bp = ar.alloc<double>(size_t(N0));
-    const SoaMat &A0 = h->lv[0].Am;
-    h->part = ar.alloc<double>(size_t(std::max(dot_blocks(N0), spmv_blocks(A0))));
+    // partial sums of the dots and of the SpMV's fused p.q: the SpMV launches one workgroup per
+    // kBlock / G rows, so size for the widest row team it can be given (G = 64, the most
+    // workgroups), whatever the autotuner picks later
+    SoaMat widest = h->lv[0].Am;
+    widest.group = 64;
+    h->part_cap = std::max(dot_blocks(N0), spmv_blocks(widest));
+    h->part = ar.alloc<double>(size_t(h->part_cap));
     h->scal = ar.alloc<double>(SC_COUNT);
 
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&h->scal_h), sizeof(double) * SC_COUNT, 0),
@@ -1040,8 +1048,8 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       auto fwd_part = [&] {
         for (int c = 0; c < L.ncolors; ++c)
           hip_check(launch_gs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
-        hip_check(launch_resid_upper<double>(L.Am, x, L.r, s), "resid");
       };
+      auto resid_part = [&] { hip_check(launch_resid_upper<double>(L.resid_mat(), x, L.r, s), "resid"); };
       auto bwd_part = [&] {
         for (int c = L.ncolors - 1; c >= 0; --c)
           hip_check(launch_gs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
@@ -1054,23 +1062,30 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
           fail(EAMG_ERR_INVALID_ARG, "EAMG_FORCE_GROUP must be 8, 16, 32, 64, 128 or 256");
         L.Am.group = g;
         L.Am.group_bwd = 0;
+        L.group_resid = 0;
         continue;
       }
-      // forward sweep + residual update, then the backward sweep: lanes per row chosen apart
+      // forward sweep, residual update and backward sweep: lanes per row chosen apart
       const int cand[] = {8, 16, 32, 64, 128, kBlock};
       L.Am.group_bwd = 0;
+      L.group_resid = 0;
       const int orig = L.Am.group;
-      const double f0 = time_ms(fwd_part), b0 = time_ms(bwd_part);
-      double bf = f0, bb = b0;
-      int gf = orig, gb = orig;
+      const double f0 = time_ms(fwd_part), r0 = time_ms(resid_part), b0 = time_ms(bwd_part);
+      double bf = f0, br = r0, bb = b0;
+      int gf = orig, gr = orig, gb = orig;
       for (int g : cand) {
         if (g == orig) continue;
         L.Am.group = g;
         L.Am.group_bwd = g;
-        const double tf = time_ms(fwd_part), tb = time_ms(bwd_part);
+        L.group_resid = g;
+        const double tf = time_ms(fwd_part), tr = time_ms(resid_part), tb = time_ms(bwd_part);
         if (tf < bf) {
           bf = tf;
           gf = g;
+        }
+        if (tr < br) {
+          br = tr;
+          gr = g;
         }
         if (tb < bb) {
           bb = tb;
@@ -1079,8 +1094,9 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       }
       L.Am.group = gf;
       L.Am.group_bwd = gb == gf ? 0 : gb;
-      before += f0 + b0;
-      after += bf + bb;
+      L.group_resid = gr == gf ? 0 : gr;
+      before += f0 + r0 + b0;
+      after += bf + br + bb;
     }
     for (int p = 0; p < 2; ++p) {
       if (h->g_iter[p]) (void)hipGraphExecDestroy(h->g_iter[p]);

@@ -133,6 +133,13 @@ struct Level {
   std::vector<int> perm, inv, color_ptr;
   int *perm_d = nullptr;
   SoaMat Am, Pm, Rm;
+  // lanes per row of the residual update (upper halves of all rows, one launch), or 0 for Am.group
+  int group_resid = 0;
+  SoaMat resid_mat() const {
+    SoaMat m = Am;
+    if (group_resid) m.group = group_resid;
+    return m;
+  }
   double *Dinv = nullptr;
   int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
   double *x = nullptr, *b = nullptr, *r = nullptr;
@@ -195,6 +202,7 @@ struct eamg_hierarchy {
   uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;
+  int part_cap = 0;   // entries of part: the largest partial-sum count any launch shape can need
   double *scal_h = nullptr;   // pinned
   // profiler: events around every launch while enabled
   bool prof_on = false;
