@@ -21,6 +21,7 @@ struct BatchWork {
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;
   double *scal_h = nullptr;   // pinned
+  double *dense = nullptr;    // slices of the coarsest panel product
   // V-cycle panels per precision ([0] FP64, [1] FP32) and level: x, b, r
   bool have[2] = {false, false};
   std::vector<void *> vx[2], vb[2], vr[2];
@@ -67,6 +68,7 @@ BatchWork *ensure_work(eamg_hierarchy *h, int K, bool f32) {
     const int nparts = std::max(pdot_blocks(N), pspmv_blocks(L0.Am, K));
     w->part = w->arena.alloc<double>(size_t(nparts) * K);
     w->scal = w->arena.alloc<double>(size_t(PS_COUNT) * K);
+    w->dense = w->arena.alloc<double>(std::max<size_t>(1, dense_panel_work_doubles(h->nL, K)));
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&w->scal_h), sizeof(double) * PS_COUNT * K,
                             hipHostMallocDefault),
               "hipHostMalloc");
@@ -109,8 +111,8 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   Level &L = h->lv[l];
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * K * vs;
-    timed(h, "coarsest", lvname(h, l, "k_dense_panel<" + ty + ">"), by, s,
-          [&] { return launch_dense_panel<T>(h->nL, h->ldL, K, h->Ainv, b, x, s); });
+    timed(h, "coarsest", lvname(h, l, "k_dense_panel_mfma<" + ty + ">"), by, s,
+          [&] { return launch_dense_panel<T>(h->nL, h->ldL, K, h->Ainv, b, x, w->dense, s); });
     return;
   }
   const int bs = L.bs;

@@ -220,64 +220,78 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemv(int n, int ld, const do
   if (lane == 0) y[row] = T(acc);
 }
 
-// Y = D X, K columns: a workgroup owns 16 rows and walks the columns in chunks of 64, the chunk
-// of D (16 x 64) and of X (64 x K) staged in LDS while the next chunk is loaded into registers.
-// Thread t computes column t mod K of rows t / K + a (256 / K).
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_dense_panel(int n, int ld, int K,
+// Y = D X for a panel of K columns on the matrix cores (v_mfma_f64_16x16x4): a dense FP64
+// contraction, n x n by n x K.  One wavefront per 16-row tile of D and slice of the inner
+// dimension (the slices give the chip enough wavefronts).  The inner indices go in blocks of 16:
+// in step s (0..3) of a block, lane l supplies A[l % 16][l / 16] = D(row, kb + 4 (l / 16) + s) and,
+// for each 16-column tile of the panel, B[l / 16][l % 16] = X(kb + 4 (l / 16) + s, column), so a
+// lane's four D operands of a block are one contiguous 32-byte load (a row's 16 values of the
+// block are one 128-byte line).  Lane l accumulates rows l / 16 + 4 v (v = 0..3) of column l % 16.
+// D is read once in all; the partial products of the slices go to P (slice-major) and are summed
+// in slice order by k_dense_panel_sum, so the result is deterministic.  NCT: 16-column tiles.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <class T, int NCT>
+__global__ __launch_bounds__(64) void k_dense_panel_mfma(int n, int ld, int K, int S,
                                                          const double *__restrict__ D,
-                                                         const T *__restrict__ X, T *__restrict__ Y) {
-  constexpr int RT = 16, CH = 64;
-  __shared__ double Ds[RT][CH + 1];
-  __shared__ double Xs[CH * 64];
-  const int t = threadIdx.x;
-  const int row0 = int(blockIdx.x) * RT;
-  const int k = t & (K - 1);
-  const int i0 = t / K;
-  const int rstep = kThreads / K;
-  const int nxe = CH * K;   // X entries of a chunk
-  double dreg[RT * CH / kThreads], xreg[CH * 64 / kThreads];
-  auto load = [&](int c0) {
+                                                         const T *__restrict__ X,
+                                                         double *__restrict__ P) {
+  const int l = threadIdx.x;
+  const int r0 = int(blockIdx.x) * 16, sl = int(blockIdx.y);
+  const int blocks = (n + 15) / 16;                  // inner blocks of 16
+  const int per = (blocks + S - 1) / S;
+  const int k_begin = sl * per * 16;
+  const int k_end = min(n, (sl + 1) * per * 16);
+  const int ko = l >> 4, cl = l & 15;
+  // rows r0..r0+15 are below ld (16-row tiles of n, ld a multiple of 128 >= n); rows >= n hold
+  // the identity padding and their products are not stored.  Row starts are 1 KiB aligned and
+  // kb + 4 ko is a multiple of 4, so the 32-byte loads are aligned.
+  const double *Drow = D + size_t(r0 + cl) * ld;
+  dbl4 acc[NCT];
 #pragma unroll
-    for (int q = 0; q < RT * CH / kThreads; ++q) {
-      const int e = t + kThreads * q, i = e / CH, c = e % CH;
-      dreg[q] = row0 + i < n ? D[size_t(row0 + i) * ld + c0 + c] : 0.0;
+  for (int t = 0; t < NCT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int kb = k_begin; kb < k_end; kb += 16) {
+    const int kq = kb + 4 * ko;
+    dbl4 a4;
+    if (kq + 4 <= k_end) {
+      a4 = *reinterpret_cast<const dbl4 *>(Drow + kq);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a4[q] = kq + q < k_end ? Drow[kq + q] : 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < CH * 64 / kThreads; ++q) {
-      const int e = t + kThreads * q;
-      const int c = e / K, kk = e % K;
-      xreg[q] = (e < nxe && c0 + c < n) ? double(X[size_t(c0 + c) * K + kk]) : 0.0;
-    }
-  };
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  load(0);
-  for (int c0 = 0; c0 < ld; c0 += CH) {
+    for (int st = 0; st < 4; ++st) {
+      const int k = kq + st;
+      const bool kin = k < k_end;
 #pragma unroll
-    for (int q = 0; q < RT * CH / kThreads; ++q) {
-      const int e = t + kThreads * q;
-      Ds[e / CH][e % CH] = dreg[q];
+      for (int t = 0; t < NCT; ++t) {
+        const int col = 16 * t + cl;
+        const double bv = (kin && col < K) ? double(X[size_t(k) * K + col]) : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[st], bv, acc[t], 0, 0, 0);
+      }
     }
-#pragma unroll
-    for (int q = 0; q < CH * 64 / kThreads; ++q) {
-      const int e = t + kThreads * q;
-      if (e < nxe) Xs[e] = xreg[q];
-    }
-    __syncthreads();
-    if (c0 + CH < ld) load(c0 + CH);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = i0 + a * rstep;
-      if (i < RT)
-        for (int c = 0; c < CH; ++c) acc[a] = fma(Ds[i][c], Xs[c * K + k], acc[a]);
-    }
-    __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + a * rstep;
-    if (i < RT && row0 + i < n) Y[size_t(row0 + i) * K + k] = T(acc[a]);
+  for (int t = 0; t < NCT; ++t) {
+    const int col = 16 * t + cl;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + ko + 4 * v;
+      if (row < n && col < K) P[(size_t(sl) * n + row) * K + col] = acc[t][v];
+    }
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_dense_panel_sum(int64_t nk, int S,
+                                                              const double *__restrict__ P,
+                                                              T *__restrict__ Y) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i >= nk) return;
+  double v = P[i];
+  for (int sl = 1; sl < S; ++sl) v += P[int64_t(sl) * nk + i];
+  Y[i] = T(v);
 }
 
 }  // namespace
@@ -319,18 +333,37 @@ hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, h
   return hipGetLastError();
 }
 
+int dense_panel_splits(int n) {
+  const int tiles = (n + 15) / 16;
+  const int S = tiles > 0 ? (4096 + tiles - 1) / tiles : 1;
+  return S < 1 ? 1 : (S > 32 ? 32 : S);
+}
+
+size_t dense_panel_work_doubles(int n, int K) { return size_t(dense_panel_splits(n)) * n * K; }
+
 template <class T>
 hipError_t launch_dense_panel(int n, int ld, int K, const double *D, const T *X, T *Y,
-                              hipStream_t s) {
+                              double *work, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (ld < n || ld % 128 != 0 || K < 1 || K > 64 || (K & (K - 1))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dense_panel<T>, dim3(cdiv(n, 16)), dim3(kThreads), 0, s, n, ld, K, D, X, Y);
+  if (ld < n || ld % 128 != 0 || K < 1 || K > 64 || (K & (K - 1)) || !work)
+    return hipErrorInvalidValue;
+  const int S = dense_panel_splits(n);
+  const dim3 grid(cdiv(n, 16), S);
+  if (K <= 16)
+    hipLaunchKernelGGL((k_dense_panel_mfma<T, 1>), grid, dim3(64), 0, s, n, ld, K, S, D, X, work);
+  else if (K == 32)
+    hipLaunchKernelGGL((k_dense_panel_mfma<T, 2>), grid, dim3(64), 0, s, n, ld, K, S, D, X, work);
+  else
+    hipLaunchKernelGGL((k_dense_panel_mfma<T, 4>), grid, dim3(64), 0, s, n, ld, K, S, D, X, work);
+  const int64_t nk = int64_t(n) * K;
+  hipLaunchKernelGGL(k_dense_panel_sum<T>, dim3(unsigned((nk + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, nk, S, work, Y);
   return hipGetLastError();
 }
 
 template hipError_t launch_dense_gemv<double>(int, int, const double *, const double *, double *, hipStream_t);
 template hipError_t launch_dense_gemv<float>(int, int, const double *, const float *, float *, hipStream_t);
-template hipError_t launch_dense_panel<double>(int, int, int, const double *, const double *, double *, hipStream_t);
-template hipError_t launch_dense_panel<float>(int, int, int, const double *, const float *, float *, hipStream_t);
+template hipError_t launch_dense_panel<double>(int, int, int, const double *, const double *, double *, double *, hipStream_t);
+template hipError_t launch_dense_panel<float>(int, int, int, const double *, const float *, float *, double *, hipStream_t);
 
 }  // namespace eamg

@@ -47,9 +47,13 @@ hipError_t launch_gj_invert(int ld, double *A, double *work, int *flag, hipStrea
 template <class T>
 hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, hipStream_t s);
 
-// Y = D X for a panel of K columns (K a power of two in [1, 64]; entry (dof, k) at dof * K + k).
+// Y = D X for a panel of K columns (K a power of two in [1, 64]; entry (dof, k) at dof * K + k),
+// on the matrix cores in FP64, summed over dense_panel_splits(n) slices of the inner dimension
+// through `work` (device, dense_panel_work_doubles(n, K) doubles); deterministic.
+int dense_panel_splits(int n);
+size_t dense_panel_work_doubles(int n, int K);
 template <class T>
 hipError_t launch_dense_panel(int n, int ld, int K, const double *D, const T *X, T *Y,
-                              hipStream_t s);
+                              double *work, hipStream_t s);
 
 }  // namespace eamg
