@@ -384,6 +384,8 @@ __global__ __launch_bounds__(kPB) void k_preduce(int nparts, int K, const double
   __shared__ double sh[kPB];
   const int k = threadIdx.x & (K - 1);
   double s = 0.0;
+  // unrolled so that the loads are in flight together; the sum keeps its order
+#pragma unroll 16
   for (int j = threadIdx.x / K; j < nparts; j += kPB / K) s += part[int64_t(j) * K + k];
   const double t = pcol_sum(s, K, sh);
   if (int(threadIdx.x) >= K) return;
