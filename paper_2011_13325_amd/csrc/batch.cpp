@@ -133,7 +133,7 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   });
   timed(h, "presid_upper", lvname(h, l, "k_presid_upper<" + ty + ", " + std::to_string(bs) + ">"),
         launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, K), s,
-        [&] { return launch_presid_upper<T>(L.Am, K, x, R, s); });
+        [&] { return launch_presid_upper<T>(L.panel_mat(L.pw_resid), K, x, R, s); });
   T *Cb = vp<T>(w->vb[pi][l + 1]);
   T *Cx = vp<T>(w->vx[pi][l + 1]);
   timed(h, "prestrict", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">"),
@@ -143,9 +143,10 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   timed(h, "pprolong", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, K), s,
         [&] { return launch_prect<T>(L.Pm, K, Cx, x, true, s); });
+  const SoaMat Mb = L.panel_mat(L.pw_bwd);
   timed_n(h, "pgs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
-      const hipError_t e = launch_pgs_bwd<T>(L.Am, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s);
+      const hipError_t e = launch_pgs_bwd<T>(Mb, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -371,36 +372,43 @@ std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s) {
     const int64_t nv = level_dofs(L) * K, nc = level_dofs(h->lv[l + 1]) * K;
     for (double *v : {b, x, r}) hip_check(launch_fill(nv, 0.0, v, s), "fill");
     for (double *v : {cb, cx}) hip_check(launch_fill(nc, 0.0, v, s), "fill");
-    auto sweeps = [&] {
+    // forward sweep, residual update and backward sweep tuned apart (each reads a different part
+    // of the rows), then the transfers
+    auto fwd = [&] {
       for (int c = 0; c < L.ncolors; ++c)
         hip_check(launch_pgs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, r, s), "pgs");
-      hip_check(launch_presid_upper<double>(L.Am, K, x, r, s), "presid");
+    };
+    auto resid = [&] {
+      hip_check(launch_presid_upper<double>(L.panel_mat(L.pw_resid), K, x, r, s), "presid");
+    };
+    auto bwd = [&] {
+      const SoaMat Mb = L.panel_mat(L.pw_bwd);
       for (int c = L.ncolors - 1; c >= 0; --c)
-        hip_check(launch_pgs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s), "pgs");
+        hip_check(launch_pgs_bwd<double>(Mb, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s), "pgs");
     };
     auto restrict_ = [&] { hip_check(launch_prect<double>(L.Rm, K, r, cb, false, s), "prect"); };
     auto prolong = [&] { hip_check(launch_prect<double>(L.Pm, K, cx, x, true, s), "prect"); };
+    L.pw_resid = L.pw_bwd = 0;
     struct Item {
-      SoaMat *M;
+      int *pw;   // the choice: 0 (built-in / the forward sweep's), 1 or 4 wavefronts per row
       std::function<void()> run;
-    } items[] = {{&L.Am, sweeps}, {&L.Rm, restrict_}, {&L.Pm, prolong}};
+    } items[] = {{&L.Am.panel_waves, fwd}, {&L.pw_resid, resid}, {&L.pw_bwd, bwd},
+                 {&L.Rm.panel_waves, restrict_}, {&L.Pm.panel_waves, prolong}};
     for (Item &it : items) {
-      const int orig = it.M->panel_waves;
-      double best = 0.0;
+      const int orig = *it.pw;
       int best_w = orig;
-      it.M->panel_waves = orig;
       const double t0 = time_ms(s, reps, it.run);
       before += t0;
-      best = t0;
+      double best = t0;
       for (int wv : {1, 4}) {
-        it.M->panel_waves = wv;
+        *it.pw = wv;
         const double t = time_ms(s, reps, it.run);
         if (t < best) {
           best = t;
           best_w = wv;
         }
       }
-      it.M->panel_waves = best_w;
+      *it.pw = best_w;
       after += best;
     }
   }

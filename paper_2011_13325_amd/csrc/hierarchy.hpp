@@ -140,6 +140,14 @@ struct Level {
     if (group_resid) m.group = group_resid;
     return m;
   }
+  // panel kernels: wavefronts per row of the residual update and of the backward sweep, or 0 for
+  // Am.panel_waves (the forward sweep's)
+  int pw_resid = 0, pw_bwd = 0;
+  SoaMat panel_mat(int pw) const {
+    SoaMat m = Am;
+    if (pw) m.panel_waves = pw;
+    return m;
+  }
   double *Dinv = nullptr;
   int64_t nnz_lower = 0;     // blocks strictly below the diagonal (colour-major)
   double *x = nullptr, *b = nullptr, *r = nullptr;
