@@ -153,8 +153,9 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
   const int64_t m = int64_t(el.size());
   out.e0.resize(size_t(m));
   out.e1.resize(size_t(m));
-  out.E.assign(size_t(m) * k * k, 0.0);
-  out.M.assign(size_t(n) * k * k, 0.0);
+  out.E.resize(size_t(m) * k * k);   // every entry written below
+  out.M.resize(size_t(n) * k * k);
+  parallel_for(int64_t(out.M.size()), [&](int64_t q) { out.M[q] = 0.0; });
   std::atomic<bool> same_pos{false};
   parallel_for(m, [&](int64_t e) {
     const int i = el[e].first, j = el[e].second;
@@ -162,6 +163,7 @@ bool finest_aux(int dim, int n, const double *coords, const int32_t *row_ptr, co
     out.e1[e] = j;
     const double *blk = vals + size_t(find_block(i, j)) * bs2;
     double *Ee = &out.E[size_t(e) * k * k];
+    for (int q = 0; q < k * k; ++q) Ee[q] = 0.0;
     if (dim == 3) {
       double c = 0.0;
       for (int q = 0; q < 9; ++q) c += std::fabs(blk[q]);
@@ -259,7 +261,7 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
       return out;
     }
   }
-  out.M.assign(size_t(nc) * kk, 0.0);
+  out.M.resize(size_t(nc) * kk);   // every entry written below
   parallel_for(nc, [&](int64_t I) {
     std::vector<int> mem = aggs[I];
     std::sort(mem.begin(), mem.end());
@@ -273,7 +275,7 @@ AuxLevel coarse_aux(const AuxLevel &lev, const std::vector<std::vector<int>> &ag
     }
     std::copy(acc.a, acc.a + kk, &out.M[size_t(I) * kk]);
   });
-  out.E.assign(size_t(ne) * kk, 0.0);
+  out.E.resize(size_t(ne) * kk);   // every entry written below
   parallel_for(ne, [&](int64_t g) {
     Sq acc(k);
     for (int64_t q = start[g]; q < start[g + 1]; ++q) {

@@ -19,6 +19,7 @@
 #include <atomic>
 #include <functional>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "crit_core.hpp"
@@ -98,6 +99,28 @@ using PairScorer = std::function<void(const PassSamples &, std::vector<float> &)
 
 struct AuxLevel;
 
+// Allocator that leaves new elements uninitialized on resize(), so that a large weight array is
+// not written twice: every writer of an AuxLevel's E and M fills all their entries.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <class U>
+  NoInitAlloc(const NoInitAlloc<U> &) {}
+  template <class U>
+  void construct(U *p) noexcept {
+    ::new (static_cast<void *>(p)) U;
+  }
+  template <class U, class... Args>
+  void construct(U *p, Args &&...args) {
+    ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+  }
+};
+using WeightVec = std::vector<double, NoInitAlloc<double>>;
+
 // Batched evaluation of the exact criteria of a matching pass on another processor (the device
 // implementation is in criteria.hip).  level(): the level being coarsened and its D-hat blocks
 // (the data of mu_g); work(): the working level of the current pass and its D-hat blocks (the
@@ -119,8 +142,8 @@ struct CritBatch {
   virtual bool coarse_weights(const AuxLevel &fine, const std::vector<std::vector<int>> &aggs,
                               const std::vector<int> &agg_of, const std::vector<char> &dmask,
                               const std::vector<double> &cc, const std::vector<int64_t> &order,
-                              const std::vector<int64_t> &start, std::vector<double> &M,
-                              std::vector<double> &E) = 0;
+                              const std::vector<int64_t> &start, WeightVec &M,
+                              WeightVec &E) = 0;
 };
 
 struct MatchParams {
@@ -148,8 +171,8 @@ struct AuxLevel {
   int n = 0, k = 6;
   std::vector<double> x;          // n*3 positions
   std::vector<int> e0, e1;        // edges, e0 < e1, ascending (e0, e1)
-  std::vector<double> E;          // m*k*k
-  std::vector<double> M;          // n*k*k
+  WeightVec E;                    // m*k*k
+  WeightVec M;                    // n*k*k
   std::vector<int64_t> nb_ptr;    // adjacency sorted by neighbour id
   std::vector<int> nb, nb_e;
 

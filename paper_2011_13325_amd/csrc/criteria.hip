@@ -628,8 +628,8 @@ class DeviceCriteria final : public CritBatch {
   bool coarse_weights(const AuxLevel &fine, const std::vector<std::vector<int>> &aggs,
                       const std::vector<int> &agg_of, const std::vector<char> &dmask,
                       const std::vector<double> &cc, const std::vector<int64_t> &order,
-                      const std::vector<int64_t> &start, std::vector<double> &M,
-                      std::vector<double> &E) override {
+                      const std::vector<int64_t> &start, WeightVec &M,
+                      WeightVec &E) override {
     const DevLevel *dl = nullptr;
     if (&fine == lev_src_)
       dl = &lev_;
@@ -679,8 +679,8 @@ class DeviceCriteria final : public CritBatch {
                          d_agg, d_cc, ne, d_start, d_order, d_E);
       hip_check(hipGetLastError(), "k_coarse_E");
     }
-    M.assign(size_t(nc) * kk, 0.0);
-    E.assign(size_t(ne) * kk, 0.0);
+    M.resize(size_t(nc) * kk);   // every entry is downloaded below
+    E.resize(size_t(ne) * kk);
     if (nc > 0)
       hip_check(hipMemcpyAsync(M.data(), d_M, M.size() * sizeof(double), hipMemcpyDeviceToHost, s_),
                 "download");

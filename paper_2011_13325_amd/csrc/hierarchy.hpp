@@ -45,8 +45,8 @@ struct DevArena {
     ptrs.push_back(p);
     return static_cast<T *>(p);
   }
-  template <class T>
-  T *upload(const std::vector<T> &v, hipStream_t s) {
+  template <class T, class A>
+  T *upload(const std::vector<T, A> &v, hipStream_t s) {
     return upload(v.data(), v.size(), s);
   }
   template <class T>
