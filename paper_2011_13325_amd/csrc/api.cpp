@@ -7,9 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/eamg.h"
@@ -270,6 +272,9 @@ LaunchShape matrix_shape(const Pattern &M) {
   return sh;
 }
 
+static_assert(std::is_nothrow_move_constructible<Level>::value,
+              "levels must move without copying their patterns");
+
 void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   Level &L = h->lv[l];
   DevArena &ar = h->arena;
@@ -284,9 +289,11 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
     L.color.assign(size_t(L.n), -1);
     L.color_ptr = {0, L.n};
   } else {
-    PhaseTimer tc;
-    L.color = greedy_coloring(L.A, L.ncolors);
-    tc.mark("layout: colouring");
+    if (L.color.size() != size_t(L.n)) {
+      PhaseTimer tc;
+      L.color = greedy_coloring(L.A, L.ncolors);
+      tc.mark("layout: colouring");
+    }
     L.color_ptr.assign(size_t(L.ncolors) + 1, 0);
     for (int c : L.color) L.color_ptr[c + 1]++;
     for (int c = 0; c < L.ncolors; ++c) L.color_ptr[c + 1] += L.color_ptr[c];
@@ -307,14 +314,20 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
   L.sh_spmv = matrix_shape(Ap);
   if (!coarsest) {
-    std::vector<int> mark(size_t(L.n), -1);
-    int stamp = 0;
-    for (int c = 0; c < L.ncolors; ++c) {
-      const int r0 = L.color_ptr[c], r1 = L.color_ptr[c + 1];
-      L.sh_fwd.push_back(range_shape(Ap, dg, r0, r1, 0, mark, stamp++));
-      L.sh_bwd.push_back(range_shape(Ap, dg, r0, r1, 1, mark, stamp++));
-    }
-    L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, stamp++);
+    // one task per colour and sweep part plus the residual, each with its own marks
+    const int nc = L.ncolors;
+    L.sh_fwd.assign(size_t(nc), LaunchShape());
+    L.sh_bwd.assign(size_t(nc), LaunchShape());
+    parallel_for_dynamic(2 * int64_t(nc) + 1, [&](int64_t t) {
+      std::vector<int> mark(size_t(L.n), -1);
+      if (t == 2 * int64_t(nc)) {
+        L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, 0);
+        return;
+      }
+      const int c = int(t / 2), part = int(t % 2);
+      (part == 0 ? L.sh_fwd : L.sh_bwd)[size_t(c)] =
+          range_shape(Ap, dg, L.color_ptr[c], L.color_ptr[c + 1], part, mark, 0);
+    }, 1);
   }
   tl.mark("layout: launch shapes");
   if (coarsest) {
@@ -858,11 +871,27 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
         gnn_logits(net, dg, s, z);
       };
     }
+    // The smoother's colouring of a level depends on its pattern only: it runs on a thread of its
+    // own beside the matching of that level and of the levels below.  The thread reads the
+    // pattern's buffers, which stay in place while the levels move (nothrow moves).
+    struct Colouring {
+      std::vector<int> color;
+      int ncolors = 0;
+    };
+    std::vector<std::future<Colouring>> colourings;
     while (true) {
       const size_t l = h->lv.size() - 1;
       {
         const Level &L = h->lv[l];
         if (int64_t(L.bs) * L.n < prm.coarsest_max_dofs || int(h->lv.size()) >= prm.max_levels) break;
+        const int nr = L.A.n_rows;
+        const int64_t *rp = L.A.rp.data();
+        const int *cl = L.A.col.data();
+        colourings.push_back(std::async(std::launch::async, [nr, rp, cl] {
+          Colouring c;
+          c.color = greedy_coloring(nr, rp, cl, c.ncolors);
+          return c;
+        }));
       }
       tm.mark("setup: level upload");
       MatchResult mr = successive_matching(aux, l == 0 ? vd : std::vector<char>(), mp);
@@ -959,6 +988,12 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     }
     coarsest_factor(h.get(), s);
     tm.mark("setup: coarsest factor");
+    for (size_t l = 0; l < colourings.size(); ++l) {
+      Colouring c = colourings[l].get();
+      h->lv[l].color = std::move(c.color);
+      h->lv[l].ncolors = c.ncolors;
+    }
+    tm.mark("setup: colouring (wait)");
     for (size_t l = h->lv.size(); l-- > 0;) build_level_layout(h.get(), l, s);
     tm.mark("setup: solve layout");
     const int64_t N0 = int64_t(n) * dim;

@@ -163,16 +163,15 @@ Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src) {
   return T;
 }
 
-std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
-  const int n = A.n_rows;
+std::vector<int> greedy_coloring(int n, const int64_t *rp, const int *col, int &n_colors) {
   // smallest-last order: remove a vertex of minimum remaining degree (lowest id on ties).
   // Indexed binary min-heap on the key (degree, id), one entry per vertex; a removal lowers
   // its neighbours' keys in place.
   std::vector<int64_t> key(static_cast<size_t>(n));
   for (int i = 0; i < n; ++i) {
     int64_t d = 0;
-    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p)
-      if (A.col[p] != i) ++d;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p)
+      if (col[p] != i) ++d;
     key[i] = (d << 32) | int64_t(i);
   }
   std::vector<int> heap(static_cast<size_t>(n)), where(static_cast<size_t>(n));
@@ -213,8 +212,8 @@ std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
     sift_down(0);
     removed[v] = 1;
     seq.push_back(v);
-    for (int64_t p = A.rp[v]; p < A.rp[v + 1]; ++p) {
-      const int u = A.col[p];
+    for (int64_t p = rp[v]; p < rp[v + 1]; ++p) {
+      const int u = col[p];
       if (u == v || removed[u]) continue;
       key[u] -= int64_t(1) << 32;
       sift_up(where[u]);
@@ -226,8 +225,8 @@ std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
   for (auto it = seq.rbegin(); it != seq.rend(); ++it) {
     const int i = *it;
     used.clear();
-    for (int64_t p = A.rp[i]; p < A.rp[i + 1]; ++p) {
-      const int j = A.col[p];
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+      const int j = col[p];
       if (j != i && color[j] >= 0) used.push_back(color[j]);
     }
     std::sort(used.begin(), used.end());

@@ -44,7 +44,10 @@ Pattern transpose_pattern(const Pattern &P, std::vector<int64_t> &src);
 
 // Greedy colouring in smallest-last order (vertices removed by minimum remaining degree, lowest
 // id on ties; coloured in reverse removal order with the smallest colour unused by neighbours).
-std::vector<int> greedy_coloring(const Pattern &A, int &n_colors);
+std::vector<int> greedy_coloring(int n, const int64_t *rp, const int *col, int &n_colors);
+inline std::vector<int> greedy_coloring(const Pattern &A, int &n_colors) {
+  return greedy_coloring(A.n_rows, A.rp.data(), A.col.data(), n_colors);
+}
 
 // Symmetric permutation of a square pattern: row/col v -> inv[v].  Columns re-sorted;
 // src[q] = index in A of entry q of the result.
