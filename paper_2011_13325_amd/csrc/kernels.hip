@@ -15,6 +15,20 @@ namespace {
 
 inline int cdiv64(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup b to XCD b mod 8), each
+// XCD with its own L2.  The colour sweeps use this logical workgroup index instead of
+// blockIdx.x: XCD x gets one contiguous run of logical workgroups (the first nb mod 8 XCDs one
+// more), so the rows of a colour that one XCD updates are neighbours in the numbering and share
+// their gathered x blocks in that XCD's L2 (sweeps 3 % faster at 64^3).  A bijection on
+// [0, gridDim.x), so results do not change.  Not used where row lengths drift along the
+// numbering: the residual update over all colour-major rows (upper blocks only, long rows first)
+// would load one XCD with the longest rows (+33 % measured).
+__device__ inline int xcd_block() {
+  const int nb = int(gridDim.x), b = int(blockIdx.x);
+  const int x = b & 7, q = nb >> 3, rem = nb & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
 // ---- small dense helpers (one thread) ----------------------------------------------------
 
 __device__ inline void dev_skew_q(const double *t, int k, double *Q) {
@@ -497,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, cons
                                                     const T *__restrict__ b, T *x, T *r) {
   __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
-  const int row = r0 + blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int row = r0 + xcd_block() * (kBlock / G) + threadIdx.x / G;
   gs_row<T, B, FWD, W>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r, sh);
 }
 

@@ -16,6 +16,16 @@ inline unsigned pgrid(int64_t items, int per_block) {
   return unsigned((items + per_block - 1) / per_block);
 }
 
+// Logical workgroup index of the colour sweeps: workgroup b runs on XCD b mod 8 (round-robin
+// dispatch, one L2 per XCD); XCD x takes one contiguous run of logical workgroups so that the
+// rows it updates are neighbours and share their gathered x panel blocks in its L2.  A
+// bijection on [0, gridDim.x): results do not change.
+__device__ inline int xcd_block() {
+  const int nb = int(gridDim.x), b = int(blockIdx.x);
+  const int x = b & 7, q = nb >> 3, rem = nb & 7;
+  return x * q + min(x, rem) + (b >> 3);
+}
+
 template <class T>
 const T *pvals(const SoaMat &M);
 template <>
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const 
                                                    const T *__restrict__ b, T *x, T *r) {
   __shared__ T red[PRed<T, B, C, W>::n];
   const PTeam<C, W> tm(K);
-  const int row = r0 + blockIdx.x * (kPB / (kWave * W)) + tm.row_in_wg;
+  const int row = r0 + xcd_block() * (kPB / (kWave * W)) + tm.row_in_wg;
   if (row >= r1) return;   // W = 4: the whole workgroup leaves together
   const int p0 = rp[row];
   const int dp = diag[row];
