@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeamg.so")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp"]
+HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp",
+                "staging.cpp"]
 HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip"]
 # the criteria must round like the host code (no fused multiply-add)
 FILE_FLAGS = {"criteria.hip": ["-ffp-contract=off"]}

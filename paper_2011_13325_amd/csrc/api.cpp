@@ -835,6 +835,8 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
       L0.A_rp = ar.upload(L0.A.rp, s);
       L0.A_col = ar.upload(L0.A.col, s);
       L0.A_val = ar.upload(pb->vals, size_t(L0.A.nnz()) * dim * dim, s);
+      hip_check(hipStreamSynchronize(s), "sync");
+      tm.mark("setup: level-0 matrix upload");
       std::vector<uint8_t> dir(static_cast<size_t>(n), 0);
       if (pb->dirichlet)
         for (int i = 0; i < n; ++i) dir[i] = pb->dirichlet[i] ? 1 : 0;
@@ -853,6 +855,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     mp.tie_rtol = prm.tie_rtol;
     mp.tau = prm.pinv_rtol;
     mp.record = prm.gnn_record != 0;
+    tm.mark("setup: Dirichlet rows");
     std::unique_ptr<CritBatch> crit_dev;
     if (prm.gpu_criteria) {
       crit_dev = make_device_criteria(s);

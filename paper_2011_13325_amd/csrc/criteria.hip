@@ -575,7 +575,7 @@ struct DBuf {
   template <class T>
   T *put(const T *h, size_t count, hipStream_t s) {
     T *d = static_cast<T *>(reserve(count * sizeof(T)));
-    if (count) hip_check(hipMemcpyAsync(d, h, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+    hip_check(copy_h2d_sync(d, h, count * sizeof(T), s), "upload");
     return d;
   }
 };
@@ -681,13 +681,8 @@ class DeviceCriteria final : public CritBatch {
     }
     M.resize(size_t(nc) * kk);   // every entry is downloaded below
     E.resize(size_t(ne) * kk);
-    if (nc > 0)
-      hip_check(hipMemcpyAsync(M.data(), d_M, M.size() * sizeof(double), hipMemcpyDeviceToHost, s_),
-                "download");
-    if (ne > 0)
-      hip_check(hipMemcpyAsync(E.data(), d_E, E.size() * sizeof(double), hipMemcpyDeviceToHost, s_),
-                "download");
-    hip_check(hipStreamSynchronize(s_), "sync");
+    hip_check(copy_d2h_sync(M.data(), d_M, M.size() * sizeof(double), s_), "download");
+    hip_check(copy_d2h_sync(E.data(), d_E, E.size() * sizeof(double), s_), "download");
     note("coarse weights", int(ne), t0);
     return true;
   }
@@ -710,9 +705,7 @@ class DeviceCriteria final : public CritBatch {
     hipLaunchKernelGGL(k_mu_b, dim3(grid), dim3(kCritBlock), 0, s_, work_->v, work_->d, np, dp,
                        tau, dout);
     hip_check(hipGetLastError(), "k_mu_b");
-    hip_check(hipMemcpyAsync(out.data(), dout, size_t(np) * sizeof(double), hipMemcpyDeviceToHost,
-                             s_), "download");
-    hip_check(hipStreamSynchronize(s_), "sync");
+    hip_check(copy_d2h_sync(out.data(), dout, size_t(np) * sizeof(double), s_), "download");
     note("mu_b", np, t0);
   }
   void mu_g(const std::vector<int32_t> &unions, double tau, std::vector<double> &out) override {
@@ -738,9 +731,7 @@ class DeviceCriteria final : public CritBatch {
     hipLaunchKernelGGL(k_mu_g_wave, dim3(grid), dim3(kCritBlock), 0, s_, lev_.v, lev_.d, nu, du,
                        tau, dout);
     hip_check(hipGetLastError(), "k_mu_g");
-    hip_check(hipMemcpyAsync(out.data(), dout, size_t(nu) * sizeof(double), hipMemcpyDeviceToHost,
-                             s_), "download");
-    hip_check(hipStreamSynchronize(s_), "sync");
+    hip_check(copy_d2h_sync(out.data(), dout, size_t(nu) * sizeof(double), s_), "download");
     if (verbose_) {
       int nan = 0;
       for (double v : out) nan += std::isnan(v) ? 1 : 0;

@@ -15,6 +15,7 @@
 #include "coarse.hpp"
 #include "kernels.hpp"
 #include "coarsen.hpp"
+#include "staging.hpp"
 #include "structure.hpp"
 
 namespace eamg {
@@ -53,10 +54,7 @@ struct DevArena {
   T *upload(const T *p, size_t count, hipStream_t s) {
     // setup-time upload from pageable memory: wait so the source may be freed on return
     T *d = alloc<T>(count);
-    if (count) {
-      hip_check(hipMemcpyAsync(d, p, count * sizeof(T), hipMemcpyHostToDevice, s), "upload");
-      hip_check(hipStreamSynchronize(s), "sync");
-    }
+    hip_check(copy_h2d_sync(d, p, count * sizeof(T), s), "upload");
     return d;
   }
   void release(void *p) {
@@ -74,8 +72,7 @@ struct DevArena {
 template <class T>
 std::vector<T> download(const T *d, size_t count, hipStream_t s) {
   std::vector<T> h(count);
-  if (count) hip_check(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s), "download");
-  hip_check(hipStreamSynchronize(s), "sync");
+  hip_check(copy_d2h_sync(h.data(), d, count * sizeof(T), s), "download");
   return h;
 }
 
