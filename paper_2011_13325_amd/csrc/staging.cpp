@@ -50,16 +50,7 @@ struct Events {
   }
 };
 
-}  // namespace
-
-hipError_t copy_h2d_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
-  if (bytes < kDirect) {
-    EAMG_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
-    return hipStreamSynchronize(s);
-  }
-  Stage &st = stage();
-  std::lock_guard<std::mutex> lock(st.mu);
+hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s, Stage &st) {
   EAMG_TRY(ensure_chunks(st));
   Events ev;
   EAMG_TRY(ev.init());
@@ -77,14 +68,7 @@ hipError_t copy_h2d_sync(void *dst, const void *src, size_t bytes, hipStream_t s
   return hipStreamSynchronize(s);
 }
 
-hipError_t copy_d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
-  if (bytes < kDirect) {
-    EAMG_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
-    return hipStreamSynchronize(s);
-  }
-  Stage &st = stage();
-  std::lock_guard<std::mutex> lock(st.mu);
+hipError_t d2h(void *dst, const void *src, size_t bytes, hipStream_t s, Stage &st) {
   EAMG_TRY(ensure_chunks(st));
   Events ev;
   EAMG_TRY(ev.init());
@@ -105,6 +89,36 @@ hipError_t copy_d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s
     std::memcpy(out + off, st.buf[i & 1], len);
   }
   return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+// On an error the stream is drained before the staging lock is released, so that no copy still
+// queued reads or writes a chunk that the next caller refills.
+hipError_t copy_h2d_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes < kDirect) {
+    EAMG_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return hipStreamSynchronize(s);
+  }
+  Stage &st = stage();
+  std::lock_guard<std::mutex> lock(st.mu);
+  const hipError_t e = h2d(dst, src, bytes, s, st);
+  if (e != hipSuccess) (void)hipStreamSynchronize(s);
+  return e;
+}
+
+hipError_t copy_d2h_sync(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes < kDirect) {
+    EAMG_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    return hipStreamSynchronize(s);
+  }
+  Stage &st = stage();
+  std::lock_guard<std::mutex> lock(st.mu);
+  const hipError_t e = d2h(dst, src, bytes, s, st);
+  if (e != hipSuccess) (void)hipStreamSynchronize(s);
+  return e;
 }
 
 }  // namespace eamg
