@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <deque>
+#include <future>
 #include <limits>
 #include <memory>
 #include <unordered_map>
@@ -540,8 +541,11 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   std::vector<char> in_T(static_cast<size_t>(n));
   for (int i = 0; i < n; ++i) in_T[i] = !res.dmask[i];
   tm.mark("mu_D");
-  std::vector<int> order = cuthill_mckee(lev, in_T);
-  tm.mark("cuthill-mckee");
+  // The walk order runs on a thread of its own while the first pass computes its per-edge data
+  // (trace strengths, mu_s), which does not depend on it; it is joined before the first use.
+  std::future<std::vector<int>> order_job =
+      std::async(std::launch::async, [&lev, mask = in_T] { return cuthill_mckee(lev, mask); });
+  std::vector<int> order;
 
   AuxLevel work_store;
   const AuxLevel *work = &lev;
@@ -569,8 +573,6 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
   bool batch_level = false;
   for (int p = 1; p <= prm.rounds; ++p) {
     bool batch_work = false;
-    pos.assign(size_t(work->n), 0);
-    for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
     trace_strength(*work, mtr);
     const size_t nq = work->nb.size();
     ms_q.assign(nq, 0.0);
@@ -578,6 +580,12 @@ MatchResult successive_matching(const AuxLevel &lev, const std::vector<char> &vd
       for (int64_t q = work->nb_ptr[i]; q < work->nb_ptr[i + 1]; ++q)
         ms_q[q] = mu_s_edge(*work, int(i), work->nb[q], work->nb_e[q], mtr);
     });
+    if (p == 1) {
+      order = order_job.get();
+      tm.mark("cuthill-mckee (beside mu_s)");
+    }
+    pos.assign(size_t(work->n), 0);
+    for (size_t a = 0; a < order.size(); ++a) pos[order[a]] = int(a);
     crit_q.assign(nq, Crit{0.0, 0.0});
     has_q.assign(nq, 0);
     // adjacency entry of j in the list of i (-1: not adjacent)
