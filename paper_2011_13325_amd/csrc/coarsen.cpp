@@ -473,16 +473,19 @@ double mu_g(const AuxLevel &lev, const std::vector<int> &Cin, const std::vector<
 
 std::vector<int> cuthill_mckee(const AuxLevel &lev, const std::vector<char> &free_mask) {
   const int n = lev.n;
-  std::vector<std::vector<int>> adj(static_cast<size_t>(n));
-  for (int64_t e = 0; e < lev.m(); ++e) {
-    const int i = lev.e0[e], j = lev.e1[e];
-    if (sq_trace(lev.Emat(e)) > 0.0 && free_mask[i] && free_mask[j]) {
-      adj[i].push_back(j);
-      adj[j].push_back(i);
-    }
-  }
+  // the graph: edges of positive trace between free vertices, read through the level's
+  // adjacency lists (the order of a vertex's neighbours does not matter: they are visited sorted
+  // by (degree, id))
+  std::vector<char> live(static_cast<size_t>(lev.m()));
+  parallel_for(lev.m(), [&](int64_t e) {
+    live[e] = sq_trace(lev.Emat(e)) > 0.0 && free_mask[lev.e0[e]] && free_mask[lev.e1[e]];
+  });
   std::vector<int> deg(static_cast<size_t>(n));
-  for (int v = 0; v < n; ++v) deg[v] = int(adj[v].size());
+  parallel_for(n, [&](int64_t v) {
+    int d = 0;
+    for (int64_t q = lev.nb_ptr[v]; q < lev.nb_ptr[v + 1]; ++q) d += live[lev.nb_e[q]];
+    deg[v] = d;
+  });
   std::vector<std::pair<int, int>> starts;
   for (int v = 0; v < n; ++v)
     if (free_mask[v]) starts.emplace_back(deg[v], v);
@@ -503,8 +506,10 @@ std::vector<int> cuthill_mckee(const AuxLevel &lev, const std::vector<char> &fre
       queue.pop_front();
       order.push_back(v);
       nbv.clear();
-      for (int u : adj[v])
-        if (!visited[u]) nbv.emplace_back(deg[u], u);
+      for (int64_t q = lev.nb_ptr[v]; q < lev.nb_ptr[v + 1]; ++q) {
+        const int u = lev.nb[q];
+        if (live[lev.nb_e[q]] && !visited[u]) nbv.emplace_back(deg[u], u);
+      }
       std::sort(nbv.begin(), nbv.end());
       for (const auto &du : nbv) {
         visited[du.second] = 1;
