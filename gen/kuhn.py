@@ -118,40 +118,100 @@ def kuhn_mesh(n: int, ny: Optional[int] = None, nz: Optional[int] = None,
     return KuhnMesh(n, ny, nz, float(h))
 
 
-def _assemble(mesh: KuhnMesh, bs: int, blocks_fn):
-    """Stencil assembly.  ``blocks_fn(t, a, b)`` returns the (cells..., bs, bs) or (bs, bs)
-    contribution of local pair (a, b) of tet type t in every cell."""
+def _shift_slices(shape, d):
+    """Slices (target, source) of a (nz, ny, nx) grid such that target[v] = source[v - d] for
+    every vertex v with v - d inside the grid; d is an (x, y, z) offset."""
+    tgt, src = [], []
+    for axis, s in ((0, d[2]), (1, d[1]), (2, d[0])):
+        m = shape[axis]
+        tgt.append(slice(max(s, 0), m + min(s, 0)))
+        src.append(slice(max(-s, 0), m - max(s, 0)))
+    return tuple(tgt), tuple(src)
+
+
+def _assemble(mesh: KuhnMesh, parts):
+    """Stencil assembly on the structured Kuhn mesh.
+
+    ``parts`` is a list of ``(coef, K)``: ``coef`` a scalar or a per-(tet type, cell) array
+    (6, nz-1, ny-1, nx-1), ``K`` (6, 4 bs, 4 bs) the element matrix of each tet type for a unit
+    coefficient.  The element matrix of tet type t in cell c is ``sum_p coef_p[t, c] K_p[t]``.
+
+    The block of vertex v and direction d (a neighbour offset) sums, over the tet types t, the
+    one local pair (a, b) of t with offset d, taken in the cell v - offs[t, a].  So the blocks of
+    all vertices for the directions d >= 0 (in vertex-id order) are one product of the shifted
+    per-cell coefficients (vertices x (part, t, a)) with the matching element blocks; the blocks
+    of direction -d are the transposes of those of d at v - d, which keeps A exactly symmetric.
+    """
     offs = _tet_offsets()
+    bs = parts[0][1].shape[-1] // 4
     nz, ny, nx = mesh.nz, mesh.ny, mesh.nx
-    stencil = {}
-    touched = {}
     cz, cy, cx = mesh.cell_shape
+    n = mesh.n_vertices
+    lin = lambda d: int(d[0] + nx * (d[1] + ny * d[2]))
+    dset = {tuple(int(x) for x in offs[t, b] - offs[t, a])
+            for t in range(6) for a in range(4) for b in range(4)}
+    dirs = sorted(dset, key=lin)
+    pos = [d for d in dirs if lin(d) >= 0]
+    npart = len(parts)
+    # shifted coefficients: column (p, t, a) holds coef_p[t] of the cell v - offs[t, a]
+    C = np.zeros((npart * 24, nz, ny, nx))
+    inside = np.zeros((24, nz, ny, nx), dtype=bool)
     for t in range(6):
         for a in range(4):
             oa = offs[t, a]
             sl = (slice(oa[2], oa[2] + cz), slice(oa[1], oa[1] + cy), slice(oa[0], oa[0] + cx))
+            inside[(4 * t + a,) + sl] = True
+            for p, (coef, _) in enumerate(parts):
+                C[(24 * p + 4 * t + a,) + sl] = coef[t] if np.ndim(coef) else coef
+    S = np.zeros((npart * 24, len(pos), bs * bs))
+    contrib = [[] for _ in pos]
+    for t in range(6):
+        for a in range(4):
             for b in range(4):
-                d = tuple(int(x) for x in (offs[t, b] - oa))
-                if d not in stencil:
-                    stencil[d] = np.zeros((nz, ny, nx, bs, bs))
-                    touched[d] = np.zeros((nz, ny, nx), dtype=bool)
-                stencil[d][sl] += blocks_fn(t, a, b)
-                touched[d][sl] = True
-    ds = sorted(stencil, key=lambda d: d[0] + nx * (d[1] + ny * d[2]))
-    dlin = np.array([d[0] + nx * (d[1] + ny * d[2]) for d in ds], dtype=np.int64)
-    n = mesh.n_vertices
-    valid = np.stack([touched[d].ravel() for d in ds], axis=1)
-    rows, which = np.nonzero(valid)
-    col = rows + dlin[which]
+                d = tuple(int(x) for x in offs[t, b] - offs[t, a])
+                if d not in pos:
+                    continue
+                w = pos.index(d)
+                contrib[w].append(4 * t + a)
+                for p, (_, K) in enumerate(parts):
+                    S[24 * p + 4 * t + a, w] = K[t, bs * a:bs * a + bs, bs * b:bs * b + bs].ravel()
+    half = (C.reshape(npart * 24, n).T @ S.reshape(npart * 24, -1)).reshape(nz, ny, nx, len(pos),
+                                                                            bs, bs)
+    del C
+    blocks, touched = {}, {}
+    for w, d in enumerate(pos):
+        blocks[d] = half[:, :, :, w]
+        tw = np.zeros((nz, ny, nx), dtype=bool)
+        for ta in contrib[w]:
+            tw |= inside[ta]
+        touched[d] = tw
+    for d in pos:
+        if lin(d) == 0:
+            continue
+        nd = tuple(-x for x in d)
+        tgt, src = _shift_slices((nz, ny, nx), d)
+        bl = np.zeros((nz, ny, nx, bs, bs))
+        bl[tgt] = np.swapaxes(blocks[d][src], -1, -2)
+        tw = np.zeros((nz, ny, nx), dtype=bool)
+        tw[tgt] = touched[d][src]
+        blocks[nd], touched[nd] = bl, tw
+    dlin = np.array([lin(d) for d in dirs], dtype=np.int64)
+    valid = np.stack([touched[d].ravel() for d in dirs], axis=1)
     counts = valid.sum(axis=1)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
-    vals = np.empty((rows.size, bs, bs))
-    for w, d in enumerate(ds):
-        sel = which == w
-        vals[sel] = stencil[d].reshape(n, bs, bs)[rows[sel]]
-        del stencil[d]
-    return row_ptr.astype(np.int32), col.astype(np.int32), vals
+    slot = row_ptr[:-1, None] + np.cumsum(valid, axis=1) - 1
+    nnzb = int(row_ptr[-1])
+    col = np.empty(nnzb, dtype=np.int32)
+    vals = np.empty((nnzb, bs, bs))
+    vid = np.arange(n, dtype=np.int64)
+    for w, d in enumerate(dirs):
+        m = valid[:, w]
+        at = slot[m, w]
+        col[at] = vid[m] + dlin[w]
+        vals[at] = blocks[d].reshape(n, bs, bs)[m]
+        del blocks[d]
+    return row_ptr.astype(np.int32), col, vals
 
 
 def _coef_array(mesh: KuhnMesh, c):
@@ -173,30 +233,15 @@ def assemble_elasticity(mesh: KuhnMesh, mu, lam):
     mu_arr, mu_s = _coef_array(mesh, mu)
     lam_arr, lam_s = _coef_array(mesh, lam)
     h = mesh.h
-
-    def blocks(t, a, b):
-        km = h * Kmu[t, 3 * a:3 * a + 3, 3 * b:3 * b + 3]
-        kl = h * Klam[t, 3 * a:3 * a + 3, 3 * b:3 * b + 3]
-        out = (mu_arr[t][..., None, None] * km) if mu_arr is not None else mu_s * km
-        out = out + ((lam_arr[t][..., None, None] * kl) if lam_arr is not None else lam_s * kl)
-        return out
-
-    return _assemble(mesh, 3, blocks)
+    return _assemble(mesh, [(mu_arr if mu_arr is not None else mu_s, h * Kmu),
+                            (lam_arr if lam_arr is not None else lam_s, h * Klam)])
 
 
 def assemble_poisson(mesh: KuhnMesh, alpha=1.0):
     """Block CSR (1x1) of the P1 Laplacian ``int alpha grad u . grad v`` without BCs."""
     _, _, _, Klap = _unit_element_matrices()
     al_arr, al_s = _coef_array(mesh, alpha)
-    h = mesh.h
-
-    def blocks(t, a, b):
-        k = h * Klap[t, a, b]
-        if al_arr is not None:
-            return (al_arr[t] * k)[..., None, None]
-        return np.full((1, 1), al_s * k)
-
-    return _assemble(mesh, 1, blocks)
+    return _assemble(mesh, [(al_arr if al_arr is not None else al_s, mesh.h * Klap)])
 
 
 def sphere_inclusions(mesh: KuhnMesh, count: int, seed: int, E_host=1.0, nu_host=0.3,
