@@ -1188,6 +1188,10 @@ eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const doub
     MultiStreams ms;
     ms.ensure(size_t(std::min(nsys, kMultiStreams)));
     for (int m = 0; m < nsys; ++m) runs[m]->s = ms.st[size_t(m) % ms.st.size()];
+    // the caller's work on `s` (b and x0 written asynchronously, say) comes before anything the
+    // systems' streams do
+    hip_check(hipEventRecord(ms.fork, s), "event");
+    for (hipStream_t x : ms.st) hip_check(hipStreamWaitEvent(x, ms.fork, 0), "wait");
     auto phase = [&](auto &&enq, auto &&done) {
       for (int m = 0; m < nsys; ++m)
         if (live[m]) guard_sys(m, [&] { enq(m); });
@@ -1263,6 +1267,11 @@ eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const doub
     for (int m = 0; m < nsys; ++m) {
       runs[m]->s = ms.st[size_t(m) % ms.st.size()];
       if (sst[m] == EAMG_OK) runs[m]->enqueue_finish(x_dev[m]);
+    }
+    // and the caller's later work on `s` comes after every x is written
+    for (size_t i = 0; i < ms.st.size(); ++i) {
+      hip_check(hipEventRecord(ms.ev[i], ms.st[i]), "event");
+      hip_check(hipStreamWaitEvent(s, ms.ev[i], 0), "wait");
     }
     for (hipStream_t x : ms.st) hip_check(hipStreamSynchronize(x), "sync");
     for (int m = 0; m < nsys; ++m) {

@@ -1,11 +1,13 @@
 """GPU tests of eamg_solve_multi: independent systems of uneven size solved together.
 
 Each system follows eamg_solve's recurrence with the same kernels in the same order, so its
-result must equal its own eamg_solve bit for bit (and eamg_solve is checked against the FP64
-oracle in test_gpu_parity.py).  Covered: meshes of different sizes and Poisson ratios
-(including one without coarsening), FP64 and FP32 V-cycles, graph replay against eager
-launches, a system with a non-finite right-hand side among healthy ones, a zero right-hand side,
-and argument checks.
+result must equal its own eamg_solve bit for bit.  Each system is also compared with the FP64
+oracle's PCG (CG preconditioned by one V-cycle, section "res") on its own hierarchy: at a
+fixed iteration count the iterates agree within 1e-10 relative (the FP64 parity bar).
+Covered: meshes of different sizes and Poisson ratios (including one without coarsening),
+FP64 and FP32 V-cycles, graph replay against eager launches, a system with a non-finite
+right-hand side among healthy ones, a zero right-hand side, ordering after the caller's stream
+(b and x0 written there just before the call), and argument checks.
 """
 import os
 
@@ -13,6 +15,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import oracle
 import paper_2011_13325_amd as E
 from gen import make_problem
 
@@ -58,6 +61,59 @@ def test_multi_equals_individual_solves(systems, precond):
         assert torch.equal(x, xr), m
         assert _true_res(p, x.cpu().numpy()) <= 1e-8
     print(f"[multi precond={precond}] its {[i['iterations'] for i in infos]}", flush=True)
+
+
+def test_multi_matches_oracle_at_fixed_iteration_count(systems):
+    # every system's iterate after K iterations against the oracle's PCG after K iterations;
+    # K is the smallest iteration count the oracle needs to reach 1e-8 on any of the systems
+    ors, kstar = [], []
+    for p, _ in systems:
+        ho = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
+        _, it, _, rel_true, conv = oracle.pcg(ho, p.b, rtol=1e-8)
+        assert conv and rel_true <= 1e-8
+        ors.append(ho)
+        kstar.append(it)
+    K = min(kstar)
+    bs = [torch.tensor(p.b, device="cuda") for p, _ in systems]
+    xs = [torch.zeros_like(b) for b in bs]
+    st, infos = E.eamg_solve_multi([h.h for _, h in systems], bs, xs, rtol=0.0, max_it=K)
+    worst = 0.0
+    for m, ((p, _), ho, x, inf) in enumerate(zip(systems, ors, xs, infos)):
+        xo, it, *_ = oracle.pcg(ho, p.b, rtol=0.0, max_it=K)
+        if inf["iterations"] < K:       # a system without coarsening can be solved exactly
+            assert inf["status"] == E.EAMG_OK and it == inf["iterations"], (m, inf, it)
+        else:
+            assert it == K and inf["iterations"] == K, (m, inf, it)
+        err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+        worst = max(worst, err)
+        assert err <= 1e-10, (m, err)
+    print(f"[multi vs oracle] K={K} oracle its {kstar} max rel err {worst:.1e}", flush=True)
+
+
+def test_multi_waits_for_callers_stream(systems):
+    # b and x0 are written on the caller's stream behind a long-running kernel, right before
+    # the call on that stream: the systems' own streams must not read them earlier
+    hs = [h.h for _, h in systems]
+    ref = []
+    x0s = [torch.tensor(np.random.default_rng(40 + m).uniform(-1, 1, p.n_dofs), device="cuda")
+           for m, (p, _) in enumerate(systems)]
+    for (p, h), x0 in zip(systems, x0s):
+        x, info = h.solve(torch.tensor(p.b, device="cuda"), x0.clone(), rtol=1e-8, use_x0=True)
+        ref.append(x)
+    cs = torch.cuda.Stream()
+    bs = [torch.zeros(p.n_dofs, dtype=torch.float64, device="cuda") for p, _ in systems]
+    xs = [torch.zeros_like(b) for b in bs]
+    srcb = [torch.tensor(p.b, device="cuda") for p, _ in systems]
+    torch.cuda.synchronize()
+    with torch.cuda.stream(cs):
+        torch.cuda._sleep(50_000_000)
+        for b, sb, x, x0 in zip(bs, srcb, xs, x0s):
+            b.copy_(sb)
+            x.copy_(x0)
+        st, infos = E.eamg_solve_multi(hs, bs, xs, rtol=1e-8, use_x0=True, stream=cs)
+    assert st == E.EAMG_OK
+    for m, (x, xr) in enumerate(zip(xs, ref)):
+        assert torch.equal(x, xr), m
 
 
 def test_multi_graph_equals_eager(systems):
