@@ -1,20 +1,26 @@
 """Benchmark: edge-matrix AMG-PCG on one MI355X.
 
-Workload: 3D linear elasticity on the unit cube, 64^3 vertices (786,432 dofs, 774,144 free),
-P1 Kuhn tetrahedra, E = 1, nu = 0.3, clamped at x = 0, seeded uniform RHS (seed 1); FP64
-hierarchy and V-cycle; two matching passes per level, coarsening stopped below 8192 dofs
-(the coarsest level, 1051 vertices here, is inverted on the GPU at setup and applied as one dense
-product), one symmetric multicolour block Gauss-Seidel sweep pre / post; PCG to
-||r|| <= 1e-8 ||b||.  The same problem with coarsening stopped below 500 dofs (seven levels) is
-reported beside it as "coarsest_500".
+Headline workload: 3D linear elasticity on the unit cube with 128^3 vertices (6,291,456 dofs,
+6,242,304 free), P1 Kuhn tetrahedra, E = 1, nu = 0.45, clamped at x = 0, RHS uniform[-1, 1] from
+seed 3; two matching passes per level, coarsening until a level has fewer than 500 dofs, one
+symmetric multicolour block Gauss-Seidel sweep pre / post; the V-cycle in FP32 (matrices,
+vectors and accumulation) inside an FP64 CG (operator, vectors, inner products, stopping test)
+to ||r|| <= 1e-8 ||b||.  The V-cycle below the first level of at most 16384 dofs is applied as
+its dense matrix (computed at setup from the same hierarchy; the coarsest level is still the
+< 500-dof one).
 
-A step is one PCG solve to 1e-8 (V-cycle + CG kernels) on the hierarchy, with b resident in
-HBM when the timed region starts.  Setup (host coarsening + device P_s / Galerkin / D^+ /
-coarsest factor) is timed separately and reported in the same line.  The same solve with the
-FP32 V-cycle inside the FP64 CG is timed after it and reported as "mixed_fp32_vcycle", and the
-batched block-panel solve of 32 seeded load cases on the same hierarchy (FP64 and FP32 V-cycle)
-as "batched", 16 independent cubes of uneven size solved together as "multi_mesh", and the
-learned coarsening against the exact one on a heterogeneous cube as "learned_coarsening".
+A step is one PCG solve to 1e-8, with b resident in HBM when the timed region starts.  Setup
+(host coarsening + device P_s / Galerkin / D^+ / coarsest inverse / dense tail) is timed
+separately, with its phases split into host, device and copies.  Reported beside the headline
+in the same line:
+  fp64_vcycle        the same solve with the FP64 V-cycle, and the FP32 solution's distance to it
+  sparse_tail        the same hierarchy with every level's sweeps run sparse (no dense tail)
+  cube64             64^3, nu = 0.3, RHS seed 1, FP64 and FP32 V-cycle; its 32 seeded load
+                     cases as one block-panel solve ("batched")
+  multi_mesh         16 cubes of 8^3..48^3 vertices, nu uniform in [0.2, 0.45], solved together
+  learned_coarsening 96^3 with 200 stiff spherical inclusions: exact against learned walk,
+                     with the condition number estimated from the PCG coefficients
+  cpu_baseline       the CPU oracle and the GPU on the same 17^3 cube (nu = 0.3, seed 0)
 
 Prints ONE JSON line.
 """
@@ -27,66 +33,54 @@ import time
 import numpy as np
 
 
-# Coarsening stops below this many dofs: on one GPU the dense inverse of a coarsest level of a
-# few thousand dofs (one HBM-bound product per V-cycle) is cheaper than the launch-bound colour
-# sweeps of the small levels it replaces.
-COARSEST_DOFS = 8192
-
-
 def _args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=64, help="vertices per cube side")
+    ap.add_argument("--n", type=int, default=128, help="vertices per cube side of the headline")
+    ap.add_argument("--nu", type=float, default=0.45)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--coarsest", type=int, default=500,
+                    help="coarsening stops once a level has fewer dofs than this")
+    ap.add_argument("--dense-tail", type=int, default=16384,
+                    help="dofs of the largest level whose V-cycle is applied as a dense matrix (0: none)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline solve (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=17, help="cube side of the oracle sample")
     ap.add_argument("--batch", type=int, default=32,
-                    help="right-hand sides of the batched block-panel solve (0: skip)")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarsening section")
-    ap.add_argument("--learned-n", type=int, default=40,
-                    help="cube side of the learned-coarsening comparison (96: the full configuration)")
-    ap.add_argument("--learned-inclusions", type=int, default=60,
-                    help="stiff spherical inclusions of that cube (200 at 96^3)")
-    ap.add_argument("--counter-pass", action="store_true",
-                    help="run only the workload of the rocprofv3 counter passes (no JSON line)")
+                    help="right-hand sides of the batched block-panel solve at 64^3 (0: skip)")
     ap.add_argument("--multi", type=int, default=16,
                     help="independent meshes of the multi-system solve (0: skip)")
-    ap.add_argument("--coarsest", type=int, default=COARSEST_DOFS,
-                    help="coarsening stops once a level has fewer dofs than this")
-    ap.add_argument("--no-coarsest-500", action="store_true",
-                    help="skip the comparison with coarsening stopped below 500 dofs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarsening section")
+    ap.add_argument("--learned-n", type=int, default=96)
+    ap.add_argument("--learned-inclusions", type=int, default=200)
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="run only the workload of the rocprofv3 counter passes (no JSON line)")
     return ap.parse_args()
 
 
-def cpu_baseline(n):
-    """The CPU oracle (FP64 NumPy/SciPy, one process, BLAS limited to one thread) on a bounded
-    sample: setup and PCG solve to 1e-8 on an n^3 cube of the same problem family; the solve
-    is timed."""
-    from threadpoolctl import threadpool_limits
+def _params(E, args, **kw):
+    prm = dict(vcycle_fp32=1, coarsest_max_dofs=args.coarsest, dense_tail_dofs=args.dense_tail)
+    prm.update(kw)
+    return E.eamg_default_setup_params(**prm)
 
-    import oracle
-    from gen import make_problem
-    p = make_problem(n, seed=1)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        h = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
-        t_setup = time.perf_counter() - t0
-        times = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            x, it, rel, rel_true, conv = oracle.pcg(h, p.b, rtol=1e-8)
-            times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": p.n_free_dofs / t, "unit": "dofs/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle setup ({t_setup:.1f} s) + PCG to 1e-8 ({it} its, median of 3: "
-                      f"{t:.2f} s) on the {n}^3-vertex cube ({p.n_free_dofs} free dofs) of the "
-                      f"same elasticity problem, one thread"}
+
+def _setup(E, torch, p, prm, stream=None):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, prm, stream=stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    ph = E.eamg_setup_phases(h.h)
+    split = {w: round(sum(s for _, s, ww in ph if ww == w), 3) for w in ("host", "device", "copy")}
+    return h, {"setup_s": round(setup_s, 3), "split_s": split,
+               "phases_s": {n: round(s, 3) for n, s, _ in ph}}
 
 
 def _timed_solves(E, torch, hier, b, x, stream, steps, warmup, precond):
     for _ in range(warmup):
-        hier.solve(b, x, precond=precond)
+        hier.solve(b, x, precond=precond, stream=stream)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -94,7 +88,7 @@ def _timed_solves(E, torch, hier, b, x, stream, steps, warmup, precond):
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(steps):
-        _, info = hier.solve(b, x, precond=precond)
+        _, info = hier.solve(b, x, precond=precond, stream=stream)
         infos.append(info)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -103,11 +97,34 @@ def _timed_solves(E, torch, hier, b, x, stream, steps, warmup, precond):
     return ms, infos[-1]
 
 
-def _profiled(E, hier, b, x, steps, precond):
-    """Per-kernel durations with events on the solve stream, over the same number of steps."""
+def _kappa(E, h):
+    """Condition number of the preconditioned operator estimated by Lanczos from the last
+    solve's CG coefficients: T_jj = 1/alpha_j + beta_j/alpha_{j-1}, T_{j,j+1} =
+    sqrt(beta_{j+1})/alpha_j; and the CG error reduction factor it implies per iteration."""
+    al, be = E.eamg_solve_coefficients(h.h)
+    k = len(al)
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / al[j] + (be[j] / al[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(be[j + 1]) / al[j]
+    ev = np.linalg.eigvalsh(T)
+    kap = float(ev[-1] / ev[0])
+    return {"kappa": round(kap, 3), "lambda_min": float(ev[0]), "lambda_max": float(ev[-1]),
+            "cg_factor": round((np.sqrt(kap) - 1.0) / (np.sqrt(kap) + 1.0), 4)}
+
+
+# CG kernels of the iteration (everything else the profiler records is the preconditioner)
+_CG_KERNELS = ("k_spmv", "k_dot", "k_reduce", "k_update_xr", "k_update_p")
+
+
+def _profiled(E, hier, b, x, steps, precond, stream):
+    """Per-kernel durations with events on the solve stream, over `steps` profiled solves:
+    the dominant kernel's roofline and the V-cycle aggregate (algorithmic bytes of all
+    preconditioner kernels over their summed durations)."""
     E.eamg_profile_enable(hier.h, True)
     for _ in range(steps):
-        hier.solve(b, x, precond=precond)
+        hier.solve(b, x, precond=precond, stream=stream)
     kstats = E.eamg_profile_read(hier.h)
     E.eamg_profile_enable(hier.h, False)
     dom = kstats[0]
@@ -117,32 +134,36 @@ def _profiled(E, hier, b, x, steps, precond):
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3,
             "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"]}
+    vk = [k for k in kstats if not k["name"].startswith(_CG_KERNELS)]
+    vb, vt = sum(k["bytes"] for k in vk), sum(k["total_ms"] for k in vk)
+    vagg = {"GBps": vb / (vt / 1e3) / 1e9, "frac": vb / (vt / 1e3) / 8e12,
+            "ms_per_solve": vt / steps, "bytes_per_solve": vb / steps}
     kern = [{"name": k["name"], "launches_per_step": k["launches"] / steps,
              "ms_per_step": k["total_ms"] / steps,
              "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9 if k["total_ms"] else None}
             for k in kstats[:12]]
-    return roof, kern
+    return roof, vagg, kern
 
 
-def _coarsest_500(E, torch, p, stream, steps, warmup, ms_headline):
-    """The headline problem with coarsening stopped below 500 dofs (the small-problem setting):
-    setup, autotune and the FP64 solve timed the same way."""
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                    E.eamg_default_setup_params(coarsest_max_dofs=500), stream=stream)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    E.eamg_autotune(h.h, 0, stream=stream)
-    b = torch.tensor(p.b, device="cuda")
-    x = torch.zeros_like(b)
-    ms, info = _timed_solves(E, torch, h, b, x, stream, steps, warmup, E.EAMG_PRECOND_VCYCLE)
+def _per_level(E, hier, b, x, precond, stream):
+    """Milliseconds per solve of every V-cycle kernel on every level (one profiled solve)."""
+    E.eamg_profile_enable(hier.h, 2)
+    hier.solve(b, x, precond=precond, stream=stream)
+    ks = E.eamg_profile_read(hier.h, 256)
+    E.eamg_profile_enable(hier.h, False)
+    return [{"name": k["name"], "launches": k["launches"], "ms": round(k["total_ms"], 3),
+             "GBps": round(k["bytes"] / (k["total_ms"] / 1e3) / 1e9, 1) if k["total_ms"] else None}
+            for k in ks[:30]]
+
+
+def _levels(E, h):
     st = h.stats()
-    h.close()
-    return {"value": p.n_free_dofs / (ms / 1e3), "unit": "dofs/s", "ms_per_step": ms,
-            "iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
-            "levels": st["n_levels"], "level_vertices": st["n"], "setup_s": round(setup_s, 3),
-            "headline_speedup": ms / ms_headline}
+    out = []
+    for l in range(st["n_levels"]):
+        li = E.eamg_level_info_get(h.h, l)
+        out.append({"n": li["n"], "bs": li["bs"], "nnzb": li["nnzb_A"], "colors": li["n_colors"],
+                    "nnzb_P": li["nnzb_P"]})
+    return st, out
 
 
 def _batch_rhs(p, m):
@@ -152,7 +173,7 @@ def _batch_rhs(p, m):
     return B
 
 
-def _batched(E, torch, hier, p, m, steps, warmup):
+def _batched(E, torch, hier, p, m, steps, warmup, single_ms):
     """Batched block-panel solves of m right-hand sides, FP64 and FP32 V-cycle."""
     B = torch.tensor(_batch_rhs(p, m), device="cuda")
     X = torch.zeros_like(B)
@@ -177,6 +198,7 @@ def _batched(E, torch, hier, p, m, steps, warmup):
         out[key] = {"ms_per_batch_solve": ms, "value": p.n_free_dofs * m / (ms / 1e3),
                     "unit": "dofs*rhs/s", "iterations_min_max": [min(its), max(its)],
                     "max_rel_res_true": max(i["rel_res_true"] for i in infos),
+                    "speedup_per_rhs_vs_single_fp64": single_ms * m / ms,
                     "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
                                  "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
                                  "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3},
@@ -186,7 +208,33 @@ def _batched(E, torch, hier, p, m, steps, warmup):
     return out
 
 
-def _multi_mesh(E, torch, steps, count=16, seed=4, coarsest=COARSEST_DOFS):
+def _cube64(E, torch, args, stream):
+    """64^3, nu = 0.3, RHS seed 1: FP64 V-cycle (the plain FP64 hierarchy and V-cycle) and FP32
+    V-cycle, then the batched panel solve of its load cases."""
+    from gen import make_problem
+    p = make_problem(64, seed=1)
+    h, su = _setup(E, torch, p, _params(E, args), stream)
+    E.eamg_autotune(h.h, panel_width=max(args.batch, 0), stream=stream)
+    b = torch.tensor(p.b, device="cuda")
+    x = torch.zeros_like(b)
+    out = {"workload": "elasticity cube 64^3 vertices (786,432 dofs), nu=0.3, RHS seed 1",
+           "free_dofs": p.n_free_dofs, **su}
+    for prec, key in ((E.EAMG_PRECOND_VCYCLE, "fp64_vcycle"), (E.EAMG_PRECOND_VCYCLE_FP32, "fp32_vcycle")):
+        ms, info = _timed_solves(E, torch, h, b, x, stream, args.steps, args.warmup, prec)
+        out[key] = {"ms_per_solve": ms, "value": p.n_free_dofs / (ms / 1e3), "unit": "dofs/s",
+                    "iterations": info["iterations"], "rel_res_true": info["rel_res_true"]}
+    out["fp32_speedup_vs_fp64"] = out["fp64_vcycle"]["ms_per_solve"] / out["fp32_vcycle"]["ms_per_solve"]
+    st, lv = _levels(E, h)
+    out.update({"levels": st["n_levels"], "level_vertices": st["n"], "oc": round(st["oc"], 4),
+                "dense_tail": E.eamg_dense_tail(h.h)})
+    if args.batch > 0:
+        out["batched"] = _batched(E, torch, h, p, args.batch, args.steps, args.warmup,
+                                  out["fp64_vcycle"]["ms_per_solve"])
+    h.close()
+    return out
+
+
+def _multi_mesh(E, torch, args, count=16, seed=4):
     """Independent meshes of uneven size solved together (eamg_solve_multi): count cubes with
     sides uniform in [8, 48] and Poisson ratios uniform in [0.2, 0.45], FP32 V-cycle in FP64 CG;
     against the same systems solved one after another."""
@@ -198,8 +246,7 @@ def _multi_mesh(E, torch, steps, count=16, seed=4, coarsest=COARSEST_DOFS):
     sysm = []
     for c, (n, nu) in enumerate(zip(sides, nus)):
         p = make_problem(int(n), nu=float(nu), seed=100 + c)
-        h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                        E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=coarsest))
+        h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, _params(E, args))
         sysm.append((p, h))
     setup_s = time.perf_counter() - t0
     bs = [torch.tensor(p.b, device="cuda") for p, _ in sysm]
@@ -210,46 +257,45 @@ def _multi_mesh(E, torch, steps, count=16, seed=4, coarsest=COARSEST_DOFS):
         h.solve(b, x, precond=prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(args.steps):
         for (p, h), b, x in zip(sysm, bs, xs):
             h.solve(b, x, precond=prec)
     torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - t0) * 1e3 / steps
+    seq_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     E.eamg_solve_multi(hs, bs, xs, precond=prec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(args.steps):
         st, infos = E.eamg_solve_multi(hs, bs, xs, precond=prec)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
     assert st == E.EAMG_OK and max(i["rel_res_true"] for i in infos) <= 1e-8
     dofs = sum(p.n_free_dofs for p, _ in sysm)
     for _, h in sysm:
         h.close()
     return {"meshes": [int(n) for n in sides], "free_dofs": dofs, "setup_s": round(setup_s, 3),
-            "coarsest_max_dofs": coarsest,
             "dtype": "f32 V-cycle in f64 CG", "ms_per_solve_all": ms,
             "value": dofs / (ms / 1e3), "unit": "dofs/s",
             "ms_one_after_another": seq_ms, "speedup_vs_one_after_another": seq_ms / ms,
             "iterations": [i["iterations"] for i in infos]}
 
 
-def _learned(E, torch, n=40, inclusions=60):
-    """Learned coarsening on a heterogeneous cube (stiff spherical inclusions, E = 1e4): the
-    edge network is trained on the GPU on small meshes of the same kind (their exact
-    criterion decisions), then the exact and the learned walk build hierarchies of the n^3
-    mesh; criteria evaluations, setup time and PCG iterations are compared."""
+def _learned(E, torch, args, stream):
+    """Learned coarsening on a heterogeneous cube (stiff spherical inclusions, E = 1e4, nu of each
+    inclusion uniform in [0.3, 0.49]): the edge network is trained on the GPU on small meshes of
+    the same kind (their exact criterion decisions), then the exact and the learned walk build
+    hierarchies of the large mesh; criteria evaluations, setup time, PCG iterations, and the
+    condition number of the preconditioned operator (Lanczos from the PCG coefficients) are
+    compared."""
     from gen import make_problem
-
-    def hier(p, **kw):
-        return E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                           E.eamg_default_setup_params(**kw))
+    n, inclusions = args.learned_n, args.learned_inclusions
 
     t0 = time.perf_counter()
     graphs = []
     for c, (m, inc, nu) in enumerate([(12, 8, 0.3), (14, 12, 0.4), (16, 16, 0.35), (13, 10, 0.45)]):
         p = make_problem(m, inclusions=inc, nu=nu, geometry_seed=10 + c, seed=c)
-        h = hier(p, gnn_record=1)
+        h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                        E.eamg_default_setup_params(gnn_record=1))
         for k in range(E.eamg_coarsening_stats(h.h)["sample_passes"]):
             X, edges, nn, y, w = E.eamg_gnn_samples(h.h, k)
             if len(y) and w.sum() > 0:
@@ -258,27 +304,81 @@ def _learned(E, torch, n=40, inclusions=60):
     net = E.EdgeNet(seed=3)
     hist = net.train(graphs, epochs=200, lr=3e-3)
     train_s = time.perf_counter() - t0
-    p = make_problem(n, inclusions=inclusions, nu=0.35, geometry_seed=96, seed=5)
+    p = make_problem(n, inclusions=inclusions, nu=0.3, geometry_seed=5, seed=5)
     b = torch.tensor(p.b, device="cuda")
-    out = {"workload": f"elasticity cube {n}^3, {inclusions} stiff spherical inclusions (E=1e4), "
-                       f"nu=0.35; network trained on 4 meshes of 12^3..16^3",
+    out = {"workload": f"elasticity cube {n}^3, {inclusions} stiff spherical inclusions (E=1e4, "
+                       f"nu uniform [0.3, 0.49]) in E=1, nu=0.3, RHS seed 5; network trained on "
+                       f"4 meshes of 12^3..16^3",
            "train_s": round(train_s, 3), "train_loss": [float(hist[0]), float(hist[-1])]}
     for key, kw in (("exact", {}), ("learned", {"gnn": net.h.value, "gnn_skip": 0.2})):
+        h, su = _setup(E, torch, p, _params(E, args, **kw), stream)
+        st = E.eamg_coarsening_stats(h.h)
+        x, info = h.solve(b, precond=E.EAMG_PRECOND_VCYCLE_FP32, stream=stream)
+        kap = _kappa(E, h)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        h = hier(p, **kw)
+        h.solve(b, x, precond=E.EAMG_PRECOND_VCYCLE_FP32, stream=stream)
         torch.cuda.synchronize()
-        setup_s = time.perf_counter() - t0
-        st = E.eamg_coarsening_stats(h.h)
-        _, info = h.solve(b)
-        out[key] = {"setup_s": round(setup_s, 3), "criteria_evaluations": st["evaluated"],
+        out[key] = {**su, "criteria_evaluations": st["evaluated"],
                     "mu_g_evaluations": st["evaluated_g"], "passed_over": st["skipped"],
                     "pcg_iterations": info["iterations"], "rel_res_true": info["rel_res_true"],
-                    "oc": round(h.stats()["oc"], 4)}
+                    "solve_ms": round((time.perf_counter() - t0) * 1e3, 2),
+                    "oc": round(h.stats()["oc"], 4), **kap}
         h.close()
     net.close()
     out["evaluations_saved"] = 1.0 - out["learned"]["criteria_evaluations"] / out["exact"]["criteria_evaluations"]
     return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(E, torch, args, stream):
+    """The CPU oracle (FP64 NumPy/SciPy, one process, BLAS held to one thread) and the GPU on the
+    same bounded sample: the 17^3-vertex cube (14,739 dofs), nu = 0.3, RHS seed 0, PCG to 1e-8;
+    the oracle's solve (median of 3) and setup are timed, and the library's FP64 solve of the
+    same problem with the headline's settings beside it."""
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from gen import make_problem
+    p = make_problem(17, seed=0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ho = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet)
+        t_setup = time.perf_counter() - t0
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            xo, it, rel, rel_true, conv = oracle.pcg(ho, p.b, rtol=1e-8)
+            times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    h, su = _setup(E, torch, p, _params(E, args), stream)
+    b = torch.tensor(p.b, device="cuda")
+    x = torch.zeros_like(b)
+    gms, ginfo = _timed_solves(E, torch, h, b, x, stream, max(args.steps, 5), 1, E.EAMG_PRECOND_VCYCLE)
+    err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    h.close()
+    return {"value": p.n_free_dofs / t, "unit": "dofs/s", "cores": 1, "kind": "oracle",
+            "sample": f"17^3-vertex cube ({p.n_free_dofs} free dofs), nu=0.3, RHS seed 0: oracle "
+                      f"setup {t_setup:.1f} s, PCG to 1e-8 in {it} iterations, median of 3 solves "
+                      f"{t:.3f} s, one thread (the 64^3 and 128^3 oracle setups would take "
+                      f"minutes to hours and are not run)",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "oracle_setup_s": round(t_setup, 2), "oracle_solve_s": round(t, 4),
+            "oracle_iterations": it,
+            "gpu_same_input": {"dtype": "f64", "ms_per_solve": gms,
+                               "value": p.n_free_dofs / (gms / 1e3), "iterations": ginfo["iterations"],
+                               "rel_res_true": ginfo["rel_res_true"], "setup_s": su["setup_s"],
+                               "x_rel_diff_vs_oracle": err},
+            "gpu_speedup_solve": t * 1e3 / gms}
 
 
 def _traffic(kernel):
@@ -288,7 +388,7 @@ def _traffic(kernel):
     import re
     root = os.path.dirname(os.path.abspath(__file__))
     try:
-        txt = open(os.path.join(root, "profiles", "traffic_k_gs_color_cube64.md")).read()
+        txt = open(os.path.join(root, "profiles", "traffic_k_gs_color_cube128.md")).read()
         src = open(os.path.join(root, "paper_2011_13325_amd", "csrc", "kernels.hip"), "rb").read()
     except OSError:
         return None
@@ -302,9 +402,9 @@ def _traffic(kernel):
     return float(v.group(1))
 
 
-def _counter_pass():
-    """Workload of the rocprofv3 counter passes (profiles/traffic_*.md): a calibration copy of
-    64 MiB, then one FP64 solve of the bench problem with eager launches."""
+def _counter_pass(args):
+    """Workload of the rocprofv3 counter passes: a calibration copy of 64 MiB, then one solve of
+    the headline problem (FP32 V-cycle) with eager launches."""
     os.environ["EAMG_GRAPH"] = "0"
     import torch
     import paper_2011_13325_amd as E
@@ -312,15 +412,14 @@ def _counter_pass():
     torch.cuda.set_device(0)
     n = 8 * 1024 * 1024
     a = torch.ones(n, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
+    c = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        c.copy_(a)
     torch.cuda.synchronize()
-    p = make_problem(64, seed=1)
-    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                    E.eamg_default_setup_params(coarsest_max_dofs=COARSEST_DOFS))
+    p = make_problem(args.n, nu=args.nu, seed=args.seed)
+    h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, _params(E, args))
     E.eamg_autotune(h.h, 0)
-    x, info = h.solve(torch.tensor(p.b, device="cuda"))
+    x, info = h.solve(torch.tensor(p.b, device="cuda"), precond=E.EAMG_PRECOND_VCYCLE_FP32)
     torch.cuda.synchronize()
     print(f"counter pass: copy of {8 * n} bytes; solve {info['iterations']} iterations", flush=True)
     h.close()
@@ -328,93 +427,93 @@ def _counter_pass():
 
 def main():
     args = _args()
-    if args.counter_pass:
-        _counter_pass()
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.counter_pass:
+        _counter_pass(args)
+        return
     import torch
     import paper_2011_13325_amd as E
     from gen import make_problem
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    p = make_problem(args.n, seed=1)
     stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
+    p = make_problem(args.n, nu=args.nu, seed=args.seed)
+    hier, su = _setup(E, torch, p, _params(E, args), stream)
     t0 = time.perf_counter()
-    # FP32 copies of the V-cycle matrices are kept too, so that the same hierarchy serves the
-    # FP64 solve (the headline) and the mixed-precision comparison
-    prm = E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=args.coarsest)
-    hier = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, prm,
-                       stream=stream)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    # launch shapes measured on this hierarchy (single vector and 32-wide panels), once
-    t0 = time.perf_counter()
-    tune_before, tune_after = E.eamg_autotune(hier.h, panel_width=max(args.batch, 0), stream=stream)
+    tune_before, tune_after = E.eamg_autotune(hier.h, panel_width=0, stream=stream)
     tune_s = time.perf_counter() - t0
-    st = hier.stats()
+    st, level_info = _levels(E, hier)
     b = torch.tensor(p.b, device=dev)
-    x = torch.zeros_like(b)
-    ms, info = _timed_solves(E, torch, hier, b, x, stream, args.steps, args.warmup,
-                             E.EAMG_PRECOND_VCYCLE)
-    roof, kern = _profiled(E, hier, b, x, args.steps, E.EAMG_PRECOND_VCYCLE)
-    ms32, info32 = _timed_solves(E, torch, hier, b, x, stream, args.steps, args.warmup,
-                                 E.EAMG_PRECOND_VCYCLE_FP32)
-    roof32, kern32 = _profiled(E, hier, b, x, args.steps, E.EAMG_PRECOND_VCYCLE_FP32)
+    x32 = torch.zeros_like(b)
+    P32, P64 = E.EAMG_PRECOND_VCYCLE_FP32, E.EAMG_PRECOND_VCYCLE
+    ms, info = _timed_solves(E, torch, hier, b, x32, stream, args.steps, args.warmup, P32)
+    kap32 = _kappa(E, hier)
+    roof, vagg, kern = _profiled(E, hier, b, torch.zeros_like(b), args.steps, P32, stream)
+    x64 = torch.zeros_like(b)
+    ms64, info64 = _timed_solves(E, torch, hier, b, x64, stream, args.steps, args.warmup, P64)
+    kap64 = _kappa(E, hier)
+    _, vagg64, kern64 = _profiled(E, hier, b, torch.zeros_like(b), 1, P64, stream)
+    xdiff = float((x32 - x64).norm() / x64.norm())
+    vbytes, itbytes = E.eamg_traffic_model(hier.h, P32)
+    vbytes64, itbytes64 = E.eamg_traffic_model(hier.h, P64)
     its = info["iterations"]
-    vbytes, itbytes = E.eamg_traffic_model(hier.h, E.EAMG_PRECOND_VCYCLE)
-    vbytes32, itbytes32 = E.eamg_traffic_model(hier.h, E.EAMG_PRECOND_VCYCLE_FP32)
     value = p.n_free_dofs / (ms / 1e3)
+    tail = E.eamg_dense_tail(hier.h)
     out = {
         "metric": "AMG-PCG time to 1e-8 and dofs/s, FP64 vs mixed/batched; V-cycle HBM GB/s",
         "value": value, "unit": "dofs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"elasticity cube {args.n}^3 vertices (Kuhn P1, E=1, nu=0.3, "
-                               f"clamped x=0, RHS seed 1), FP64 AMG-PCG to 1e-8, coarsening "
-                               f"stopped below {args.coarsest} dofs",
-                   "coarsest_max_dofs": args.coarsest,
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"elasticity cube {args.n}^3 vertices ({p.n_dofs} dofs; Kuhn P1, "
+                               f"E=1, nu={args.nu}, clamped x=0, RHS seed {args.seed}), FP32 "
+                               f"V-cycle in FP64 CG to 1e-8, coarsening to < {args.coarsest} "
+                               f"dofs, dense V-cycle tail <= {args.dense_tail} dofs",
+                   "precision": "V-cycle FP32 (matrices, vectors, accumulation; dense tail FP32 "
+                                "with FP64 sums); CG FP64",
+                   "coarsest_max_dofs": args.coarsest, "dense_tail": {"level": tail[0], "dofs": tail[1]},
                    "dofs": p.n_dofs, "free_dofs": p.n_free_dofs, "iterations": its,
                    "rel_res_true": info["rel_res_true"], "levels": st["n_levels"],
                    "level_vertices": st["n"], "vc": round(st["vc"], 4), "oc": round(st["oc"], 4),
-                   "setup_s": round(setup_s, 3),
+                   "setup": su,
                    "autotune": {"s": round(tune_s, 3), "tuned_ms_before": tune_before,
                                 "tuned_ms_after": tune_after},
                    "model_bytes_per_iteration": itbytes,
-                   "model_GBps_whole_solve": itbytes * its / (ms / 1e3) / 1e9},
+                   "model_GBps_whole_solve": itbytes * its / (ms / 1e3) / 1e9,
+                   "level_info": level_info},
     }
     out["roofline"] = roof
+    out["vcycle_aggregate"] = vagg
+    out["kappa_estimate"] = kap32
     out["kernels"] = kern
-    out["mixed_fp32_vcycle"] = {
-        "value": p.n_free_dofs / (ms32 / 1e3), "unit": "dofs/s", "ms_per_step": ms32,
-        "speedup_vs_fp64": ms / ms32, "iterations": info32["iterations"],
-        "rel_res_true": info32["rel_res_true"], "dtype": "f32 V-cycle in f64 CG",
-        "model_bytes_per_iteration": itbytes32,
-        "model_GBps_whole_solve": itbytes32 * info32["iterations"] / (ms32 / 1e3) / 1e9,
-        "roofline": roof32, "kernels": kern32[:8]}
-    if args.batch > 0:
-        out["batched"] = _batched(E, torch, hier, p, args.batch, args.steps, args.warmup)
-        out["batched"]["speedup_per_rhs_vs_single_fp64"] = {
-            k: out["batched"][k]["value"] / value for k in ("fp64_vcycle", "fp32_vcycle")}
-    if not args.no_coarsest_500 and args.coarsest != 500:
-        out["coarsest_500"] = _coarsest_500(E, torch, p, stream, args.steps, args.warmup, ms)
-    if args.multi > 0:
-        out["multi_mesh"] = _multi_mesh(E, torch, args.steps, count=args.multi,
-                                        coarsest=args.coarsest)
-    if not args.no_learned:
-        out["learned_coarsening"] = _learned(E, torch, args.learned_n, args.learned_inclusions)
-    levels = []
-    for l in range(st["n_levels"]):
-        li = E.eamg_level_info_get(hier.h, l)
-        levels.append({"n": li["n"], "bs": li["bs"], "nnzb": li["nnzb_A"], "colors": li["n_colors"],
-                       "nnzb_P": li["nnzb_P"]})
-    out["config"]["level_info"] = levels
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    out["fp64_vcycle"] = {
+        "value": p.n_free_dofs / (ms64 / 1e3), "unit": "dofs/s", "ms_per_step": ms64,
+        "iterations": info64["iterations"], "rel_res_true": info64["rel_res_true"],
+        "fp32_speedup": ms64 / ms, "model_bytes_per_iteration": itbytes64,
+        "vcycle_aggregate": vagg64, "kappa_estimate": kap64, "kernels": kern64[:8],
+        "fp32_solution_rel_diff": xdiff}
+    if not args.headline_only:
+        out["per_level_fp32"] = _per_level(E, hier, b, torch.zeros_like(b), P32, stream)
     hier.close()
+    if not args.headline_only:
+        if args.dense_tail > 0:
+            h2, su2 = _setup(E, torch, p, _params(E, args, dense_tail_dofs=0), stream)
+            E.eamg_autotune(h2.h, panel_width=0, stream=stream)
+            ms2, info2 = _timed_solves(E, torch, h2, b, torch.zeros_like(b), stream, args.steps,
+                                       args.warmup, P32)
+            out["sparse_tail"] = {"ms_per_step": ms2, "value": p.n_free_dofs / (ms2 / 1e3),
+                                  "iterations": info2["iterations"], "setup_s": su2["setup_s"],
+                                  "dense_tail_speedup": ms2 / ms}
+            h2.close()
+        out["cube64"] = _cube64(E, torch, args, stream)
+        if args.multi > 0:
+            out["multi_mesh"] = _multi_mesh(E, torch, args, count=args.multi)
+        if not args.no_learned:
+            out["learned_coarsening"] = _learned(E, torch, args, stream)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(E, torch, args, stream)
     print(json.dumps(out), flush=True)
 
 

@@ -119,6 +119,18 @@ typedef struct {
  *                     bit-identical to the host code, so the same hierarchy; default); batches
  *                     too small to gain from a launch (under 4096 pairs, 128 unions) stay on host
  *                     threads.  2: every batch on the GPU.  0: host threads only.
+ *  dense_tail_dofs    0: every level below the finest runs its own sweeps, residual and
+ *                     transfers in the V-cycle (default).  > 0 (at most 16384): the V-cycle on
+ *                     the first level l >= 1 with bs_l * n_l <= dense_tail_dofs and on every level
+ *                     below it is one fixed linear map of that level's right-hand side (Alg.
+ *                     alg:tg applied recursively, starting from x = 0); it is computed at setup
+ *                     by running that part of the V-cycle on the columns of the identity
+ *                     (the batched V-cycle of eamg_solve_batch, 64 columns per pass) and
+ *                     applied as one dense product per V-cycle (FP64, plus an FP32 copy with
+ *                     vcycle_fp32).  The hierarchy, and the V-cycle as an operator, are those of
+ *                     the sparse path; only the rounding differs.  No tail when that level is
+ *                     the coarsest or no level qualifies.  Memory: ld^2 doubles (+ floats), ld =
+ *                     the tail's dofs rounded up to 128 (256).
  */
 typedef struct eamg_gnn eamg_gnn;
 typedef struct {
@@ -133,6 +145,7 @@ typedef struct {
   int32_t gnn_record;
   int32_t mu_s_only;
   int32_t gpu_criteria;
+  int32_t dense_tail_dofs;
 } eamg_setup_params;
 
 /* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,
@@ -336,6 +349,36 @@ eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *a
  * EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32. */
 eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, double *vcycle_bytes,
                                double *iteration_bytes);
+
+/* The CG coefficients of the last eamg_solve (or of its system in eamg_solve_multi) on h, one
+ * pair per iteration: alpha_k = rho_{k-1} / (p_k . A p_k) and beta_k = rho_{k-1} / rho_{k-2}
+ * (beta_1 = 0), rho = r . z (section "res": CG with the V-cycle as preconditioner).  They give
+ * the Lanczos tridiagonal matrix of the preconditioned operator, whose extreme eigenvalues
+ * estimate its condition number.  Up to max_entries pairs are copied to the HOST arrays alpha
+ * and beta (either may be NULL); *n_out = the number of iterations recorded. */
+eamg_status eamg_solve_coefficients(const eamg_hierarchy *h, int32_t max_entries, double *alpha,
+                                    double *beta, int32_t *n_out);
+
+/* Wall time of the setup phases of h (each summed over the levels), in the order the phases
+ * first ran.  where: 0 host (the weights of the finest level, the matching walks -- whose
+ * criteria batches may run on the GPU inside them --, the P_s plan, the symbolic Galerkin
+ * products, the colouring and the solve layout), 1 device (Dirichlet rows, the P_s and
+ * Galerkin numerics, the coarsest inverse, the dense tail, the solve vectors), 2 host-to-device
+ * copies of the input.  Up to max_entries phases are copied to out (HOST); *n_out = the number
+ * of phases. */
+typedef struct {
+  char name[48];
+  double seconds;
+  int32_t where;
+} eamg_setup_phase;
+
+eamg_status eamg_setup_phases(const eamg_hierarchy *h, int32_t max_entries, eamg_setup_phase *out,
+                              int32_t *n_out);
+
+/* The dense V-cycle tail of a hierarchy (setup parameter dense_tail_dofs): *level = the first
+ * level whose V-cycle is applied as one dense matrix, or -1 when there is none; *dofs = its
+ * size (0 when none).  Either pointer may be NULL. */
+eamg_status eamg_dense_tail(const eamg_hierarchy *h, int32_t *level, int32_t *dofs);
 
 /*
  * Per-kernel timing, for measuring each kernel against its bandwidth roofline.  While enabled,

@@ -40,7 +40,7 @@ EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setu
             "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
             "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
             "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy", "eamg_coarsening_stats",
-            "eamg_gnn_samples"]
+            "eamg_gnn_samples", "eamg_dense_tail", "eamg_solve_coefficients", "eamg_setup_phases"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -61,7 +61,7 @@ class eamg_setup_params(ctypes.Structure):
                 ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32),
                 ("gnn", ctypes.c_void_p), ("gnn_skip", ctypes.c_double),
                 ("gnn_record", ctypes.c_int32), ("mu_s_only", ctypes.c_int32),
-                ("gpu_criteria", ctypes.c_int32)]
+                ("gpu_criteria", ctypes.c_int32), ("dense_tail_dofs", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):
@@ -79,6 +79,10 @@ class eamg_level_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("bs", ctypes.c_int32), ("nnzb_A", ctypes.c_int64),
                 ("n_coarse", ctypes.c_int32), ("k_coarse", ctypes.c_int32),
                 ("nnzb_P", ctypes.c_int64), ("n_colors", ctypes.c_int32)]
+
+
+class eamg_setup_phase(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("seconds", ctypes.c_double), ("where", ctypes.c_int32)]
 
 
 class eamg_kernel_stat(ctypes.Structure):
@@ -155,6 +159,12 @@ def lib():
     L.eamg_profile_enable.restype = ctypes.c_int
     L.eamg_profile_read.argtypes = [vp, i32, P(eamg_kernel_stat), P(i32)]
     L.eamg_profile_read.restype = ctypes.c_int
+    L.eamg_setup_phases.argtypes = [vp, i32, P(eamg_setup_phase), P(i32)]
+    L.eamg_setup_phases.restype = ctypes.c_int
+    L.eamg_dense_tail.argtypes = [vp, P(i32), P(i32)]
+    L.eamg_dense_tail.restype = ctypes.c_int
+    L.eamg_solve_coefficients.argtypes = [vp, i32, vp, vp, P(i32)]
+    L.eamg_solve_coefficients.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -450,6 +460,39 @@ def eamg_traffic_model(h, precision=EAMG_PRECOND_VCYCLE):
     if st != EAMG_OK:
         raise EamgError(st, "eamg_traffic_model")
     return v.value, it.value
+
+
+def eamg_solve_coefficients(h, max_entries=100000):
+    """(alpha, beta) of the last single-vector solve on h, one entry per CG iteration."""
+    a = np.zeros(max_entries)
+    b = np.zeros(max_entries)
+    n = ctypes.c_int32()
+    st = lib().eamg_solve_coefficients(h, max_entries, _ptr(a), _ptr(b), ctypes.byref(n))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_solve_coefficients")
+    m = min(n.value, max_entries)
+    return a[:m].copy(), b[:m].copy()
+
+
+def eamg_setup_phases(h, max_entries=64):
+    """[(name, seconds, where)] with where "host", "device" or "copy"."""
+    buf = (eamg_setup_phase * max_entries)()
+    n = ctypes.c_int32()
+    st = lib().eamg_setup_phases(h, max_entries, buf, ctypes.byref(n))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_setup_phases")
+    names = {0: "host", 1: "device", 2: "copy"}
+    return [(buf[i].name.decode(), buf[i].seconds, names[buf[i].where])
+            for i in range(min(n.value, max_entries))]
+
+
+def eamg_dense_tail(h):
+    """(first level applied as the dense tail or -1, its dofs)."""
+    lvl, dofs = ctypes.c_int32(), ctypes.c_int32()
+    st = lib().eamg_dense_tail(h, ctypes.byref(lvl), ctypes.byref(dofs))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_dense_tail")
+    return lvl.value, dofs.value
 
 
 def eamg_profile_enable(h, on=True):

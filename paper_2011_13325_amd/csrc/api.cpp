@@ -49,6 +49,7 @@ eamg_setup_params defaults() {
   p.gnn_record = 0;
   p.mu_s_only = 0;
   p.gpu_criteria = 1;
+  p.dense_tail_dofs = 0;
   return p;
 }
 
@@ -72,6 +73,8 @@ void validate_params(const eamg_setup_params &p) {
   if (p.mu_s_only != 0 && p.mu_s_only != 1) fail(EAMG_ERR_INVALID_ARG, "mu_s_only must be 0 or 1");
   if (p.gpu_criteria < 0 || p.gpu_criteria > 2)
     fail(EAMG_ERR_INVALID_ARG, "gpu_criteria must be 0, 1 or 2");
+  if (p.dense_tail_dofs < 0 || p.dense_tail_dofs > kMaxCoarsestDofs)
+    fail(EAMG_ERR_INVALID_ARG, "dense_tail_dofs must be in [0, 16384]");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -425,6 +428,21 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   Level &L = h->lv[l];
   const bool f32 = sizeof(T) == 4;
   const std::string ty = type_name<T>();
+  if (int(l) == h->tail_level) {
+    // the V-cycle of this level and every level below it, as one dense matrix
+    const double by = double(h->nT) * h->nT * double(sizeof(T)) + 2.0 * h->nT * double(sizeof(T));
+    if (f32)
+      timed(h, "dense tail", lvname(h, l, "k_dense_gemv32"), by, s, [&] {
+        return launch_dense_gemv32(h->nT, h->ldT32, h->tail32, reinterpret_cast<const float *>(b),
+                                   reinterpret_cast<float *>(x), s);
+      });
+    else
+      timed(h, "dense tail", lvname(h, l, "k_dense_gemv<double>"), by, s, [&] {
+        return launch_dense_gemv<double>(h->nT, h->ldT, h->tail, reinterpret_cast<const double *>(b),
+                                         reinterpret_cast<double *>(x), s);
+      });
+    return;
+  }
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * double(sizeof(T));
     timed(h, "coarsest", lvname(h, l, "k_dense_gemv<" + ty + ">"), by, s,
@@ -606,6 +624,8 @@ struct SolveRun {
   void enqueue_start_a(const double *b_dev, const double *x_dev) {
     const Level &L0 = h->lv[0];
     const SoaMat &A = L0.Am;
+    h->cg_alpha.clear();
+    h->cg_beta.clear();
     hip_check(hipEventRecord(e0, s), "event");
     hip_check(launch_fill(SC_COUNT, 0.0, h->scal, s), "fill");
     hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, b_dev, h->bp, s), "perm_in");
@@ -683,6 +703,8 @@ struct SolveRun {
   bool next() {
     if (converged) return false;
     ++iters;
+    h->cg_alpha.push_back(h->scal_h[SC_ALPHA]);
+    h->cg_beta.push_back(iters == 1 ? 0.0 : h->scal_h[SC_BETA]);
     if (h->scal_h[SC_BAD] != 0.0) fail(EAMG_ERR_BREAKDOWN, "p.Ap <= 0 or r.z <= 0 (operator or preconditioner not SPD)");
     const double rr = h->scal_h[SC_RR];
     if (!std::isfinite(rr)) fail(EAMG_ERR_BREAKDOWN, "residual is not finite");
@@ -782,6 +804,7 @@ struct MultiStreams {
 };
 
 }  // namespace
+
 }  // namespace eamg
 
 using namespace eamg;
@@ -820,6 +843,8 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     h->n0 = n;
     h->prm = prm;
     PhaseTimer tm;
+    std::vector<std::pair<std::string, double>> phases;
+    tm.sink = &phases;
     AuxLevel aux;
     std::string err;
     if (!finest_aux(dim, n, pb->coords, pb->row_ptr, pb->col_idx, pb->vals, pb->edges, pb->n_edges,
@@ -999,6 +1024,14 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     tm.mark("setup: colouring (wait)");
     for (size_t l = h->lv.size(); l-- > 0;) build_level_layout(h.get(), l, s);
     tm.mark("setup: solve layout");
+    if (prm.dense_tail_dofs > 0) {
+      for (size_t l = 1; l + 1 < h->lv.size(); ++l)
+        if (int64_t(h->lv[l].n) * h->lv[l].bs <= prm.dense_tail_dofs) {
+          build_dense_tail(h.get(), l, s);
+          break;
+        }
+      tm.mark("setup: dense tail");
+    }
     const int64_t N0 = int64_t(n) * dim;
     h->x = ar.alloc<double>(size_t(N0));
     h->r = ar.alloc<double>(size_t(N0));
@@ -1018,6 +1051,15 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&h->scal_h), sizeof(double) * SC_COUNT, 0),
               "hipHostMalloc");
     hip_check(hipStreamSynchronize(s), "sync");
+    tm.mark("setup: solve vectors");
+    for (const auto &ph : phases) {
+      auto it = std::find_if(h->setup_phases.begin(), h->setup_phases.end(),
+                             [&](const std::pair<std::string, double> &q) { return q.first == ph.first; });
+      if (it == h->setup_phases.end())
+        h->setup_phases.push_back(ph);
+      else
+        it->second += ph.second;
+    }
     *out = h.release();
   });
 }
@@ -1079,6 +1121,7 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
     // single right-hand side: lanes per row of each level's sweeps (FP64 kernels; the FP32 ones
     // share the choice)
     for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
+      if (h->tail_level >= 0 && int(l) >= h->tail_level) break;   // applied as the dense tail
       Level &L = h->lv[l];
       const int64_t nv = int64_t(L.n) * L.bs;
       double *b = l == 0 ? h->r : L.b, *x = l == 0 ? h->z : L.x;
@@ -1408,6 +1451,11 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
     double v = f32 ? 24.0 * double(h->lv[0].n) * h->lv[0].bs : 0.0;
     for (size_t l = 0; l < h->lv.size(); ++l) {
       const Level &L = h->lv[l];
+      if (int(l) == h->tail_level) {
+        const double s = f32 ? 4.0 : 8.0;
+        v += double(h->nT) * h->nT * s + 2.0 * h->nT * s;
+        break;
+      }
       if (l + 1 == h->lv.size()) {
         v += double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * (f32 ? 4.0 : 8.0);
         break;
@@ -1426,6 +1474,53 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
     const double it = launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0;
     if (vcycle_bytes) *vcycle_bytes = v;
     if (iteration_bytes) *iteration_bytes = it + v;
+  });
+}
+
+eamg_status eamg_solve_coefficients(const eamg_hierarchy *h, int32_t max_entries, double *alpha,
+                                    double *beta, int32_t *n_out) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (max_entries < 0) fail(EAMG_ERR_INVALID_ARG, "max_entries < 0");
+    const int n = int(h->cg_alpha.size());
+    const int m = std::min(n, max_entries);
+    for (int k = 0; k < m; ++k) {
+      if (alpha) alpha[k] = h->cg_alpha[size_t(k)];
+      if (beta) beta[k] = h->cg_beta[size_t(k)];
+    }
+    if (n_out) *n_out = n;
+  });
+}
+
+eamg_status eamg_setup_phases(const eamg_hierarchy *h, int32_t max_entries, eamg_setup_phase *out,
+                              int32_t *n_out) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (max_entries < 0) fail(EAMG_ERR_INVALID_ARG, "max_entries < 0");
+    // where each phase runs: 0 host, 1 device, 2 host-to-device copies
+    auto where = [](const std::string &name) {
+      if (name.find("upload") != std::string::npos) return 2;
+      for (const char *d : {"Dirichlet", "numeric", "coarsest factor", "dense tail", "solve vectors"})
+        if (name.find(d) != std::string::npos) return 1;
+      return 0;
+    };
+    const int n = int(h->setup_phases.size());
+    for (int k = 0; k < std::min(n, max_entries); ++k) {
+      const auto &ph = h->setup_phases[size_t(k)];
+      std::string nm = ph.first.rfind("setup: ", 0) == 0 ? ph.first.substr(7) : ph.first;
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", nm.c_str());
+      out[k].seconds = ph.second;
+      out[k].where = where(nm);
+    }
+    if (n_out) *n_out = n;
+  });
+}
+
+eamg_status eamg_dense_tail(const eamg_hierarchy *h, int32_t *level, int32_t *dofs) {
+  return guarded([&] {
+    if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    if (level) *level = h->tail_level;
+    if (dofs) *dofs = h->tail_level >= 0 ? h->nT : 0;
   });
 }
 

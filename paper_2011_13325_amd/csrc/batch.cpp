@@ -68,7 +68,8 @@ BatchWork *ensure_work(eamg_hierarchy *h, int K, bool f32) {
     const int nparts = std::max(pdot_blocks(N), pspmv_blocks(L0.Am, K));
     w->part = w->arena.alloc<double>(size_t(nparts) * K);
     w->scal = w->arena.alloc<double>(size_t(PS_COUNT) * K);
-    w->dense = w->arena.alloc<double>(std::max<size_t>(1, dense_panel_work_doubles(h->nL, K)));
+    w->dense = w->arena.alloc<double>(std::max<size_t>(
+        1, std::max(dense_panel_work_doubles(h->nL, K), dense_panel_work_doubles(h->nT, K))));
     hip_check(hipHostMalloc(reinterpret_cast<void **>(&w->scal_h), sizeof(double) * PS_COUNT * K,
                             hipHostMallocDefault),
               "hipHostMalloc");
@@ -109,6 +110,12 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   const std::string ty = type_name<T>();
   const double vs = sizeof(T);
   Level &L = h->lv[l];
+  if (int(l) == h->tail_level) {
+    const double by = double(h->nT) * h->nT * 8.0 + 2.0 * h->nT * K * vs;
+    timed(h, "dense tail", lvname(h, l, "k_dense_panel_mfma<" + ty + ">"), by, s,
+          [&] { return launch_dense_panel<T>(h->nT, h->ldT, K, h->tail, b, x, w->dense, s); });
+    return;
+  }
   if (l + 1 == h->lv.size()) {
     const double by = double(h->nL) * h->nL * 8.0 + 2.0 * h->nL * K * vs;
     timed(h, "coarsest", lvname(h, l, "k_dense_panel_mfma<" + ty + ">"), by, s,
@@ -358,11 +365,59 @@ double time_ms(hipStream_t s, int reps, F &&f) {
 // kernels): per level, the sweep + upper-residual sequence and each transfer with one or four
 // wavefronts per row; the faster is kept in SoaMat::panel_waves.  Returns the summed time of the
 // tuned kernels before / after (ms).
+void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
+  if (t == 0 || t + 1 >= h->lv.size()) fail(EAMG_ERR_INVALID_ARG, "dense tail must start above the coarsest level, below the finest");
+  const Level &Lt = h->lv[t];
+  const int n = Lt.n * Lt.bs;
+  if (n > kMaxCoarsestDofs) fail(EAMG_ERR_INVALID_ARG, "dense tail too large");
+  // a workspace of 64-column panels for levels t .. coarsest only (the batched solve's own is
+  // sized for level 0)
+  constexpr int K = 64;
+  BatchWork w;
+  w.K = K;
+  w.dense = w.arena.alloc<double>(std::max<size_t>(1, dense_panel_work_doubles(h->nL, K)));
+  const size_t nl = h->lv.size();
+  w.vx[0].assign(nl, nullptr);
+  w.vb[0].assign(nl, nullptr);
+  w.vr[0].assign(nl, nullptr);
+  for (size_t l = t; l < nl; ++l) {
+    const size_t nd = size_t(level_dofs(h->lv[l])) * K;
+    w.vx[0][l] = w.arena.alloc<double>(nd);
+    w.vb[0][l] = w.arena.alloc<double>(nd);
+    if (l + 1 < nl) w.vr[0][l] = w.arena.alloc<double>(nd);
+  }
+  w.have[0] = true;
+  const int ld = dense_ld(n);
+  double *T = h->arena.alloc<double>(size_t(ld) * ld);
+  hip_check(launch_fill(int64_t(ld) * ld, 0.0, T, s), "fill");
+  double *B = vp<double>(w.vb[0][t]), *X = vp<double>(w.vx[0][t]);
+  const bool prof = h->prof_on;
+  h->prof_on = false;
+  for (int j0 = 0; j0 < n; j0 += K) {
+    hip_check(launch_identity_panel(n, K, j0, B, s), "identity panel");
+    pvcycle_t<double>(h, &w, t, B, X, s);
+    hip_check(launch_scatter_panel(n, K, j0, std::min(K, n - j0), X, ld, T, s), "scatter panel");
+  }
+  h->prof_on = prof;
+  h->tail = T;
+  h->nT = n;
+  h->ldT = ld;
+  if (h->prm.vcycle_fp32) {
+    const int ld32 = dense_ld32(n);
+    h->tail32 = h->arena.alloc<float>(size_t(ld32) * ld32);
+    h->ldT32 = ld32;
+    hip_check(launch_dense_to_f32(n, ld, T, ld32, h->tail32, s), "tail to f32");
+  }
+  hip_check(hipStreamSynchronize(s), "sync");
+  h->tail_level = int(t);
+}
+
 std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s) {
   BatchWork *w = ensure_work(h, K, false);
   const int reps = 5;
   double before = 0.0, after = 0.0;
   for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
+    if (h->tail_level >= 0 && int(l) >= h->tail_level) break;   // applied as the dense tail
     Level &L = h->lv[l];
     double *b = l == 0 ? w->r : vp<double>(w->vb[0][l]);
     double *x = l == 0 ? w->z : vp<double>(w->vx[0][l]);

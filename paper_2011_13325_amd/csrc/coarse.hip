@@ -220,6 +220,80 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemv(int n, int ld, const do
   if (lane == 0) y[row] = T(acc);
 }
 
+// y = D x with an FP32 matrix (leading dimension ld, a multiple of 256) and FP32 vectors: one
+// wavefront per row; lane l reads columns 256 c + 4 l .. 256 c + 4 l + 3 of the row and of x
+// (one 16-byte load each) for every chunk c, four chunks in flight; FP64 accumulation; the
+// padding columns of D are zero and x is read as zero past n.
+__global__ __launch_bounds__(kThreads) void k_dense_gemv32(int n, int ld, const float *__restrict__ D,
+                                                          const float *__restrict__ x,
+                                                          float *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64;
+  if (row >= n) return;   // whole wavefronts
+  const float4 *Dr = reinterpret_cast<const float4 *>(D + size_t(row) * ld);
+  const int nc = ld / 256;
+  const int nfull = n / 4;   // float4 groups of x entirely inside [0, n)
+  double acc0 = 0.0, acc1 = 0.0;
+  auto xload = [&](int g) {   // x[4 g .. 4 g + 3]
+    if (g < nfull) return reinterpret_cast<const float4 *>(x)[g];
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int j = 4 * g;
+    if (j < n) v.x = x[j];
+    if (j + 1 < n) v.y = x[j + 1];
+    if (j + 2 < n) v.z = x[j + 2];
+    return v;
+  };
+  auto add = [&](const float4 d, const float4 v) {
+    acc0 = fma(double(d.x), double(v.x), acc0);
+    acc1 = fma(double(d.y), double(v.y), acc1);
+    acc0 = fma(double(d.z), double(v.z), acc0);
+    acc1 = fma(double(d.w), double(v.w), acc1);
+  };
+  int c = 0;
+  for (; c + 4 <= nc; c += 4) {
+    float4 d[4], v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      d[u] = Dr[(c + u) * 64 + lane];
+      v[u] = xload((c + u) * 64 + lane);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(d[u], v[u]);
+  }
+  for (; c < nc; ++c) add(Dr[c * 64 + lane], xload(c * 64 + lane));
+  double acc = acc0 + acc1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) y[row] = float(acc);
+}
+
+// Panel of K columns (entry (dof, k) at dof * K + k) holding columns j0 .. j0 + K - 1 of the
+// n x n identity (zero where j0 + k >= n).
+__global__ void k_identity_panel(int n, int K, int j0, double *__restrict__ B) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * K) return;
+  const int d = int(t / K), k = int(t % K);
+  B[t] = (d == j0 + k) ? 1.0 : 0.0;
+}
+
+// Columns j0 .. j0 + ncols - 1 of the row-major matrix D (leading dimension ld, first n rows)
+// := the first ncols columns of the panel X (n x K).
+__global__ void k_scatter_panel(int n, int K, int j0, int ncols, const double *__restrict__ X, int ld,
+                                double *__restrict__ D) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * ncols) return;
+  const int d = int(t / ncols), k = int(t % ncols);
+  D[size_t(d) * ld + j0 + k] = X[size_t(d) * K + k];
+}
+
+// D32 (ld32 x ld32, zero padded) := D (ld x ld, first n rows and columns) rounded to FP32.
+__global__ void k_dense_to_f32(int n, int ld, const double *__restrict__ D, int ld32, float *__restrict__ D32) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(ld32) * ld32) return;
+  const int i = int(t / ld32), j = int(t % ld32);
+  D32[t] = (i < n && j < n) ? float(D[size_t(i) * ld + j]) : 0.0f;
+}
+
 // Y = D X for a panel of K columns on the matrix cores (v_mfma_f64_16x16x4): a dense FP64
 // contraction, n x n by n x K.  One wavefront per 16-row tile of D and slice of the inner
 // dimension (the slices give the chip enough wavefronts).  The inner indices go in blocks of 16:
@@ -330,6 +404,37 @@ hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, h
   if (n == 0) return hipSuccess;
   if (ld < n || ld % 128 != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_dense_gemv<T>, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, s, n, ld, D, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_gemv32(int n, int ld, const float *D, const float *x, float *y, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ld < n || ld % 256 != 0 || (reinterpret_cast<uintptr_t>(x) & 15) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dense_gemv32, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, s, n, ld, D, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s) {
+  const int64_t nk = int64_t(n) * K;
+  if (nk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_identity_panel, dim3(cdiv(nk, kThreads)), dim3(kThreads), 0, s, n, K, j0, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_panel(int n, int K, int j0, int ncols, const double *X, int ld, double *D,
+                                hipStream_t s) {
+  if (ncols < 1 || ncols > K || j0 + ncols > ld) return hipErrorInvalidValue;
+  const int64_t nk = int64_t(n) * ncols;
+  if (nk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_panel, dim3(cdiv(nk, kThreads)), dim3(kThreads), 0, s, n, K, j0, ncols,
+                     X, ld, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_to_f32(int n, int ld, const double *D, int ld32, float *D32, hipStream_t s) {
+  if (ld32 % 256 != 0 || ld32 < n) return hipErrorInvalidValue;
+  const int64_t nn = int64_t(ld32) * ld32;
+  hipLaunchKernelGGL(k_dense_to_f32, dim3(cdiv(nn, kThreads)), dim3(kThreads), 0, s, n, ld, D, ld32, D32);
   return hipGetLastError();
 }
 

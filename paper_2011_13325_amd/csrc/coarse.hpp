@@ -47,6 +47,24 @@ hipError_t launch_gj_invert(int ld, double *A, double *work, int *flag, hipStrea
 template <class T>
 hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, hipStream_t s);
 
+// y = D x with an FP32 matrix D (leading dimension ld, a multiple of 256, zero padding) and FP32
+// vectors (x 16-byte aligned); FP64 accumulation.
+hipError_t launch_dense_gemv32(int n, int ld, const float *D, const float *x, float *y, hipStream_t s);
+
+inline int dense_ld32(int n) { return (n + 255) / 256 * 256; }
+
+// B (n x K panel, entry (dof, k) at dof * K + k) := columns j0 .. j0 + K - 1 of the identity.
+hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s);
+
+// Columns j0 .. j0 + ncols - 1 (ncols <= K) of the row-major D (leading dimension ld) := the
+// first ncols columns of the n x K panel X.
+hipError_t launch_scatter_panel(int n, int K, int j0, int ncols, const double *X, int ld, double *D,
+                                hipStream_t s);
+
+// D32 (ld32 x ld32, ld32 a multiple of 256) := the leading n x n block of D rounded to FP32,
+// zero elsewhere.
+hipError_t launch_dense_to_f32(int n, int ld, const double *D, int ld32, float *D32, hipStream_t s);
+
 // Y = D X for a panel of K columns (K a power of two in [1, 64]; entry (dof, k) at dof * K + k),
 // on the matrix cores in FP64, summed over dense_panel_splits(n) slices of the inner dimension
 // through `work` (device, dense_panel_work_doubles(n, K) doubles); deterministic.

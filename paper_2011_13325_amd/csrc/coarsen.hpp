@@ -55,11 +55,15 @@ void parallel_for(int64_t n, F &&f) {
 struct PhaseTimer {
   bool on;
   std::chrono::steady_clock::time_point t0;
+  // when set, every phase's (name, seconds) is appended here
+  std::vector<std::pair<std::string, double>> *sink = nullptr;
   PhaseTimer() : on(std::getenv("EAMG_VERBOSE") != nullptr), t0(std::chrono::steady_clock::now()) {}
   void mark(const char *what) {
-    if (!on) return;
+    if (!on && !sink) return;
     const auto t1 = std::chrono::steady_clock::now();
-    std::fprintf(stderr, "[eamg] %-28s %8.3f s\n", what, std::chrono::duration<double>(t1 - t0).count());
+    const double dt = std::chrono::duration<double>(t1 - t0).count();
+    if (sink) sink->emplace_back(what, dt);
+    if (on) std::fprintf(stderr, "[eamg] %-28s %8.3f s\n", what, dt);
     t0 = t1;
   }
 };

@@ -193,6 +193,9 @@ struct BatchWork;
 void destroy_batch(BatchWork *w);
 // Panel launch shapes tuned on the hierarchy for K columns; (time before, after) in ms.
 std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
+// The V-cycle on levels t .. coarsest as a dense matrix (h->tail, h->tail32), from the batched
+// V-cycle applied to the columns of the identity; sets h->tail_level = t.
+void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s);
 
 }  // namespace eamg
 
@@ -204,6 +207,12 @@ struct eamg_hierarchy {
   double *Ainv = nullptr;
   int nL = 0;                 // coarsest dofs
   int ldL = 0;                // leading dimension of Ainv (nL rounded up to 128)
+  // dense V-cycle tail: the V-cycle on levels tail_level .. coarsest as one dense matrix in the
+  // colour-major numbering of tail_level (row-major, zero padding), or tail_level = -1
+  int tail_level = -1;
+  int nT = 0, ldT = 0, ldT32 = 0;
+  double *tail = nullptr;
+  float *tail32 = nullptr;    // FP32 copy (with vcycle_fp32)
   uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;
@@ -222,6 +231,10 @@ struct eamg_hierarchy {
   bool graph_tried[2] = {false, false};
   // block-panel (multi right-hand side) workspace, allocated by the first batched call
   eamg::BatchWork *batch = nullptr;
+  // wall time of each setup phase (summed over levels), in the order phases first ran
+  std::vector<std::pair<std::string, double>> setup_phases;
+  // CG coefficients alpha_k, beta_k of the last single-vector solve (beta_1 = 0)
+  std::vector<double> cg_alpha, cg_beta;
   // coarsening: criteria evaluations of the matching walks, candidates passed over by the
   // learned walk, and (when asked for) every pass's candidate pairs with features and labels
   int64_t crit_evaluated = 0, crit_evaluated_g = 0, crit_skipped = 0;

@@ -466,3 +466,106 @@ def test_every_row_team_shape_keeps_parity(group):
     print(f"\n[group {group}] V-cycle {err:.2e} (FP32 kernels {err32:.2e}), x at k* {xerr:.2e}", flush=True)
     assert err <= X_TOL and xerr <= X_TOL and err32 <= F32_VC_TOL
     hl.close()
+
+
+# --- dense V-cycle tail ----------------------------------------------------------------------
+# With dense_tail_dofs the V-cycle from the first qualifying level down is applied as one dense
+# matrix, computed at setup by the batched V-cycle on the identity.  The hierarchy is unchanged
+# and the V-cycle is the same linear map, so every FP64 parity bar of the sparse path holds.
+
+def _tail_lib(p, dofs, **prm):
+    return E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                       E.eamg_default_setup_params(dense_tail_dofs=dofs, vcycle_fp32=1, **prm))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("where", ["first", "deepest"])
+def test_dense_tail_parity(name, where):
+    p = make_problem(**CASES[name])
+    ho = _oracle_cached(name, p)
+    if ho.n_levels < 3:
+        pytest.skip("needs a level between the finest and the coarsest")
+    dofs = [lv.n * lv.bs for lv in ho.levels]
+    # "first": tail from level 1; "deepest": from the level just above the coarsest
+    t = 1 if where == "first" else ho.n_levels - 2
+    thr = dofs[t] if where == "deepest" else max(dofs[1:])
+    if any(d <= thr for d in dofs[1:t]) or thr > 16384:
+        pytest.skip("no threshold selects this level")
+    hl = _tail_lib(p, thr)
+    try:
+        lvl, nT = E.eamg_dense_tail(hl.h)
+        assert lvl == t and nT == dofs[t], (lvl, nT, t)
+        assert hl.stats()["n_levels"] == ho.n_levels
+        r = np.random.default_rng(3).standard_normal(p.n_dofs)
+        r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+        zo = oracle.vcycle(ho, r)
+        for prec, tol in ((E.EAMG_PRECOND_VCYCLE, X_TOL), (E.EAMG_PRECOND_VCYCLE_FP32, 1e-5)):
+            z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+            E.eamg_vcycle(hl.h, _dev(r), z, prec)
+            torch.cuda.synchronize()
+            err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
+            print(f"[tail {name} L{t} prec={prec}] V-cycle rel err {err:.2e}", flush=True)
+            assert err <= tol
+        xo, it, _, _, conv = oracle.pcg(ho, p.b, rtol=1e-8)
+        b = _dev(p.b)
+        x, info = hl.solve(b, rtol=1e-8)
+        assert info["status"] == E.EAMG_OK and info["rel_res_true"] <= 1e-8
+        xk, _ = hl.solve(b, rtol=0.0, max_it=it)
+        assert np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo) <= X_TOL
+        x32, i32 = hl.solve(b, rtol=1e-8, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+        assert i32["status"] == E.EAMG_OK and i32["rel_res_true"] <= 1e-8
+        # batched panels use the same tail (FP64 panel product on the matrix cores)
+        B = np.stack([np.random.default_rng([4, c]).uniform(-1, 1, p.n_dofs) for c in range(5)])
+        B[:, np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+        X, st, infos = hl.solve_batch(_dev(B), rtol=0.0, max_it=3)
+        for c in range(5):
+            xc, *_ = oracle.pcg(ho, B[c], rtol=0.0, max_it=3)
+            assert np.linalg.norm(X[c].cpu().numpy() - xc) / np.linalg.norm(xc) <= X_TOL
+    finally:
+        hl.close()
+
+
+def test_dense_tail_off_below_coarsest_and_rejected_sizes():
+    p = make_problem(9)
+    # a threshold only the coarsest level meets: no tail
+    ho = _oracle_cached("cube9", p)
+    hl = _tail_lib(p, ho.levels[-1].n * ho.levels[-1].bs)
+    assert E.eamg_dense_tail(hl.h) == (-1, 0)
+    hl.close()
+    with pytest.raises(E.EamgError) as ei:
+        _tail_lib(p, 20000)
+    assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+
+
+def test_cg_coefficients_match_the_oracle():
+    # alpha_k and beta_k of the library's PCG against a plain CG recurrence with the oracle's
+    # V-cycle (section "res"), over the oracle's iteration count
+    name = "cube17"
+    p = make_problem(**CASES[name])
+    ho = _oracle_cached(name, p)
+    hl = _lib(p)
+    try:
+        x, info = hl.solve(_dev(p.b), rtol=1e-8)
+        al, be = E.eamg_solve_coefficients(hl.h)
+        assert len(al) == info["iterations"] and be[0] == 0.0
+        A = sp.bsr_matrix((p.vals, p.col_idx, p.row_ptr), shape=(p.n_dofs,) * 2).tocsr()
+        dm = np.repeat(p.dirichlet.astype(bool), 3)
+        Dm = sp.diags((~dm).astype(float))
+        Ab = (Dm @ A @ Dm + sp.diags(dm.astype(float))).tocsr()
+        r = p.b.copy()
+        z = oracle.vcycle(ho, r)
+        pv, rz = z.copy(), r @ z
+        ao, bo = [], [0.0]
+        for k in range(len(al)):
+            q = Ab @ pv
+            a = rz / (pv @ q)
+            ao.append(a)
+            r = r - a * q
+            z = oracle.vcycle(ho, r)
+            rzn = r @ z
+            bo.append(rzn / rz)
+            pv, rz = z + (rzn / rz) * pv, rzn
+        assert np.allclose(al, ao, rtol=1e-8, atol=0)
+        assert np.allclose(be, bo[:len(al)], rtol=1e-8, atol=0)
+    finally:
+        hl.close()
