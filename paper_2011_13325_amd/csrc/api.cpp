@@ -325,6 +325,10 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
       std::vector<int> mark(size_t(L.n), -1);
       if (t == 2 * int64_t(nc)) {
         L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, 0);
+        L.upper_blocks.assign(size_t(nc), 0.0);
+        for (int c = 0; c < nc; ++c)
+          for (int i = L.color_ptr[c]; i < L.color_ptr[c + 1]; ++i)
+            L.upper_blocks[size_t(c)] += double(Ap.rp[i + 1] - dg[i] - 1);
         return;
       }
       const int c = int(t / 2), part = int(t % 2);
@@ -423,6 +427,22 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
   if (bad) fail(EAMG_ERR_NOT_SPD, "coarsest level matrix is not positive definite");
 }
 
+// r -= (blocks right of the diagonal) x on every row of level L: one launch, or one per colour
+// range of L.resid_cut, each with its own lanes per row.
+template <class T>
+hipError_t resid_update(const Level &L, const T *x, T *r, hipStream_t s) {
+  const SoaMat M = L.resid_mat();
+  if (L.resid_cut.empty()) return launch_resid_upper<T>(M, 0, L.n, x, r, s);
+  for (size_t k = 0; k + 1 < L.resid_cut.size(); ++k) {
+    SoaMat m = M;
+    if (k < L.g_resid.size() && L.g_resid[k]) m.group = L.g_resid[k];
+    const hipError_t e = launch_resid_upper<T>(m, L.color_ptr[size_t(L.resid_cut[k])],
+                                               L.color_ptr[size_t(L.resid_cut[k + 1])], x, r, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <class T>
 void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   Level &L = h->lv[l];
@@ -462,14 +482,16 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   // per launch would add their own dispatch to every launch)
   timed_n(h, "gs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
     for (int c = 0; c < L.ncolors; ++c) {
-      const hipError_t e = launch_gs_fwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
+      const hipError_t e = launch_gs_fwd<T>(L.fwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
-  timed(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
-        launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), s,
-        [&] { return launch_resid_upper<T>(L.resid_mat(), x, B.r, s); });
+  const int nres = L.resid_cut.empty() ? 1 : int(L.resid_cut.size()) - 1;
+  timed_n(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
+          launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), nres, s, [&] {
+            return resid_update<T>(L, x, B.r, s);
+          });
   Level &C = h->lv[l + 1];
   const LevelBufs<T> CB = bufs<T>(C);
   timed(h, "restrict", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(L.kc) + ", " + std::to_string(bs) + ">"),
@@ -479,7 +501,7 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1), s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
   timed_n(h, "gs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
-      const hipError_t e = launch_gs_bwd<T>(L.Am, B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+      const hipError_t e = launch_gs_bwd<T>(L.bwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1118,6 +1140,39 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       std::sort(t.begin(), t.end());
       return double(t[t.size() / 2]);
     };
+    // median time of each of the nparts launches of run_all(mark), which calls mark(k) right
+    // after enqueueing part k
+    std::vector<hipEvent_t> pev;
+    auto part_times = [&](int nparts, auto &&run_all) {
+      while (int(pev.size()) < nparts + 1) {
+        hipEvent_t e;
+        hip_check(hipEventCreate(&e), "event");
+        pev.push_back(e);
+      }
+      std::vector<std::vector<float>> t(static_cast<size_t>(nparts));
+      for (int r = 0; r < 3; ++r) {
+        hip_check(hipEventRecord(pev[0], s), "event");
+        run_all([&](int k) { hip_check(hipEventRecord(pev[size_t(k) + 1], s), "event"); });
+        hip_check(hipEventSynchronize(pev[size_t(nparts)]), "sync");
+        for (int k = 0; k < nparts; ++k) {
+          float ms = 0.0f;
+          hip_check(hipEventElapsedTime(&ms, pev[size_t(k)], pev[size_t(k) + 1]), "event");
+          t[size_t(k)].push_back(ms);
+        }
+      }
+      std::vector<double> med(static_cast<size_t>(nparts));
+      for (int k = 0; k < nparts; ++k) {
+        std::sort(t[size_t(k)].begin(), t[size_t(k)].end());
+        med[size_t(k)] = t[size_t(k)][1];
+      }
+      return med;
+    };
+    struct EventPool {
+      std::vector<hipEvent_t> &ev;
+      ~EventPool() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+      }
+    } pev_guard{pev};
     // single right-hand side: lanes per row of each level's sweeps (FP64 kernels; the FP32 ones
     // share the choice)
     for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
@@ -1128,13 +1183,17 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       for (double *v : {b, x, L.r}) hip_check(launch_fill(nv, 0.0, v, s), "fill");
       auto fwd_part = [&] {
         for (int c = 0; c < L.ncolors; ++c)
-          hip_check(launch_gs_fwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
+          hip_check(launch_gs_fwd<double>(L.fwd_mat(c), L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
       };
-      auto resid_part = [&] { hip_check(launch_resid_upper<double>(L.resid_mat(), x, L.r, s), "resid"); };
+      auto resid_part = [&] { hip_check(resid_update<double>(L, x, L.r, s), "resid"); };
       auto bwd_part = [&] {
         for (int c = L.ncolors - 1; c >= 0; --c)
-          hip_check(launch_gs_bwd<double>(L.Am, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
+          hip_check(launch_gs_bwd<double>(L.bwd_mat(c), L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
       };
+      L.g_fwd.clear();
+      L.g_bwd.clear();
+      L.resid_cut.clear();
+      L.g_resid.clear();
       // EAMG_FORCE_GROUP = 8, 16, 32, 64, 128 or 256 sets every level's lanes per row without
       // timing (tests use it to run each row-team shape)
       if (const char *fg = std::getenv("EAMG_FORCE_GROUP")) {
@@ -1176,6 +1235,63 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       L.Am.group = gf;
       L.Am.group_bwd = gb == gf ? 0 : gb;
       L.group_resid = gr == gf ? 0 : gr;
+      // then per colour (the sweeps) and per range of colours (the residual update): each part
+      // is timed inside whole sweeps, so its matrix streams from memory as in a V-cycle; a
+      // refinement is kept only if the whole part gets faster
+      const int nc = L.ncolors;
+      auto refine = [&](std::vector<int> &choice, int nparts, auto &&run_all, double level_best) {
+        std::vector<std::vector<double>> t(static_cast<size_t>(nparts));
+        for (int g : cand) {
+          choice.assign(size_t(nparts), g);
+          const std::vector<double> tg = part_times(nparts, run_all);
+          for (int k = 0; k < nparts; ++k) t[size_t(k)].push_back(tg[size_t(k)]);
+        }
+        for (int k = 0; k < nparts; ++k) {
+          const auto &tk = t[size_t(k)];
+          choice[size_t(k)] = cand[std::min_element(tk.begin(), tk.end()) - tk.begin()];
+        }
+        const double tsum = time_ms([&] { run_all([](int) {}); });
+        if (tsum >= level_best) choice.clear();
+        return choice.empty() ? level_best : tsum;
+      };
+      bf = refine(L.g_fwd, nc, [&](auto &&mark) {
+        for (int c = 0; c < nc; ++c) {
+          hip_check(launch_gs_fwd<double>(L.fwd_mat(c), L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, L.r, s), "gs");
+          mark(c);
+        }
+      }, bf);
+      bb = refine(L.g_bwd, nc, [&](auto &&mark) {
+        for (int c = nc - 1; c >= 0; --c) {
+          hip_check(launch_gs_bwd<double>(L.bwd_mat(c), L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s), "gs");
+          mark(nc - 1 - c);
+        }
+      }, bb);
+      // residual update in up to four launches over colour ranges of about equal upper blocks
+      {
+        std::vector<int> cut{0};
+        double tot = 0.0, acc = 0.0;
+        for (double u : L.upper_blocks) tot += u;
+        for (int c = 0; c < nc; ++c) {
+          acc += L.upper_blocks[size_t(c)];
+          if (c + 1 < nc && acc >= tot * double(cut.size()) / 4.0) cut.push_back(c + 1);
+        }
+        cut.push_back(nc);
+        if (cut.size() > 2) {
+          L.resid_cut = cut;
+          const int nr = int(cut.size()) - 1;
+          br = refine(L.g_resid, nr, [&](auto &&mark) {
+            for (int k = 0; k < nr; ++k) {
+              SoaMat m = L.resid_mat();
+              if (size_t(k) < L.g_resid.size() && L.g_resid[size_t(k)]) m.group = L.g_resid[size_t(k)];
+              hip_check(launch_resid_upper<double>(m, L.color_ptr[size_t(cut[size_t(k)])],
+                                                   L.color_ptr[size_t(cut[size_t(k) + 1])], x, L.r, s),
+                        "resid");
+              mark(k);
+            }
+          }, br);
+          if (L.g_resid.empty()) L.resid_cut.clear();
+        }
+      }
       before += f0 + r0 + b0;
       after += bf + br + bb;
     }

@@ -137,6 +137,25 @@ struct Level {
     if (group_resid) m.group = group_resid;
     return m;
   }
+  // per colour: lanes per row of the forward / backward sweep, 0 (or empty) for the level's
+  // choice; the first row of a colour's lower blocks grows from none (colour 0) to a whole row
+  // (the last colour), so one choice per level fits neither end
+  std::vector<int> g_fwd, g_bwd;
+  SoaMat fwd_mat(int c) const {
+    SoaMat m = Am;
+    if (size_t(c) < g_fwd.size() && g_fwd[size_t(c)]) m.group = g_fwd[size_t(c)];
+    return m;
+  }
+  SoaMat bwd_mat(int c) const {
+    SoaMat m = Am;
+    if (size_t(c) < g_bwd.size() && g_bwd[size_t(c)]) m.group_bwd = g_bwd[size_t(c)];
+    return m;
+  }
+  // the residual update as launches over consecutive colour ranges [resid_cut[k],
+  // resid_cut[k+1]) with lanes per row g_resid[k] (0: resid_mat()'s); empty: one launch
+  std::vector<int> resid_cut, g_resid;
+  // blocks right of the diagonal in each colour's rows (to split the residual update)
+  std::vector<double> upper_blocks;
   // panel kernels: wavefronts per row of the residual update and of the backward sweep, or 0 for
   // Am.panel_waves (the forward sweep's)
   int pw_resid = 0, pw_bwd = 0;

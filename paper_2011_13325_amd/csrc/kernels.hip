@@ -536,15 +536,15 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, cons
 }
 
 template <class T, int B, int W>
-__global__ __launch_bounds__(kBlock) void k_resid_upper(int n_rows, int G, const int *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) void k_resid_upper(int r0, int r1, int G, const int *__restrict__ rp,
                                                        const int *__restrict__ col,
                                                        const int *__restrict__ diag,
                                                        const T *__restrict__ val, int64_t nnz,
                                                        const T *x, T *r) {
   __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-  resid_row<T, B, W>(row, row < n_rows, lane, G, rp, col, diag, val, nnz, x, r, sh);
+  const int row = r0 + int(blockIdx.x) * (kBlock / G) + int(threadIdx.x) / G;
+  resid_row<T, B, W>(row, row < r1, lane, G, rp, col, diag, val, nnz, x, r, sh);
 }
 
 template <class T, int BR, int BC>
@@ -818,16 +818,17 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
 }
 
 template <class T>
-hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s) {
-  if (A.n_rows == 0) return hipSuccess;
+hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r, hipStream_t s) {
+  if (r0 < 0 || r1 > A.n_rows) return hipErrorInvalidValue;
+  if (r1 <= r0) return hipSuccess;
   const T *val = soa_vals<T>(A);
   if (!val) return hipErrorInvalidValue;
   const int G = A.group;
-  const dim3 grid(cdiv64(A.n_rows, groups_for(G)));
+  const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, A.n_rows, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -871,8 +872,8 @@ template hipError_t launch_gs_fwd<double>(const SoaMat &, const double *, int, i
 template hipError_t launch_gs_fwd<float>(const SoaMat &, const float *, int, int, const float *, float *, float *, hipStream_t);
 template hipError_t launch_gs_bwd<double>(const SoaMat &, const double *, int, int, const double *, double *, hipStream_t);
 template hipError_t launch_gs_bwd<float>(const SoaMat &, const float *, int, int, const float *, float *, hipStream_t);
-template hipError_t launch_resid_upper<double>(const SoaMat &, const double *, double *, hipStream_t);
-template hipError_t launch_resid_upper<float>(const SoaMat &, const float *, float *, hipStream_t);
+template hipError_t launch_resid_upper<double>(const SoaMat &, int, int, const double *, double *, hipStream_t);
+template hipError_t launch_resid_upper<float>(const SoaMat &, int, int, const float *, float *, hipStream_t);
 template hipError_t launch_rect<double>(const SoaMat &, const double *, double *, bool, hipStream_t);
 template hipError_t launch_rect<float>(const SoaMat &, const float *, float *, bool, hipStream_t);
 template hipError_t launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);

@@ -93,9 +93,9 @@ int spmv_blocks(const SoaMat &A);
 template <class T>
 hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
                          hipStream_t s);
-// r_i -= sum_{j > i} A_ij x_j on all rows (completes r = b - A x after the forward sweep).
+// r_i -= sum_{j > i} A_ij x_j on rows [r0, r1) (completes r = b - A x after the forward sweep).
 template <class T>
-hipError_t launch_resid_upper(const SoaMat &A, const T *x, T *r, hipStream_t s);
+hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r, hipStream_t s);
 // Backward colour sweep on rows [r0, r1): x_i += Dinv_i (b_i - sum_j A_ij x_j).
 template <class T>
 hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
