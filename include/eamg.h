@@ -324,6 +324,24 @@ eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const doub
 eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, int32_t precision,
                         void *stream);
 
+/*
+ * eamg_vcycle without allocating or synchronizing, for callers that cannot call hipMalloc or
+ * wait on the stream: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same operation, arguments and errors as eamg_vcycle (z = B^{-1} r, DEVICE
+ * arrays of n*dim doubles in level-0 natural order, Dirichlet dofs of r treated as 0), but
+ *  - the colour-major copies of r and z are staged in a fixed device array of the library
+ *    (32 MiB per device, held until the process ends) instead of the hierarchy's buffers: a
+ *    level 0 of more than 2,097,152 dofs gives EAMG_ERR_INVALID_ARG;
+ *  - the work is only enqueued on `stream`; the call returns without waiting, so z is valid
+ *    once the stream has reached that point;
+ *  - the profiler must be off (EAMG_ERR_INVALID_ARG otherwise) and the current device must be
+ *    the one the hierarchy was set up on.
+ * Every call on one GPU shares that staging array, and every call on one hierarchy its level
+ * vectors: calls that overlap in time on one GPU (other streams, other threads) race.
+ */
+eamg_status eamg_vcycle_noalloc(eamg_hierarchy *h, const double *r_dev, double *z_dev,
+                                int32_t precision, void *stream);
+
 /* Hierarchy statistics (HOST outputs, any may be NULL).  per_level_n / per_level_nnzb must hold
  * max_levels entries.  vc = sum n_l / n_0, oc = sum nnz_l / nnz_0 counting scalar entries. */
 eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,

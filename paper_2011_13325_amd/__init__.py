@@ -40,7 +40,8 @@ EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setu
             "eamg_profile_enable", "eamg_profile_read", "eamg_solve_batch", "eamg_solve_multi",
             "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
             "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy", "eamg_coarsening_stats",
-            "eamg_gnn_samples", "eamg_dense_tail", "eamg_solve_coefficients", "eamg_setup_phases"]
+            "eamg_gnn_samples", "eamg_dense_tail", "eamg_solve_coefficients", "eamg_setup_phases",
+            "eamg_vcycle_noalloc"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -137,6 +138,8 @@ def lib():
     L.eamg_solve_multi.restype = ctypes.c_int
     L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.eamg_vcycle.restype = ctypes.c_int
+    L.eamg_vcycle_noalloc.argtypes = [vp, vp, vp, i32, vp]
+    L.eamg_vcycle_noalloc.restype = ctypes.c_int
     L.eamg_stats.argtypes = [vp, P(i32), vp, vp, P(dp), P(dp)]
     L.eamg_stats.restype = ctypes.c_int
     L.eamg_level_info_get.argtypes = [vp, i32, P(eamg_level_info)]
@@ -411,6 +414,13 @@ def eamg_vcycle(h, r, z, precision=EAMG_PRECOND_VCYCLE, stream=None):
     st = lib().eamg_vcycle(h, _dptr(r), _dptr(z), int(precision), _stream(stream))
     if st != EAMG_OK:
         raise EamgError(st, "eamg_vcycle")
+
+
+def eamg_vcycle_noalloc(h, r, z, precision=EAMG_PRECOND_VCYCLE, stream=None):
+    """z = V(r) without allocation or synchronization (r, z: float64 device tensors)."""
+    st = lib().eamg_vcycle_noalloc(h, _dptr(r), _dptr(z), int(precision), _stream(stream))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_vcycle_noalloc")
 
 
 def eamg_stats(h):

@@ -15,7 +15,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp",
                 "staging.cpp"]
-HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip"]
+HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip", "noalloc.hip"]
 # the criteria must round like the host code (no fused multiply-add)
 FILE_FLAGS = {"criteria.hip": ["-ffp-contract=off"]}
 

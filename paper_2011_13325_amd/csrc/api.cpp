@@ -827,6 +827,14 @@ struct MultiStreams {
 
 }  // namespace
 
+void vcycle_staged(eamg_hierarchy *h, const double *r_dev, double *z_dev, bool f32, double *rp,
+                   double *zp, hipStream_t s) {
+  const Level &L0 = h->lv[0];
+  hip_check(launch_perm_in(L0.n, L0.bs, L0.perm_d, h->dir, r_dev, rp, s), "perm_in");
+  vcycle(h, rp, zp, f32, s);
+  hip_check(launch_perm_out(L0.n, L0.bs, L0.perm_d, zp, z_dev, s), "perm_out");
+}
+
 }  // namespace eamg
 
 using namespace eamg;
@@ -859,6 +867,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     validate_params(prm);
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::unique_ptr<eamg_hierarchy> h(new eamg_hierarchy());
+    hip_check(hipGetDevice(&h->device), "hipGetDevice");
     const int n = pb->n_vertices, dim = pb->dim;
     h->dim = dim;
     h->k = pb->k_kernel;

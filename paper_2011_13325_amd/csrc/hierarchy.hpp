@@ -212,6 +212,11 @@ struct BatchWork;
 void destroy_batch(BatchWork *w);
 // Panel launch shapes tuned on the hierarchy for K columns; (time before, after) in ms.
 std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
+// z = V(r) for level-0 vectors in the natural numbering (eamg_vcycle's operation), with the
+// colour-major copies of r and z in the caller's device buffers rp and zp (n0 * dim doubles
+// each): launches on s only -- no allocation, no synchronization; the profiler must be off.
+void vcycle_staged(eamg_hierarchy *h, const double *r_dev, double *z_dev, bool f32, double *rp,
+                   double *zp, hipStream_t s);
 // The V-cycle on levels t .. coarsest as a dense matrix (h->tail, h->tail32), from the batched
 // V-cycle applied to the columns of the identity; sets h->tail_level = t.
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s);
@@ -220,6 +225,7 @@ void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s);
 
 struct eamg_hierarchy {
   int dim = 0, k = 0, n0 = 0;
+  int device = 0;             // the HIP device the hierarchy was set up on
   eamg_setup_params prm{};
   std::vector<eamg::Level> lv;
   eamg::DevArena arena;
