@@ -197,7 +197,13 @@ void eamg_default_solve_params(eamg_solve_params *out);
 
 /*
  * Build the hierarchy (host coarsening; device P_s assembly, Galerkin products, smoother
- * diagonals and coarsest factor).  On success *out owns all device memory of the hierarchy.
+ * diagonals and coarsest factor).  Paper: the system of section "fem" (Problems prob:gg /
+ * prob:epseps on V_h0) with the auxiliary topology of section "deng" (finest edge and vertex
+ * weights); per level the successive matching of Algorithm alg:pwagg with the criteria of
+ * section "crs" and the coarse weights of Thm thm:cemats, the auxiliary smoothed prolongation
+ * P_s of Def. def:aux_sp, A_{l+1} = P_s^T A_l P_s (section "prol"), and the pseudo-inverted
+ * smoother diagonals and regularized coarsest level of section "amg".  On success *out owns
+ * all device memory of the hierarchy.
  * Errors: INVALID_ARG (NULL pointers, sizes, unsorted/asymmetric pattern, missing diagonal,
  * parameters out of range), UNSUPPORTED_KERNEL, NOT_SPD (coarsest level), HIP, OOM.
  */
@@ -205,8 +211,10 @@ eamg_status eamg_setup(const eamg_problem *problem, const eamg_setup_params *par
                        void *stream, eamg_hierarchy **out);
 
 /*
- * Solve A x = b by PCG.  b_dev, x_dev: DEVICE arrays of n*dim doubles, caller-owned, may not
- * alias.  b is ignored at Dirichlet dofs; x is 0 there on return.  Returns OK, NOT_CONVERGED
+ * Solve A x = b by PCG, preconditioned by one V-cycle per iteration: CG with the AMG V-cycle
+ * as in section "res", the V-cycle being Alg. alg:tg (smoother M before, M^T after the coarse
+ * correction) applied recursively down the levels.  b_dev, x_dev: DEVICE arrays of n*dim
+ * doubles, caller-owned, may not alias.  b is ignored at Dirichlet dofs; x is 0 there on return.  Returns OK, NOT_CONVERGED
  * (x = last iterate), BREAKDOWN (non-finite b or residual, or a non-positive curvature /
  * preconditioned inner product), INVALID_ARG or HIP.  info may be NULL.
  */
@@ -343,7 +351,9 @@ eamg_status eamg_vcycle_noalloc(eamg_hierarchy *h, const double *r_dev, double *
                                 int32_t precision, void *stream);
 
 /* Hierarchy statistics (HOST outputs, any may be NULL).  per_level_n / per_level_nnzb must hold
- * max_levels entries.  vc = sum n_l / n_0, oc = sum nnz_l / nnz_0 counting scalar entries. */
+ * max_levels entries.  vc and oc are the vertex and operator complexities of the tables of
+ * section "res" (Tables tab:ucu, tab:3dbeam, tab:co3d): vc = sum n_l / n_0, oc = sum nnz_l /
+ * nnz_0 counting scalar entries. */
 eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_level_n,
                        int64_t *per_level_nnzb, double *vc, double *oc);
 
@@ -351,7 +361,8 @@ eamg_status eamg_level_info_get(const eamg_hierarchy *h, int32_t level, eamg_lev
 
 /*
  * Copy one level to HOST buffers in the level's natural vertex numbering (coarse vertex I is
- * the I-th agglomerate of the matching).  Any pointer may be NULL to skip it.  Sizes from
+ * the I-th agglomerate of the matching): the agglomerates of Algorithm alg:pwagg, P_s of
+ * Def. def:aux_sp, A_l = P_s^T A_{l-1} P_s (section "prol") and the smoother's colours.  Any pointer may be NULL to skip it.  Sizes from
  * eamg_level_info_get:
  *   agg      n       coarse vertex of each vertex, -1 for the dropped set D (coarsest: all -1)
  *   P_rowptr n+1, P_col nnzb_P, P_val nnzb_P*bs*k_coarse (row-major blocks)

@@ -78,9 +78,13 @@ inline double trace(const Mat &X) {
 }
 
 // Symmetric eigen-decomposition for larger matrices: Householder reduction to tridiagonal form
-// (accumulating the reflections), then the implicit QL iteration with Wilkinson shifts on the
-// tridiagonal matrix (Golub & Van Loan sections 8.3.1 and 8.3.3).  w ascending, V columns are
-// the eigenvectors.
+// (accumulating the reflections; Golub & Van Loan section 8.3.1), then the implicit QL
+// iteration with shifts from the leading 2 x 2 block on the tridiagonal matrix, in the form of
+// procedure tql2 of Bowdler, Martin, Reinsch and Wilkinson, "The QR and QL algorithms for
+// symmetric matrices", Numer. Math. 11 (1968) 293-306 (Handbook for Automatic Computation
+// vol. II, contribution II/3; the EISPACK routine TQL2): the sweep over the rotations, its
+// variables and the premature-deflation exit follow that procedure.  w ascending, V columns
+// are the eigenvectors.
 inline void eigh_tridiag_ql(const Mat &Ain, std::vector<double> &w, Mat &V, bool vectors = true) {
   const int n = Ain.r;
   Mat A = Ain;
