@@ -514,6 +514,8 @@ def main():
             out["learned_coarsening"] = _learned(E, torch, args, stream)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(E, torch, args, stream)
+    E.close_all()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -7,8 +7,10 @@ built (``python -m paper_2011_13325_amd.build``) or loading fails loudly.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -295,6 +297,23 @@ GNN_FEATURES = 12
 GNN_PARAMS = 9153
 
 
+# Owning wrappers still open.  They are closed at interpreter exit by an atexit hook, which runs
+# before the C-level exit handlers (the HIP runtime's and a profiler tool's): freeing device
+# objects from __del__ during the interpreter's final collection could otherwise reach a
+# runtime or tool that has already shut down.
+_OPEN = weakref.WeakSet()
+
+
+@atexit.register
+def close_all():
+    """Close every Hierarchy and EdgeNet that is still open."""
+    for obj in list(_OPEN):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 class EdgeNet:
     """The edge-scoring network (eamg_gnn_*): parameters on the device, host arrays in/out."""
 
@@ -309,6 +328,7 @@ class EdgeNet:
         if st != EAMG_OK:
             raise EamgError(st, "eamg_gnn_create")
         self.h = h
+        _OPEN.add(self)
 
     @staticmethod
     def _graph(X, edges):
@@ -576,7 +596,9 @@ class Hierarchy:
                  stream=None, **kw):
         self.dim = dim
         self.n_dofs = np.asarray(coords).shape[0] * dim
+        self.h = None
         self.h = eamg_setup(dim, coords, row_ptr, col_idx, vals, dirichlet, params, stream, **kw)
+        _OPEN.add(self)
 
     def solve(self, b, x=None, **kw):
         import torch

@@ -17,3 +17,12 @@ def pytest_configure(config):
 def cube5():
     from gen import make_problem
     return make_problem(5)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _close_library_objects():
+    """Close every Hierarchy / EdgeNet a test left open when the session ends (before the
+    interpreter shuts down), instead of leaving them to garbage collection at exit."""
+    yield
+    import paper_2011_13325_amd as E
+    E.close_all()
