@@ -419,7 +419,8 @@ eamg_status eamg_dense_tail(const eamg_hierarchy *h, int32_t *level, int32_t *do
  * by kernel name (the template instance, e.g. "k_gs_color<double, 6, false>"), sorts them by
  * total time, copies up to max_entries of them into out, stores the number of kernels in
  * *n_out and clears the records.  on: 0 off, 1 per kernel, 2 per kernel and level (V-cycle
- * names prefixed "L<level> ").  Enabling resets the records.
+ * names prefixed "L<level> "), 3 as 2 with every colour launch of the single-vector sweeps
+ * timed on its own (names "L<level> c<colour> ...").  Enabling resets the records.
  */
 typedef struct {
   char name[48];

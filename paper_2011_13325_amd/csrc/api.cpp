@@ -312,6 +312,46 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   std::vector<int> dg;
   const bool f32 = h->prm.vcycle_fp32 != 0;
   L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
+  if (!coarsest) {
+    // the blocks left of the diagonal, right of it, and the diagonal blocks, each stored on its
+    // own for the forward sweep and the residual update (SoaMat)
+    Pattern Plo, Pup, Pd;
+    std::vector<int64_t> slo, sup, sd;
+    for (Pattern *P : {&Plo, &Pup, &Pd}) {
+      P->n_rows = P->n_cols = L.n;
+      P->rp.assign(size_t(L.n) + 1, 0);
+    }
+    for (int i = 0; i < L.n; ++i) {
+      for (int64_t q = Ap.rp[i]; q < dg[i]; ++q) {
+        Plo.col.push_back(Ap.col[q]);
+        slo.push_back(src[q]);
+      }
+      for (int64_t q = dg[i] + 1; q < Ap.rp[i + 1]; ++q) {
+        Pup.col.push_back(Ap.col[q]);
+        sup.push_back(src[q]);
+      }
+      Pd.col.push_back(i);
+      sd.push_back(src[size_t(dg[i])]);
+      Plo.rp[i + 1] = int64_t(Plo.col.size());
+      Pup.rp[i + 1] = int64_t(Pup.col.size());
+      Pd.rp[i + 1] = i + 1;
+    }
+    const SoaMat lo = make_soa(ar, Plo, slo, bs, bs, L.A_val, s, nullptr, false, f32);
+    const SoaMat up = make_soa(ar, Pup, sup, bs, bs, L.A_val, s, nullptr, false, f32);
+    const SoaMat dm = make_soa(ar, Pd, sd, bs, bs, L.A_val, s, nullptr, false, f32);
+    L.Am.lo_rp = lo.rp;
+    L.Am.lo_col = lo.col;
+    L.Am.lo_val = lo.val;
+    L.Am.lo_val32 = lo.val32;
+    L.Am.lo_nnz = lo.nnz;
+    L.Am.up_rp = up.rp;
+    L.Am.up_col = up.col;
+    L.Am.up_val = up.val;
+    L.Am.up_val32 = up.val32;
+    L.Am.up_nnz = up.nnz;
+    L.Am.dg_val = dm.val;
+    L.Am.dg_val32 = dm.val32;
+  }
   tl.mark("layout: A planes");
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
@@ -480,13 +520,21 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   const std::string gs = "k_gs_color<" + ty + ", " + std::to_string(bs);
   // the colours of a sweep are back-to-back launches of one kernel: one profiler record (events
   // per launch would add their own dispatch to every launch)
-  timed_n(h, "gs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
-    for (int c = 0; c < L.ncolors; ++c) {
-      const hipError_t e = launch_gs_fwd<T>(L.fwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  });
+  if (h->prof_colours) {
+    for (int c = 0; c < L.ncolors; ++c)
+      timed(h, "gs_fwd", lvname(h, l, "c" + std::to_string(c) + " " + gs + ", true>"),
+            launch_bytes(L.sh_fwd[c], LK_GS_FWD, bs, bs, vs, 1), s, [&] {
+              return launch_gs_fwd<T>(L.fwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
+            });
+  } else {
+    timed_n(h, "gs_fwd", lvname(h, l, gs + ", true>"), fwd_bytes, L.ncolors, s, [&] {
+      for (int c = 0; c < L.ncolors; ++c) {
+        const hipError_t e = launch_gs_fwd<T>(L.fwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, B.r, s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    });
+  }
   const int nres = L.resid_cut.empty() ? 1 : int(L.resid_cut.size()) - 1;
   timed_n(h, "resid_upper", lvname(h, l, "k_resid_upper<" + ty + ", " + std::to_string(bs) + ">"),
           launch_bytes(L.sh_resid, LK_RESID, bs, bs, vs, 1), nres, s, [&] {
@@ -499,6 +547,14 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   vcycle_t<T>(h, l + 1, CB.b, CB.x, s);
   timed(h, "prolong", lvname(h, l, "k_rect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, 1), s, [&] { return launch_rect<T>(L.Pm, CB.x, x, true, s); });
+  if (h->prof_colours) {
+    for (int c = L.ncolors - 1; c >= 0; --c)
+      timed(h, "gs_bwd", lvname(h, l, "c" + std::to_string(c) + " " + gs + ", false>"),
+            launch_bytes(L.sh_bwd[c], LK_GS_BWD, bs, bs, vs, 1), s, [&] {
+              return launch_gs_bwd<T>(L.bwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
+            });
+    return;
+  }
   timed_n(h, "gs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
       const hipError_t e = launch_gs_bwd<T>(L.bwd_mat(c), B.Dinv, L.color_ptr[c], L.color_ptr[c + 1], b, x, s);
@@ -1653,7 +1709,8 @@ eamg_status eamg_profile_enable(eamg_hierarchy *h, int32_t on) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
     h->prof_on = on != 0;
-    h->prof_levels = on == 2;
+    h->prof_levels = on >= 2;
+    h->prof_colours = on == 3;
     h->prof.clear();
     h->ev_used = 0;
   });

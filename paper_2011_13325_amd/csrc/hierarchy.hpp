@@ -246,6 +246,7 @@ struct eamg_hierarchy {
   // profiler: events around every launch while enabled
   bool prof_on = false;
   bool prof_levels = false;   // V-cycle records per level
+  bool prof_colours = false;  // ... and per colour launch of the single-vector sweeps
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<eamg::ProfRec> prof;

@@ -430,23 +430,23 @@ __device__ inline T pick(const T (&v)[B], int i) {
 }
 
 // One row of a multicolour block Gauss-Seidel sweep, computed by the G lanes of a row group.
-// FWD: x = 0 before the sweep, so only the blocks left of the diagonal (lower colours) are read;
-// also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row.
+// FWD: x = 0 before the sweep, so only the blocks left of the diagonal (lower colours) are read
+// (rp, col, val: the lower part) and A_ii comes from the diagonal planes dval (nd = rows);
+// also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row
+// (rp, col, val: the full matrix).
 // Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
 // together with the row's blocks, so a row costs one round of row loads plus the x gathers;
 // a butterfly all-reduce leaves the row sum on every lane.
 template <class T, int B, bool FWD, int W>
 __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
-                              const int *__restrict__ col, const int *__restrict__ diag,
-                              const T *__restrict__ val, int64_t nnz, const T *__restrict__ Dinv,
+                              const int *__restrict__ col, const T *__restrict__ val, int64_t nnz,
+                              const T *__restrict__ dval, int64_t nd, const T *__restrict__ Dinv,
                               const T *__restrict__ b, T *x, T *r, T *sh) {
   const bool own = valid && lane < B;
   int p0 = 0, p1 = 0;
-  int64_t dp = 0;
   if (valid) {
     p0 = rp[row];
-    dp = diag[row];
-    p1 = FWD ? int(dp) : rp[row + 1];
+    p1 = rp[row + 1];
   }
   T bq = T(0), Dq[B], Aq[B];
 #pragma unroll
@@ -459,7 +459,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 #pragma unroll
     for (int c = 0; c < B; ++c) {
       Dq[c] = Dinv[int64_t(row) * B * B + lane * B + c];
-      if (FWD) Aq[c] = val[int64_t(lane * B + c) * nnz + dp];
+      if (FWD) Aq[c] = dval[int64_t(lane * B + c) * nd + row];
     }
   }
   T acc[B];
@@ -496,15 +496,15 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
   }
 }
 
-// r_i -= sum_{j > i} A_ij x_j for one row.
+// r_i -= sum_{j > i} A_ij x_j for one row (rp, col, val: the blocks right of the diagonal).
 template <class T, int B, int W>
 __device__ inline void resid_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
-                                 const int *__restrict__ col, const int *__restrict__ diag,
-                                 const T *__restrict__ val, int64_t nnz, const T *x, T *r, T *sh) {
+                                 const int *__restrict__ col, const T *__restrict__ val,
+                                 int64_t nnz, const T *x, T *r, T *sh) {
   T rq = T(0);
   int p0 = 0, p1 = 0;
   if (valid) {
-    p0 = diag[row] + 1;
+    p0 = rp[row];
     p1 = rp[row + 1];
     if (lane < B) rq = r[int64_t(row) * B + lane];
   }
@@ -525,26 +525,25 @@ __device__ inline void resid_row(int row, bool valid, int lane, int G, const int
 template <class T, int B, bool FWD, int W>
 __global__ __launch_bounds__(kBlock) void k_gs_color(int r0, int r1, int G, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
-                                                    const int *__restrict__ diag,
                                                     const T *__restrict__ val, int64_t nnz,
+                                                    const T *__restrict__ dval, int64_t nd,
                                                     const T *__restrict__ Dinv,
                                                     const T *__restrict__ b, T *x, T *r) {
   __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = r0 + xcd_block() * (kBlock / G) + threadIdx.x / G;
-  gs_row<T, B, FWD, W>(row, row < r1, lane, G, rp, col, diag, val, nnz, Dinv, b, x, r, sh);
+  gs_row<T, B, FWD, W>(row, row < r1, lane, G, rp, col, val, nnz, dval, nd, Dinv, b, x, r, sh);
 }
 
 template <class T, int B, int W>
 __global__ __launch_bounds__(kBlock) void k_resid_upper(int r0, int r1, int G, const int *__restrict__ rp,
                                                        const int *__restrict__ col,
-                                                       const int *__restrict__ diag,
                                                        const T *__restrict__ val, int64_t nnz,
                                                        const T *x, T *r) {
   __shared__ T sh[W > 1 ? (kBlock / 64) * B : 1];
   const int lane = threadIdx.x & (G - 1);
   const int row = r0 + int(blockIdx.x) * (kBlock / G) + int(threadIdx.x) / G;
-  resid_row<T, B, W>(row, row < r1, lane, G, rp, col, diag, val, nnz, x, r, sh);
+  resid_row<T, B, W>(row, row < r1, lane, G, rp, col, val, nnz, x, r, sh);
 }
 
 template <class T, int BR, int BC>
@@ -786,14 +785,16 @@ template <class T>
 hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
                          hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
-  const T *val = soa_vals<T>(A);
-  if (!val) return hipErrorInvalidValue;
+  const T *lo = sizeof(T) == 4 ? reinterpret_cast<const T *>(A.lo_val32) : reinterpret_cast<const T *>(A.lo_val);
+  const T *dg = sizeof(T) == 4 ? reinterpret_cast<const T *>(A.dg_val32) : reinterpret_cast<const T *>(A.dg_val);
+  if (!lo || !dg || !A.lo_rp || r0 < 0 || r1 > A.n_rows) return hipErrorInvalidValue;
   const int G = A.group;
   const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
+  const int64_t nd = A.n_rows;
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, r)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.lo_rp, A.lo_col, lo, A.lo_nnz, dg, nd, Dinv, b, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.lo_rp, A.lo_col, lo, A.lo_nnz, dg, nd, Dinv, b, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, true, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.lo_rp, A.lo_col, lo, A.lo_nnz, dg, nd, Dinv, b, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -808,10 +809,11 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
   const int G = A.group_bwd ? A.group_bwd : A.group;
   const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
   T *none = nullptr;
+  const T *none_c = nullptr;
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, Dinv, b, x, none)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 1, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, val, A.nnz, none_c, int64_t(0), Dinv, b, x, none)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 3, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, val, A.nnz, none_c, int64_t(0), Dinv, b, x, none)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_gs_color<T, 6, false, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, val, A.nnz, none_c, int64_t(0), Dinv, b, x, none)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();
@@ -821,14 +823,14 @@ template <class T>
 hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r, hipStream_t s) {
   if (r0 < 0 || r1 > A.n_rows) return hipErrorInvalidValue;
   if (r1 <= r0) return hipSuccess;
-  const T *val = soa_vals<T>(A);
-  if (!val) return hipErrorInvalidValue;
+  const T *up = sizeof(T) == 4 ? reinterpret_cast<const T *>(A.up_val32) : reinterpret_cast<const T *>(A.up_val);
+  if (!up || !A.up_rp) return hipErrorInvalidValue;
   const int G = A.group;
   const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
   switch (A.br) {
-    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
-    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.rp, A.col, A.diag, val, A.nnz, x, r)); break;
+    case 1: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 1, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.up_rp, A.up_col, up, A.up_nnz, x, r)); break;
+    case 3: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 3, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.up_rp, A.up_col, up, A.up_nnz, x, r)); break;
+    case 6: EAMG_GS_W(W_, hipLaunchKernelGGL((k_resid_upper<T, 6, W_>), grid, dim3(kBlock), 0, s, r0, r1, G, A.up_rp, A.up_col, up, A.up_nnz, x, r)); break;
     default: return hipErrorInvalidValue;
   }
   EAMG_LAUNCH_CHECK();

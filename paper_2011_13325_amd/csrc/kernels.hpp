@@ -80,6 +80,21 @@ struct SoaMat {
   const double *val = nullptr;
   const float *val32 = nullptr;  // FP32 copy of val (FP32 V-cycle), or nullptr
   const int *diag = nullptr; // square matrices only
+  // Square colour-major level matrices also hold the blocks left of the diagonal, the blocks
+  // right of it and the diagonal blocks each in storage of their own (row offsets, columns,
+  // element planes; the diagonal blocks in planes indexed by row), so that the forward sweep
+  // and the residual update, which read one side of every row, stream contiguous planes instead
+  // of touching partly used cache lines at both ends of every row segment.
+  const int *lo_rp = nullptr, *lo_col = nullptr;
+  const double *lo_val = nullptr;
+  const float *lo_val32 = nullptr;
+  int64_t lo_nnz = 0;
+  const int *up_rp = nullptr, *up_col = nullptr;
+  const double *up_val = nullptr;
+  const float *up_val32 = nullptr;
+  int64_t up_nnz = 0;
+  const double *dg_val = nullptr;   // nnz = n_rows
+  const float *dg_val32 = nullptr;
 };
 
 // y = A x ; if part != nullptr also writes per-workgroup partial sums of x.y (spmv_blocks(A)
