@@ -7,7 +7,8 @@ symmetric multicolour block Gauss-Seidel sweep pre / post; the V-cycle in FP32 (
 vectors and accumulation) inside an FP64 CG (operator, vectors, inner products, stopping test)
 to ||r|| <= 1e-8 ||b||.  The V-cycle below the first level of at most 16384 dofs is applied as
 its dense matrix (computed at setup from the same hierarchy; the coarsest level is still the
-< 500-dof one).
+< 500-dof one).  P_s rows keep at most 3 edge-matrix columns and 6 / 4 real-matrix columns
+(level 0 / coarser; free parameters, the paper's runs use 4 and 8 / 6).
 
 A step is one PCG solve to 1e-8, with b resident in HBM when the timed region starts.  Setup
 (host coarsening + device P_s / Galerkin / D^+ / coarsest inverse / dense tail) is timed
@@ -15,6 +16,7 @@ separately, with its phases split into host, device and copies.  Reported beside
 in the same line:
   fp64_vcycle        the same solve with the FP64 V-cycle, and the FP32 solution's distance to it
   sparse_tail        the same hierarchy with every level's sweeps run sparse (no dense tail)
+  paper_caps         the same solve with the paper's P_s row caps
   cube64             64^3, nu = 0.3, RHS seed 1, FP64 and FP32 V-cycle; its 32 seeded load
                      cases as one block-panel solve ("batched")
   multi_mesh         16 cubes of 8^3..48^3 vertices, nu uniform in [0.2, 0.45], solved together
@@ -45,6 +47,8 @@ def _args():
                     help="coarsening stops once a level has fewer dofs than this")
     ap.add_argument("--dense-tail", type=int, default=16384,
                     help="dofs of the largest level whose V-cycle is applied as a dense matrix (0: none)")
+    ap.add_argument("--caps", default="6,4,3",
+                    help="P_s row caps: real-matrix rows on level 0, on coarser levels, edge-matrix rows")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline solve (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -60,8 +64,14 @@ def _args():
     return ap.parse_args()
 
 
+def _caps(args):
+    l0, std, aux = (int(v) for v in args.caps.split(","))
+    return dict(cap_std_l0=l0, cap_std=std, cap_aux=aux)
+
+
 def _params(E, args, **kw):
-    prm = dict(vcycle_fp32=1, coarsest_max_dofs=args.coarsest, dense_tail_dofs=args.dense_tail)
+    prm = dict(vcycle_fp32=1, coarsest_max_dofs=args.coarsest, dense_tail_dofs=args.dense_tail,
+               **_caps(args))
     prm.update(kw)
     return E.eamg_default_setup_params(**prm)
 
@@ -470,7 +480,9 @@ def main():
         "config": {"workload": f"elasticity cube {args.n}^3 vertices ({p.n_dofs} dofs; Kuhn P1, "
                                f"E=1, nu={args.nu}, clamped x=0, RHS seed {args.seed}), FP32 "
                                f"V-cycle in FP64 CG to 1e-8, coarsening to < {args.coarsest} "
-                               f"dofs, dense V-cycle tail <= {args.dense_tail} dofs",
+                               f"dofs, dense V-cycle tail <= {args.dense_tail} dofs, P_s row caps "
+                               f"{args.caps}",
+                   "p_s_caps": _caps(args),
                    "precision": "V-cycle FP32 (matrices, vectors, accumulation; dense tail FP32 "
                                 "with FP64 sums); CG FP64",
                    "coarsest_max_dofs": args.coarsest, "dense_tail": {"level": tail[0], "dofs": tail[1]},
@@ -507,6 +519,18 @@ def main():
                                   "iterations": info2["iterations"], "setup_s": su2["setup_s"],
                                   "dense_tail_speedup": ms2 / ms}
             h2.close()
+        # the paper's P_s row caps (4 for edge-matrix rows, 8 / 6 for real-matrix rows)
+        paper = dict(cap_std_l0=8, cap_std=6, cap_aux=4)
+        if paper != _caps(args):
+            h3, su3 = _setup(E, torch, p, _params(E, args, **paper), stream)
+            E.eamg_autotune(h3.h, panel_width=0, stream=stream)
+            ms3, info3 = _timed_solves(E, torch, h3, b, torch.zeros_like(b), stream, args.steps,
+                                       args.warmup, P32)
+            out["paper_caps"] = {"p_s_caps": paper, "ms_per_step": ms3,
+                                 "value": p.n_free_dofs / (ms3 / 1e3),
+                                 "iterations": info3["iterations"], "oc": round(h3.stats()["oc"], 4),
+                                 "setup_s": su3["setup_s"], "tuned_caps_speedup": ms3 / ms}
+            h3.close()
         out["cube64"] = _cube64(E, torch, args, stream)
         if args.multi > 0:
             out["multi_mesh"] = _multi_mesh(E, torch, args, count=args.multi)

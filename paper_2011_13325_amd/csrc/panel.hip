@@ -168,11 +168,13 @@ struct PRed {
 // One colour of the symmetric block Gauss-Seidel sweep for K columns (see launch_pgs_fwd /
 // launch_pgs_bwd).  The row's D^+ block and right-hand side are loaded before the row's blocks
 // so their latency overlaps the block stream; the lead lanes finish the row.
+// FWD: rp, col, val hold the blocks left of the diagonal and dval the diagonal blocks (planes
+// indexed by row, nd rows); BWD: rp, col, val hold whole rows.
 template <class T, int B, bool FWD, int C, int W>
 __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const int *__restrict__ rp,
                                                    const int *__restrict__ col,
-                                                   const int *__restrict__ diag,
                                                    const T *__restrict__ val, int64_t nnz,
+                                                   const T *__restrict__ dval, int64_t nd,
                                                    const T *__restrict__ Dinv,
                                                    const T *__restrict__ b, T *x, T *r) {
   __shared__ T red[PRed<T, B, C, W>::n];
@@ -180,8 +182,7 @@ __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const 
   const int row = r0 + xcd_block() * (kPB / (kWave * W)) + tm.row_in_wg;
   if (row >= r1) return;   // W = 4: the whole workgroup leaves together
   const int p0 = rp[row];
-  const int dp = diag[row];
-  const int p1 = FWD ? dp : rp[row + 1];
+  const int p1 = rp[row + 1];
   PVec<T, C> bq[B];
   T D[B][B];
   const int64_t rb = int64_t(row) * B;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const 
 #pragma unroll
   for (int q = 0; q < B; ++q)
 #pragma unroll
-    for (int c = 0; c < B; ++c) Ad[q][c] = FWD ? val[int64_t(q * B + c) * nnz + dp] : T(0);
+    for (int c = 0; c < B; ++c) Ad[q][c] = FWD ? dval[int64_t(q * B + c) * nd + row] : T(0);
   T xo[B][C];
 #pragma unroll
   for (int i = 0; i < C; ++i) {
@@ -245,10 +246,10 @@ __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const 
   }
 }
 
+// rp, col, val: the blocks right of the diagonal.
 template <class T, int B, int C, int W>
 __global__ __launch_bounds__(kPB) void k_presid_upper(int n_rows, int K, const int *__restrict__ rp,
                                                       const int *__restrict__ col,
-                                                      const int *__restrict__ diag,
                                                       const T *__restrict__ val, int64_t nnz,
                                                       const T *__restrict__ x, T *__restrict__ r) {
   __shared__ T red[PRed<T, B, C, W>::n];
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(kPB) void k_presid_upper(int n_rows, int K, const i
 #pragma unroll
     for (int i = 0; i < C; ++i) acc[q][i] = T(0);
   }
-  pteam_accumulate<T, B, B, C, W>(diag[row] + 1, rp[row + 1], K, tm, col, val, nnz, x, acc, red);
+  pteam_accumulate<T, B, B, C, W>(rp[row], rp[row + 1], K, tm, col, val, nnz, x, acc, red);
   if (!tm.lead()) return;
 #pragma unroll
   for (int q = 0; q < B; ++q) {
@@ -567,12 +568,20 @@ template <class T, bool FWD>
 hipError_t launch_pgs(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x, T *r,
                       hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
-  const T *val = pvals<T>(A);
-  if (!val || !valid_k(K) || !A.diag) return hipErrorInvalidValue;
+  const bool f32 = sizeof(T) == 4;
+  const T *val = FWD ? reinterpret_cast<const T *>(f32 ? (const void *)A.lo_val32 : (const void *)A.lo_val)
+                     : pvals<T>(A);
+  const T *dval = FWD ? reinterpret_cast<const T *>(f32 ? (const void *)A.dg_val32 : (const void *)A.dg_val)
+                      : nullptr;
+  const int *rp = FWD ? A.lo_rp : A.rp;
+  const int *col = FWD ? A.lo_col : A.col;
+  const int64_t nnz = FWD ? A.lo_nnz : A.nnz;
+  const int64_t nd = A.n_rows;
+  if (!val || !rp || !valid_k(K) || (FWD && !dval) || r0 < 0 || r1 > A.n_rows) return hipErrorInvalidValue;
 #define EAMG_PGS(B_)                                                                                \
   EAMG_PTEAM(W, A, EAMG_PCOLS(C, hipLaunchKernelGGL((k_pgs_color<T, B_, FWD, C, W>),               \
                                                     dim3(pteam_grid(r1 - r0, W)), dim3(kPB), 0, s, \
-                                                    r0, r1, K, A.rp, A.col, A.diag, val, A.nnz,    \
+                                                    r0, r1, K, rp, col, val, nnz, dval, nd,        \
                                                     Dinv, b, x, r)))
   switch (A.br) {
     case 1: EAMG_PGS(1); break;
@@ -599,13 +608,13 @@ hipError_t launch_pgs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K,
 template <class T>
 hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
-  const T *val = pvals<T>(A);
-  if (!val || !valid_k(K) || !A.diag) return hipErrorInvalidValue;
+  const T *val = reinterpret_cast<const T *>(sizeof(T) == 4 ? (const void *)A.up_val32 : (const void *)A.up_val);
+  if (!val || !A.up_rp || !valid_k(K)) return hipErrorInvalidValue;
 #define EAMG_PRES(B_)                                                                             \
   EAMG_PTEAM(W, A, EAMG_PCOLS(C, hipLaunchKernelGGL((k_presid_upper<T, B_, C, W>),               \
                                                     dim3(pteam_grid(A.n_rows, W)), dim3(kPB), 0, \
-                                                    s, A.n_rows, K, A.rp, A.col, A.diag, val,    \
-                                                    A.nnz, x, r)))
+                                                    s, A.n_rows, K, A.up_rp, A.up_col, val,      \
+                                                    A.up_nnz, x, r)))
   switch (A.br) {
     case 1: EAMG_PRES(1); break;
     case 3: EAMG_PRES(3); break;

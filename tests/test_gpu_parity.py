@@ -569,3 +569,53 @@ def test_cg_coefficients_match_the_oracle():
         assert np.allclose(be, bo[:len(al)], rtol=1e-8, atol=0)
     finally:
         hl.close()
+
+
+# --- the P_s row caps the bench uses ---------------------------------------------------------
+# The caps of the auxiliary smoothed prolongation are free parameters (the paper's runs use 4
+# for edge-matrix rows and 8 / 6 for real-matrix rows); the bench runs 3 and 6 / 4, which trade
+# a sparser hierarchy for more iterations.  The oracle takes the same caps, so every parity bar
+# holds at that setting too.
+TUNED_CAPS = dict(cap_std_l0=6, cap_std=4, cap_aux=3)
+
+
+@pytest.mark.parametrize("name", ["cube17", "box_ragged"])
+def test_tuned_caps_parity(name):
+    p = make_problem(**CASES[name])
+    ho = _oracle(p, **TUNED_CAPS)
+    hl = _lib(p, **TUNED_CAPS)
+    try:
+        assert hl.stats()["n_levels"] == ho.n_levels
+        worstP = worstA = 0.0
+        for l, lev in enumerate(ho.levels):
+            ex = hl.export(l)
+            assert np.array_equal(ex["A_rowptr"], lev.A.row_ptr)
+            assert np.array_equal(ex["A_col"], lev.A.col)
+            worstA = max(worstA, _block_rel_err(lev.A.row_ptr, ex["A_val"], lev.A.val))
+            if l + 1 < ho.n_levels:
+                assert np.array_equal(ex["agg"], lev.agg_of)
+                assert np.array_equal(ex["color"], lev.colors)
+                assert np.array_equal(ex["P_rowptr"], lev.P.row_ptr)
+                assert np.array_equal(ex["P_col"], lev.P.col)
+                assert np.diff(lev.P.row_ptr).max() <= max(TUNED_CAPS.values())
+                worstP = max(worstP, _block_rel_err(lev.P.row_ptr, ex["P_val"], lev.P.val))
+        assert worstP <= PS_TOL and worstA <= A_TOL
+        r = np.random.default_rng(3).standard_normal(p.n_dofs)
+        r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+        zo = oracle.vcycle(ho, r)
+        z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+        E.eamg_vcycle(hl.h, _dev(r), z)
+        torch.cuda.synchronize()
+        assert np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo) <= X_TOL
+        xo, it, _, rel_true, conv = oracle.pcg(ho, p.b, rtol=1e-8)
+        assert conv and rel_true <= 1e-8
+        b = _dev(p.b)
+        x, info = hl.solve(b, rtol=1e-8)
+        assert info["status"] == E.EAMG_OK and info["rel_res_true"] <= 1e-8
+        xk, _ = hl.solve(b, rtol=0.0, max_it=it)
+        err = np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo)
+        print(f"[caps {name}] levels={ho.n_levels} its={it} P_s {worstP:.1e} A {worstA:.1e} x {err:.1e}",
+              flush=True)
+        assert err <= X_TOL
+    finally:
+        hl.close()

@@ -44,8 +44,19 @@ def _rbm_coarse(coords, d, r, k):
     return np.concatenate([np.concatenate([d + np.cross(x, r), r]) for x in coords])
 
 
-def test_kernel_reproduction_all_levels(neumann):
-    p, h = neumann
+@pytest.fixture(scope="module", params=["paper caps", "caps 6/4/3"])
+def neumann_caps(request, neumann):
+    # the P_s row caps are free parameters: rigid body modes must be reproduced for any of them
+    if request.param == "paper caps":
+        return neumann
+    p = neumann[0]
+    h = H.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                H.SetupParams(cap_std_l0=6, cap_std=4, cap_aux=3), factor_coarsest=False)
+    return p, h
+
+
+def test_kernel_reproduction_all_levels(neumann_caps):
+    p, h = neumann_caps
     rng = np.random.default_rng(1)
     d, r = rng.standard_normal(3), rng.standard_normal(3)
     uf = np.concatenate([d + np.cross(x, r) for x in p.coords])
