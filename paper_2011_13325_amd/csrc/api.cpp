@@ -189,11 +189,12 @@ std::vector<int> to_i32(const std::vector<int64_t> &v) {
   return o;
 }
 
-// Build one solve-phase SoA matrix from natural AoS values with a host permutation map.
-SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br, int bc,
+// Build one solve-phase matrix (blocks in the permuted order) from natural AoS values with a host
+// permutation map.
+SolveMat make_solve_mat(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br, int bc,
                 const double *aos, hipStream_t s, std::vector<int> *diag_out = nullptr,
                 bool transpose_blocks = false, bool fp32 = false) {
-  SoaMat M;
+  SolveMat M;
   M.n_rows = Pp.n_rows;
   M.n_cols = Pp.n_cols;
   M.br = br;
@@ -209,20 +210,13 @@ SoaMat make_soa(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src
   double *v = ar.alloc<double>(size_t(M.nnz) * br * bc);
   float *v32 = fp32 ? ar.alloc<float>(size_t(M.nnz) * br * bc) : nullptr;
   if (transpose_blocks) {
-    // input blocks are bc x br; transpose into a temporary AoS array, then to planes
-    double *tmp = ar.alloc<double>(size_t(M.nnz) * br * bc);
-    hip_check(launch_transpose_blocks(M.nnz, bc, br, src_d, aos, tmp, s), "transpose");
-    std::vector<int64_t> iota(size_t(M.nnz));
-    for (int64_t q = 0; q < M.nnz; ++q) iota[q] = q;
-    int64_t *id = ar.upload(iota, s);
-    hip_check(launch_gather_soa(M.nnz, br * bc, id, tmp, v, s), "gather_soa");
-    if (fp32) hip_check(launch_gather_soa_f32(M.nnz, br * bc, id, tmp, v32, s), "gather_soa_f32");
+    // input blocks are bc x br: gathered and transposed in one pass
+    hip_check(launch_transpose_blocks(M.nnz, bc, br, src_d, aos, v, s), "transpose");
+    if (fp32) hip_check(launch_convert<double, float>(M.nnz * br * bc, v, v32, s), "convert");
     hip_check(hipStreamSynchronize(s), "sync");
-    ar.release(tmp);
-    ar.release(id);
   } else {
-    hip_check(launch_gather_soa(M.nnz, br * bc, src_d, aos, v, s), "gather_soa");
-    if (fp32) hip_check(launch_gather_soa_f32(M.nnz, br * bc, src_d, aos, v32, s), "gather_soa_f32");
+    hip_check(launch_gather_blocks(M.nnz, br * bc, src_d, aos, v, s), "gather_blocks");
+    if (fp32) hip_check(launch_gather_blocks_f32(M.nnz, br * bc, src_d, aos, v32, s), "gather_blocks_f32");
     hip_check(hipStreamSynchronize(s), "sync");
   }
   ar.release(src_d);
@@ -311,10 +305,10 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   tl.mark("layout: permute");
   std::vector<int> dg;
   const bool f32 = h->prm.vcycle_fp32 != 0;
-  L.Am = make_soa(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
+  L.Am = make_solve_mat(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
   if (!coarsest) {
     // the blocks left of the diagonal, right of it, and the diagonal blocks, each stored on its
-    // own for the forward sweep and the residual update (SoaMat)
+    // own for the forward sweep and the residual update (SolveMat)
     Pattern Plo, Pup, Pd;
     std::vector<int64_t> slo, sup, sd;
     for (Pattern *P : {&Plo, &Pup, &Pd}) {
@@ -336,9 +330,9 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
       Pup.rp[i + 1] = int64_t(Pup.col.size());
       Pd.rp[i + 1] = i + 1;
     }
-    const SoaMat lo = make_soa(ar, Plo, slo, bs, bs, L.A_val, s, nullptr, false, f32);
-    const SoaMat up = make_soa(ar, Pup, sup, bs, bs, L.A_val, s, nullptr, false, f32);
-    const SoaMat dm = make_soa(ar, Pd, sd, bs, bs, L.A_val, s, nullptr, false, f32);
+    const SolveMat lo = make_solve_mat(ar, Plo, slo, bs, bs, L.A_val, s, nullptr, false, f32);
+    const SolveMat up = make_solve_mat(ar, Pup, sup, bs, bs, L.A_val, s, nullptr, false, f32);
+    const SolveMat dm = make_solve_mat(ar, Pd, sd, bs, bs, L.A_val, s, nullptr, false, f32);
     L.Am.lo_rp = lo.rp;
     L.Am.lo_col = lo.col;
     L.Am.lo_val = lo.val;
@@ -352,7 +346,7 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
     L.Am.dg_val = dm.val;
     L.Am.dg_val32 = dm.val32;
   }
-  tl.mark("layout: A planes");
+  tl.mark("layout: A blocks");
   L.nnz_lower = 0;
   for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
   L.sh_spmv = matrix_shape(Ap);
@@ -401,12 +395,12 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   const Level &C = h->lv[l + 1];
   std::vector<int64_t> srcP;
   const Pattern Pp = permute_rect(L.P, L.perm, C.inv, srcP);
-  L.Pm = make_soa(ar, Pp, srcP, bs, L.kc, L.P_val, s, nullptr, false, f32);
+  L.Pm = make_solve_mat(ar, Pp, srcP, bs, L.kc, L.P_val, s, nullptr, false, f32);
   std::vector<int64_t> srcT;
   const Pattern Rp = transpose_pattern(Pp, srcT);
   std::vector<int64_t> srcR(srcT.size());
   for (size_t q = 0; q < srcT.size(); ++q) srcR[q] = srcP[size_t(srcT[q])];
-  L.Rm = make_soa(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true, f32);
+  L.Rm = make_solve_mat(ar, Rp, srcR, L.kc, bs, L.P_val, s, nullptr, true, f32);
   L.sh_R = matrix_shape(Rp);
   L.sh_P = matrix_shape(Pp);
   tl.mark("layout: D+ and transfers");
@@ -471,10 +465,10 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
 // range of L.resid_cut, each with its own lanes per row.
 template <class T>
 hipError_t resid_update(const Level &L, const T *x, T *r, hipStream_t s) {
-  const SoaMat M = L.resid_mat();
+  const SolveMat M = L.resid_mat();
   if (L.resid_cut.empty()) return launch_resid_upper<T>(M, 0, L.n, x, r, s);
   for (size_t k = 0; k + 1 < L.resid_cut.size(); ++k) {
-    SoaMat m = M;
+    SolveMat m = M;
     if (k < L.g_resid.size() && L.g_resid[k]) m.group = L.g_resid[k];
     const hipError_t e = launch_resid_upper<T>(m, L.color_ptr[size_t(L.resid_cut[k])],
                                                L.color_ptr[size_t(L.resid_cut[k + 1])], x, r, s);
@@ -583,7 +577,7 @@ void vcycle(eamg_hierarchy *h, const double *r, double *z, bool f32, hipStream_t
 // x += alpha p, r -= alpha q, r.r, and the scalars copied to pinned host memory.
 void enqueue_iteration(eamg_hierarchy *h, bool f32, hipStream_t s) {
   const Level &L0 = h->lv[0];
-  const SoaMat &A = L0.Am;
+  const SolveMat &A = L0.Am;
   const int64_t N = int64_t(L0.n) * L0.bs;
   const int nd = dot_blocks(N);
   const int ns = spmv_blocks(A);
@@ -701,7 +695,7 @@ struct SolveRun {
 
   void enqueue_start_a(const double *b_dev, const double *x_dev) {
     const Level &L0 = h->lv[0];
-    const SoaMat &A = L0.Am;
+    const SolveMat &A = L0.Am;
     h->cg_alpha.clear();
     h->cg_beta.clear();
     hip_check(hipEventRecord(e0, s), "event");
@@ -751,7 +745,7 @@ struct SolveRun {
   // first iteration (p = z already set)
   void enqueue_start_c() {
     const Level &L0 = h->lv[0];
-    const SoaMat &A = L0.Am;
+    const SolveMat &A = L0.Am;
     timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), spmv_bytes(), s,
           [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
     timed(h, "reduce", "k_reduce", 8.0 * ns, s,
@@ -796,7 +790,7 @@ struct SolveRun {
 
   void eager_iteration() {
     const Level &L0 = h->lv[0];
-    const SoaMat &A = L0.Am;
+    const SolveMat &A = L0.Am;
     precondition();
     timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
           [&] { return launch_dot(N, h->r, h->z, h->part, s); });
@@ -1129,7 +1123,7 @@ eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, 
     // partial sums of the dots and of the SpMV's fused p.q: the SpMV launches one workgroup per
     // kBlock / G rows, so size for the widest row team it can be given (G = 64, the most
     // workgroups), whatever the autotuner picks later
-    SoaMat widest = h->lv[0].Am;
+    SolveMat widest = h->lv[0].Am;
     widest.group = 64;
     h->part_cap = std::max(dot_blocks(N0), spmv_blocks(widest));
     h->part = ar.alloc<double>(size_t(h->part_cap));
@@ -1346,7 +1340,7 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
           const int nr = int(cut.size()) - 1;
           br = refine(L.g_resid, nr, [&](auto &&mark) {
             for (int k = 0; k < nr; ++k) {
-              SoaMat m = L.resid_mat();
+              SolveMat m = L.resid_mat();
               if (size_t(k) < L.g_resid.size() && L.g_resid[size_t(k)]) m.group = L.g_resid[size_t(k)];
               hip_check(launch_resid_upper<double>(m, L.color_ptr[size_t(cut[size_t(k)])],
                                                    L.color_ptr[size_t(cut[size_t(k) + 1])], x, L.r, s),

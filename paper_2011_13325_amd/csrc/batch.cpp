@@ -150,7 +150,7 @@ void pvcycle_t(eamg_hierarchy *h, BatchWork *w, size_t l, const T *b, T *x, hipS
   timed(h, "pprolong", lvname(h, l, "k_prect<" + ty + ", " + std::to_string(bs) + ", " + std::to_string(L.kc) + ">"),
         launch_bytes(L.sh_P, LK_RECT_ACC, bs, L.kc, vs, K), s,
         [&] { return launch_prect<T>(L.Pm, K, Cx, x, true, s); });
-  const SoaMat Mb = L.panel_mat(L.pw_bwd);
+  const SolveMat Mb = L.panel_mat(L.pw_bwd);
   timed_n(h, "pgs_bwd", lvname(h, l, gs + ", false>"), bwd_bytes, L.ncolors, s, [&] {
     for (int c = L.ncolors - 1; c >= 0; --c) {
       const hipError_t e = launch_pgs_bwd<T>(Mb, Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s);
@@ -251,7 +251,7 @@ bool solve_panel(eamg_hierarchy *h, int m, const double *B, int64_t ld, double *
   const bool f32 = sp.precond == EAMG_PRECOND_VCYCLE_FP32;
   BatchWork *w = ensure_work(h, K, f32);
   const Level &L0 = h->lv[0];
-  const SoaMat &A = L0.Am;
+  const SolveMat &A = L0.Am;
   const int64_t N = level_dofs(L0) * K;
   const int nd = pdot_blocks(N), ns = pspmv_blocks(A, K);
   struct Events {
@@ -363,7 +363,7 @@ double time_ms(hipStream_t s, int reps, F &&f) {
 
 // Panel launch shapes measured on the hierarchy's own matrices for K columns (FP64 V-cycle
 // kernels): per level, the sweep + upper-residual sequence and each transfer with one or four
-// wavefronts per row; the faster is kept in SoaMat::panel_waves.  Returns the summed time of the
+// wavefronts per row; the faster is kept in SolveMat::panel_waves.  Returns the summed time of the
 // tuned kernels before / after (ms).
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
   if (t == 0 || t + 1 >= h->lv.size()) fail(EAMG_ERR_INVALID_ARG, "dense tail must start above the coarsest level, below the finest");
@@ -437,7 +437,7 @@ std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s) {
       hip_check(launch_presid_upper<double>(L.panel_mat(L.pw_resid), K, x, r, s), "presid");
     };
     auto bwd = [&] {
-      const SoaMat Mb = L.panel_mat(L.pw_bwd);
+      const SolveMat Mb = L.panel_mat(L.pw_bwd);
       for (int c = L.ncolors - 1; c >= 0; --c)
         hip_check(launch_pgs_bwd<double>(Mb, L.Dinv, L.color_ptr[c], L.color_ptr[c + 1], K, b, x, s), "pgs");
     };

@@ -129,11 +129,11 @@ struct Level {
   // colour-major solve layout
   std::vector<int> perm, inv, color_ptr;
   int *perm_d = nullptr;
-  SoaMat Am, Pm, Rm;
+  SolveMat Am, Pm, Rm;
   // lanes per row of the residual update (upper halves of all rows, one launch), or 0 for Am.group
   int group_resid = 0;
-  SoaMat resid_mat() const {
-    SoaMat m = Am;
+  SolveMat resid_mat() const {
+    SolveMat m = Am;
     if (group_resid) m.group = group_resid;
     return m;
   }
@@ -141,13 +141,13 @@ struct Level {
   // choice; the first row of a colour's lower blocks grows from none (colour 0) to a whole row
   // (the last colour), so one choice per level fits neither end
   std::vector<int> g_fwd, g_bwd;
-  SoaMat fwd_mat(int c) const {
-    SoaMat m = Am;
+  SolveMat fwd_mat(int c) const {
+    SolveMat m = Am;
     if (size_t(c) < g_fwd.size() && g_fwd[size_t(c)]) m.group = g_fwd[size_t(c)];
     return m;
   }
-  SoaMat bwd_mat(int c) const {
-    SoaMat m = Am;
+  SolveMat bwd_mat(int c) const {
+    SolveMat m = Am;
     if (size_t(c) < g_bwd.size() && g_bwd[size_t(c)]) m.group_bwd = g_bwd[size_t(c)];
     return m;
   }
@@ -159,8 +159,8 @@ struct Level {
   // panel kernels: wavefronts per row of the residual update and of the backward sweep, or 0 for
   // Am.panel_waves (the forward sweep's)
   int pw_resid = 0, pw_bwd = 0;
-  SoaMat panel_mat(int pw) const {
-    SoaMat m = Am;
+  SolveMat panel_mat(int pw) const {
+    SolveMat m = Am;
     if (pw) m.panel_waves = pw;
     return m;
   }
@@ -170,7 +170,7 @@ struct Level {
   // what every launch streams (for the traffic model and the profiler)
   std::vector<LaunchShape> sh_fwd, sh_bwd;   // per colour
   LaunchShape sh_resid, sh_R, sh_P, sh_spmv;
-  // FP32 V-cycle: values in SoaMat::val32, D^+ and level vectors in float
+  // FP32 V-cycle: values in SolveMat::val32, D^+ and level vectors in float
   float *Dinv32 = nullptr, *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
 };
 

@@ -294,12 +294,13 @@ __global__ void k_transpose_blocks(int64_t nnz, int r, int c, const int64_t *src
   out[q * bsz + e] = in[src[q] * bsz + oj * c + oi];
 }
 
-__global__ void k_gather_soa(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out) {
+// Block q of out := block src[q] of in (blocks of bsz values).
+__global__ void k_gather_blocks(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out) {
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= nnz * bsz) return;
-  const int64_t q = gid % nnz;
-  const int e = int(gid / nnz);
-  out[int64_t(e) * nnz + q] = in[src[q] * bsz + e];
+  const int64_t q = gid / bsz;
+  const int e = int(gid % bsz);
+  out[gid] = in[src[q] * bsz + e];
 }
 
 __global__ void k_gather_rows(int n, int bsz, const int *perm, const double *in, double *out) {
@@ -381,7 +382,7 @@ __device__ inline void row_accumulate(int p0, int p1, int lane, int G, const int
     const int64_t c = col[p];
     T v[BR * BC];
 #pragma unroll
-    for (int e = 0; e < BR * BC; ++e) v[e] = val[int64_t(e) * nnz + p];
+    for (int e = 0; e < BR * BC; ++e) v[e] = val[int64_t(p) * (BR * BC) + e];
     // every value load is issued before the gathers of x, which wait for the column index
     __builtin_amdgcn_sched_barrier(0);
     T xv[BC];
@@ -431,7 +432,7 @@ __device__ inline T pick(const T (&v)[B], int i) {
 
 // One row of a multicolour block Gauss-Seidel sweep, computed by the G lanes of a row group.
 // FWD: x = 0 before the sweep, so only the blocks left of the diagonal (lower colours) are read
-// (rp, col, val: the lower part) and A_ii comes from the diagonal planes dval (nd = rows);
+// (rp, col, val: the lower part) and A_ii is block `row` of dval;
 // also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row
 // (rp, col, val: the full matrix).
 // Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
@@ -459,7 +460,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
 #pragma unroll
     for (int c = 0; c < B; ++c) {
       Dq[c] = Dinv[int64_t(row) * B * B + lane * B + c];
-      if (FWD) Aq[c] = dval[int64_t(lane * B + c) * nd + row];
+      if (FWD) Aq[c] = dval[int64_t(row) * (B * B) + lane * B + c];
     }
   }
   T acc[B];
@@ -576,12 +577,12 @@ __global__ void k_convert(int64_t n, const S *__restrict__ in, D *__restrict__ o
   if (i < n) out[i] = D(in[i]);
 }
 
-__global__ void k_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in, float *out) {
+__global__ void k_gather_blocks_f32(int64_t nnz, int bsz, const int64_t *src, const double *in, float *out) {
   const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gid >= nnz * bsz) return;
-  const int64_t q = gid % nnz;
-  const int e = int(gid / nnz);
-  out[int64_t(e) * nnz + q] = float(in[src[q] * bsz + e]);
+  const int64_t q = gid / bsz;
+  const int e = int(gid % bsz);
+  out[gid] = float(in[src[q] * bsz + e]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
@@ -720,10 +721,10 @@ hipError_t launch_transpose_blocks(int64_t nnz, int r, int c, const int64_t *src
   EAMG_LAUNCH_CHECK();
 }
 
-hipError_t launch_gather_soa(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out,
+hipError_t launch_gather_blocks(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out,
                              hipStream_t s) {
   if (nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_soa, dim3(cdiv64(nnz * bsz, 256)), dim3(256), 0, s, nnz, bsz, src, in,
+  hipLaunchKernelGGL(k_gather_blocks, dim3(cdiv64(nnz * bsz, 256)), dim3(256), 0, s, nnz, bsz, src, in,
                      out);
   EAMG_LAUNCH_CHECK();
 }
@@ -746,11 +747,11 @@ hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in,
 
 // k_spmv reduces within wavefronts: a matrix with one row per workgroup runs it with 64 lanes
 // per row.
-inline int spmv_group(const SoaMat &A) { return A.group > 64 ? 64 : A.group; }
+inline int spmv_group(const SolveMat &A) { return A.group > 64 ? 64 : A.group; }
 
-int spmv_blocks(const SoaMat &A) { return int(cdiv64(A.n_rows, groups_for(spmv_group(A)))); }
+int spmv_blocks(const SolveMat &A) { return int(cdiv64(A.n_rows, groups_for(spmv_group(A)))); }
 
-hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part, hipStream_t s) {
+hipError_t launch_spmv(const SolveMat &A, const double *x, double *y, double *part, hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
   const int G = spmv_group(A);
   const dim3 grid(spmv_blocks(A));
@@ -765,13 +766,13 @@ hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part
 }
 
 template <class T>
-const T *soa_vals(const SoaMat &M);
+const T *solve_vals(const SolveMat &M);
 template <>
-const double *soa_vals<double>(const SoaMat &M) {
+const double *solve_vals<double>(const SolveMat &M) {
   return M.val;
 }
 template <>
-const float *soa_vals<float>(const SoaMat &M) {
+const float *solve_vals<float>(const SolveMat &M) {
   return M.val32;
 }
 
@@ -782,7 +783,7 @@ const float *soa_vals<float>(const SoaMat &M) {
   else { constexpr int W_ = 1; __VA_ARGS__; }
 
 template <class T>
-hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
+hipError_t launch_gs_fwd(const SolveMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
                          hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
   const T *lo = sizeof(T) == 4 ? reinterpret_cast<const T *>(A.lo_val32) : reinterpret_cast<const T *>(A.lo_val);
@@ -801,10 +802,10 @@ hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
 }
 
 template <class T>
-hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
+hipError_t launch_gs_bwd(const SolveMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
                          hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
-  const T *val = soa_vals<T>(A);
+  const T *val = solve_vals<T>(A);
   if (!val) return hipErrorInvalidValue;
   const int G = A.group_bwd ? A.group_bwd : A.group;
   const dim3 grid(cdiv64(r1 - r0, groups_for(G)));
@@ -820,7 +821,7 @@ hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T
 }
 
 template <class T>
-hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r, hipStream_t s) {
+hipError_t launch_resid_upper(const SolveMat &A, int r0, int r1, const T *x, T *r, hipStream_t s) {
   if (r0 < 0 || r1 > A.n_rows) return hipErrorInvalidValue;
   if (r1 <= r0) return hipSuccess;
   const T *up = sizeof(T) == 4 ? reinterpret_cast<const T *>(A.up_val32) : reinterpret_cast<const T *>(A.up_val);
@@ -837,9 +838,9 @@ hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r,
 }
 
 template <class T>
-hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipStream_t s) {
+hipError_t launch_rect(const SolveMat &M, const T *x, T *y, bool accumulate, hipStream_t s) {
   if (M.n_rows == 0) return hipSuccess;
-  const T *val = soa_vals<T>(M);
+  const T *val = solve_vals<T>(M);
   if (!val) return hipErrorInvalidValue;
   const dim3 grid(cdiv64(M.n_rows, groups_for(M.group)));
   const int accf = accumulate ? 1 : 0;
@@ -862,22 +863,22 @@ hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s) {
   EAMG_LAUNCH_CHECK();
 }
 
-hipError_t launch_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
+hipError_t launch_gather_blocks_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
                                  float *out, hipStream_t s) {
   if (nnz == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_soa_f32, dim3(cdiv64(nnz * bsz, 256)), dim3(256), 0, s, nnz, bsz, src,
+  hipLaunchKernelGGL(k_gather_blocks_f32, dim3(cdiv64(nnz * bsz, 256)), dim3(256), 0, s, nnz, bsz, src,
                      in, out);
   EAMG_LAUNCH_CHECK();
 }
 
-template hipError_t launch_gs_fwd<double>(const SoaMat &, const double *, int, int, const double *, double *, double *, hipStream_t);
-template hipError_t launch_gs_fwd<float>(const SoaMat &, const float *, int, int, const float *, float *, float *, hipStream_t);
-template hipError_t launch_gs_bwd<double>(const SoaMat &, const double *, int, int, const double *, double *, hipStream_t);
-template hipError_t launch_gs_bwd<float>(const SoaMat &, const float *, int, int, const float *, float *, hipStream_t);
-template hipError_t launch_resid_upper<double>(const SoaMat &, int, int, const double *, double *, hipStream_t);
-template hipError_t launch_resid_upper<float>(const SoaMat &, int, int, const float *, float *, hipStream_t);
-template hipError_t launch_rect<double>(const SoaMat &, const double *, double *, bool, hipStream_t);
-template hipError_t launch_rect<float>(const SoaMat &, const float *, float *, bool, hipStream_t);
+template hipError_t launch_gs_fwd<double>(const SolveMat &, const double *, int, int, const double *, double *, double *, hipStream_t);
+template hipError_t launch_gs_fwd<float>(const SolveMat &, const float *, int, int, const float *, float *, float *, hipStream_t);
+template hipError_t launch_gs_bwd<double>(const SolveMat &, const double *, int, int, const double *, double *, hipStream_t);
+template hipError_t launch_gs_bwd<float>(const SolveMat &, const float *, int, int, const float *, float *, hipStream_t);
+template hipError_t launch_resid_upper<double>(const SolveMat &, int, int, const double *, double *, hipStream_t);
+template hipError_t launch_resid_upper<float>(const SolveMat &, int, int, const float *, float *, hipStream_t);
+template hipError_t launch_rect<double>(const SolveMat &, const double *, double *, bool, hipStream_t);
+template hipError_t launch_rect<float>(const SolveMat &, const float *, float *, bool, hipStream_t);
 template hipError_t launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
 template hipError_t launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
 

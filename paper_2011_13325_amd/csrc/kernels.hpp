@@ -1,11 +1,13 @@
 // Launchers of the gfx950 kernels (kernels.hip).  All pointers are device pointers; every
 // launcher enqueues on `s` and returns the launch status.
 //
-// Solve-phase matrices are block CSR in "element planes" (SoA): value (r, c) of block q lives at
-// val[(r * BC + c) * nnz + q], so a wavefront reading consecutive blocks of one element reads
-// consecutive doubles.  Rows of every level are numbered colour-major, so a colour is a
-// contiguous row range and, within a row, the columns below the row index are exactly the
-// neighbours of lower colour.  diag[i] is the position of the diagonal block of row i.
+// Solve-phase matrices (SolveMat) are block CSR with row-major blocks stored one after another:
+// value (r, c) of block q lives at val[q * BR * BC + r * BC + c], so a lane that owns a block
+// reads it as a few wide loads of consecutive bytes (measured on a level-1-shaped 6 x 6 FP32
+// matrix: 11 % more bandwidth than element planes, where value (r, c) of every block forms one
+// array).  Rows of every level are numbered colour-major, so a colour is a contiguous row range
+// and, within a row, the columns below the row index are exactly the neighbours of lower colour.
+// diag[i] is the position of the diagonal block of row i.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,9 +55,9 @@ hipError_t launch_spgemm_numeric(int64_t nnzC, int ra, int ca, int cb, const int
 hipError_t launch_transpose_blocks(int64_t nnz, int r, int c, const int64_t *src, const double *in,
                                    double *out, hipStream_t s);
 
-// AoS -> SoA gather: out[e * nnz + q] = in[src[q] * bsz + e].
-hipError_t launch_gather_soa(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out,
-                             hipStream_t s);
+// Block gather: out[q * bsz + e] = in[src[q] * bsz + e].
+hipError_t launch_gather_blocks(int64_t nnz, int bsz, const int64_t *src, const double *in, double *out,
+                                hipStream_t s);
 
 // AoS -> AoS row gather: out[r * bsz + e] = in[perm[r] * bsz + e].
 hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in, double *out,
@@ -65,7 +67,7 @@ hipError_t launch_gather_rows(int n, int bsz, const int *perm, const double *in,
 constexpr int kBlock = 256;          // threads per workgroup of the solve kernels
 constexpr double kWideRowBlocks = 96; // square matrices with longer average rows: group = kBlock
 
-struct SoaMat {
+struct SolveMat {
   // group: lanes per row (a power of two <= 64), or 128 / kBlock for two wavefronts / a whole
   // workgroup per row (square matrices with diag only)
   int n_rows = 0, n_cols = 0, br = 0, bc = 0, group = 16;
@@ -82,9 +84,9 @@ struct SoaMat {
   const int *diag = nullptr; // square matrices only
   // Square colour-major level matrices also hold the blocks left of the diagonal, the blocks
   // right of it and the diagonal blocks each in storage of their own (row offsets, columns,
-  // element planes; the diagonal blocks in planes indexed by row), so that the forward sweep
-  // and the residual update, which read one side of every row, stream contiguous planes instead
-  // of touching partly used cache lines at both ends of every row segment.
+  // blocks; the diagonal block of row i is block i of dg_val), so that the forward sweep and
+  // the residual update, which read one side of every row, stream contiguous memory instead of
+  // touching partly used cache lines at both ends of every row segment.
   const int *lo_rp = nullptr, *lo_col = nullptr;
   const double *lo_val = nullptr;
   const float *lo_val32 = nullptr;
@@ -99,31 +101,31 @@ struct SoaMat {
 
 // y = A x ; if part != nullptr also writes per-workgroup partial sums of x.y (spmv_blocks(A)
 // entries)
-hipError_t launch_spmv(const SoaMat &A, const double *x, double *y, double *part, hipStream_t s);
-int spmv_blocks(const SoaMat &A);
-// The V-cycle kernels are instantiated for T = double (values SoaMat::val) and T = float
-// (values SoaMat::val32); they accumulate in T.
+hipError_t launch_spmv(const SolveMat &A, const double *x, double *y, double *part, hipStream_t s);
+int spmv_blocks(const SolveMat &A);
+// The V-cycle kernels are instantiated for T = double (values SolveMat::val) and T = float
+// (values SolveMat::val32); they accumulate in T.
 // Forward colour sweep with x = 0 initially on rows [r0, r1):
 //   t = b_i - sum_{j < i} A_ij x_j ; x_i = Dinv_i t ; r_i = t - A_ii x_i
 template <class T>
-hipError_t launch_gs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
+hipError_t launch_gs_fwd(const SolveMat &A, const T *Dinv, int r0, int r1, const T *b, T *x, T *r,
                          hipStream_t s);
 // r_i -= sum_{j > i} A_ij x_j on rows [r0, r1) (completes r = b - A x after the forward sweep).
 template <class T>
-hipError_t launch_resid_upper(const SoaMat &A, int r0, int r1, const T *x, T *r, hipStream_t s);
+hipError_t launch_resid_upper(const SolveMat &A, int r0, int r1, const T *x, T *r, hipStream_t s);
 // Backward colour sweep on rows [r0, r1): x_i += Dinv_i (b_i - sum_j A_ij x_j).
 template <class T>
-hipError_t launch_gs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
+hipError_t launch_gs_bwd(const SolveMat &A, const T *Dinv, int r0, int r1, const T *b, T *x,
                          hipStream_t s);
 // y = M x (rectangular, overwrite) or y += M x (accumulate = true).
 template <class T>
-hipError_t launch_rect(const SoaMat &M, const T *x, T *y, bool accumulate, hipStream_t s);
+hipError_t launch_rect(const SolveMat &M, const T *x, T *y, bool accumulate, hipStream_t s);
 // out[i] = D(in[i])
 template <class S, class D>
 hipError_t launch_convert(int64_t n, const S *in, D *out, hipStream_t s);
-// AoS double -> SoA float gather: out[e * nnz + q] = float(in[src[q] * bsz + e]).
-hipError_t launch_gather_soa_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
-                                 float *out, hipStream_t s);
+// Block gather to FP32: out[q * bsz + e] = float(in[src[q] * bsz + e]).
+hipError_t launch_gather_blocks_f32(int64_t nnz, int bsz, const int64_t *src, const double *in,
+                                    float *out, hipStream_t s);
 
 // Vector operations with deterministic reductions; grid size fixed by the length.
 int dot_blocks(int64_t n);

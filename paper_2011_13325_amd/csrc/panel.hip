@@ -27,13 +27,13 @@ __device__ inline int xcd_block() {
 }
 
 template <class T>
-const T *pvals(const SoaMat &M);
+const T *pvals(const SolveMat &M);
 template <>
-const double *pvals<double>(const SoaMat &M) {
+const double *pvals<double>(const SolveMat &M) {
   return M.val;
 }
 template <>
-const float *pvals<float>(const SoaMat &M) {
+const float *pvals<float>(const SolveMat &M) {
   return M.val32;
 }
 
@@ -42,8 +42,8 @@ const float *pvals<float>(const SoaMat &M) {
 // consecutive columns (register blocking: every matrix value it loads serves C columns, and the
 // C values of one dof are one vector load); the K / C lanes covering a panel form a sub-team,
 // and the S = 64 W C / K sub-teams of the team take the row's blocks in turn: sub-team s reads
-// blocks p0 + s, p0 + s + S, ...  At every step the S sub-teams read S consecutive blocks (the
-// same cache lines of every element plane), and the column index of a sub-team's next block is
+// blocks p0 + s, p0 + s + S, ...  At every step the S sub-teams read S consecutive blocks (one
+// contiguous run of memory), and the column index of a sub-team's next block is
 // fetched one step ahead, so a step waits for one round of gathers only.  The row sums of
 // column group g end in lane g of the team (sub-team 0).
 constexpr int kWave = 64;
@@ -119,7 +119,7 @@ __device__ inline void pteam_accumulate(int p0, int p1, int K, const PTeam<C, W>
     cn = pn < p1 ? col[pn] : 0;
     T a[BR * BC];
 #pragma unroll
-    for (int e = 0; e < BR * BC; ++e) a[e] = val[int64_t(e) * nnz + p];
+    for (int e = 0; e < BR * BC; ++e) a[e] = val[int64_t(p) * (BR * BC) + e];
     PVec<T, C> xv[BC];
 #pragma unroll
     for (int cc = 0; cc < BC; ++cc) xv[cc] = pload<T, C>(x + (c * BC + cc) * K + tm.g * C);
@@ -168,8 +168,8 @@ struct PRed {
 // One colour of the symmetric block Gauss-Seidel sweep for K columns (see launch_pgs_fwd /
 // launch_pgs_bwd).  The row's D^+ block and right-hand side are loaded before the row's blocks
 // so their latency overlaps the block stream; the lead lanes finish the row.
-// FWD: rp, col, val hold the blocks left of the diagonal and dval the diagonal blocks (planes
-// indexed by row, nd rows); BWD: rp, col, val hold whole rows.
+// FWD: rp, col, val hold the blocks left of the diagonal and dval the diagonal blocks (block i
+// for row i); BWD: rp, col, val hold whole rows.
 template <class T, int B, bool FWD, int C, int W>
 __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const int *__restrict__ rp,
                                                    const int *__restrict__ col,
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kPB) void k_pgs_color(int r0, int r1, int K, const 
 #pragma unroll
   for (int q = 0; q < B; ++q)
 #pragma unroll
-    for (int c = 0; c < B; ++c) Ad[q][c] = FWD ? dval[int64_t(q * B + c) * nd + row] : T(0);
+    for (int c = 0; c < B; ++c) Ad[q][c] = FWD ? dval[int64_t(row) * (B * B) + q * B + c] : T(0);
   T xo[B][C];
 #pragma unroll
   for (int i = 0; i < C; ++i) {
@@ -546,7 +546,7 @@ inline int pcols(int K) { return K >= 4 ? 4 : K; }
 
 // Team width: a whole workgroup per row when its 64 * 4 * C / K sub-teams still find a block
 // each in an average row, else one wavefront per row.
-inline int pwaves(const SoaMat &M, int K) {
+inline int pwaves(const SolveMat &M, int K) {
   if (M.panel_waves == 1 || M.panel_waves == 4) return M.panel_waves;   // tuned
   const double avg = M.n_rows ? double(M.nnz) / M.n_rows : 0.0;
   return (kWave * 4.0 * pcols(K) / K <= avg) ? 4 : 1;
@@ -565,7 +565,7 @@ inline unsigned pteam_grid(int rows, int W) { return pgrid(rows, kPB / (kWave * 
   else { constexpr int W_ = 1; __VA_ARGS__; }
 
 template <class T, bool FWD>
-hipError_t launch_pgs(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x, T *r,
+hipError_t launch_pgs(const SolveMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x, T *r,
                       hipStream_t s) {
   if (r1 <= r0) return hipSuccess;
   const bool f32 = sizeof(T) == 4;
@@ -594,19 +594,19 @@ hipError_t launch_pgs(const SoaMat &A, const T *Dinv, int r0, int r1, int K, con
 }
 
 template <class T>
-hipError_t launch_pgs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
+hipError_t launch_pgs_fwd(const SolveMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
                           T *r, hipStream_t s) {
   return launch_pgs<T, true>(A, Dinv, r0, r1, K, b, x, r, s);
 }
 
 template <class T>
-hipError_t launch_pgs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
+hipError_t launch_pgs_bwd(const SolveMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
                           hipStream_t s) {
   return launch_pgs<T, false>(A, Dinv, r0, r1, K, b, x, nullptr, s);
 }
 
 template <class T>
-hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStream_t s) {
+hipError_t launch_presid_upper(const SolveMat &A, int K, const T *x, T *r, hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
   const T *val = reinterpret_cast<const T *>(sizeof(T) == 4 ? (const void *)A.up_val32 : (const void *)A.up_val);
   if (!val || !A.up_rp || !valid_k(K)) return hipErrorInvalidValue;
@@ -626,7 +626,7 @@ hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStre
 }
 
 template <class T>
-hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulate, hipStream_t s) {
+hipError_t launch_prect(const SolveMat &M, int K, const T *x, T *y, bool accumulate, hipStream_t s) {
   if (M.n_rows == 0) return hipSuccess;
   const T *val = pvals<T>(M);
   if (!val || !valid_k(K)) return hipErrorInvalidValue;
@@ -645,12 +645,12 @@ hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulat
   EAMG_PCHECK();
 }
 
-int pspmv_blocks(const SoaMat &A, int K) {
+int pspmv_blocks(const SolveMat &A, int K) {
   const int g = K > 0 ? int(pgrid(A.n_rows, kPB / kWave)) : 0;
   return g < kPSpmvMax ? (g < 1 ? 1 : g) : kPSpmvMax;
 }
 
-hipError_t launch_pspmv(const SoaMat &A, int K, const double *x, double *y, double *part,
+hipError_t launch_pspmv(const SolveMat &A, int K, const double *x, double *y, double *part,
                         hipStream_t s) {
   if (A.n_rows == 0) return hipSuccess;
   if (!valid_k(K) || A.br != A.bc) return hipErrorInvalidValue;
@@ -734,13 +734,13 @@ hipError_t launch_punpack(int n, int bs, int K, int nrhs, const int *perm, const
   EAMG_PCHECK();
 }
 
-template hipError_t launch_pgs_fwd<double>(const SoaMat &, const double *, int, int, int, const double *, double *, double *, hipStream_t);
-template hipError_t launch_pgs_fwd<float>(const SoaMat &, const float *, int, int, int, const float *, float *, float *, hipStream_t);
-template hipError_t launch_pgs_bwd<double>(const SoaMat &, const double *, int, int, int, const double *, double *, hipStream_t);
-template hipError_t launch_pgs_bwd<float>(const SoaMat &, const float *, int, int, int, const float *, float *, hipStream_t);
-template hipError_t launch_presid_upper<double>(const SoaMat &, int, const double *, double *, hipStream_t);
-template hipError_t launch_presid_upper<float>(const SoaMat &, int, const float *, float *, hipStream_t);
-template hipError_t launch_prect<double>(const SoaMat &, int, const double *, double *, bool, hipStream_t);
-template hipError_t launch_prect<float>(const SoaMat &, int, const float *, float *, bool, hipStream_t);
+template hipError_t launch_pgs_fwd<double>(const SolveMat &, const double *, int, int, int, const double *, double *, double *, hipStream_t);
+template hipError_t launch_pgs_fwd<float>(const SolveMat &, const float *, int, int, int, const float *, float *, float *, hipStream_t);
+template hipError_t launch_pgs_bwd<double>(const SolveMat &, const double *, int, int, int, const double *, double *, hipStream_t);
+template hipError_t launch_pgs_bwd<float>(const SolveMat &, const float *, int, int, int, const float *, float *, hipStream_t);
+template hipError_t launch_presid_upper<double>(const SolveMat &, int, const double *, double *, hipStream_t);
+template hipError_t launch_presid_upper<float>(const SolveMat &, int, const float *, float *, hipStream_t);
+template hipError_t launch_prect<double>(const SolveMat &, int, const double *, double *, bool, hipStream_t);
+template hipError_t launch_prect<float>(const SolveMat &, int, const float *, float *, bool, hipStream_t);
 
 }  // namespace eamg

@@ -9,7 +9,7 @@
 // power of two in [1, 64]; lanes of different columns never combine values, so the columns
 // stay independent in every kernel.
 //
-// Matrices are the SoaMat element planes of the single-vector path (kernels.hpp), with rows
+// Matrices are the SolveMat block storage of the single-vector path (kernels.hpp), with rows
 // in the level's colour-major order.  All pointers are device pointers; every launcher
 // enqueues on `s` and returns the launch status.
 #pragma once
@@ -25,23 +25,23 @@ namespace eamg {
 // Forward colour sweep with X = 0 initially on rows [r0, r1):
 //   T_i = B_i - sum_{j < i} A_ij X_j ; X_i = Dinv_i T_i ; R_i = T_i - A_ii X_i
 template <class T>
-hipError_t launch_pgs_fwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
+hipError_t launch_pgs_fwd(const SolveMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
                           T *r, hipStream_t s);
 // Backward colour sweep on rows [r0, r1): X_i += Dinv_i (B_i - sum_j A_ij X_j).
 template <class T>
-hipError_t launch_pgs_bwd(const SoaMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
+hipError_t launch_pgs_bwd(const SolveMat &A, const T *Dinv, int r0, int r1, int K, const T *b, T *x,
                           hipStream_t s);
 // R_i -= sum_{j > i} A_ij X_j on all rows.
 template <class T>
-hipError_t launch_presid_upper(const SoaMat &A, int K, const T *x, T *r, hipStream_t s);
+hipError_t launch_presid_upper(const SolveMat &A, int K, const T *x, T *r, hipStream_t s);
 // Y = M X or Y += M X (rectangular transfer).
 template <class T>
-hipError_t launch_prect(const SoaMat &M, int K, const T *x, T *y, bool accumulate, hipStream_t s);
+hipError_t launch_prect(const SolveMat &M, int K, const T *x, T *y, bool accumulate, hipStream_t s);
 // FP64 CG operator: Y = A X; if part != nullptr also per-workgroup, per-column partial sums of
 // X.Y into part[wg * K + k] (pspmv_blocks(A, K) workgroups).
-hipError_t launch_pspmv(const SoaMat &A, int K, const double *x, double *y, double *part,
+hipError_t launch_pspmv(const SolveMat &A, int K, const double *x, double *y, double *part,
                         hipStream_t s);
-int pspmv_blocks(const SoaMat &A, int K);
+int pspmv_blocks(const SolveMat &A, int K);
 
 // ---- panel CG vectors (FP64, n = dofs * K entries) -------------------------------------------
 // Per-column state of the batched PCG, scal[slot * K + k].
