@@ -64,6 +64,11 @@ def _args():
     return ap.parse_args()
 
 
+def _progress(msg):
+    """One progress line on stderr per finished section (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def _caps(args):
     l0, std, aux = (int(v) for v in args.caps.split(","))
     return dict(cap_std_l0=l0, cap_std=std, cap_aux=aux)
@@ -353,8 +358,8 @@ def _cpu_model():
 def cpu_baseline(E, torch, args, stream):
     """The CPU oracle (FP64 NumPy/SciPy, one process, BLAS held to one thread) and the GPU on the
     same bounded sample: the 17^3-vertex cube (14,739 dofs), nu = 0.3, RHS seed 0, PCG to 1e-8;
-    the oracle's solve (median of 3) and setup are timed, and the library's FP64 solve of the
-    same problem with the headline's settings beside it."""
+    the oracle's solve (median of 3) and setup are timed, and beside it the library's FP64 solve
+    of the same problem with the oracle's settings and with the headline's."""
     from threadpoolctl import threadpool_limits
 
     import oracle
@@ -370,12 +375,21 @@ def cpu_baseline(E, torch, args, stream):
             xo, it, rel, rel_true, conv = oracle.pcg(ho, p.b, rtol=1e-8)
             times.append(time.perf_counter() - t0)
     t = float(np.median(times))
-    h, su = _setup(E, torch, p, _params(E, args), stream)
     b = torch.tensor(p.b, device="cuda")
-    x = torch.zeros_like(b)
-    gms, ginfo = _timed_solves(E, torch, h, b, x, stream, max(args.steps, 5), 1, E.EAMG_PRECOND_VCYCLE)
-    err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
-    h.close()
+    gpu = {}
+    # the oracle's own settings (default setup parameters: the same hierarchy, so the same
+    # iterations), then the headline's
+    for key, prm in (("gpu_same_input", E.eamg_default_setup_params()),
+                     ("gpu_headline_settings", _params(E, args))):
+        h, su = _setup(E, torch, p, prm, stream)
+        x = torch.zeros_like(b)
+        gms, ginfo = _timed_solves(E, torch, h, b, x, stream, max(args.steps, 5), 1,
+                                   E.EAMG_PRECOND_VCYCLE)
+        err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+        h.close()
+        gpu[key] = {"dtype": "f64", "ms_per_solve": gms, "value": p.n_free_dofs / (gms / 1e3),
+                    "iterations": ginfo["iterations"], "rel_res_true": ginfo["rel_res_true"],
+                    "setup_s": su["setup_s"], "x_rel_diff_vs_oracle": err}
     return {"value": p.n_free_dofs / t, "unit": "dofs/s", "cores": 1, "kind": "oracle",
             "sample": f"17^3-vertex cube ({p.n_free_dofs} free dofs), nu=0.3, RHS seed 0: oracle "
                       f"setup {t_setup:.1f} s, PCG to 1e-8 in {it} iterations, median of 3 solves "
@@ -383,12 +397,8 @@ def cpu_baseline(E, torch, args, stream):
                       f"minutes to hours and are not run)",
             "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
             "oracle_setup_s": round(t_setup, 2), "oracle_solve_s": round(t, 4),
-            "oracle_iterations": it,
-            "gpu_same_input": {"dtype": "f64", "ms_per_solve": gms,
-                               "value": p.n_free_dofs / (gms / 1e3), "iterations": ginfo["iterations"],
-                               "rel_res_true": ginfo["rel_res_true"], "setup_s": su["setup_s"],
-                               "x_rel_diff_vs_oracle": err},
-            "gpu_speedup_solve": t * 1e3 / gms}
+            "oracle_iterations": it, **gpu,
+            "gpu_speedup_solve": t * 1e3 / gpu["gpu_same_input"]["ms_per_solve"]}
 
 
 def _traffic(kernel):
@@ -414,7 +424,8 @@ def _traffic(kernel):
 
 def _counter_pass(args):
     """Workload of the rocprofv3 counter passes: a calibration copy of 64 MiB, then one solve of
-    the headline problem (FP32 V-cycle) with eager launches."""
+    the headline problem (FP32 V-cycle) with eager launches.  Prints the launches of every kernel
+    in that solve (the last dispatches of each kernel in the counter output are the solve's)."""
     os.environ["EAMG_GRAPH"] = "0"
     import torch
     import paper_2011_13325_amd as E
@@ -429,9 +440,14 @@ def _counter_pass(args):
     p = make_problem(args.n, nu=args.nu, seed=args.seed)
     h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, _params(E, args))
     E.eamg_autotune(h.h, 0)
+    E.eamg_profile_enable(h.h, True)
     x, info = h.solve(torch.tensor(p.b, device="cuda"), precond=E.EAMG_PRECOND_VCYCLE_FP32)
     torch.cuda.synchronize()
+    ks = E.eamg_profile_read(h.h)
+    E.eamg_profile_enable(h.h, False)
     print(f"counter pass: copy of {8 * n} bytes; solve {info['iterations']} iterations", flush=True)
+    print("solve launches: " + json.dumps({k["name"]: {"launches": k["launches"], "bytes": k["bytes"]}
+                                           for k in ks}), flush=True)
     h.close()
 
 
@@ -452,6 +468,7 @@ def main():
     stream = torch.cuda.current_stream()
     p = make_problem(args.n, nu=args.nu, seed=args.seed)
     hier, su = _setup(E, torch, p, _params(E, args), stream)
+    _progress(f"headline setup {su['setup_s']} s")
     t0 = time.perf_counter()
     tune_before, tune_after = E.eamg_autotune(hier.h, panel_width=0, stream=stream)
     tune_s = time.perf_counter() - t0
@@ -461,12 +478,14 @@ def main():
     P32, P64 = E.EAMG_PRECOND_VCYCLE_FP32, E.EAMG_PRECOND_VCYCLE
     ms, info = _timed_solves(E, torch, hier, b, x32, stream, args.steps, args.warmup, P32)
     kap32 = _kappa(E, hier)
+    _progress(f"headline FP32 solve {ms:.3f} ms, {info['iterations']} iterations")
     roof, vagg, kern = _profiled(E, hier, b, torch.zeros_like(b), args.steps, P32, stream)
     x64 = torch.zeros_like(b)
     ms64, info64 = _timed_solves(E, torch, hier, b, x64, stream, args.steps, args.warmup, P64)
     kap64 = _kappa(E, hier)
     _, vagg64, kern64 = _profiled(E, hier, b, torch.zeros_like(b), 1, P64, stream)
     xdiff = float((x32 - x64).norm() / x64.norm())
+    _progress(f"headline FP64 solve {ms64:.3f} ms")
     vbytes, itbytes = E.eamg_traffic_model(hier.h, P32)
     vbytes64, itbytes64 = E.eamg_traffic_model(hier.h, P64)
     its = info["iterations"]
@@ -519,6 +538,7 @@ def main():
                                   "iterations": info2["iterations"], "setup_s": su2["setup_s"],
                                   "dense_tail_speedup": ms2 / ms}
             h2.close()
+            _progress(f"sparse tail {ms2:.3f} ms")
         # the paper's P_s row caps (4 for edge-matrix rows, 8 / 6 for real-matrix rows)
         paper = dict(cap_std_l0=8, cap_std=6, cap_aux=4)
         if paper != _caps(args):
@@ -531,11 +551,15 @@ def main():
                                  "iterations": info3["iterations"], "oc": round(h3.stats()["oc"], 4),
                                  "setup_s": su3["setup_s"], "tuned_caps_speedup": ms3 / ms}
             h3.close()
+            _progress(f"paper caps {ms3:.3f} ms")
         out["cube64"] = _cube64(E, torch, args, stream)
+        _progress("64^3 and batched panel done")
         if args.multi > 0:
             out["multi_mesh"] = _multi_mesh(E, torch, args, count=args.multi)
+            _progress("multi-mesh done")
         if not args.no_learned:
             out["learned_coarsening"] = _learned(E, torch, args, stream)
+            _progress("learned coarsening done")
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(E, torch, args, stream)
     E.close_all()
