@@ -325,6 +325,62 @@ eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const doub
                              eamg_solve_info *infos);
 
 /*
+ * Fuse nsys hierarchies into one block-diagonal hierarchy for eamg_solve_fused.  Level l of the
+ * fused hierarchy holds level l of every system whose V-cycle reaches it, numbered colour by
+ * colour and, inside a colour, system by system; a colour is then still an independent set
+ * (the systems share no couplings), so each colour launch, transfer and CG vector operation of
+ * the fused solve covers every system at once.  A system whose V-cycle ends on a level (its
+ * dense tail, or the coarsest inverse) has its rows there after the colour ranges and is
+ * applied as a dense operator, all such systems in one launch (a system whose CG has stopped
+ * skips its dense operator).  Every system keeps exactly its
+ * own preconditioner: the V-cycle of Algorithm alg:tg with the multicolour block Gauss-Seidel
+ * smoother, its transfers P_s (Def. def:aux_sp) and Galerkin levels (section "prol"); only the
+ * order in which sums are formed can differ from eamg_solve.
+ *   hs[nsys]  distinct hierarchies on the current device, with equal dimension and block sizes
+ *             level by level.  Their level matrices, transfers and smoother diagonals are copied;
+ *             their own dense tails and coarsest inverses are read in place, so each stays alive as
+ *             long as a fused hierarchy uses it (eamg_destroy on it then only marks it, and the
+ *             last such fused hierarchy frees it).
+ *   dense_tail_dofs  where each system's V-cycle ends (the operator is the same up to rounding
+ *             in every case: a dense tail is the V-cycle of the levels below as a matrix):
+ *             -1  at the system's own dense tail (dense_tail_dofs at its setup) if it has one,
+ *                 as in eamg_solve, else at its coarsest inverse;
+ *              0  at the coarsest inverse (every level smoothed);
+ *             >0  at the first level below the finest with at most this many dofs (not the
+ *                 coarsest), as a dense tail the fused hierarchy computes and owns (or the
+ *                 system's own tail if it starts on that level); at most 16384.
+ *             Fused, a small level's launches serve every system at once while the tails'
+ *             bytes add up, so tails far smaller than a single system's best pay off.
+ *             Anything else: INVALID_ARG.
+ *   stream    the setup work is enqueued on it and waited for
+ *   out       the fused hierarchy (free with eamg_destroy).  It accepts eamg_solve_fused,
+ *             eamg_autotune (panel_width 0: lanes per row of its colour sweeps),
+ *             eamg_profile_enable / eamg_profile_read and eamg_destroy; every other entry point
+ *             returns EAMG_ERR_INVALID_ARG for it.
+ * Returns OK, INVALID_ARG (repeated, fused or mismatched systems, another device), OOM or HIP.
+ */
+eamg_status eamg_fuse(int32_t nsys, eamg_hierarchy *const *hs, int32_t dense_tail_dofs,
+                      void *stream, eamg_hierarchy **out);
+
+/*
+ * PCG with one V-cycle per iteration (section "res") on every system of a fused hierarchy at
+ * once, each system with its own CG scalars and its own stopping test; a system that stops keeps
+ * its x while the others go on.  The host reads the systems' flags once every 4 iterations.
+ *   b_dev[m], x_dev[m]  DEVICE arrays of system m (hs order of eamg_fuse), n_m * dim doubles in
+ *                       its natural order; Dirichlet dofs of b are treated as 0
+ *   params              shared by all systems (rtol, max_it, use_x0, precond; precond FP32
+ *                       needs vcycle_fp32 on every fused hierarchy)
+ *   infos               HOST array of nsys reports (may be NULL): iterations, residuals,
+ *                       status OK, NOT_CONVERGED or BREAKDOWN (that system's x is not written);
+ *                       ms is the whole call
+ * Runs on `stream` and waits for it.  Returns OK when every system converged, NOT_CONVERGED
+ * otherwise, INVALID_ARG (not a fused hierarchy, NULL or aliased vectors) or HIP.
+ */
+eamg_status eamg_solve_fused(eamg_hierarchy *fused, const double *const *b_dev,
+                             double *const *x_dev, const eamg_solve_params *params, void *stream,
+                             eamg_solve_info *infos);
+
+/*
  * Apply one V-cycle z = B^{-1} r (DEVICE arrays, n*dim doubles, level-0 natural order).
  * Dirichlet dofs of r are treated as 0.  precision: EAMG_PRECOND_VCYCLE (FP64) or
  * EAMG_PRECOND_VCYCLE_FP32 (needs vcycle_fp32 = 1 at setup); anything else is INVALID_ARG.
@@ -433,7 +489,8 @@ eamg_status eamg_profile_enable(eamg_hierarchy *h, int32_t on);
 eamg_status eamg_profile_read(eamg_hierarchy *h, int32_t max_entries, eamg_kernel_stat *out,
                               int32_t *n_out);
 
-/* Free a hierarchy (NULL-safe). */
+/* Free a hierarchy (NULL-safe).  A hierarchy that a fused hierarchy (eamg_fuse) still reads is
+ * only marked, and freed with the last such fused hierarchy. */
 void eamg_destroy(eamg_hierarchy *h);
 
 /* Message of the last failure on the calling thread ("" if none). */

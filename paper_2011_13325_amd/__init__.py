@@ -43,7 +43,7 @@ EXPORTED = ["eamg_default_setup_params", "eamg_default_solve_params", "eamg_setu
             "eamg_autotune", "eamg_gnn_create", "eamg_gnn_params", "eamg_gnn_forward",
             "eamg_gnn_loss_grad", "eamg_gnn_train", "eamg_gnn_destroy", "eamg_coarsening_stats",
             "eamg_gnn_samples", "eamg_dense_tail", "eamg_solve_coefficients", "eamg_setup_phases",
-            "eamg_vcycle_noalloc"]
+            "eamg_vcycle_noalloc", "eamg_fuse", "eamg_solve_fused"]
 
 
 class eamg_problem(ctypes.Structure):
@@ -138,6 +138,10 @@ def lib():
     L.eamg_autotune.restype = ctypes.c_int
     L.eamg_solve_multi.argtypes = [i32, P(vp), P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
     L.eamg_solve_multi.restype = ctypes.c_int
+    L.eamg_fuse.argtypes = [i32, P(vp), i32, vp, P(vp)]
+    L.eamg_fuse.restype = ctypes.c_int
+    L.eamg_solve_fused.argtypes = [vp, P(vp), P(vp), P(eamg_solve_params), vp, P(eamg_solve_info)]
+    L.eamg_solve_fused.restype = ctypes.c_int
     L.eamg_vcycle.argtypes = [vp, vp, vp, i32, vp]
     L.eamg_vcycle.restype = ctypes.c_int
     L.eamg_vcycle_noalloc.argtypes = [vp, vp, vp, i32, vp]
@@ -293,6 +297,33 @@ def eamg_solve_multi(hs, bs, xs, rtol=1e-8, max_it=1000, use_x0=False, precond=T
                      ms=i.ms, status=i.status) for i in infos]
 
 
+def eamg_fuse(hs, dense_tail_dofs=0, stream=None):
+    """Fused hierarchy handle of the hierarchy handles hs (eamg_destroy frees it)."""
+    n = len(hs)
+    H = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h) if not isinstance(h, ctypes.c_void_p) else h for h in hs])
+    out = ctypes.c_void_p()
+    st = lib().eamg_fuse(n, H, int(dense_tail_dofs), _stream(stream), ctypes.byref(out))
+    if st != EAMG_OK:
+        raise EamgError(st, "eamg_fuse")
+    return out.value
+
+
+def eamg_solve_fused(hf, bs, xs, rtol=1e-8, max_it=1000, use_x0=False, precond=True, stream=None):
+    """hf: fused hierarchy handle; bs, xs: float64 device tensors, one per system.
+    Returns (status, [info dict per system])."""
+    n = len(bs)
+    assert len(xs) == n
+    Bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+    Xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    sp = eamg_solve_params(rtol, max_it, int(use_x0), int(precond))
+    infos = (eamg_solve_info * n)()
+    st = lib().eamg_solve_fused(hf, Bp, Xp, ctypes.byref(sp), _stream(stream), infos)
+    if st < 0:
+        raise EamgError(st, "eamg_solve_fused")
+    return st, [dict(iterations=i.iterations, rel_res=i.rel_res, rel_res_true=i.rel_res_true,
+                     ms=i.ms, status=i.status) for i in infos]
+
+
 GNN_FEATURES = 12
 GNN_PARAMS = 9153
 
@@ -306,7 +337,7 @@ _OPEN = weakref.WeakSet()
 
 @atexit.register
 def close_all():
-    """Close every Hierarchy and EdgeNet that is still open."""
+    """Close every Hierarchy, Fused and EdgeNet that is still open."""
     for obj in list(_OPEN):
         try:
             obj.close()
@@ -625,6 +656,37 @@ class Hierarchy:
         if self.h is not None:
             eamg_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fused:
+    """Owning wrapper of a fused hierarchy (eamg_fuse) over Hierarchy objects; it keeps them
+    referenced while it is open."""
+
+    def __init__(self, hierarchies, dense_tail_dofs=0, stream=None):
+        self.parts = list(hierarchies)
+        self.dense_tail_dofs = int(dense_tail_dofs)
+        self.h = None
+        self.h = eamg_fuse([p.h for p in self.parts], dense_tail_dofs, stream)
+        _OPEN.add(self)
+
+    def solve(self, bs, xs=None, **kw):
+        import torch
+        if xs is None:
+            xs = [torch.zeros_like(b) for b in bs]
+        st, infos = eamg_solve_fused(self.h, bs, xs, **kw)
+        return xs, st, infos
+
+    def close(self):
+        if self.h is not None:
+            eamg_destroy(self.h)
+            self.h = None
+        self.parts = []
 
     def __del__(self):
         try:

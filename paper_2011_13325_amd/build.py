@@ -14,8 +14,9 @@ LIB = os.path.join(HERE, "libeamg.so")
 ARCH = "gfx950"
 
 HOST_SOURCES = ["coarsen.cpp", "structure.cpp", "api.cpp", "batch.cpp", "gnn_api.cpp",
-                "staging.cpp"]
-HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip", "noalloc.hip"]
+                "staging.cpp", "fused.cpp"]
+HIP_SOURCES = ["kernels.hip", "panel.hip", "gnn.hip", "coarse.hip", "criteria.hip", "noalloc.hip",
+               "fused.hip"]
 # the criteria must round like the host code (no fused multiply-add)
 FILE_FLAGS = {"criteria.hip": ["-ffp-contract=off"]}
 

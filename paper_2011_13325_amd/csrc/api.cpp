@@ -189,11 +189,11 @@ std::vector<int> to_i32(const std::vector<int64_t> &v) {
   return o;
 }
 
-// Build one solve-phase matrix (blocks in the permuted order) from natural AoS values with a host
-// permutation map.
+}  // namespace
+
 SolveMat make_solve_mat(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br, int bc,
-                const double *aos, hipStream_t s, std::vector<int> *diag_out = nullptr,
-                bool transpose_blocks = false, bool fp32 = false) {
+                        const double *aos, hipStream_t s, std::vector<int> *diag_out,
+                        bool transpose_blocks, bool fp32) {
   SolveMat M;
   M.n_rows = Pp.n_rows;
   M.n_cols = Pp.n_cols;
@@ -269,6 +269,74 @@ LaunchShape matrix_shape(const Pattern &M) {
   return sh;
 }
 
+void attach_split_parts(DevArena &ar, const Pattern &Ap, const std::vector<int64_t> &src,
+                        const std::vector<int> &dg, int bs, const double *vals, hipStream_t s,
+                        bool f32, SolveMat &Am) {
+  const int n = Ap.n_rows;
+  Pattern Plo, Pup, Pd;
+  std::vector<int64_t> slo, sup, sd;
+  for (Pattern *P : {&Plo, &Pup, &Pd}) {
+    P->n_rows = P->n_cols = n;
+    P->rp.assign(size_t(n) + 1, 0);
+  }
+  for (int i = 0; i < n; ++i) {
+    for (int64_t q = Ap.rp[i]; q < dg[i]; ++q) {
+      Plo.col.push_back(Ap.col[q]);
+      slo.push_back(src[q]);
+    }
+    for (int64_t q = dg[i] + 1; q < Ap.rp[i + 1]; ++q) {
+      Pup.col.push_back(Ap.col[q]);
+      sup.push_back(src[q]);
+    }
+    Pd.col.push_back(i);
+    sd.push_back(src[size_t(dg[i])]);
+    Plo.rp[i + 1] = int64_t(Plo.col.size());
+    Pup.rp[i + 1] = int64_t(Pup.col.size());
+    Pd.rp[i + 1] = i + 1;
+  }
+  const SolveMat lo = make_solve_mat(ar, Plo, slo, bs, bs, vals, s, nullptr, false, f32);
+  const SolveMat up = make_solve_mat(ar, Pup, sup, bs, bs, vals, s, nullptr, false, f32);
+  const SolveMat dm = make_solve_mat(ar, Pd, sd, bs, bs, vals, s, nullptr, false, f32);
+  Am.lo_rp = lo.rp;
+  Am.lo_col = lo.col;
+  Am.lo_val = lo.val;
+  Am.lo_val32 = lo.val32;
+  Am.lo_nnz = lo.nnz;
+  Am.up_rp = up.rp;
+  Am.up_col = up.col;
+  Am.up_val = up.val;
+  Am.up_val32 = up.val32;
+  Am.up_nnz = up.nnz;
+  Am.dg_val = dm.val;
+  Am.dg_val32 = dm.val32;
+}
+
+void level_shapes(Level &L, const Pattern &Ap, const std::vector<int> &dg) {
+  L.nnz_lower = 0;
+  for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
+  L.sh_spmv = matrix_shape(Ap);
+  // one task per colour and sweep part plus the residual, each with its own marks
+  const int nc = L.ncolors;
+  L.sh_fwd.assign(size_t(nc), LaunchShape());
+  L.sh_bwd.assign(size_t(nc), LaunchShape());
+  parallel_for_dynamic(2 * int64_t(nc) + 1, [&](int64_t t) {
+    std::vector<int> mark(size_t(L.n), -1);
+    if (t == 2 * int64_t(nc)) {
+      L.sh_resid = range_shape(Ap, dg, 0, L.smooth_rows(), 2, mark, 0);
+      L.upper_blocks.assign(size_t(nc), 0.0);
+      for (int c = 0; c < nc; ++c)
+        for (int i = L.color_ptr[c]; i < L.color_ptr[c + 1]; ++i)
+          L.upper_blocks[size_t(c)] += double(Ap.rp[i + 1] - dg[i] - 1);
+      return;
+    }
+    const int c = int(t / 2), part = int(t % 2);
+    (part == 0 ? L.sh_fwd : L.sh_bwd)[size_t(c)] =
+        range_shape(Ap, dg, L.color_ptr[c], L.color_ptr[c + 1], part, mark, 0);
+  }, 1);
+}
+
+namespace {
+
 static_assert(std::is_nothrow_move_constructible<Level>::value,
               "levels must move without copying their patterns");
 
@@ -306,69 +374,16 @@ void build_level_layout(eamg_hierarchy *h, size_t l, hipStream_t s) {
   std::vector<int> dg;
   const bool f32 = h->prm.vcycle_fp32 != 0;
   L.Am = make_solve_mat(ar, Ap, src, bs, bs, L.A_val, s, &dg, false, f32);
-  if (!coarsest) {
-    // the blocks left of the diagonal, right of it, and the diagonal blocks, each stored on its
-    // own for the forward sweep and the residual update (SolveMat)
-    Pattern Plo, Pup, Pd;
-    std::vector<int64_t> slo, sup, sd;
-    for (Pattern *P : {&Plo, &Pup, &Pd}) {
-      P->n_rows = P->n_cols = L.n;
-      P->rp.assign(size_t(L.n) + 1, 0);
-    }
-    for (int i = 0; i < L.n; ++i) {
-      for (int64_t q = Ap.rp[i]; q < dg[i]; ++q) {
-        Plo.col.push_back(Ap.col[q]);
-        slo.push_back(src[q]);
-      }
-      for (int64_t q = dg[i] + 1; q < Ap.rp[i + 1]; ++q) {
-        Pup.col.push_back(Ap.col[q]);
-        sup.push_back(src[q]);
-      }
-      Pd.col.push_back(i);
-      sd.push_back(src[size_t(dg[i])]);
-      Plo.rp[i + 1] = int64_t(Plo.col.size());
-      Pup.rp[i + 1] = int64_t(Pup.col.size());
-      Pd.rp[i + 1] = i + 1;
-    }
-    const SolveMat lo = make_solve_mat(ar, Plo, slo, bs, bs, L.A_val, s, nullptr, false, f32);
-    const SolveMat up = make_solve_mat(ar, Pup, sup, bs, bs, L.A_val, s, nullptr, false, f32);
-    const SolveMat dm = make_solve_mat(ar, Pd, sd, bs, bs, L.A_val, s, nullptr, false, f32);
-    L.Am.lo_rp = lo.rp;
-    L.Am.lo_col = lo.col;
-    L.Am.lo_val = lo.val;
-    L.Am.lo_val32 = lo.val32;
-    L.Am.lo_nnz = lo.nnz;
-    L.Am.up_rp = up.rp;
-    L.Am.up_col = up.col;
-    L.Am.up_val = up.val;
-    L.Am.up_val32 = up.val32;
-    L.Am.up_nnz = up.nnz;
-    L.Am.dg_val = dm.val;
-    L.Am.dg_val32 = dm.val32;
-  }
+  // the blocks left of the diagonal, right of it, and the diagonal blocks, each stored on its
+  // own for the forward sweep and the residual update (SolveMat)
+  if (!coarsest) attach_split_parts(ar, Ap, src, dg, bs, L.A_val, s, f32, L.Am);
   tl.mark("layout: A blocks");
-  L.nnz_lower = 0;
-  for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
-  L.sh_spmv = matrix_shape(Ap);
-  if (!coarsest) {
-    // one task per colour and sweep part plus the residual, each with its own marks
-    const int nc = L.ncolors;
-    L.sh_fwd.assign(size_t(nc), LaunchShape());
-    L.sh_bwd.assign(size_t(nc), LaunchShape());
-    parallel_for_dynamic(2 * int64_t(nc) + 1, [&](int64_t t) {
-      std::vector<int> mark(size_t(L.n), -1);
-      if (t == 2 * int64_t(nc)) {
-        L.sh_resid = range_shape(Ap, dg, 0, L.n, 2, mark, 0);
-        L.upper_blocks.assign(size_t(nc), 0.0);
-        for (int c = 0; c < nc; ++c)
-          for (int i = L.color_ptr[c]; i < L.color_ptr[c + 1]; ++i)
-            L.upper_blocks[size_t(c)] += double(Ap.rp[i + 1] - dg[i] - 1);
-        return;
-      }
-      const int c = int(t / 2), part = int(t % 2);
-      (part == 0 ? L.sh_fwd : L.sh_bwd)[size_t(c)] =
-          range_shape(Ap, dg, L.color_ptr[c], L.color_ptr[c + 1], part, mark, 0);
-    }, 1);
+  if (coarsest) {
+    L.nnz_lower = 0;
+    for (int i = 0; i < L.n; ++i) L.nnz_lower += dg[i] - Ap.rp[i];
+    L.sh_spmv = matrix_shape(Ap);
+  } else {
+    level_shapes(L, Ap, dg);
   }
   tl.mark("layout: launch shapes");
   if (coarsest) {
@@ -466,7 +481,7 @@ void coarsest_factor(eamg_hierarchy *h, hipStream_t s) {
 template <class T>
 hipError_t resid_update(const Level &L, const T *x, T *r, hipStream_t s) {
   const SolveMat M = L.resid_mat();
-  if (L.resid_cut.empty()) return launch_resid_upper<T>(M, 0, L.n, x, r, s);
+  if (L.resid_cut.empty()) return launch_resid_upper<T>(M, 0, L.smooth_rows(), x, r, s);
   for (size_t k = 0; k + 1 < L.resid_cut.size(); ++k) {
     SolveMat m = M;
     if (k < L.g_resid.size() && L.g_resid[k]) m.group = L.g_resid[k];
@@ -477,11 +492,40 @@ hipError_t resid_update(const Level &L, const T *x, T *r, hipStream_t s) {
   return hipSuccess;
 }
 
+// The dense operators of a fused hierarchy's level: x = D b on each of their systems' rows.
+template <class T>
+void dense_sets(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s);
+template <>
+void dense_sets<double>(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t s) {
+  const DenseSet &d = h->lv[l].dense[0];
+  if (!d.count) return;
+  timed(h, "dense parts", lvname(h, l, "k_dense_multi<double, double>"), d.bytes, s, [&] {
+    return launch_dense_multi<double, double>(d.count, d.parts, d.rows, d.active, b, x, s);
+  });
+}
+template <>
+void dense_sets<float>(eamg_hierarchy *h, size_t l, const float *b, float *x, hipStream_t s) {
+  const DenseSet &d32 = h->lv[l].dense[1], &d64 = h->lv[l].dense[2];
+  if (d32.count)
+    timed(h, "dense parts", lvname(h, l, "k_dense_multi<float, float>"), d32.bytes, s, [&] {
+      return launch_dense_multi<float, float>(d32.count, d32.parts, d32.rows, d32.active, b, x, s);
+    });
+  if (d64.count)
+    timed(h, "dense parts", lvname(h, l, "k_dense_multi<double, float>"), d64.bytes, s, [&] {
+      return launch_dense_multi<double, float>(d64.count, d64.parts, d64.rows, d64.active, b, x, s);
+    });
+}
+
 template <class T>
 void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
   Level &L = h->lv[l];
   const bool f32 = sizeof(T) == 4;
   const std::string ty = type_name<T>();
+  if (h->fused) {
+    // systems whose V-cycle ends here are applied as dense operators; the others are smoothed
+    dense_sets<T>(h, l, b, x, s);
+    if (L.smooth_rows() == 0) return;
+  }
   if (int(l) == h->tail_level) {
     // the V-cycle of this level and every level below it, as one dense matrix
     const double by = double(h->nT) * h->nT * double(sizeof(T)) + 2.0 * h->nT * double(sizeof(T));
@@ -877,6 +921,10 @@ struct MultiStreams {
 
 }  // namespace
 
+void vcycle_apply(eamg_hierarchy *h, const double *r, double *z, bool f32, hipStream_t s) {
+  vcycle(h, r, z, f32, s);
+}
+
 void vcycle_staged(eamg_hierarchy *h, const double *r_dev, double *z_dev, bool f32, double *rp,
                    double *zp, hipStream_t s) {
   const Level &L0 = h->lv[0];
@@ -905,7 +953,13 @@ void eamg_default_solve_params(eamg_solve_params *out) {
 
 const char *eamg_last_error(void) { return g_last_error.c_str(); }
 
-void eamg_destroy(eamg_hierarchy *h) { delete h; }
+void eamg_destroy(eamg_hierarchy *h) {
+  if (h && h->fused_users > 0) {
+    h->destroy_pending = true;   // freed with the last fused hierarchy that reads it
+    return;
+  }
+  delete h;
+}
 
 eamg_status eamg_setup(const eamg_problem *pb, const eamg_setup_params *params, void *stream,
                        eamg_hierarchy **out) {
@@ -1149,6 +1203,7 @@ eamg_status eamg_coarsening_stats(const eamg_hierarchy *h, int64_t *evaluated, i
                                   int64_t *skipped, int32_t *sample_passes) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (evaluated) *evaluated = h->crit_evaluated;
     if (evaluated_g) *evaluated_g = h->crit_evaluated_g;
     if (skipped) *skipped = h->crit_skipped;
@@ -1160,6 +1215,7 @@ eamg_status eamg_gnn_samples(const eamg_hierarchy *h, int32_t pass, int64_t *m, 
                              int32_t *edges, float *y, float *w) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (pass < 0 || pass >= int(h->samples.size())) fail(EAMG_ERR_INVALID_ARG, "pass out of range");
     const PassSamples &ps = h->samples[size_t(pass)];
     const size_t np = ps.edges.size() / 2;
@@ -1359,7 +1415,9 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
       h->g_iter[p] = nullptr;
       h->graph_tried[p] = false;
     }
+    invalidate_fused_graphs(h);
     if (panel_width > 0) {
+      reject_fused(h);
       int K = 1;
       while (K < panel_width) K <<= 1;
       const auto pa = tune_panels(h, K, s);
@@ -1380,6 +1438,7 @@ eamg_status eamg_solve_multi(int32_t nsys, eamg_hierarchy *const *hs, const doub
     if (nsys < 1 || !hs || !b_dev || !x_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument or nsys < 1");
     for (int m = 0; m < nsys; ++m) {
       if (!hs[m] || !b_dev[m] || !x_dev[m]) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy or vector");
+      reject_fused(hs[m]);
       if (b_dev[m] == x_dev[m]) fail(EAMG_ERR_INVALID_ARG, "b and x may not alias");
       for (int l = 0; l < m; ++l)
         if (hs[l] == hs[m]) fail(EAMG_ERR_INVALID_ARG, "a hierarchy may appear only once");
@@ -1509,6 +1568,7 @@ eamg_status eamg_vcycle(eamg_hierarchy *h, const double *r_dev, double *z_dev, i
                         void *stream) {
   return guarded([&] {
     if (!h || !r_dev || !z_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    reject_fused(h);
     if (precision != EAMG_PRECOND_VCYCLE && precision != EAMG_PRECOND_VCYCLE_FP32)
       fail(EAMG_ERR_INVALID_ARG, "precision must be EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32");
     if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
@@ -1527,6 +1587,7 @@ eamg_status eamg_solve(eamg_hierarchy *h, const double *b_dev, double *x_dev,
   SolveRun run;
   const eamg_status st = guarded([&] {
     if (!h || !b_dev || !x_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    reject_fused(h);
     run.init(h, params, static_cast<hipStream_t>(stream));
     run.start(b_dev, x_dev);
     if (!run.converged) {
@@ -1550,6 +1611,7 @@ eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_
                        int64_t *per_level_nnzb, double *vc, double *oc) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (n_levels) *n_levels = int32_t(h->lv.size());
     double sn = 0.0, snz = 0.0;
     for (size_t l = 0; l < h->lv.size(); ++l) {
@@ -1568,6 +1630,7 @@ eamg_status eamg_stats(const eamg_hierarchy *h, int32_t *n_levels, int64_t *per_
 eamg_status eamg_level_info_get(const eamg_hierarchy *h, int32_t level, eamg_level_info *out) {
   return guarded([&] {
     if (!h || !out) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    reject_fused(h);
     if (level < 0 || level >= int(h->lv.size())) fail(EAMG_ERR_INVALID_ARG, "level out of range");
     const Level &L = h->lv[level];
     const bool last = level + 1 == int(h->lv.size());
@@ -1586,6 +1649,7 @@ eamg_status eamg_export_level(const eamg_hierarchy *h, int32_t level, int32_t *a
                               int32_t *A_col, double *A_val, int32_t *color) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (level < 0 || level >= int(h->lv.size())) fail(EAMG_ERR_INVALID_ARG, "level out of range");
     const Level &L = h->lv[level];
     const bool last = level + 1 == int(h->lv.size());
@@ -1617,6 +1681,7 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
                                double *iteration_bytes) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (precision != EAMG_PRECOND_VCYCLE && precision != EAMG_PRECOND_VCYCLE_FP32)
       fail(EAMG_ERR_INVALID_ARG, "precision must be EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32");
     if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
@@ -1656,6 +1721,7 @@ eamg_status eamg_solve_coefficients(const eamg_hierarchy *h, int32_t max_entries
                                     double *beta, int32_t *n_out) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (max_entries < 0) fail(EAMG_ERR_INVALID_ARG, "max_entries < 0");
     const int n = int(h->cg_alpha.size());
     const int m = std::min(n, max_entries);
@@ -1671,6 +1737,7 @@ eamg_status eamg_setup_phases(const eamg_hierarchy *h, int32_t max_entries, eamg
                               int32_t *n_out) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (max_entries < 0) fail(EAMG_ERR_INVALID_ARG, "max_entries < 0");
     // where each phase runs: 0 host, 1 device, 2 host-to-device copies
     auto where = [](const std::string &name) {
@@ -1694,6 +1761,7 @@ eamg_status eamg_setup_phases(const eamg_hierarchy *h, int32_t max_entries, eamg
 eamg_status eamg_dense_tail(const eamg_hierarchy *h, int32_t *level, int32_t *dofs) {
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
+    reject_fused(h);
     if (level) *level = h->tail_level;
     if (dofs) *dofs = h->tail_level >= 0 ? h->nT : 0;
   });

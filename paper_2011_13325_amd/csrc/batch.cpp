@@ -365,7 +365,7 @@ double time_ms(hipStream_t s, int reps, F &&f) {
 // kernels): per level, the sweep + upper-residual sequence and each transfer with one or four
 // wavefronts per row; the faster is kept in SolveMat::panel_waves.  Returns the summed time of the
 // tuned kernels before / after (ms).
-void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
+DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32, hipStream_t s) {
   if (t == 0 || t + 1 >= h->lv.size()) fail(EAMG_ERR_INVALID_ARG, "dense tail must start above the coarsest level, below the finest");
   const Level &Lt = h->lv[t];
   const int n = Lt.n * Lt.bs;
@@ -388,7 +388,7 @@ void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
   }
   w.have[0] = true;
   const int ld = dense_ld(n);
-  double *T = h->arena.alloc<double>(size_t(ld) * ld);
+  double *T = out.alloc<double>(size_t(ld) * ld);
   hip_check(launch_fill(int64_t(ld) * ld, 0.0, T, s), "fill");
   double *B = vp<double>(w.vb[0][t]), *X = vp<double>(w.vx[0][t]);
   const bool prof = h->prof_on;
@@ -399,16 +399,26 @@ void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
     hip_check(launch_scatter_panel(n, K, j0, std::min(K, n - j0), X, ld, T, s), "scatter panel");
   }
   h->prof_on = prof;
-  h->tail = T;
-  h->nT = n;
-  h->ldT = ld;
-  if (h->prm.vcycle_fp32) {
-    const int ld32 = dense_ld32(n);
-    h->tail32 = h->arena.alloc<float>(size_t(ld32) * ld32);
-    h->ldT32 = ld32;
-    hip_check(launch_dense_to_f32(n, ld, T, ld32, h->tail32, s), "tail to f32");
+  DenseTail d;
+  d.T = T;
+  d.n = n;
+  d.ld = ld;
+  if (fp32) {
+    d.ld32 = dense_ld32(n);
+    d.T32 = out.alloc<float>(size_t(d.ld32) * d.ld32);
+    hip_check(launch_dense_to_f32(n, ld, T, d.ld32, d.T32, s), "tail to f32");
   }
   hip_check(hipStreamSynchronize(s), "sync");
+  return d;
+}
+
+void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
+  const DenseTail d = make_dense_tail(h, t, h->arena, h->prm.vcycle_fp32 != 0, s);
+  h->tail = d.T;
+  h->nT = d.n;
+  h->ldT = d.ld;
+  h->tail32 = d.T32;
+  h->ldT32 = d.ld32;
   h->tail_level = int(t);
 }
 
@@ -486,6 +496,7 @@ extern "C" eamg_status eamg_solve_batch(eamg_hierarchy *h, int32_t nrhs, const d
   bool all = true;
   const eamg_status st = guarded([&] {
     if (!h || !B_dev || !X_dev) fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    reject_fused(h);
     if (nrhs < 1) fail(EAMG_ERR_INVALID_ARG, "nrhs must be >= 1");
     const int64_t ndof = level_dofs(h->lv[0]);
     if (ld < ndof) fail(EAMG_ERR_INVALID_ARG, "ld must be >= n*dim");

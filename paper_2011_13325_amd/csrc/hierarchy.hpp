@@ -13,6 +13,7 @@
 
 #include "../../include/eamg.h"
 #include "coarse.hpp"
+#include "fused.hpp"
 #include "kernels.hpp"
 #include "coarsen.hpp"
 #include "staging.hpp"
@@ -113,8 +114,25 @@ inline double launch_bytes(const LaunchShape &sh, LaunchKind kind, int br, int b
   return 0.0;
 }
 
+// Dense operators applied on one level of a fused hierarchy, one part per system (device array
+// of `count` DensePart entries covering `rows` rows), and their algorithmic bytes per launch.
+struct DenseSet {
+  const DensePart *parts = nullptr;
+  int count = 0, rows = 0;
+  double bytes = 0.0;
+  const double *active = nullptr;   // per-system CG activity flags: stopped systems are skipped
+};
+
 struct Level {
   int n = 0, bs = 0;
+  // rows the smoother covers (the colour ranges), -1 for all n rows; a fused hierarchy's level
+  // puts the rows of systems whose V-cycle ends on it after them
+  int n_smooth = -1;
+  int smooth_rows() const { return n_smooth < 0 ? n : n_smooth; }
+  // fused hierarchies: dense operators of the systems whose V-cycle ends on this level;
+  // [0] FP64 V-cycle (double matrices), [1] FP32 V-cycle with float matrices, [2] FP32 V-cycle
+  // with double matrices
+  DenseSet dense[3];
   Pattern A;                 // natural pattern
   int64_t *A_rp = nullptr;   // natural pattern on the device
   int *A_col = nullptr;
@@ -210,6 +228,27 @@ struct ProfRec {
 
 struct BatchWork;
 void destroy_batch(BatchWork *w);
+struct FusedInfo;
+void destroy_fused(FusedInfo *f);
+// Solve-phase matrix from a host pattern in the solve numbering, src[q] = natural position of
+// block q in the AoS values aos (br x bc blocks; transpose_blocks: aos holds bc x br blocks);
+// diag_out (square matrices) receives each row's diagonal position.
+SolveMat make_solve_mat(DevArena &ar, const Pattern &Pp, const std::vector<int64_t> &src, int br,
+                        int bc, const double *aos, hipStream_t s, std::vector<int> *diag_out = nullptr,
+                        bool transpose_blocks = false, bool fp32 = false);
+// The blocks left of the diagonal, right of it and the diagonal blocks of a square solve matrix,
+// each in storage of its own (SolveMat::lo_*, up_*, dg_*).
+void attach_split_parts(DevArena &ar, const Pattern &Ap, const std::vector<int64_t> &src,
+                        const std::vector<int> &dg, int bs, const double *vals, hipStream_t s,
+                        bool f32, SolveMat &Am);
+LaunchShape range_shape(const Pattern &Ap, const std::vector<int> &dg, int r0, int r1, int part,
+                        std::vector<int> &mark, int stamp);
+LaunchShape matrix_shape(const Pattern &M);
+// Launch shapes of a smoothed level (colours, residual update over smooth_rows(), SpMV).
+void level_shapes(Level &L, const Pattern &Ap, const std::vector<int> &dg);
+// z = V(r) on level-0 vectors in the hierarchy's solve numbering (FP64, or the FP32 V-cycle
+// with conversions at the boundary).
+void vcycle_apply(eamg_hierarchy *h, const double *r, double *z, bool f32, hipStream_t s);
 // Panel launch shapes tuned on the hierarchy for K columns; (time before, after) in ms.
 std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
 // z = V(r) for level-0 vectors in the natural numbering (eamg_vcycle's operation), with the
@@ -217,8 +256,17 @@ std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
 // each): launches on s only -- no allocation, no synchronization; the profiler must be off.
 void vcycle_staged(eamg_hierarchy *h, const double *r_dev, double *z_dev, bool f32, double *rp,
                    double *zp, hipStream_t s);
-// The V-cycle on levels t .. coarsest as a dense matrix (h->tail, h->tail32), from the batched
-// V-cycle applied to the columns of the identity; sets h->tail_level = t.
+// The V-cycle on levels t .. coarsest of h as a dense matrix in the colour-major numbering of
+// level t, from the batched V-cycle applied to the columns of the identity: FP64 (row-major, ld a
+// multiple of 128, zero padding) and, with fp32, an FP32 copy (ld32 a multiple of 256), both
+// allocated in `out`.
+struct DenseTail {
+  double *T = nullptr;
+  float *T32 = nullptr;
+  int n = 0, ld = 0, ld32 = 0;
+};
+DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32, hipStream_t s);
+// make_dense_tail into h's own arena, kept as h->tail / h->tail32; sets h->tail_level = t.
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s);
 
 }  // namespace eamg
@@ -257,6 +305,12 @@ struct eamg_hierarchy {
   bool graph_tried[2] = {false, false};
   // block-panel (multi right-hand side) workspace, allocated by the first batched call
   eamg::BatchWork *batch = nullptr;
+  // fused hierarchies (eamg_fuse): the systems, their level-0 maps and the segmented CG state
+  eamg::FusedInfo *fused = nullptr;
+  // fused hierarchies that read this one's dense operators; eamg_destroy while there are any
+  // only marks it, and the last of them frees it
+  int fused_users = 0;
+  bool destroy_pending = false;
   // wall time of each setup phase (summed over levels), in the order phases first ran
   std::vector<std::pair<std::string, double>> setup_phases;
   // CG coefficients alpha_k, beta_k of the last single-vector solve (beta_1 = 0)
@@ -267,6 +321,7 @@ struct eamg_hierarchy {
   std::vector<eamg::PassSamples> samples;
   ~eamg_hierarchy() {
     eamg::destroy_batch(batch);
+    eamg::destroy_fused(fused);
     for (hipGraphExec_t g : g_iter)
       if (g) (void)hipGraphExecDestroy(g);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -317,6 +372,16 @@ inline std::string tname(const char *base, int a) { return std::string(base) + "
 inline std::string tname(const char *base, int a, int b) {
   return std::string(base) + "<" + std::to_string(a) + ", " + std::to_string(b) + ">";
 }
+
+// Entry points other than eamg_solve_fused, eamg_autotune, the profiler and eamg_destroy need a
+// hierarchy of one system.
+inline void reject_fused(const eamg_hierarchy *h) {
+  if (h && h->fused)
+    fail(EAMG_ERR_INVALID_ARG, "a fused hierarchy (eamg_fuse) supports only eamg_solve_fused, "
+                               "eamg_autotune, the profiler and eamg_destroy");
+}
+// Drop a fused hierarchy's captured iteration graphs (their launch shapes changed).
+void invalidate_fused_graphs(eamg_hierarchy *h);
 
 inline void fetch_scalars(eamg_hierarchy *h, hipStream_t s) {
   hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s), "copy");

@@ -39,6 +39,7 @@ extern "C" eamg_status eamg_vcycle_noalloc(eamg_hierarchy *h, const double *r_de
                                            int32_t precision, void *stream) {
   return eamg::guarded([&] {
     if (!h || !r_dev || !z_dev) eamg::fail(EAMG_ERR_INVALID_ARG, "NULL argument");
+    eamg::reject_fused(h);
     if (precision != EAMG_PRECOND_VCYCLE && precision != EAMG_PRECOND_VCYCLE_FP32)
       eamg::fail(EAMG_ERR_INVALID_ARG, "precision must be EAMG_PRECOND_VCYCLE or EAMG_PRECOND_VCYCLE_FP32");
     if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
