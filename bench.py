@@ -51,6 +51,8 @@ def _args():
                     help="P_s row caps: real-matrix rows on level 0, on coarser levels, edge-matrix rows")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline solve (for profiler runs)")
+    ap.add_argument("--per-level", action="store_true",
+                    help="per-level kernel records of both V-cycle precisions, also with --headline-only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=32,
                     help="right-hand sides of the batched block-panel solve at 64^3 (0: skip)")
@@ -167,8 +169,9 @@ def _per_level(E, hier, b, x, precond, stream):
     ks = E.eamg_profile_read(hier.h, 256)
     E.eamg_profile_enable(hier.h, False)
     return [{"name": k["name"], "launches": k["launches"], "ms": round(k["total_ms"], 3),
+             "us_per_launch": round(k["total_ms"] / k["launches"] * 1e3, 2),
              "GBps": round(k["bytes"] / (k["total_ms"] / 1e3) / 1e9, 1) if k["total_ms"] else None}
-            for k in ks[:30]]
+            for k in ks[:40]]
 
 
 def _levels(E, h):
@@ -555,8 +558,10 @@ def main():
         "fp32_speedup": ms64 / ms, "model_bytes_per_iteration": itbytes64,
         "vcycle_aggregate": vagg64, "kappa_estimate": kap64, "kernels": kern64[:8],
         "fp32_solution_rel_diff": xdiff}
-    if not args.headline_only:
+    if not args.headline_only or args.per_level:
         out["per_level_fp32"] = _per_level(E, hier, b, torch.zeros_like(b), P32, stream)
+    if args.per_level:
+        out["per_level_fp64"] = _per_level(E, hier, b, torch.zeros_like(b), P64, stream)
     hier.close()
     if not args.headline_only:
         if args.dense_tail > 0:

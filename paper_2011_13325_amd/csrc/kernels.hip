@@ -402,7 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n_rows, int G, const int *_
                                                 double *part) {
   __shared__ double sh[kBlock];
   const int lane = threadIdx.x & (G - 1);
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int wg = xcd_block();
+  const int row = wg * (kBlock / G) + threadIdx.x / G;
   double acc[BR];
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = 0.0;
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int n_rows, int G, const int *_
   }
   if (part) {
     const double s = block_sum(d, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0) part[wg] = s;
   }
 }
 
@@ -554,7 +555,7 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
                                                 const T *__restrict__ x, T *__restrict__ y,
                                                 int accumulate) {
   const int lane = threadIdx.x & (G - 1);
-  const int row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+  const int row = xcd_block() * (kBlock / G) + threadIdx.x / G;
   T acc[BR];
 #pragma unroll
   for (int r = 0; r < BR; ++r) acc[r] = T(0);
@@ -599,6 +600,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int nparts, const double *__r
                                                   double *scal, int slot, int op) {
   __shared__ double sh[kBlock];
   double s = 0.0;
+  // unrolled so that the loads are in flight together (the CG SpMV leaves one partial per
+  // workgroup: hundreds of thousands on a large level); the sum keeps its order
+#pragma unroll 16
   for (int i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) {

@@ -12,6 +12,8 @@ Cholesky factor.  Checked here:
   iteration count within 1e-10 relative of the oracle run with the same parameters;
 * the panel product for 5 and 40 right-hand sides (panel widths 8 and 64) against the dense
   solve per column (FP64 1e-10; FP32 vectors: true residual 1e-9, error 1e-6);
+* the Gauss-Jordan inverse against a Cholesky solve (the oracle's factorization) on a
+  nu = 0.45 level of 6591 dofs, within the FP64 bar (the measured error and cond(A) printed);
 * the limit on coarsest_max_dofs, and an indefinite matrix reported as not SPD.
 """
 import numpy as np
@@ -74,6 +76,30 @@ def test_single_level_dense_inverse():
     assert info["status"] == E.EAMG_OK and info["iterations"] <= 2
     xs = np.linalg.solve(Ad, p.b)
     assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-10 * np.linalg.norm(xs)
+    hl.close()
+
+
+def test_gauss_jordan_inverse_against_cholesky_nu045():
+    # the oracle factors the coarsest matrix by Cholesky, the library inverts it by Gauss-Jordan
+    # elimination without pivoting (on an SPD matrix both are backward stable; the applied
+    # inverse's forward error is bounded by a small multiple of cond(A) * eps): one level of
+    # 6591 dofs at nu = 0.45 (ld 6656), the apply against a LAPACK Cholesky solve
+    import scipy.linalg as sl
+    p = make_problem(13, nu=0.45, seed=7)
+    hl = _lib(p, coarsest_max_dofs=16384)
+    assert hl.stats()["n_levels"] == 1
+    Ad, dm = _bound_dense(p)
+    cond = np.linalg.cond(Ad)
+    r = np.random.default_rng(2).standard_normal(p.n_dofs)
+    r[dm] = 0.0
+    zc = sl.cho_solve(sl.cho_factor(Ad), r)
+    z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+    E.eamg_vcycle(hl.h, _dev(r), z)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(z.cpu().numpy() - zc) / np.linalg.norm(zc)
+    print(f"\n[GJ vs Cholesky, 6591 dofs, nu=0.45] cond {cond:.2e} rel err {err:.2e} "
+          f"(cond * eps = {cond * 2.2e-16:.2e})", flush=True)
+    assert err <= max(X_TOL, 100 * cond * 2.2e-16)
     hl.close()
 
 
