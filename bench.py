@@ -51,6 +51,9 @@ def _args():
                     help="P_s row caps: real-matrix rows on level 0, on coarser levels, edge-matrix rows")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline solve (for profiler runs)")
+    ap.add_argument("--sections", default="all",
+                    help="sub-records after the headline: all, or a comma list of sparse_tail, "
+                         "paper_caps, cube64, multi, learned, cpu")
     ap.add_argument("--per-level", action="store_true",
                     help="per-level kernel records of both V-cycle precisions, also with --headline-only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -220,7 +223,8 @@ def _batched(E, torch, hier, p, m, steps, warmup, single_ms):
                     "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": ach,
                                  "peak": 8000.0, "unit": "GB/s", "frac": ach / 8000.0,
                                  "avg_launch_us": dom["total_ms"] / dom["launches"] * 1e3},
-                    "kernels": [{"name": k["name"], "ms_per_solve": k["total_ms"],
+                    "kernels": [{"name": k["name"], "launches_per_solve": k["launches"],
+                                 "ms_per_solve": k["total_ms"],
                                  "GBps": k["bytes"] / (k["total_ms"] / 1e3) / 1e9}
                                 for k in ks[:6]]}
     return out
@@ -563,8 +567,12 @@ def main():
     if args.per_level:
         out["per_level_fp64"] = _per_level(E, hier, b, torch.zeros_like(b), P64, stream)
     hier.close()
+
+    def want(name):
+        return not args.headline_only and (args.sections == "all" or name in args.sections.split(","))
+
     if not args.headline_only:
-        if args.dense_tail > 0:
+        if want("sparse_tail") and args.dense_tail > 0:
             h2, su2 = _setup(E, torch, p, _params(E, args, dense_tail_dofs=0), stream)
             E.eamg_autotune(h2.h, panel_width=0, stream=stream)
             ms2, info2 = _timed_solves(E, torch, h2, b, torch.zeros_like(b), stream, args.steps,
@@ -576,7 +584,7 @@ def main():
             _progress(f"sparse tail {ms2:.3f} ms")
         # the paper's P_s row caps (4 for edge-matrix rows, 8 / 6 for real-matrix rows)
         paper = dict(cap_std_l0=8, cap_std=6, cap_aux=4)
-        if paper != _caps(args):
+        if want("paper_caps") and paper != _caps(args):
             h3, su3 = _setup(E, torch, p, _params(E, args, **paper), stream)
             E.eamg_autotune(h3.h, panel_width=0, stream=stream)
             ms3, info3 = _timed_solves(E, torch, h3, b, torch.zeros_like(b), stream, args.steps,
@@ -587,15 +595,16 @@ def main():
                                  "setup_s": su3["setup_s"], "tuned_caps_speedup": ms3 / ms}
             h3.close()
             _progress(f"paper caps {ms3:.3f} ms")
-        out["cube64"] = _cube64(E, torch, args, stream)
-        _progress("64^3 and batched panel done")
-        if args.multi > 0:
+        if want("cube64"):
+            out["cube64"] = _cube64(E, torch, args, stream)
+            _progress("64^3 and batched panel done")
+        if want("multi") and args.multi > 0:
             out["multi_mesh"] = _multi_mesh(E, torch, args, count=args.multi)
             _progress("multi-mesh done")
-        if not args.no_learned:
+        if want("learned") and not args.no_learned:
             out["learned_coarsening"] = _learned(E, torch, args, stream)
             _progress("learned coarsening done")
-        if not args.no_cpu_baseline:
+        if want("cpu") and not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(E, torch, args, stream)
     E.close_all()
     torch.cuda.synchronize()
