@@ -365,7 +365,8 @@ eamg_status eamg_fuse(int32_t nsys, eamg_hierarchy *const *hs, int32_t dense_tai
 /*
  * PCG with one V-cycle per iteration (section "res") on every system of a fused hierarchy at
  * once, each system with its own CG scalars and its own stopping test; a system that stops keeps
- * its x while the others go on.  The host reads the systems' flags once every 4 iterations.
+ * its x while the others go on.  Iterations run in rounds of 4, each round one captured graph
+ * (eager launches while profiling); the host reads the systems' flags once a round.
  *   b_dev[m], x_dev[m]  DEVICE arrays of system m (hs order of eamg_fuse), n_m * dim doubles in
  *                       its natural order; Dirichlet dofs of b are treated as 0
  *   params              shared by all systems (rtol, max_it, use_x0, precond; precond FP32

@@ -336,6 +336,11 @@ void fused_iteration(eamg_hierarchy *F, int precond, hipStream_t s) {
   hip_check(launch_sreduce(T, F->part, F->scal, PS_RR, PRED_RR, s), "sreduce");
 }
 
+// Iterations per round: the host reads the systems' active flags once a round (a system that
+// stops inside a round keeps its x, r and p through the rest of it).
+constexpr int kRound = 4;
+
+// Capture one round of kRound iterations as one graph.
 void fused_graph(eamg_hierarchy *F, int precond) {
   FusedInfo &I = *F->fused;
   I.tried[precond] = true;
@@ -349,7 +354,7 @@ void fused_graph(eamg_hierarchy *F, int precond) {
   if (hipStreamBeginCapture(I.cap, hipStreamCaptureModeRelaxed) != hipSuccess) return;
   bool ok = true;
   try {
-    fused_iteration(F, precond, I.cap);
+    for (int k = 0; k < kRound; ++k) fused_iteration(F, precond, I.cap);
   } catch (const Failure &) {
     ok = false;
   }
@@ -560,9 +565,7 @@ eamg_status eamg_solve_fused(eamg_hierarchy *F, const double *const *b_dev, doub
     hip_check(launch_sreduce(T, F->part, F->scal, PS_RR, PRED_RR, s), "sreduce");
     const bool graphs = !F->prof_on;
     if (graphs && !I.tried[pc]) fused_graph(F, pc);
-    // iterations in rounds of kRound; the host looks at the systems' active flags once a round
-    // (a system that stops inside a round keeps its x, r and p through the rest of it)
-    constexpr int kRound = 4;
+    // rounds of kRound iterations, one graph launch each
     for (;;) {
       hip_check(hipMemcpyAsync(F->scal_h, F->scal + size_t(PS_ACTIVE) * nsys, sizeof(double) * nsys,
                                hipMemcpyDeviceToHost, s),
@@ -571,12 +574,10 @@ eamg_status eamg_solve_fused(eamg_hierarchy *F, const double *const *b_dev, doub
       bool any = false;
       for (int m = 0; m < nsys; ++m) any = any || F->scal_h[m] != 0.0;
       if (!any) break;
-      for (int k = 0; k < kRound; ++k) {
-        if (graphs && I.g[pc])
-          hip_check(hipGraphLaunch(I.g[pc], s), "graph launch");
-        else
-          fused_iteration(F, pc, s);
-      }
+      if (graphs && I.g[pc])
+        hip_check(hipGraphLaunch(I.g[pc], s), "graph launch");
+      else
+        for (int k = 0; k < kRound; ++k) fused_iteration(F, pc, s);
     }
     // true residuals (slot RZ), then x out
     hip_check(launch_spmv(A, F->x, F->q, nullptr, s), "spmv");

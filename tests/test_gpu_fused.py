@@ -221,6 +221,30 @@ def test_fused_autotune_and_profiler():
             h.close()
 
 
+def test_fused_single_system_and_plain_cg():
+    # one system alone: the fused solve is that system's PCG; without a preconditioner the fused
+    # CG follows each system's plain CG
+    sysl = [_hier(*c) for c in [(10, 0.4, 31, 16384), (5, 0.3, 32, 0)]]
+    try:
+        bs = _bs(sysl)
+        f1 = E.Fused([sysl[0][1]], dense_tail_dofs=-1)
+        xs, st, infos = f1.solve(bs[:1], rtol=1e-14, max_it=6)
+        xr, ir = sysl[0][1].solve(bs[0], rtol=1e-14, max_it=6)
+        assert infos[0]["iterations"] == ir["iterations"]
+        assert float((xs[0] - xr).norm() / xr.norm()) <= 1e-10
+        f1.close()
+        f2 = E.Fused([h for _, h in sysl], dense_tail_dofs=0)
+        xs, st, infos = f2.solve(bs, rtol=1e-14, max_it=8, precond=E.EAMG_PRECOND_NONE)
+        for m, ((p, h), b, x, inf) in enumerate(zip(sysl, bs, xs, infos)):
+            xr, ir = h.solve(b, rtol=1e-14, max_it=8, precond=E.EAMG_PRECOND_NONE)
+            assert inf["iterations"] == ir["iterations"] == 8, (m, inf, ir)
+            assert float((x - xr).norm() / xr.norm()) <= 1e-10, m
+        f2.close()
+    finally:
+        for _, h in sysl:
+            h.close()
+
+
 def test_fused_component_destroyed_first():
     sysl = [_hier(*c) for c in [(6, 0.3, 21, 0), (9, 0.35, 22, 16384)]]
     f = E.Fused([h for _, h in sysl], dense_tail_dofs=-1)
