@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, FP64 NumPy/SciPy implementation
 of the method of Kogler & Schoeberl, "Auxiliary topology AMG" (arXiv 2011.13325).  It is the
-checker the GPU library is compared against.  Only ``tests/``, ``__graft_entry__.smoke()``
+reference the GPU library is compared against.  Only ``tests/``, ``__graft_entry__.smoke()``
 and the ``cpu_baseline`` leg of ``bench.py`` may import it; the library never does, and it
 shares no code with the library (only the seeded input generator ``gen`` serves both).
 
