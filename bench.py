@@ -54,6 +54,9 @@ def _args():
     ap.add_argument("--sections", default="all",
                     help="sub-records after the headline: all, or a comma list of sparse_tail, "
                          "paper_caps, cube64, multi, learned, cpu")
+    ap.add_argument("--per-colour", action="store_true",
+                    help="per-colour records of the FP32 colour sweeps (events around every colour "
+                         "launch), also with --headline-only")
     ap.add_argument("--per-level", action="store_true",
                     help="per-level kernel records of both V-cycle precisions, also with --headline-only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -175,6 +178,26 @@ def _per_level(E, hier, b, x, precond, stream):
              "us_per_launch": round(k["total_ms"] / k["launches"] * 1e3, 2),
              "GBps": round(k["bytes"] / (k["total_ms"] / 1e3) / 1e9, 1) if k["total_ms"] else None}
             for k in ks[:40]]
+
+
+def _per_colour(E, hier, b, x, precond, stream):
+    """Time and algorithmic bytes of every colour launch of the sweeps (one profiled solve with
+    events around each colour launch, which adds their own dispatch to every launch)."""
+    import re
+    E.eamg_profile_enable(hier.h, 3)
+    hier.solve(b, x, precond=precond, stream=stream)
+    ks = E.eamg_profile_read(hier.h, 4096)
+    E.eamg_profile_enable(hier.h, False)
+    out = []
+    for k in ks:
+        m = re.match(r"L(\d+) c(\d+) k_gs_color<\w+, (\d+), (true|false)>", k["name"])
+        if m:
+            out.append({"level": int(m.group(1)), "sweep": "fwd" if m.group(4) == "true" else "bwd",
+                        "colour": int(m.group(2)),
+                        "us_per_launch": round(k["total_ms"] / k["launches"] * 1e3, 2),
+                        "MB_per_launch": round(k["bytes"] / k["launches"] / 1e6, 4)})
+    out.sort(key=lambda r: (r["level"], r["sweep"], r["colour"]))
+    return out
 
 
 def _levels(E, h):
@@ -566,6 +589,8 @@ def main():
         out["per_level_fp32"] = _per_level(E, hier, b, torch.zeros_like(b), P32, stream)
     if args.per_level:
         out["per_level_fp64"] = _per_level(E, hier, b, torch.zeros_like(b), P64, stream)
+    if args.per_colour:
+        out["per_colour_fp32"] = _per_colour(E, hier, b, torch.zeros_like(b), P32, stream)
     hier.close()
 
     def want(name):
