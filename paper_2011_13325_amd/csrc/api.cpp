@@ -1233,6 +1233,7 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
   return guarded([&] {
     if (!h) fail(EAMG_ERR_INVALID_ARG, "NULL hierarchy");
     if (panel_width < 0 || panel_width > 64) fail(EAMG_ERR_INVALID_ARG, "panel_width must be in [0, 64]");
+    if (h->fused && panel_width > 0) fail(EAMG_ERR_INVALID_ARG, "a fused hierarchy has no panel kernels to tune");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int reps = 5;
     double before = 0.0, after = 0.0;
@@ -1417,7 +1418,6 @@ eamg_status eamg_autotune(eamg_hierarchy *h, int32_t panel_width, void *stream, 
     }
     invalidate_fused_graphs(h);
     if (panel_width > 0) {
-      reject_fused(h);
       int K = 1;
       while (K < panel_width) K <<= 1;
       const auto pa = tune_panels(h, K, s);

@@ -281,9 +281,14 @@ def test_fused_argument_checks(systems):
     finally:
         hq.close()
     b = torch.zeros(10, dtype=torch.float64, device="cuda")
-    with pytest.raises(E.EamgError) as e:
-        E.eamg_solve(f.h, b, torch.zeros_like(b))
-    assert e.value.status == E.EAMG_ERR_INVALID_ARG
+    for call in (lambda: E.eamg_solve(f.h, b, torch.zeros_like(b)),
+                 lambda: E.eamg_vcycle(f.h, b, torch.zeros_like(b)),
+                 lambda: E.eamg_vcycle_noalloc(f.h, b, torch.zeros_like(b)),
+                 lambda: E.eamg_stats(f.h),
+                 lambda: E.eamg_autotune(f.h, 8)):
+        with pytest.raises(E.EamgError) as e:
+            call()
+        assert e.value.status == E.EAMG_ERR_INVALID_ARG
     with pytest.raises(E.EamgError) as e:
         E.eamg_solve_fused(h0, [b], [torch.zeros_like(b)])
     assert e.value.status == E.EAMG_ERR_INVALID_ARG
