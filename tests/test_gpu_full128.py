@@ -1,5 +1,6 @@
 """Full-size properties of the 128^3 elasticity workload (6,291,456 dofs, nu = 0.45, RHS seed 3):
-the FP32 V-cycle inside FP64 CG, as the bench runs that size.
+the FP32 V-cycle inside FP64 CG, with the bench's headline settings (coarsening to < 500 dofs,
+dense V-cycle tail <= 16384 dofs, P_s row caps 6 / 4 / 4, sigma 18).
 
 The oracle cannot set up a problem of this size, so this checks what holds at any size, on the
 library's own hierarchy:
@@ -26,7 +27,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 N = 128
-COARSEST = 16384
+HEADLINE = dict(vcycle_fp32=1, coarsest_max_dofs=500, dense_tail_dofs=16384, cap_std_l0=6,
+                cap_std=4, cap_aux=4, sigma=18.0)
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,7 +45,7 @@ def big():
           f"{time.perf_counter() - t0:.1f} s", flush=True)
     t0 = time.perf_counter()
     h = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                    E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=COARSEST))
+                    E.eamg_default_setup_params(**HEADLINE))
     st = h.stats()
     print(f"[cube128] setup {time.perf_counter() - t0:.1f} s levels={st['n_levels']} n={st['n']} "
           f"vc={st['vc']:.3f} oc={st['oc']:.3f}", flush=True)

@@ -573,14 +573,18 @@ def test_cg_coefficients_match_the_oracle():
 
 # --- the P_s row caps the bench uses ---------------------------------------------------------
 # The caps of the auxiliary smoothed prolongation are free parameters (the paper's runs use 4
-# for edge-matrix rows and 8 / 6 for real-matrix rows); the bench runs 3 and 6 / 4, which trade
-# a sparser hierarchy for more iterations.  The oracle takes the same caps, so every parity bar
-# holds at that setting too.
-TUNED_CAPS = dict(cap_std_l0=6, cap_std=4, cap_aux=3)
+# for edge-matrix rows and 8 / 6 for real-matrix rows); the bench's headline runs 4 and 6 / 4 with
+# sigma = 18, its other workloads 3 and 6 / 4 with sigma = 20: sparser hierarchies for a few more
+# iterations.  The oracle takes the same parameters, so every parity bar holds there too.
+TUNED = {"headline": dict(cap_std_l0=6, cap_std=4, cap_aux=4, sigma=18.0),
+         "others": dict(cap_std_l0=6, cap_std=4, cap_aux=3)}
 
 
+@pytest.mark.parametrize("setting", list(TUNED))
 @pytest.mark.parametrize("name", ["cube17", "box_ragged"])
-def test_tuned_caps_parity(name):
+def test_tuned_caps_parity(name, setting):
+    TUNED_CAPS = TUNED[setting]
+    caps = [v for k, v in TUNED_CAPS.items() if k.startswith("cap_")]
     p = make_problem(**CASES[name])
     ho = _oracle(p, **TUNED_CAPS)
     hl = _lib(p, **TUNED_CAPS)
@@ -597,7 +601,7 @@ def test_tuned_caps_parity(name):
                 assert np.array_equal(ex["color"], lev.colors)
                 assert np.array_equal(ex["P_rowptr"], lev.P.row_ptr)
                 assert np.array_equal(ex["P_col"], lev.P.col)
-                assert np.diff(lev.P.row_ptr).max() <= max(TUNED_CAPS.values())
+                assert np.diff(lev.P.row_ptr).max() <= max(caps)
                 worstP = max(worstP, _block_rel_err(lev.P.row_ptr, ex["P_val"], lev.P.val))
         assert worstP <= PS_TOL and worstA <= A_TOL
         r = np.random.default_rng(3).standard_normal(p.n_dofs)
@@ -614,7 +618,7 @@ def test_tuned_caps_parity(name):
         assert info["status"] == E.EAMG_OK and info["rel_res_true"] <= 1e-8
         xk, _ = hl.solve(b, rtol=0.0, max_it=it)
         err = np.linalg.norm(xk.cpu().numpy() - xo) / np.linalg.norm(xo)
-        print(f"[caps {name}] levels={ho.n_levels} its={it} P_s {worstP:.1e} A {worstA:.1e} x {err:.1e}",
+        print(f"[caps {setting} {name}] levels={ho.n_levels} its={it} P_s {worstP:.1e} A {worstA:.1e} x {err:.1e}",
               flush=True)
         assert err <= X_TOL
     finally:

@@ -44,14 +44,17 @@ def _rbm_coarse(coords, d, r, k):
     return np.concatenate([np.concatenate([d + np.cross(x, r), r]) for x in coords])
 
 
-@pytest.fixture(scope="module", params=["paper caps", "caps 6/4/3"])
+@pytest.fixture(scope="module", params=["paper caps", "caps 6/4/3", "caps 6/4/4 sigma 18"])
 def neumann_caps(request, neumann):
-    # the P_s row caps are free parameters: rigid body modes must be reproduced for any of them
+    # the P_s row caps and sigma are free parameters: rigid body modes must be reproduced for any
+    # of them
     if request.param == "paper caps":
         return neumann
     p = neumann[0]
-    h = H.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                H.SetupParams(cap_std_l0=6, cap_std=4, cap_aux=3), factor_coarsest=False)
+    prm = (H.SetupParams(cap_std_l0=6, cap_std=4, cap_aux=3) if request.param == "caps 6/4/3"
+           else H.SetupParams(cap_std_l0=6, cap_std=4, cap_aux=4, sigma=18.0))
+    h = H.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet, prm,
+                factor_coarsest=False)
     return p, h
 
 
