@@ -7,7 +7,8 @@ symmetric multicolour block Gauss-Seidel sweep pre / post; the V-cycle in FP32 (
 vectors and accumulation) inside an FP64 CG (operator, vectors, inner products, stopping test)
 to ||r|| <= 1e-8 ||b||.  The V-cycle below the first level of at most 16384 dofs is applied as
 its dense matrix (computed at setup from the same hierarchy; the coarsest level is still the
-< 500-dof one).  P_s rows keep at most 4 edge-matrix columns and 6 / 4 real-matrix columns
+< 500-dof one); that matrix, which holds the coarsest inverse, is read in FP64 with FP64 sums,
+as the coarsest inverse is without a tail (--tail-fp32: an FP32 copy).  P_s rows keep at most 4 edge-matrix columns and 6 / 4 real-matrix columns
 (level 0 / coarser), and the matching accepts agglomerates whose two-grid bound is below sigma = 18:
 free parameters (the paper's runs use caps 4 and 8 / 6 and give no sigma), chosen by measurement
 for this workload; the other workloads use caps 3 and 6 / 4 with sigma = 20, measured best there.
@@ -18,6 +19,7 @@ separately, with its phases split into host, device and copies.  Reported beside
 in the same line:
   fp64_vcycle        the same solve with the FP64 V-cycle, and the FP32 solution's distance to it
   sparse_tail        the same hierarchy with every level's sweeps run sparse (no dense tail)
+  tail_precision     the same solve with the dense tail read in the other precision
   paper_caps         the same solve with the paper's P_s row caps
   cube64             64^3, nu = 0.3, RHS seed 1, FP64 and FP32 V-cycle; its 32 seeded load
                      cases as one block-panel solve ("batched")
@@ -49,6 +51,9 @@ def _args():
                     help="coarsening stops once a level has fewer dofs than this")
     ap.add_argument("--dense-tail", type=int, default=16384,
                     help="dofs of the largest level whose V-cycle is applied as a dense matrix (0: none)")
+    ap.add_argument("--tail-fp32", action="store_true",
+                    help="the FP32 V-cycle reads an FP32 copy of the dense tail (default: the FP64 "
+                         "tail, which holds the coarsest inverse, with FP64 sums)")
     ap.add_argument("--caps", default="6,4,4",
                     help="headline P_s row caps: real-matrix rows on level 0, on coarser levels, "
                          "edge-matrix rows")
@@ -62,7 +67,7 @@ def _args():
                     help="only the headline solve (for profiler runs)")
     ap.add_argument("--sections", default="all",
                     help="sub-records after the headline: all, or a comma list of sparse_tail, "
-                         "paper_caps, cube64, multi, learned, cpu")
+                         "tail_precision, paper_caps, cube64, multi, learned, cpu")
     ap.add_argument("--per-colour", action="store_true",
                     help="per-colour records of the FP32 colour sweeps (events around every colour "
                          "launch), also with --headline-only")
@@ -94,7 +99,7 @@ def _caps(spec):
 def _params(E, args, **kw):
     """Setup parameters of the headline."""
     prm = dict(vcycle_fp32=1, coarsest_max_dofs=args.coarsest, dense_tail_dofs=args.dense_tail,
-               sigma=args.sigma, **_caps(args.caps))
+               dense_tail_fp32=int(args.tail_fp32), sigma=args.sigma, **_caps(args.caps))
     prm.update(kw)
     return E.eamg_default_setup_params(**prm)
 
@@ -102,7 +107,7 @@ def _params(E, args, **kw):
 def _sub_params(E, args, **kw):
     """Setup parameters of the other workloads (their own measured best caps and sigma)."""
     prm = dict(vcycle_fp32=1, coarsest_max_dofs=args.coarsest, dense_tail_dofs=args.dense_tail,
-               sigma=args.sub_sigma, **_caps(args.sub_caps))
+               dense_tail_fp32=int(args.tail_fp32), sigma=args.sub_sigma, **_caps(args.sub_caps))
     prm.update(kw)
     return E.eamg_default_setup_params(**prm)
 
@@ -582,8 +587,9 @@ def main():
                                f"{args.caps}, sigma {args.sigma:g}",
                    "p_s_caps": _caps(args.caps), "sigma": args.sigma,
                    "other_workloads": {"p_s_caps": _caps(args.sub_caps), "sigma": args.sub_sigma},
-                   "precision": "V-cycle FP32 (matrices, vectors, accumulation; dense tail FP32 "
-                                "with FP64 sums); CG FP64",
+                   "precision": "V-cycle FP32 (matrices, vectors, accumulation; the dense tail "
+                                "with the coarsest inverse " +
+                                ("FP32 with FP64 sums" if args.tail_fp32 else "FP64") + "); CG FP64",
                    "coarsest_max_dofs": args.coarsest, "dense_tail": {"level": tail[0], "dofs": tail[1]},
                    "dofs": p.n_dofs, "free_dofs": p.n_free_dofs, "iterations": its,
                    "rel_res_true": info["rel_res_true"], "levels": st["n_levels"],
@@ -627,6 +633,21 @@ def main():
                                   "dense_tail_speedup": ms2 / ms}
             h2.close()
             _progress(f"sparse tail {ms2:.3f} ms")
+        if want("tail_precision") and args.dense_tail > 0:
+            # the same hierarchy with the dense tail read in the other precision
+            t32 = 0 if args.tail_fp32 else 1
+            h4, su4 = _setup(E, torch, p, _params(E, args, dense_tail_fp32=t32), stream)
+            E.eamg_autotune(h4.h, panel_width=0, stream=stream)
+            x4 = torch.zeros_like(b)
+            ms4, info4 = _timed_solves(E, torch, h4, b, x4, stream, args.steps, args.warmup, P32)
+            out["tail_precision"] = {"dense_tail_fp32": t32, "ms_per_step": ms4,
+                                     "value": p.n_free_dofs / (ms4 / 1e3),
+                                     "iterations": info4["iterations"],
+                                     "rel_res_true": info4["rel_res_true"],
+                                     "solution_rel_diff_vs_fp64_vcycle": float((x4 - x64).norm() / x64.norm()),
+                                     "speedup_vs_headline": ms / ms4}
+            h4.close()
+            _progress(f"tail precision {ms4:.3f} ms")
         # the paper's P_s row caps (4 for edge-matrix rows, 8 / 6 for real-matrix rows)
         paper = dict(cap_std_l0=8, cap_std=6, cap_aux=4)
         if want("paper_caps") and paper != _caps(args.caps):

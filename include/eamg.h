@@ -126,11 +126,17 @@ typedef struct {
  *                     alg:tg applied recursively, starting from x = 0); it is computed at setup
  *                     by running that part of the V-cycle on the columns of the identity
  *                     (the batched V-cycle of eamg_solve_batch, 64 columns per pass) and
- *                     applied as one dense product per V-cycle (FP64, plus an FP32 copy with
- *                     vcycle_fp32).  The hierarchy, and the V-cycle as an operator, are those of
- *                     the sparse path; only the rounding differs.  No tail when that level is
- *                     the coarsest or no level qualifies.  Memory: ld^2 doubles (+ floats), ld =
- *                     the tail's dofs rounded up to 128 (256).
+ *                     applied as one dense product per V-cycle (an FP64 matrix with FP64
+ *                     accumulation, in either V-cycle precision unless dense_tail_fp32).  The
+ *                     hierarchy, and the V-cycle as an operator, are those of the sparse path;
+ *                     only the rounding differs.  No tail when that level is the coarsest or no
+ *                     level qualifies.  Memory: ld^2 doubles (+ ld32^2 floats with
+ *                     dense_tail_fp32), ld = the tail's dofs rounded up to 128 (ld32: 256).
+ *  dense_tail_fp32    0: the FP32 V-cycle applies the dense tail, which holds the coarsest
+ *                     level's inverse, from its FP64 matrix with FP64 accumulation (FP32 vectors
+ *                     in and out), as it applies the coarsest inverse without a tail (default).
+ *                     1 (needs vcycle_fp32): an FP32 copy of the tail is kept and the FP32
+ *                     V-cycle reads it instead (FP64 accumulation), half the tail's bytes.
  */
 typedef struct eamg_gnn eamg_gnn;
 typedef struct {
@@ -146,11 +152,13 @@ typedef struct {
   int32_t mu_s_only;
   int32_t gpu_criteria;
   int32_t dense_tail_dofs;
+  int32_t dense_tail_fp32;
 } eamg_setup_params;
 
 /* Preconditioners of the PCG.  EAMG_PRECOND_VCYCLE_FP32 runs the whole V-cycle (smoothers,
  * residual, transfers, their matrices, D^+ and level vectors) in FP32 with FP32 accumulation,
- * except the coarsest level's inverse (FP64 matrix, FP64 accumulation, FP32 vectors); the CG
+ * except the coarsest level's inverse and the dense tail that holds it (FP64 matrix, FP64
+ * accumulation, FP32 vectors; the tail in FP32 with dense_tail_fp32 = 1); the CG
  * operator, vectors, inner products and the stopping test stay FP64, with one conversion of r
  * to FP32 and of z to FP64 per iteration.  It needs a setup with vcycle_fp32 = 1. */
 enum {

@@ -64,7 +64,8 @@ class eamg_setup_params(ctypes.Structure):
                 ("tie_rtol", ctypes.c_double), ("vcycle_fp32", ctypes.c_int32),
                 ("gnn", ctypes.c_void_p), ("gnn_skip", ctypes.c_double),
                 ("gnn_record", ctypes.c_int32), ("mu_s_only", ctypes.c_int32),
-                ("gpu_criteria", ctypes.c_int32), ("dense_tail_dofs", ctypes.c_int32)]
+                ("gpu_criteria", ctypes.c_int32), ("dense_tail_dofs", ctypes.c_int32),
+                ("dense_tail_fp32", ctypes.c_int32)]
 
 
 class eamg_solve_params(ctypes.Structure):

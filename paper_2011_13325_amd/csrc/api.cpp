@@ -50,6 +50,7 @@ eamg_setup_params defaults() {
   p.mu_s_only = 0;
   p.gpu_criteria = 1;
   p.dense_tail_dofs = 0;
+  p.dense_tail_fp32 = 0;
   return p;
 }
 
@@ -75,6 +76,9 @@ void validate_params(const eamg_setup_params &p) {
     fail(EAMG_ERR_INVALID_ARG, "gpu_criteria must be 0, 1 or 2");
   if (p.dense_tail_dofs < 0 || p.dense_tail_dofs > kMaxCoarsestDofs)
     fail(EAMG_ERR_INVALID_ARG, "dense_tail_dofs must be in [0, 16384]");
+  if (p.dense_tail_fp32 != 0 && p.dense_tail_fp32 != 1)
+    fail(EAMG_ERR_INVALID_ARG, "dense_tail_fp32 must be 0 or 1");
+  if (p.dense_tail_fp32 && !p.vcycle_fp32) fail(EAMG_ERR_INVALID_ARG, "dense_tail_fp32 needs vcycle_fp32 = 1");
 }
 
 void validate_problem(const eamg_problem *pb) {
@@ -492,6 +496,13 @@ hipError_t resid_update(const Level &L, const T *x, T *r, hipStream_t s) {
   return hipSuccess;
 }
 
+// Algorithmic bytes of one dense-tail apply: the packed upper tiles (FP32 or FP64), both passes
+// over the partial sums, and x and y.
+double tail_apply_bytes(const eamg_hierarchy *h, bool fp32_matrix, size_t vec_bytes) {
+  return double(sym_entries(h->nT)) * (fp32_matrix ? 4.0 : 8.0) + 2.0 * 8.0 * double(sym_work_doubles(h->nT)) +
+         2.0 * h->nT * double(vec_bytes);
+}
+
 // The dense operators of a fused hierarchy's level: x = D b on each of their systems' rows.
 template <class T>
 void dense_sets(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s);
@@ -527,18 +538,18 @@ void vcycle_t(eamg_hierarchy *h, size_t l, const T *b, T *x, hipStream_t s) {
     if (L.smooth_rows() == 0) return;
   }
   if (int(l) == h->tail_level) {
-    // the V-cycle of this level and every level below it, as one dense matrix
-    const double by = double(h->nT) * h->nT * double(sizeof(T)) + 2.0 * h->nT * double(sizeof(T));
-    if (f32)
-      timed(h, "dense tail", lvname(h, l, "k_dense_gemv32"), by, s, [&] {
-        return launch_dense_gemv32(h->nT, h->ldT32, h->tail32, reinterpret_cast<const float *>(b),
-                                   reinterpret_cast<float *>(x), s);
+    // the V-cycle of this level and every level below it, as one dense matrix (FP64 unless the
+    // FP32 V-cycle was set up with an FP32 copy), its upper tiles packed
+    const bool m32 = f32 && h->tailS32;
+    const double by = tail_apply_bytes(h, m32, sizeof(T));
+    if (m32)
+      timed(h, "dense tail", lvname(h, l, "k_dense_symv<float, float>"), by, s, [&] {
+        return launch_dense_symv<float, float>(h->nT, h->tailS32, reinterpret_cast<const float *>(b),
+                                               reinterpret_cast<float *>(x), h->tailW, s);
       });
     else
-      timed(h, "dense tail", lvname(h, l, "k_dense_gemv<double>"), by, s, [&] {
-        return launch_dense_gemv<double>(h->nT, h->ldT, h->tail, reinterpret_cast<const double *>(b),
-                                         reinterpret_cast<double *>(x), s);
-      });
+      timed(h, "dense tail", lvname(h, l, "k_dense_symv<double, " + ty + ">"), by, s,
+            [&] { return launch_dense_symv<double, T>(h->nT, h->tailS, b, x, h->tailW, s); });
     return;
   }
   if (l + 1 == h->lv.size()) {
@@ -1692,8 +1703,7 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
     for (size_t l = 0; l < h->lv.size(); ++l) {
       const Level &L = h->lv[l];
       if (int(l) == h->tail_level) {
-        const double s = f32 ? 4.0 : 8.0;
-        v += double(h->nT) * h->nT * s + 2.0 * h->nT * s;
+        v += tail_apply_bytes(h, f32 && h->tailS32, f32 ? 4 : 8);
         break;
       }
       if (l + 1 == h->lv.size()) {

@@ -413,12 +413,20 @@ DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32,
 }
 
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
-  const DenseTail d = make_dense_tail(h, t, h->arena, h->prm.vcycle_fp32 != 0, s);
+  const DenseTail d = make_dense_tail(h, t, h->arena, h->prm.vcycle_fp32 && h->prm.dense_tail_fp32, s);
   h->tail = d.T;
   h->nT = d.n;
   h->ldT = d.ld;
   h->tail32 = d.T32;
   h->ldT32 = d.ld32;
+  h->tailS = h->arena.alloc<double>(sym_entries(d.n));
+  hip_check(launch_pack_sym<double>(d.n, d.ld, d.T, h->tailS, s), "pack tail");
+  if (d.T32) {
+    h->tailS32 = h->arena.alloc<float>(sym_entries(d.n));
+    hip_check(launch_pack_sym<float>(d.n, d.ld, d.T, h->tailS32, s), "pack tail f32");
+  }
+  h->tailW = h->arena.alloc<double>(sym_work_doubles(d.n));
+  hip_check(hipStreamSynchronize(s), "sync");
   h->tail_level = int(t);
 }
 

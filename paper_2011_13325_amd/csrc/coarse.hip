@@ -267,6 +267,119 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemv32(int n, int ld, const 
   if (lane == 0) y[row] = float(acc);
 }
 
+// ---- symmetric packed product ----------------------------------------------------------------
+
+// Tile (i, j) of the upper block triangle from its packed index t (row by row: tile (i, j) has
+// index i * nb - i * (i - 1) / 2 + j - i).  Uniform over the workgroup.
+__device__ inline void sym_tile_of(int t, int nb, int &i, int &j) {
+  int r = t, a = 0;
+  while (r >= nb - a) {
+    r -= nb - a;
+    ++a;
+  }
+  i = a;
+  j = a + r;
+}
+
+// S (packed, TM) := the upper tiles of (D + D^T) / 2 for the first n rows and columns of D
+// (leading dimension ld), zero elsewhere.  Grid: (entries per tile / 256, tiles).
+template <class TM>
+__global__ void k_pack_sym(int n, int ld, int nb, const double *__restrict__ D, TM *__restrict__ S) {
+  int i, j;
+  sym_tile_of(int(blockIdx.y), nb, i, j);
+  const int e = int(blockIdx.x) * blockDim.x + threadIdx.x;   // < kSymTile^2
+  const int a = i * kSymTile + e / kSymTile, b = j * kSymTile + e % kSymTile;
+  double v = 0.0;
+  if (a < n && b < n) v = 0.5 * (D[size_t(a) * ld + b] + D[size_t(b) * ld + a]);
+  S[size_t(blockIdx.y) * kSymTile * kSymTile + e] = TM(v);
+}
+
+__device__ inline double2 load_pair(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+__device__ inline double2 load_pair(const float *p) {
+  const float2 v = *reinterpret_cast<const float2 *>(p);
+  return make_double2(double(v.x), double(v.y));
+}
+
+// One tile (i, j) of y = S x per workgroup of four wavefronts.  Wavefront w takes rows
+// 32 w .. 32 w + 31 of the tile, lane l columns 2 l and 2 l + 1 (one 16- or 8-byte load per
+// row).  Row sums (the tile's part of y_i) are reduced across the lanes by halving exchanges;
+// column sums (the part of y_j that the mirrored tile (j, i) would give, i < j) accumulate per
+// lane and meet across the wavefronts in LDS.  Both go to W[b][q] (128 doubles: the part of
+// output block b from source block q); every (b, q) is written exactly once.
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void k_dense_symv(int n, int nb, const TM *__restrict__ S,
+                                                    const TV *__restrict__ x, double *__restrict__ W) {
+  __shared__ double colp[4][kSymTile];
+  int i, j;
+  sym_tile_of(int(blockIdx.x), nb, i, j);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * w;
+  const TM *T = S + size_t(blockIdx.x) * kSymTile * kSymTile + size_t(r0) * kSymTile + 2 * lane;
+  // the three x loads of a lane at clamped indices (no branch between them), zero past n; x of
+  // the wavefront's 32 rows is loaded once per lane (lanes l and l + 32 alike) and read out of
+  // lane r for row r, so the loop has no load of x and no wait
+  const int cj = j * kSymTile + 2 * lane;
+  const int ri = i * kSymTile + r0 + (lane & 31);
+  const double xj0r = double(x[min(cj, n - 1)]);
+  const double xj1r = double(x[min(cj + 1, n - 1)]);
+  const double xlr = double(x[min(ri, n - 1)]);
+  const double xj0 = cj < n ? xj0r : 0.0;
+  const double xj1 = cj + 1 < n ? xj1r : 0.0;
+  const double xl = ri < n ? xlr : 0.0;
+  const int xl_lo = __double2loint(xl), xl_hi = __double2hiint(xl);
+  double p[32];
+  double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const double2 v = load_pair(T + r * kSymTile);
+    const double xi = __hiloint2double(__builtin_amdgcn_readlane(xl_hi, r), __builtin_amdgcn_readlane(xl_lo, r));
+    p[r] = fma(v.y, xj1, v.x * xj0);
+    c0 = fma(v.x, xi, c0);
+    c1 = fma(v.y, xi, c1);
+  }
+  // p[k] of lane l is its part of row k; after the exchange over lane bit b (32, 16, .., 2) a
+  // lane keeps the half of its rows that matches that bit, summed with its partner's
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    const bool up = (lane & (2 * h)) != 0;
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      const double send = up ? p[k] : p[k + h];
+      const double keep = up ? p[k + h] : p[k];
+      p[k] = keep + __shfl_xor(send, 2 * h, 64);
+    }
+  }
+  const double rs = p[0] + __shfl_xor(p[0], 1, 64);   // row (lane >> 1) of this wavefront
+  if ((lane & 1) == 0) W[(size_t(i) * nb + j) * kSymTile + r0 + (lane >> 1)] = rs;
+  if (i != j) {
+    colp[w][2 * lane] = c0;
+    colp[w][2 * lane + 1] = c1;
+    __syncthreads();
+    if (threadIdx.x < kSymTile) {
+      const int k = threadIdx.x;
+      W[(size_t(j) * nb + i) * kSymTile + k] = ((colp[0][k] + colp[1][k]) + colp[2][k]) + colp[3][k];
+    }
+  }
+}
+
+// y[g] = sum over q of W[g / 128][q][g % 128], q ascending.
+template <class TV>
+__global__ void k_dense_symv_sum(int n, int nb, const double *__restrict__ W, TV *__restrict__ y) {
+  const int g = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double *w = W + size_t(g / kSymTile) * nb * kSymTile + g % kSymTile;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int q = 0;
+  for (; q + 4 <= nb; q += 4) {
+    a0 += w[size_t(q) * kSymTile];
+    a1 += w[size_t(q + 1) * kSymTile];
+    a2 += w[size_t(q + 2) * kSymTile];
+    a3 += w[size_t(q + 3) * kSymTile];
+  }
+  for (; q < nb; ++q) a0 += w[size_t(q) * kSymTile];
+  y[g] = TV((a0 + a1) + (a2 + a3));
+}
+
 // Panel of K columns (entry (dof, k) at dof * K + k) holding columns j0 .. j0 + K - 1 of the
 // n x n identity (zero where j0 + k >= n).
 __global__ void k_identity_panel(int n, int K, int j0, double *__restrict__ B) {
@@ -466,6 +579,31 @@ hipError_t launch_dense_panel(int n, int ld, int K, const double *D, const T *X,
   return hipGetLastError();
 }
 
+template <class TM>
+hipError_t launch_pack_sym(int n, int ld, const double *D, TM *S, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ld < n || ld % kSymTile != 0) return hipErrorInvalidValue;
+  const int nb = sym_blocks(n);
+  hipLaunchKernelGGL(k_pack_sym<TM>, dim3(kSymTile * kSymTile / 256, unsigned(sym_tiles(nb))), dim3(256), 0, s,
+                     n, ld, nb, D, S);
+  return hipGetLastError();
+}
+
+template <class TM, class TV>
+hipError_t launch_dense_symv(int n, const TM *S, const TV *x, TV *y, double *W, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (!S || !W) return hipErrorInvalidValue;
+  const int nb = sym_blocks(n);
+  hipLaunchKernelGGL((k_dense_symv<TM, TV>), dim3(unsigned(sym_tiles(nb))), dim3(256), 0, s, n, nb, S, x, W);
+  hipLaunchKernelGGL(k_dense_symv_sum<TV>, dim3(cdiv(n, kThreads)), dim3(kThreads), 0, s, n, nb, W, y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pack_sym<double>(int, int, const double *, double *, hipStream_t);
+template hipError_t launch_pack_sym<float>(int, int, const double *, float *, hipStream_t);
+template hipError_t launch_dense_symv<double, double>(int, const double *, const double *, double *, double *, hipStream_t);
+template hipError_t launch_dense_symv<double, float>(int, const double *, const float *, float *, double *, hipStream_t);
+template hipError_t launch_dense_symv<float, float>(int, const float *, const float *, float *, double *, hipStream_t);
 template hipError_t launch_dense_gemv<double>(int, int, const double *, const double *, double *, hipStream_t);
 template hipError_t launch_dense_gemv<float>(int, int, const double *, const float *, float *, hipStream_t);
 template hipError_t launch_dense_panel<double>(int, int, int, const double *, const double *, double *, double *, hipStream_t);

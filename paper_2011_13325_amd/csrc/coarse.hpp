@@ -53,6 +53,30 @@ hipError_t launch_dense_gemv32(int n, int ld, const float *D, const float *x, fl
 
 inline int dense_ld32(int n) { return (n + 255) / 256 * 256; }
 
+// Packed symmetric storage: the tiles (i, j), i <= j, of kSymTile x kSymTile entries of the upper
+// block triangle of an n x n symmetric matrix (nb = ceil(n / kSymTile) block rows), tile (i, j)
+// at index i * nb - i * (i - 1) / 2 + j - i, row-major inside, zero past n: about half the bytes
+// of the full matrix.
+constexpr int kSymTile = 128;
+inline int sym_blocks(int n) { return (n + kSymTile - 1) / kSymTile; }
+inline int64_t sym_tiles(int nb) { return int64_t(nb) * (nb + 1) / 2; }
+inline size_t sym_entries(int n) { return size_t(sym_tiles(sym_blocks(n))) * kSymTile * kSymTile; }
+// Workspace of launch_dense_symv: nb * nb partial blocks of kSymTile doubles.
+inline size_t sym_work_doubles(int n) { return size_t(sym_blocks(n)) * sym_blocks(n) * kSymTile; }
+
+// S (packed, sym_entries(n) values of TM) := the upper tiles of (D + D^T) / 2, D n x n with
+// leading dimension ld (a multiple of kSymTile).
+template <class TM>
+hipError_t launch_pack_sym(int n, int ld, const double *D, TM *S, hipStream_t s);
+
+// y = S x for the packed symmetric S (TM values; FP64 accumulation; x, y of length n; TV double
+// with TM double, float with either).  Two launches: one workgroup per stored tile writes its
+// row sums and (off the diagonal) its column sums into W (sym_work_doubles(n)); a second sums
+// the parts of every output in a fixed order, so the result is reproducible.  Calls that share W
+// must not overlap.
+template <class TM, class TV>
+hipError_t launch_dense_symv(int n, const TM *S, const TV *x, TV *y, double *W, hipStream_t s);
+
 // B (n x K panel, entry (dof, k) at dof * K + k) := columns j0 .. j0 + K - 1 of the identity.
 hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s);
 

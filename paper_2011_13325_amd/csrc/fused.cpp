@@ -262,9 +262,13 @@ void build_fused_level(eamg_hierarchy *F, const std::vector<eamg_hierarchy *> &h
       if ((own.T ? own.n : H->nT) != n) fail(EAMG_ERR_INVALID_ARG, "dense tail size mismatch");
       d64.push_back({T, off, n, ld, 0, m});
       by64 += nn * 8.0 + 16.0 * n;
-      if (f32) {
+      if (f32 && F->prm.dense_tail_fp32 && T32) {
         d32f.push_back({T32, off, n, ld32, 0, m});
         by32f += nn * 4.0 + 8.0 * n;
+      } else if (f32) {
+        // the FP32 V-cycle reads the FP64 tail, as it reads a coarsest inverse
+        d32d.push_back({T, off, n, ld, 0, m});
+        by32d += nn * 8.0 + 8.0 * n;
       }
     } else {
       if (H->nL != n || !H->Ainv) fail(EAMG_ERR_INVALID_ARG, "coarsest inverse size mismatch");
@@ -413,7 +417,12 @@ eamg_status eamg_fuse(int32_t nsys, eamg_hierarchy *const *hs, int32_t dense_tai
     F->device = dev;
     F->prm = sys[0]->prm;
     F->prm.vcycle_fp32 = 1;
-    for (eamg_hierarchy *H : sys) F->prm.vcycle_fp32 = F->prm.vcycle_fp32 && H->prm.vcycle_fp32;
+    F->prm.dense_tail_fp32 = 1;
+    for (eamg_hierarchy *H : sys) {
+      F->prm.vcycle_fp32 = F->prm.vcycle_fp32 && H->prm.vcycle_fp32;
+      // FP32 dense tails only if every system asked for them
+      F->prm.dense_tail_fp32 = F->prm.dense_tail_fp32 && H->prm.dense_tail_fp32;
+    }
     F->tail_level = -1;
     auto info = std::make_unique<FusedInfo>();
     info->sys = sys;
@@ -444,7 +453,8 @@ eamg_status eamg_fuse(int32_t nsys, eamg_hierarchy *const *hs, int32_t dense_tai
         eamg_hierarchy *H = sys[size_t(m)];
         const int d = F->fused->depth[size_t(m)];
         if (d + 1 < int(H->lv.size()) && H->tail_level != d)
-          F->fused->own[size_t(m)] = make_dense_tail(H, size_t(d), F->arena, F->prm.vcycle_fp32 != 0, s);
+          F->fused->own[size_t(m)] =
+              make_dense_tail(H, size_t(d), F->arena, F->prm.vcycle_fp32 && F->prm.dense_tail_fp32, s);
       }
     for (int l = 0; l < U; ++l) build_fused_level(F.get(), sys, F->fused->depth, ord, l, s);
     // level 0: natural -> fused maps, segments of the CG vectors, CG workspace

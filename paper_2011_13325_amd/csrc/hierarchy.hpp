@@ -285,7 +285,12 @@ struct eamg_hierarchy {
   int tail_level = -1;
   int nT = 0, ldT = 0, ldT32 = 0;
   double *tail = nullptr;
-  float *tail32 = nullptr;    // FP32 copy (with vcycle_fp32)
+  float *tail32 = nullptr;    // FP32 copy (with dense_tail_fp32)
+  // the tail's upper tiles, packed (the V-cycle operator is symmetric): FP64 and, with
+  // dense_tail_fp32, FP32; the single-vector V-cycle reads these, with tailW as its workspace
+  double *tailS = nullptr;
+  float *tailS32 = nullptr;
+  double *tailW = nullptr;
   uint8_t *dir = nullptr;     // level-0 Dirichlet mask (natural)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *bp = nullptr;
   double *part = nullptr, *scal = nullptr;

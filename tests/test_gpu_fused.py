@@ -140,6 +140,39 @@ def test_fused_equals_individual_at_fixed_count(systems, precond, bar):
         assert err <= bar, (m, err)
 
 
+@pytest.mark.parametrize("mode", [-1, 2048], ids=["own_tails", "fused_tails"])
+def test_fused_fp32_tails(hierarchies, mode):
+    # systems set up with dense_tail_fp32 = 1: the fused FP32 V-cycle reads FP32 copies of the
+    # dense tails (its own and the systems'), and equals each system's own FP32 solve (which
+    # reads its FP32 tail) at a fixed count up to FP32 rounding
+    sysl = []
+    try:
+        for n, nu, seed, tail in SIZES[2:5]:
+            p = make_problem(n, nu=nu, seed=seed)
+            sysl.append((p, E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                                        E.eamg_default_setup_params(vcycle_fp32=1, dense_tail_dofs=tail,
+                                                                    dense_tail_fp32=1))))
+        f = E.Fused([h for _, h in sysl], dense_tail_dofs=mode)
+        try:
+            bs = _bs(sysl)
+            K = 6
+            xs, _, infos = f.solve(bs, rtol=1e-14, max_it=K, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+            for m, ((p, h), b, x, inf) in enumerate(zip(sysl, bs, xs, infos)):
+                xr, ir = h.solve(b, rtol=1e-14, max_it=K, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+                assert abs(inf["iterations"] - ir["iterations"]) <= 1, (m, inf, ir)
+                err = float((x - xr).norm() / xr.norm())
+                assert err <= 1e-5, (m, err)
+            xs, st, infos = f.solve(bs, rtol=1e-8, precond=E.EAMG_PRECOND_VCYCLE_FP32)
+            assert st == E.EAMG_OK
+            for (p, _), x in zip(sysl, xs):
+                assert _true_res(p, x.cpu().numpy()) <= 1e-8
+        finally:
+            f.close()
+    finally:
+        for _, h in sysl:
+            h.close()
+
+
 def test_fused_reproducible_and_graph_equals_eager(systems):
     sysl, f = systems
     bs = _bs(sysl)

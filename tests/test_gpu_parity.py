@@ -474,13 +474,15 @@ def test_every_row_team_shape_keeps_parity(group):
 # and the V-cycle is the same linear map, so every FP64 parity bar of the sparse path holds.
 
 def _tail_lib(p, dofs, **prm):
+    # the FP32 V-cycle reads the FP64 tail unless dense_tail_fp32 = 1 (then an FP32 copy)
     return E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
                        E.eamg_default_setup_params(dense_tail_dofs=dofs, vcycle_fp32=1, **prm))
 
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("where", ["first", "deepest"])
-def test_dense_tail_parity(name, where):
+@pytest.mark.parametrize("tail32", [0, 1])
+def test_dense_tail_parity(name, where, tail32):
     p = make_problem(**CASES[name])
     ho = _oracle_cached(name, p)
     if ho.n_levels < 3:
@@ -491,7 +493,7 @@ def test_dense_tail_parity(name, where):
     thr = dofs[t] if where == "deepest" else max(dofs[1:])
     if any(d <= thr for d in dofs[1:t]) or thr > 16384:
         pytest.skip("no threshold selects this level")
-    hl = _tail_lib(p, thr)
+    hl = _tail_lib(p, thr, dense_tail_fp32=tail32)
     try:
         lvl, nT = E.eamg_dense_tail(hl.h)
         assert lvl == t and nT == dofs[t], (lvl, nT, t)
@@ -504,7 +506,7 @@ def test_dense_tail_parity(name, where):
             E.eamg_vcycle(hl.h, _dev(r), z, prec)
             torch.cuda.synchronize()
             err = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
-            print(f"[tail {name} L{t} prec={prec}] V-cycle rel err {err:.2e}", flush=True)
+            print(f"[tail {name} L{t} tail32={tail32} prec={prec}] V-cycle rel err {err:.2e}", flush=True)
             assert err <= tol
         xo, it, _, _, conv = oracle.pcg(ho, p.b, rtol=1e-8)
         b = _dev(p.b)
@@ -535,6 +537,11 @@ def test_dense_tail_off_below_coarsest_and_rejected_sizes():
     with pytest.raises(E.EamgError) as ei:
         _tail_lib(p, 20000)
     assert ei.value.status == E.EAMG_ERR_INVALID_ARG
+    # an FP32 tail needs the FP32 V-cycle's copies
+    with pytest.raises(E.EamgError) as ei:
+        E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
+                    E.eamg_default_setup_params(dense_tail_dofs=4096, dense_tail_fp32=1))
+    assert ei.value.status == E.EAMG_ERR_INVALID_ARG and "vcycle_fp32" in str(ei.value)
 
 
 def test_cg_coefficients_match_the_oracle():
