@@ -128,15 +128,18 @@ typedef struct {
  *                     (the batched V-cycle of eamg_solve_batch, 64 columns per pass) and
  *                     applied as one dense product per V-cycle (an FP64 matrix with FP64
  *                     accumulation, in either V-cycle precision unless dense_tail_fp32).  The
- *                     hierarchy, and the V-cycle as an operator, are those of the sparse path;
- *                     only the rounding differs.  No tail when that level is the coarsest or no
- *                     level qualifies.  Memory: ld^2 doubles (+ ld32^2 floats with
- *                     dense_tail_fp32), ld = the tail's dofs rounded up to 128 (ld32: 256).
+ *                     operator is symmetric, so the product reads only the 128 x 128 tiles of
+ *                     its upper block triangle, symmetrized.  The hierarchy, and the V-cycle as
+ *                     an operator, are those of the sparse path; only the rounding differs.  No
+ *                     tail when that level is the coarsest or no level qualifies.  Memory: about
+ *                     1.5 ld^2 doubles (the full matrix, kept for the block panels, and the upper
+ *                     tiles; + 0.5 ld^2 floats with dense_tail_fp32), ld = the tail's dofs
+ *                     rounded up to 128.
  *  dense_tail_fp32    0: the FP32 V-cycle applies the dense tail, which holds the coarsest
  *                     level's inverse, from its FP64 matrix with FP64 accumulation (FP32 vectors
  *                     in and out), as it applies the coarsest inverse without a tail (default).
- *                     1 (needs vcycle_fp32): an FP32 copy of the tail is kept and the FP32
- *                     V-cycle reads it instead (FP64 accumulation), half the tail's bytes.
+ *                     1 (needs vcycle_fp32): the upper tiles are also kept in FP32 and the FP32
+ *                     V-cycle reads those instead (FP64 accumulation), half the bytes.
  */
 typedef struct eamg_gnn eamg_gnn;
 typedef struct {

@@ -510,20 +510,22 @@ template <>
 void dense_sets<double>(eamg_hierarchy *h, size_t l, const double *b, double *x, hipStream_t s) {
   const DenseSet &d = h->lv[l].dense[0];
   if (!d.count) return;
-  timed(h, "dense parts", lvname(h, l, "k_dense_multi<double, double>"), d.bytes, s, [&] {
-    return launch_dense_multi<double, double>(d.count, d.parts, d.rows, d.active, b, x, s);
+  timed(h, "dense parts", lvname(h, l, "k_dense_symv_multi<double, double>"), d.bytes, s, [&] {
+    return launch_dense_symv_multi<double, double>(d.count, d.parts, d.tiles, d.rows, d.active, b, x, d.W, s);
   });
 }
 template <>
 void dense_sets<float>(eamg_hierarchy *h, size_t l, const float *b, float *x, hipStream_t s) {
   const DenseSet &d32 = h->lv[l].dense[1], &d64 = h->lv[l].dense[2];
   if (d32.count)
-    timed(h, "dense parts", lvname(h, l, "k_dense_multi<float, float>"), d32.bytes, s, [&] {
-      return launch_dense_multi<float, float>(d32.count, d32.parts, d32.rows, d32.active, b, x, s);
+    timed(h, "dense parts", lvname(h, l, "k_dense_symv_multi<float, float>"), d32.bytes, s, [&] {
+      return launch_dense_symv_multi<float, float>(d32.count, d32.parts, d32.tiles, d32.rows, d32.active, b, x,
+                                                   d32.W, s);
     });
   if (d64.count)
-    timed(h, "dense parts", lvname(h, l, "k_dense_multi<double, float>"), d64.bytes, s, [&] {
-      return launch_dense_multi<double, float>(d64.count, d64.parts, d64.rows, d64.active, b, x, s);
+    timed(h, "dense parts", lvname(h, l, "k_dense_symv_multi<double, float>"), d64.bytes, s, [&] {
+      return launch_dense_symv_multi<double, float>(d64.count, d64.parts, d64.tiles, d64.rows, d64.active, b, x,
+                                                    d64.W, s);
     });
 }
 

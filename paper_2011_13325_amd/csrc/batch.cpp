@@ -365,7 +365,7 @@ double time_ms(hipStream_t s, int reps, F &&f) {
 // kernels): per level, the sweep + upper-residual sequence and each transfer with one or four
 // wavefronts per row; the faster is kept in SolveMat::panel_waves.  Returns the summed time of the
 // tuned kernels before / after (ms).
-DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32, hipStream_t s) {
+DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, hipStream_t s) {
   if (t == 0 || t + 1 >= h->lv.size()) fail(EAMG_ERR_INVALID_ARG, "dense tail must start above the coarsest level, below the finest");
   const Level &Lt = h->lv[t];
   const int n = Lt.n * Lt.bs;
@@ -403,25 +403,18 @@ DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32,
   d.T = T;
   d.n = n;
   d.ld = ld;
-  if (fp32) {
-    d.ld32 = dense_ld32(n);
-    d.T32 = out.alloc<float>(size_t(d.ld32) * d.ld32);
-    hip_check(launch_dense_to_f32(n, ld, T, d.ld32, d.T32, s), "tail to f32");
-  }
   hip_check(hipStreamSynchronize(s), "sync");
   return d;
 }
 
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s) {
-  const DenseTail d = make_dense_tail(h, t, h->arena, h->prm.vcycle_fp32 && h->prm.dense_tail_fp32, s);
+  const DenseTail d = make_dense_tail(h, t, h->arena, s);
   h->tail = d.T;
   h->nT = d.n;
   h->ldT = d.ld;
-  h->tail32 = d.T32;
-  h->ldT32 = d.ld32;
   h->tailS = h->arena.alloc<double>(sym_entries(d.n));
   hip_check(launch_pack_sym<double>(d.n, d.ld, d.T, h->tailS, s), "pack tail");
-  if (d.T32) {
+  if (h->prm.vcycle_fp32 && h->prm.dense_tail_fp32) {
     h->tailS32 = h->arena.alloc<float>(sym_entries(d.n));
     hip_check(launch_pack_sym<float>(d.n, d.ld, d.T, h->tailS32, s), "pack tail f32");
   }

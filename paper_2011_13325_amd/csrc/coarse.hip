@@ -220,53 +220,6 @@ __global__ __launch_bounds__(kThreads) void k_dense_gemv(int n, int ld, const do
   if (lane == 0) y[row] = T(acc);
 }
 
-// y = D x with an FP32 matrix (leading dimension ld, a multiple of 256) and FP32 vectors: one
-// wavefront per row; lane l reads columns 256 c + 4 l .. 256 c + 4 l + 3 of the row and of x
-// (one 16-byte load each) for every chunk c, four chunks in flight; FP64 accumulation; the
-// padding columns of D are zero and x is read as zero past n.
-__global__ __launch_bounds__(kThreads) void k_dense_gemv32(int n, int ld, const float *__restrict__ D,
-                                                          const float *__restrict__ x,
-                                                          float *__restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int row = int(blockIdx.x) * (kThreads / 64) + int(threadIdx.x) / 64;
-  if (row >= n) return;   // whole wavefronts
-  const float4 *Dr = reinterpret_cast<const float4 *>(D + size_t(row) * ld);
-  const int nc = ld / 256;
-  const int nfull = n / 4;   // float4 groups of x entirely inside [0, n)
-  double acc0 = 0.0, acc1 = 0.0;
-  auto xload = [&](int g) {   // x[4 g .. 4 g + 3]
-    if (g < nfull) return reinterpret_cast<const float4 *>(x)[g];
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int j = 4 * g;
-    if (j < n) v.x = x[j];
-    if (j + 1 < n) v.y = x[j + 1];
-    if (j + 2 < n) v.z = x[j + 2];
-    return v;
-  };
-  auto add = [&](const float4 d, const float4 v) {
-    acc0 = fma(double(d.x), double(v.x), acc0);
-    acc1 = fma(double(d.y), double(v.y), acc1);
-    acc0 = fma(double(d.z), double(v.z), acc0);
-    acc1 = fma(double(d.w), double(v.w), acc1);
-  };
-  int c = 0;
-  for (; c + 4 <= nc; c += 4) {
-    float4 d[4], v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      d[u] = Dr[(c + u) * 64 + lane];
-      v[u] = xload((c + u) * 64 + lane);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) add(d[u], v[u]);
-  }
-  for (; c < nc; ++c) add(Dr[c * 64 + lane], xload(c * 64 + lane));
-  double acc = acc0 + acc1;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (lane == 0) y[row] = float(acc);
-}
-
 // ---- symmetric packed product ----------------------------------------------------------------
 
 // Tile (i, j) of the upper block triangle from its packed index t (row by row: tile (i, j) has
@@ -300,21 +253,21 @@ __device__ inline double2 load_pair(const float *p) {
   return make_double2(double(v.x), double(v.y));
 }
 
-// One tile (i, j) of y = S x per workgroup of four wavefronts.  Wavefront w takes rows
-// 32 w .. 32 w + 31 of the tile, lane l columns 2 l and 2 l + 1 (one 16- or 8-byte load per
-// row).  Row sums (the tile's part of y_i) are reduced across the lanes by halving exchanges;
-// column sums (the part of y_j that the mirrored tile (j, i) would give, i < j) accumulate per
-// lane and meet across the wavefronts in LDS.  Both go to W[b][q] (128 doubles: the part of
-// output block b from source block q); every (b, q) is written exactly once.
+// Tile t (packed index) of y = S x for one workgroup of four wavefronts (S, x and W of one
+// matrix).  Wavefront w takes rows 32 w .. 32 w + 31 of the tile, lane l columns 2 l and 2 l + 1
+// (one 16- or 8-byte load per row).  Row sums (the tile's part of y_i) are reduced across the
+// lanes by halving exchanges; column sums (the part of y_j that the mirrored tile (j, i) would
+// give, i < j) accumulate per lane and meet across the wavefronts in LDS.  Both go to W[b][q]
+// (128 doubles: the part of output block b from source block q); every (b, q) is written exactly
+// once.
 template <class TM, class TV>
-__global__ __launch_bounds__(256) void k_dense_symv(int n, int nb, const TM *__restrict__ S,
-                                                    const TV *__restrict__ x, double *__restrict__ W) {
-  __shared__ double colp[4][kSymTile];
+__device__ inline void symv_tile(int n, int nb, int t, const TM *__restrict__ S, const TV *__restrict__ x,
+                                 double *__restrict__ W, double (&colp)[4][kSymTile]) {
   int i, j;
-  sym_tile_of(int(blockIdx.x), nb, i, j);
+  sym_tile_of(t, nb, i, j);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = 32 * w;
-  const TM *T = S + size_t(blockIdx.x) * kSymTile * kSymTile + size_t(r0) * kSymTile + 2 * lane;
+  const TM *T = S + size_t(t) * kSymTile * kSymTile + size_t(r0) * kSymTile + 2 * lane;
   // the three x loads of a lane at clamped indices (no branch between them), zero past n; x of
   // the wavefront's 32 rows is loaded once per lane (lanes l and l + 32 alike) and read out of
   // lane r for row r, so the loop has no load of x and no wait
@@ -362,12 +315,10 @@ __global__ __launch_bounds__(256) void k_dense_symv(int n, int nb, const TM *__r
   }
 }
 
-// y[g] = sum over q of W[g / 128][q][g % 128], q ascending.
-template <class TV>
-__global__ void k_dense_symv_sum(int n, int nb, const double *__restrict__ W, TV *__restrict__ y) {
-  const int g = int(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const double *w = W + size_t(g / kSymTile) * nb * kSymTile + g % kSymTile;
+// Row i of y from the partial sums W of its matrix: sum over q of W[i / 128][q][i % 128], q
+// ascending.
+__device__ inline double symv_row_sum(int nb, int i, const double *__restrict__ W) {
+  const double *w = W + size_t(i / kSymTile) * nb * kSymTile + i % kSymTile;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int q = 0;
   for (; q + 4 <= nb; q += 4) {
@@ -377,7 +328,58 @@ __global__ void k_dense_symv_sum(int n, int nb, const double *__restrict__ W, TV
     a3 += w[size_t(q + 3) * kSymTile];
   }
   for (; q < nb; ++q) a0 += w[size_t(q) * kSymTile];
-  y[g] = TV((a0 + a1) + (a2 + a3));
+  return (a0 + a1) + (a2 + a3);
+}
+
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void k_dense_symv(int n, int nb, const TM *__restrict__ S,
+                                                    const TV *__restrict__ x, double *__restrict__ W) {
+  __shared__ double colp[4][kSymTile];
+  symv_tile<TM, TV>(n, nb, int(blockIdx.x), S, x, W, colp);
+}
+
+template <class TV>
+__global__ void k_dense_symv_sum(int n, int nb, const double *__restrict__ W, TV *__restrict__ y) {
+  const int g = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  y[g] = TV(symv_row_sum(nb, g, W));
+}
+
+// The last part whose first tile (by_tile) or first row is at most t.
+__device__ inline int sym_part_of(int nparts, const SymPart *__restrict__ parts, int t, bool by_tile) {
+  int lo = 0, hi = nparts - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((by_tile ? parts[mid].t0 : parts[mid].row0) <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// One stored tile of any part per workgroup; parts whose system has stopped are skipped.
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void k_dense_symv_multi(int nparts, const SymPart *__restrict__ parts,
+                                                          const double *__restrict__ active,
+                                                          const TV *__restrict__ x, double *__restrict__ W) {
+  __shared__ double colp[4][kSymTile];
+  const int t = int(blockIdx.x);
+  const SymPart P = parts[sym_part_of(nparts, parts, t, true)];
+  if (active && active[P.sys] == 0.0) return;   // the whole workgroup
+  symv_tile<TM, TV>(P.n, P.nb, t - P.t0, static_cast<const TM *>(P.S), x + P.off, W + P.woff, colp);
+}
+
+template <class TV>
+__global__ void k_dense_symv_sum_multi(int nparts, const SymPart *__restrict__ parts, int rows,
+                                       const double *__restrict__ active, const double *__restrict__ W,
+                                       TV *__restrict__ y) {
+  const int g = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= rows) return;
+  const SymPart P = parts[sym_part_of(nparts, parts, g, false)];
+  if (active && active[P.sys] == 0.0) return;
+  const int i = g - P.row0;
+  y[P.off + i] = TV(symv_row_sum(P.nb, i, W + P.woff));
 }
 
 // Panel of K columns (entry (dof, k) at dof * K + k) holding columns j0 .. j0 + K - 1 of the
@@ -397,14 +399,6 @@ __global__ void k_scatter_panel(int n, int K, int j0, int ncols, const double *_
   if (t >= int64_t(n) * ncols) return;
   const int d = int(t / ncols), k = int(t % ncols);
   D[size_t(d) * ld + j0 + k] = X[size_t(d) * K + k];
-}
-
-// D32 (ld32 x ld32, zero padded) := D (ld x ld, first n rows and columns) rounded to FP32.
-__global__ void k_dense_to_f32(int n, int ld, const double *__restrict__ D, int ld32, float *__restrict__ D32) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(ld32) * ld32) return;
-  const int i = int(t / ld32), j = int(t % ld32);
-  D32[t] = (i < n && j < n) ? float(D[size_t(i) * ld + j]) : 0.0f;
 }
 
 // Y = D X for a panel of K columns on the matrix cores (v_mfma_f64_16x16x4): a dense FP64
@@ -520,13 +514,6 @@ hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, h
   return hipGetLastError();
 }
 
-hipError_t launch_dense_gemv32(int n, int ld, const float *D, const float *x, float *y, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (ld < n || ld % 256 != 0 || (reinterpret_cast<uintptr_t>(x) & 15) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dense_gemv32, dim3(cdiv(n, kThreads / 64)), dim3(kThreads), 0, s, n, ld, D, x, y);
-  return hipGetLastError();
-}
-
 hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s) {
   const int64_t nk = int64_t(n) * K;
   if (nk == 0) return hipSuccess;
@@ -541,13 +528,6 @@ hipError_t launch_scatter_panel(int n, int K, int j0, int ncols, const double *X
   if (nk == 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_panel, dim3(cdiv(nk, kThreads)), dim3(kThreads), 0, s, n, K, j0, ncols,
                      X, ld, D);
-  return hipGetLastError();
-}
-
-hipError_t launch_dense_to_f32(int n, int ld, const double *D, int ld32, float *D32, hipStream_t s) {
-  if (ld32 % 256 != 0 || ld32 < n) return hipErrorInvalidValue;
-  const int64_t nn = int64_t(ld32) * ld32;
-  hipLaunchKernelGGL(k_dense_to_f32, dim3(cdiv(nn, kThreads)), dim3(kThreads), 0, s, n, ld, D, ld32, D32);
   return hipGetLastError();
 }
 
@@ -599,11 +579,29 @@ hipError_t launch_dense_symv(int n, const TM *S, const TV *x, TV *y, double *W, 
   return hipGetLastError();
 }
 
+template <class TM, class TV>
+hipError_t launch_dense_symv_multi(int nparts, const SymPart *parts, int tiles, int rows,
+                                   const double *active, const TV *x, TV *y, double *W, hipStream_t s) {
+  if (nparts == 0 || rows == 0) return hipSuccess;
+  if (!parts || !W || tiles < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_dense_symv_multi<TM, TV>), dim3(unsigned(tiles)), dim3(256), 0, s, nparts, parts,
+                     active, x, W);
+  hipLaunchKernelGGL(k_dense_symv_sum_multi<TV>, dim3(cdiv(rows, kThreads)), dim3(kThreads), 0, s, nparts,
+                     parts, rows, active, W, y);
+  return hipGetLastError();
+}
+
 template hipError_t launch_pack_sym<double>(int, int, const double *, double *, hipStream_t);
 template hipError_t launch_pack_sym<float>(int, int, const double *, float *, hipStream_t);
 template hipError_t launch_dense_symv<double, double>(int, const double *, const double *, double *, double *, hipStream_t);
 template hipError_t launch_dense_symv<double, float>(int, const double *, const float *, float *, double *, hipStream_t);
 template hipError_t launch_dense_symv<float, float>(int, const float *, const float *, float *, double *, hipStream_t);
+template hipError_t launch_dense_symv_multi<double, double>(int, const SymPart *, int, int, const double *,
+                                                            const double *, double *, double *, hipStream_t);
+template hipError_t launch_dense_symv_multi<double, float>(int, const SymPart *, int, int, const double *,
+                                                           const float *, float *, double *, hipStream_t);
+template hipError_t launch_dense_symv_multi<float, float>(int, const SymPart *, int, int, const double *,
+                                                          const float *, float *, double *, hipStream_t);
 template hipError_t launch_dense_gemv<double>(int, int, const double *, const double *, double *, hipStream_t);
 template hipError_t launch_dense_gemv<float>(int, int, const double *, const float *, float *, hipStream_t);
 template hipError_t launch_dense_panel<double>(int, int, int, const double *, const double *, double *, double *, hipStream_t);

@@ -47,12 +47,6 @@ hipError_t launch_gj_invert(int ld, double *A, double *work, int *flag, hipStrea
 template <class T>
 hipError_t launch_dense_gemv(int n, int ld, const double *D, const T *x, T *y, hipStream_t s);
 
-// y = D x with an FP32 matrix D (leading dimension ld, a multiple of 256, zero padding) and FP32
-// vectors (x 16-byte aligned); FP64 accumulation.
-hipError_t launch_dense_gemv32(int n, int ld, const float *D, const float *x, float *y, hipStream_t s);
-
-inline int dense_ld32(int n) { return (n + 255) / 256 * 256; }
-
 // Packed symmetric storage: the tiles (i, j), i <= j, of kSymTile x kSymTile entries of the upper
 // block triangle of an n x n symmetric matrix (nb = ceil(n / kSymTile) block rows), tile (i, j)
 // at index i * nb - i * (i - 1) / 2 + j - i, row-major inside, zero past n: about half the bytes
@@ -77,6 +71,23 @@ hipError_t launch_pack_sym(int n, int ld, const double *D, TM *S, hipStream_t s)
 template <class TM, class TV>
 hipError_t launch_dense_symv(int n, const TM *S, const TV *x, TV *y, double *W, hipStream_t s);
 
+// One matrix of a multi-part symmetric product: packed upper tiles S (TM values) of an n x n
+// matrix (nb = sym_blocks(n)) applied to x[off .. off + n) into y[off .. off + n).  Among all
+// parts of a launch it has tiles t0 .. t0 + sym_tiles(nb) - 1 and rows row0 .. row0 + n - 1, and
+// its partial sums start at W[woff]; sys indexes its activity flag.
+struct SymPart {
+  const void *S;
+  int64_t off, woff;
+  int n, nb, row0, t0, sys;
+};
+// y = S_p x for every part p (nparts entries, device array, t0 and row0 increasing from 0; tiles
+// and rows in total; W holds every part's sym_work_doubles(n)): one workgroup per stored tile,
+// then one thread per row, as launch_dense_symv.  With active (device, indexed by sys), parts
+// whose flag is 0 are skipped and leave y as it is.
+template <class TM, class TV>
+hipError_t launch_dense_symv_multi(int nparts, const SymPart *parts, int tiles, int rows,
+                                   const double *active, const TV *x, TV *y, double *W, hipStream_t s);
+
 // B (n x K panel, entry (dof, k) at dof * K + k) := columns j0 .. j0 + K - 1 of the identity.
 hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s);
 
@@ -84,10 +95,6 @@ hipError_t launch_identity_panel(int n, int K, int j0, double *B, hipStream_t s)
 // first ncols columns of the n x K panel X.
 hipError_t launch_scatter_panel(int n, int K, int j0, int ncols, const double *X, int ld, double *D,
                                 hipStream_t s);
-
-// D32 (ld32 x ld32, ld32 a multiple of 256) := the leading n x n block of D rounded to FP32,
-// zero elsewhere.
-hipError_t launch_dense_to_f32(int n, int ld, const double *D, int ld32, float *D32, hipStream_t s);
 
 // Y = D X for a panel of K columns (K a power of two in [1, 64]; entry (dof, k) at dof * K + k),
 // on the matrix cores in FP64, summed over dense_panel_splits(n) slices of the inner dimension

@@ -243,57 +243,85 @@ void build_fused_level(eamg_hierarchy *F, const std::vector<eamg_hierarchy *> &h
   } else if (!last) {
     fail(EAMG_ERR_INVALID_ARG, "fused level without smoothed systems above the last level");
   }
-  // dense operators of the systems whose V-cycle ends here
-  std::vector<DensePart> d64, d32f, d32d;
-  double by64 = 0.0, by32f = 0.0, by32d = 0.0;
+  // dense operators of the systems whose V-cycle ends here, as packed upper tiles (each is a
+  // symmetric V-cycle operator or coarsest inverse): [0] the FP64 V-cycle, [1] the FP32 V-cycle
+  // with FP32 tails (every system set up with dense_tail_fp32), [2] the FP32 V-cycle with FP64
+  // matrices (coarsest inverses, and the tails otherwise)
+  struct Part {
+    const void *S;
+    int64_t off;
+    int n, sys;
+  };
+  std::vector<Part> d64, d32f, d32d;
   for (int m = 0; m < nsys; ++m) {
     if (depth[m] != l) continue;
     const eamg_hierarchy *H = hs[m];
     const int n = H->lv[size_t(l)].n * bs;
     const int64_t off = int64_t(o.dense_off[m]) * bs;
-    const double nn = double(n) * n;
     const DenseTail &own = F->fused->own[size_t(m)];
-    if (own.T || (H->tail_level == l && H->tail)) {
-      // the system's V-cycle from level l as a dense matrix: built for the fused hierarchy, or
-      // the system's own
-      const double *T = own.T ? own.T : H->tail;
-      const float *T32 = own.T ? own.T32 : H->tail32;
-      const int ld = own.T ? own.ld : H->ldT, ld32 = own.T ? own.ld32 : H->ldT32;
-      if ((own.T ? own.n : H->nT) != n) fail(EAMG_ERR_INVALID_ARG, "dense tail size mismatch");
-      d64.push_back({T, off, n, ld, 0, m});
-      by64 += nn * 8.0 + 16.0 * n;
-      if (f32 && F->prm.dense_tail_fp32 && T32) {
-        d32f.push_back({T32, off, n, ld32, 0, m});
-        by32f += nn * 4.0 + 8.0 * n;
-      } else if (f32) {
-        // the FP32 V-cycle reads the FP64 tail, as it reads a coarsest inverse
-        d32d.push_back({T, off, n, ld, 0, m});
-        by32d += nn * 8.0 + 8.0 * n;
+    const double *S = nullptr;
+    const float *S32 = nullptr;
+    bool tail = true;
+    if (own.T) {
+      // built for the fused hierarchy
+      if (own.n != n) fail(EAMG_ERR_INVALID_ARG, "dense tail size mismatch");
+      double *P = ar.alloc<double>(sym_entries(n));
+      hip_check(launch_pack_sym<double>(n, own.ld, own.T, P, s), "pack tail");
+      S = P;
+      if (f32 && F->prm.dense_tail_fp32) {
+        float *P32 = ar.alloc<float>(sym_entries(n));
+        hip_check(launch_pack_sym<float>(n, own.ld, own.T, P32, s), "pack tail f32");
+        S32 = P32;
       }
+    } else if (H->tail_level == l && H->tailS) {
+      // the system's own tail
+      if (H->nT != n) fail(EAMG_ERR_INVALID_ARG, "dense tail size mismatch");
+      S = H->tailS;
+      S32 = F->prm.dense_tail_fp32 ? H->tailS32 : nullptr;
     } else {
       if (H->nL != n || !H->Ainv) fail(EAMG_ERR_INVALID_ARG, "coarsest inverse size mismatch");
-      d64.push_back({H->Ainv, off, n, H->ldL, 0, m});
-      by64 += nn * 8.0 + 16.0 * n;
-      if (f32) {
-        d32d.push_back({H->Ainv, off, n, H->ldL, 0, m});
-        by32d += nn * 8.0 + 8.0 * n;
-      }
+      double *P = ar.alloc<double>(sym_entries(n));
+      hip_check(launch_pack_sym<double>(n, H->ldL, H->Ainv, P, s), "pack coarsest inverse");
+      S = P;
+      tail = false;
     }
+    d64.push_back({S, off, n, m});
+    if (f32 && tail && S32)
+      d32f.push_back({S32, off, n, m});
+    else if (f32)
+      d32d.push_back({S, off, n, m});   // FP64 matrix, as the coarsest inverse is read
   }
-  auto set_of = [&](std::vector<DensePart> &v, double by, DenseSet &d) {
-    int r = 0;
-    for (DensePart &p : v) {
-      p.row0 = r;
-      r += p.n;
+  auto set_of = [&](const std::vector<Part> &v, size_t tm, size_t tv, DenseSet &d) {
+    std::vector<SymPart> sp;
+    int rows = 0, tiles = 0;
+    int64_t wn = 0;
+    double by = 0.0;
+    for (const Part &q : v) {
+      SymPart x{};
+      x.S = q.S;
+      x.off = q.off;
+      x.woff = wn;
+      x.n = q.n;
+      x.nb = sym_blocks(q.n);
+      x.row0 = rows;
+      x.t0 = tiles;
+      x.sys = q.sys;
+      sp.push_back(x);
+      rows += q.n;
+      tiles += int(sym_tiles(x.nb));
+      wn += int64_t(sym_work_doubles(q.n));
+      by += double(sym_entries(q.n)) * tm + 2.0 * 8.0 * double(sym_work_doubles(q.n)) + 2.0 * q.n * double(tv);
     }
-    d.count = int(v.size());
-    d.rows = r;
+    d.count = int(sp.size());
+    d.rows = rows;
+    d.tiles = tiles;
     d.bytes = by;
-    d.parts = v.empty() ? nullptr : ar.upload(v, s);
+    d.parts = sp.empty() ? nullptr : ar.upload(sp, s);
+    d.W = sp.empty() ? nullptr : ar.alloc<double>(size_t(wn));
   };
-  set_of(d64, by64, L.dense[0]);
-  set_of(d32f, by32f, L.dense[1]);
-  set_of(d32d, by32d, L.dense[2]);
+  set_of(d64, 8, 8, L.dense[0]);
+  set_of(d32f, 4, 4, L.dense[1]);
+  set_of(d32d, 8, 4, L.dense[2]);
   // level vectors (level 0 in FP64 uses the CG vectors r and z)
   const size_t nv = size_t(o.n) * bs;
   if (o.n_smooth > 0) L.r = ar.alloc<double>(nv);
@@ -454,7 +482,7 @@ eamg_status eamg_fuse(int32_t nsys, eamg_hierarchy *const *hs, int32_t dense_tai
         const int d = F->fused->depth[size_t(m)];
         if (d + 1 < int(H->lv.size()) && H->tail_level != d)
           F->fused->own[size_t(m)] =
-              make_dense_tail(H, size_t(d), F->arena, F->prm.vcycle_fp32 && F->prm.dense_tail_fp32, s);
+              make_dense_tail(H, size_t(d), F->arena, s);
       }
     for (int l = 0; l < U; ++l) build_fused_level(F.get(), sys, F->fused->depth, ord, l, s);
     // level 0: natural -> fused maps, segments of the CG vectors, CG workspace

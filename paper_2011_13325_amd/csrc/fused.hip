@@ -1,5 +1,6 @@
 // Kernels of the fused multi-system solve (fused.cpp): segmented CG vector operations with one
-// set of CG scalars per system, and the dense operators of several systems in one launch.
+// set of CG scalars per system (the systems' dense operators are applied by the multi-part
+// symmetric product of coarse.hip).
 // Every sum has a fixed order (a block tree per block, then a system's blocks in order), so
 // results are bitwise reproducible; no atomics.
 #include "fused.hpp"
@@ -187,67 +188,6 @@ __global__ void k_gather_out(int n, int bs, const int *__restrict__ map,
   out[i] = in[int64_t(map[v]) * bs + c];
 }
 
-// Matrix elements per lane and step: one 16-byte load.
-template <class TM>
-struct Vec16;
-template <>
-struct Vec16<double> {
-  static constexpr int W = 2;
-  using V = double2;
-  __device__ static void get(const V &v, double (&o)[2]) {
-    o[0] = v.x;
-    o[1] = v.y;
-  }
-};
-template <>
-struct Vec16<float> {
-  static constexpr int W = 4;
-  using V = float4;
-  __device__ static void get(const V &v, double (&o)[4]) {
-    o[0] = v.x;
-    o[1] = v.y;
-    o[2] = v.z;
-    o[3] = v.w;
-  }
-};
-
-// One wavefront per row of the launch: the part it belongs to (parts in row0 order), then the
-// row's product with the part's slice of x.  Lane l takes the 16-byte groups l, l + 64, ... of
-// the row; the lane sums meet by a butterfly in a fixed order.
-template <class TM, class TV>
-__global__ __launch_bounds__(256) void k_dense_multi(int nparts, const DensePart *__restrict__ parts,
-                                                     int rows, const double *__restrict__ active,
-                                                     const TV *__restrict__ x,
-                                                     TV *__restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int row = int(blockIdx.x) * 4 + int(threadIdx.x) / 64;
-  if (row >= rows) return;   // whole wavefronts
-  int p = 0;
-  while (p + 1 < nparts && parts[p + 1].row0 <= row) ++p;
-  const DensePart P = parts[p];
-  if (active && active[P.sys] == 0.0) return;   // whole wavefronts
-  const int i = row - P.row0;
-  using VV = Vec16<TM>;
-  constexpr int W = VV::W;
-  const typename VV::V *Ar = reinterpret_cast<const typename VV::V *>(
-      static_cast<const TM *>(P.A) + int64_t(i) * P.ld);
-  const TV *xs = x + P.off;
-  const int ngroups = (P.n + W - 1) / W;
-  double acc = 0.0;
-  for (int g = lane; g < ngroups; g += 64) {
-    double a[W];
-    VV::get(Ar[g], a);
-#pragma unroll
-    for (int u = 0; u < W; ++u) {
-      const int j = g * W + u;
-      if (j < P.n) acc = fma(a[u], double(xs[j]), acc);
-    }
-  }
-#pragma unroll
-  for (int w = 32; w > 0; w >>= 1) acc += __shfl_xor(acc, w);
-  if (lane == 0) y[P.off + i] = TV(acc);
-}
-
 }  // namespace
 
 hipError_t launch_sdot(const SegTable &T, const double *a, const double *b, double *part,
@@ -311,21 +251,5 @@ hipError_t launch_gather_out(int n, int bs, const int *map, const double *in, do
                      in, out);
   return hipGetLastError();
 }
-
-template <class TM, class TV>
-hipError_t launch_dense_multi(int nparts, const DensePart *parts, int rows, const double *active,
-                              const TV *x, TV *y, hipStream_t s) {
-  if (nparts == 0 || rows == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_dense_multi<TM, TV>), dim3(unsigned(cdiv64f(rows, 4))), dim3(256), 0, s,
-                     nparts, parts, rows, active, x, y);
-  return hipGetLastError();
-}
-
-template hipError_t launch_dense_multi<double, double>(int, const DensePart *, int, const double *,
-                                                       const double *, double *, hipStream_t);
-template hipError_t launch_dense_multi<double, float>(int, const DensePart *, int, const double *,
-                                                      const float *, float *, hipStream_t);
-template hipError_t launch_dense_multi<float, float>(int, const DensePart *, int, const double *,
-                                                     const float *, float *, hipStream_t);
 
 }  // namespace eamg

@@ -53,18 +53,4 @@ hipError_t launch_scatter_in(int n, int bs, const int *map, const uint8_t *mask,
 hipError_t launch_gather_out(int n, int bs, const int *map, const double *in, double *out,
                              hipStream_t s);
 
-// One system's dense operator on a level of a fused hierarchy: y[off + i] = sum_j A[i * ld + j]
-// x[off + j] for i, j < n.  Rows row0 .. row0 + n - 1 of the launch belong to it.
-struct DensePart {
-  const void *A;   // TM matrix, row-major, ld a multiple of 128 (double) or 256 (float)
-  int64_t off;     // first entry of the system's block in x and y
-  int n, ld, row0, sys;
-};
-// Every part of `parts` (nparts entries, device array, row0 increasing, rows in total) in one
-// launch; one wavefront per row, sums in double.  If active != nullptr, parts whose system has
-// active[sys] == 0 (its CG has stopped) are skipped and leave y as it is.
-template <class TM, class TV>
-hipError_t launch_dense_multi(int nparts, const DensePart *parts, int rows, const double *active,
-                              const TV *x, TV *y, hipStream_t s);
-
 }  // namespace eamg

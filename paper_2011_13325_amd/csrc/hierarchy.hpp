@@ -115,10 +115,12 @@ inline double launch_bytes(const LaunchShape &sh, LaunchKind kind, int br, int b
 }
 
 // Dense operators applied on one level of a fused hierarchy, one part per system (device array
-// of `count` DensePart entries covering `rows` rows), and their algorithmic bytes per launch.
+// of `count` SymPart entries: packed upper tiles, `tiles` and `rows` in total, partial sums in
+// W), and their algorithmic bytes per application.
 struct DenseSet {
-  const DensePart *parts = nullptr;
-  int count = 0, rows = 0;
+  const SymPart *parts = nullptr;
+  int count = 0, rows = 0, tiles = 0;
+  double *W = nullptr;
   double bytes = 0.0;
   const double *active = nullptr;   // per-system CG activity flags: stopped systems are skipped
 };
@@ -257,16 +259,15 @@ std::pair<double, double> tune_panels(eamg_hierarchy *h, int K, hipStream_t s);
 void vcycle_staged(eamg_hierarchy *h, const double *r_dev, double *z_dev, bool f32, double *rp,
                    double *zp, hipStream_t s);
 // The V-cycle on levels t .. coarsest of h as a dense matrix in the colour-major numbering of
-// level t, from the batched V-cycle applied to the columns of the identity: FP64 (row-major, ld a
-// multiple of 128, zero padding) and, with fp32, an FP32 copy (ld32 a multiple of 256), both
-// allocated in `out`.
+// level t, from the batched V-cycle applied to the columns of the identity: FP64, row-major, ld a
+// multiple of 128, zero padding, allocated in `out`.
 struct DenseTail {
   double *T = nullptr;
-  float *T32 = nullptr;
-  int n = 0, ld = 0, ld32 = 0;
+  int n = 0, ld = 0;
 };
-DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, bool fp32, hipStream_t s);
-// make_dense_tail into h's own arena, kept as h->tail / h->tail32; sets h->tail_level = t.
+DenseTail make_dense_tail(eamg_hierarchy *h, size_t t, DevArena &out, hipStream_t s);
+// make_dense_tail into h's own arena, kept as h->tail with its packed upper tiles (h->tailS, and
+// h->tailS32 with dense_tail_fp32); sets h->tail_level = t.
 void build_dense_tail(eamg_hierarchy *h, size_t t, hipStream_t s);
 
 }  // namespace eamg
@@ -283,9 +284,8 @@ struct eamg_hierarchy {
   // dense V-cycle tail: the V-cycle on levels tail_level .. coarsest as one dense matrix in the
   // colour-major numbering of tail_level (row-major, zero padding), or tail_level = -1
   int tail_level = -1;
-  int nT = 0, ldT = 0, ldT32 = 0;
+  int nT = 0, ldT = 0;
   double *tail = nullptr;
-  float *tail32 = nullptr;    // FP32 copy (with dense_tail_fp32)
   // the tail's upper tiles, packed (the V-cycle operator is symmetric): FP64 and, with
   // dense_tail_fp32, FP32; the single-vector V-cycle reads these, with tailW as its workspace
   double *tailS = nullptr;

@@ -247,7 +247,7 @@ def test_fused_autotune_and_profiler():
         names = [k["name"] for k in E.eamg_profile_read(f.h)]
         E.eamg_profile_enable(f.h, False)
         assert any(n.startswith("k_gs_color<float, 6") for n in names), names
-        assert any(n.startswith("k_dense_multi<") for n in names), names
+        assert any(n.startswith("k_dense_symv_multi<") for n in names), names
     finally:
         f.close()
         for _, h in sysl:
