@@ -527,6 +527,40 @@ def test_dense_tail_parity(name, where, tail32):
         hl.close()
 
 
+def test_dense_tail_near_the_size_limit():
+    # 54^3: the first level of at most 16384 dofs has about 15,000 (a ragged last 128 tile);
+    # the V-cycle with the tail (packed upper tiles) equals the V-cycle of the same
+    # hierarchy without it up to rounding, in FP64; the FP32 V-cycle, reading the FP64 tail or
+    # its FP32 copy, stays within the FP32 bar of it
+    p = make_problem(54, nu=0.3, seed=7)
+    prm = dict(vcycle_fp32=1, coarsest_max_dofs=500)
+    hs = _lib(p, dense_tail_dofs=0, **prm)
+    ht = _lib(p, dense_tail_dofs=16384, **prm)
+    h32 = _lib(p, dense_tail_dofs=16384, dense_tail_fp32=1, **prm)
+    try:
+        lvl, nT = E.eamg_dense_tail(ht.h)
+        print(f"\n[tail 54^3] level {lvl}, {nT} dofs", flush=True)
+        assert 8000 <= nT <= 16384
+        r = np.random.default_rng(11).standard_normal(p.n_dofs)
+        r[np.repeat(p.dirichlet.astype(bool), p.dim)] = 0.0
+        out = {}
+        for name, h, prec in (("sparse", hs, E.EAMG_PRECOND_VCYCLE), ("tail", ht, E.EAMG_PRECOND_VCYCLE),
+                              ("tail_f32", ht, E.EAMG_PRECOND_VCYCLE_FP32),
+                              ("tail32_f32", h32, E.EAMG_PRECOND_VCYCLE_FP32)):
+            z = torch.empty(p.n_dofs, dtype=torch.float64, device="cuda")
+            E.eamg_vcycle(h.h, _dev(r), z, prec)
+            torch.cuda.synchronize()
+            out[name] = z.cpu().numpy()
+        ref = out["sparse"]
+        errs = {k: np.linalg.norm(v - ref) / np.linalg.norm(ref) for k, v in out.items() if k != "sparse"}
+        print(f"[tail 54^3] against the sparse FP64 V-cycle: {errs}", flush=True)
+        assert errs["tail"] <= 1e-11
+        assert errs["tail_f32"] <= 1e-5 and errs["tail32_f32"] <= 1e-5
+    finally:
+        for h in (hs, ht, h32):
+            h.close()
+
+
 def test_dense_tail_off_below_coarsest_and_rejected_sizes():
     p = make_problem(9)
     # a threshold only the coarsest level meets: no tail
