@@ -18,8 +18,9 @@
  *    a call is ordered on it.  eamg_setup and eamg_solve return after their work is complete.
  *  - Errors are returned as eamg_status; no exception or abort crosses the ABI.  A message for
  *    the last failure on the calling thread is available from eamg_last_error().
- *  - A hierarchy handle must not be used by two threads at once.  Separate handles are
- *    independent.
+ *  - A hierarchy handle must not be used by two threads at once, and its calls must not run on
+ *    the device at the same time (calls on two streams): they share the hierarchy's level
+ *    vectors and workspaces.  Separate handles are independent.
  */
 #ifndef EAMG_H
 #define EAMG_H
