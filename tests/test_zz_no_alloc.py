@@ -2,7 +2,8 @@
 ABI, two calls in a row -- a larger hierarchy, then a smaller one, sharing the library's fixed
 staging array -- each equal bit for bit to eamg_vcycle on the same hierarchy (same kernels in the
 same order; eamg_vcycle is itself checked against the FP64 oracle's V-cycle in
-test_gpu_parity.py), in FP64 and FP32, with and without a dense tail; and the size limit, the
+test_gpu_parity.py), in FP64 and FP32, without a dense tail and with one (FP64, or with its FP32
+copy); and the size limit, the
 profiler check and the precision check."""
 import numpy as np
 import pytest
@@ -30,11 +31,12 @@ def _r(p, seed):
     return torch.tensor(r, device="cuda")
 
 
-@pytest.mark.parametrize("tail", [0, 16384])
-def test_noalloc_vcycle_equals_vcycle_on_two_calls(tail):
+@pytest.mark.parametrize("tail,tail32", [(0, 0), (16384, 0), (16384, 1)])
+def test_noalloc_vcycle_equals_vcycle_on_two_calls(tail, tail32):
     big = make_problem(14, nu=0.35, seed=2)
     small = make_problem(7, seed=3)
-    hb, hs = _hier(big, dense_tail_dofs=tail), _hier(small, dense_tail_dofs=tail)
+    hb = _hier(big, dense_tail_dofs=tail, dense_tail_fp32=tail32)
+    hs = _hier(small, dense_tail_dofs=tail, dense_tail_fp32=tail32)
     try:
         for prec in (E.EAMG_PRECOND_VCYCLE, E.EAMG_PRECOND_VCYCLE_FP32):
             for p, h, seed in ((big, hb, 1), (small, hs, 2)):
@@ -45,8 +47,8 @@ def test_noalloc_vcycle_equals_vcycle_on_two_calls(tail):
                 stream = torch.cuda.current_stream()
                 E.eamg_vcycle_noalloc(h.h, r, z, prec, stream=stream)
                 torch.cuda.synchronize()
-                assert torch.equal(z, z_ref), (p.n_vertices, prec, tail)
-                print(f"[noalloc tail={tail} prec={prec}] n={p.n_dofs} equal", flush=True)
+                assert torch.equal(z, z_ref), (p.n_vertices, prec, tail, tail32)
+                print(f"[noalloc tail={tail} tail32={tail32} prec={prec}] n={p.n_dofs} equal", flush=True)
     finally:
         hb.close()
         hs.close()
