@@ -614,11 +614,12 @@ def test_cg_coefficients_match_the_oracle():
 
 # --- the P_s row caps the bench uses ---------------------------------------------------------
 # The caps of the auxiliary smoothed prolongation are free parameters (the paper's runs use 4
-# for edge-matrix rows and 8 / 6 for real-matrix rows); the bench's headline runs 4 and 6 / 4 with
-# sigma = 18, its other workloads 3 and 6 / 4 with sigma = 20: sparser hierarchies for a few more
-# iterations.  The oracle takes the same parameters, so every parity bar holds there too.
-TUNED = {"headline": dict(cap_std_l0=6, cap_std=4, cap_aux=4, sigma=18.0),
-         "others": dict(cap_std_l0=6, cap_std=4, cap_aux=3)}
+# for edge-matrix rows and 8 / 6 for real-matrix rows); the bench's cube workloads (128^3 and
+# 64^3) run 4 and 6 / 4 with sigma = 18, its multi-mesh and learned-coarsening workloads 3 and
+# 6 / 4 with sigma = 20: sparser hierarchies for a few more iterations.  The oracle takes the same
+# parameters, so every parity bar holds there too.
+TUNED = {"cubes": dict(cap_std_l0=6, cap_std=4, cap_aux=4, sigma=18.0),
+         "multi_learned": dict(cap_std_l0=6, cap_std=4, cap_aux=3)}
 
 
 @pytest.mark.parametrize("setting", list(TUNED))
