@@ -203,8 +203,12 @@ def test_batch_rejects_bad_arguments():
 def test_batch_full_size_cube64_32rhs():
     p = make_problem(64, seed=1)
     print(f"\n[cube64 x 32] dofs={p.n_dofs}", flush=True)
+    # the bench's 64^3 configuration (caps 6 / 4 / 4, sigma 18, dense V-cycle tail)
     hl = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, p.dirichlet,
-                     E.eamg_default_setup_params(vcycle_fp32=1))
+                     E.eamg_default_setup_params(vcycle_fp32=1, coarsest_max_dofs=500,
+                                                 dense_tail_dofs=16384, cap_std_l0=6, cap_std=4,
+                                                 cap_aux=4, sigma=18.0))
+    E.eamg_autotune(hl.h, panel_width=32)
     B = _rhs(p, 32, 4)
     Bd = torch.tensor(B, device="cuda")
     Ab = _bound_matrix(p)

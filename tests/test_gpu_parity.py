@@ -207,24 +207,31 @@ def test_indefinite_matrix_reports_not_spd():
     assert ei.value.status == E.EAMG_ERR_NOT_SPD
 
 
+# the bench's 64^3 configuration: caps 6 / 4 / 4, sigma 18, coarsening to < 500 dofs, dense tail
+BENCH64 = dict(vcycle_fp32=1, coarsest_max_dofs=500, dense_tail_dofs=16384, cap_std_l0=6, cap_std=4,
+               cap_aux=4, sigma=18.0)
+
+
 def test_full_size_cube64_properties():
     p = make_problem(64, seed=1)
     print(f"\n[cube64] dofs={p.n_dofs}", flush=True)
-    hl = _lib(p)
+    hl = _lib(p, **BENCH64)
+    E.eamg_autotune(hl.h, panel_width=32)
     st = hl.stats()
-    print(f"[cube64] levels={st['n_levels']} n={st['n']} vc={st['vc']:.3f} oc={st['oc']:.3f}",
-          flush=True)
+    print(f"[cube64] levels={st['n_levels']} n={st['n']} vc={st['vc']:.3f} oc={st['oc']:.3f} "
+          f"tail={E.eamg_dense_tail(hl.h)}", flush=True)
     b = _dev(p.b)
-    x, info = hl.solve(b, rtol=1e-8)
-    print(f"[cube64] its={info['iterations']} rel_true={info['rel_res_true']:.2e} ms={info['ms']:.1f}",
-          flush=True)
-    assert info["status"] == E.EAMG_OK
     A = sp.bsr_matrix((p.vals, p.col_idx, p.row_ptr), shape=(p.n_dofs,) * 2).tocsr()
     dm = np.repeat(p.dirichlet.astype(bool), 3)
     Dm = sp.diags((~dm).astype(float))
     Ab = Dm @ A @ Dm + sp.diags(dm.astype(float))
-    xh = x.cpu().numpy()
-    assert np.linalg.norm(p.b - Ab @ xh) <= 1e-8 * np.linalg.norm(p.b)
+    for prec in (E.EAMG_PRECOND_VCYCLE, E.EAMG_PRECOND_VCYCLE_FP32):
+        x, info = hl.solve(b, rtol=1e-8, precond=prec)
+        print(f"[cube64 precond={prec}] its={info['iterations']} rel_true={info['rel_res_true']:.2e} "
+              f"ms={info['ms']:.1f}", flush=True)
+        assert info["status"] == E.EAMG_OK
+        xh = x.cpu().numpy()
+        assert np.linalg.norm(p.b - Ab @ xh) <= 1e-8 * np.linalg.norm(p.b)
     # level 0: agglomerates partition the free vertices, at most 4 each; rigid body modes are
     # reproduced by P_s on rows whose stencil avoids D
     ex = hl.export(0)
