@@ -1,5 +1,7 @@
 // Coarsest-level direct solve: device assembly of the dense regularized matrix, its in-place
-// blocked Gauss-Jordan inversion, and the dense products that apply the inverse (coarse.hpp).
+// blocked Gauss-Jordan inversion, and the dense products that apply the inverse and the dense
+// V-cycle tails: full matrix times a vector or a panel, and the packed symmetric product
+// (coarse.hpp).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
