@@ -71,6 +71,9 @@ def test_malformed_inputs_are_rejected_before_device_work():
     p = _base()
     assert _setup_status(p, dim=2)[0] == E.EAMG_ERR_UNSUPPORTED_KERNEL
     p = _base()
+    st, msg = _setup_status(p, n_vertices=0)                 # empty problem
+    assert st == E.EAMG_ERR_INVALID_ARG and "n_vertices" in msg
+    p = _base()
     p["params"] = E.eamg_default_setup_params(delta=0)
     assert _setup_status(p)[0] == E.EAMG_ERR_INVALID_ARG
     p = _base()

@@ -166,6 +166,25 @@ def test_no_coarsening_direct_solve():
     hl.close()
 
 
+def test_every_vertex_clamped():
+    # all of V is Dirichlet: the system on V_h0 is empty (identity rows), nothing is matched, the
+    # hierarchy is the single (identity) level, and every solve returns x = 0 at once
+    p = make_problem(8, seed=2)
+    dirichlet = np.ones_like(p.dirichlet)
+    ho = oracle.setup(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, dirichlet)
+    hl = E.Hierarchy(p.dim, p.coords, p.row_ptr, p.col_idx, p.vals, dirichlet,
+                     E.eamg_default_setup_params(vcycle_fp32=1))
+    try:
+        assert ho.n_levels == 1 and hl.stats()["n_levels"] == 1
+        b = _dev(p.b)
+        for prec in (E.EAMG_PRECOND_VCYCLE, E.EAMG_PRECOND_VCYCLE_FP32):
+            x, info = hl.solve(b, precond=prec)
+            assert info["status"] == E.EAMG_OK and info["iterations"] == 0
+            assert float(x.abs().max()) == 0.0
+    finally:
+        hl.close()
+
+
 def test_initial_guess_and_statuses():
     p = make_problem(9, seed=5)
     hl = _lib(p)
