@@ -639,13 +639,23 @@ void enqueue_iteration(eamg_hierarchy *h, bool f32, hipStream_t s) {
   const int nd = dot_blocks(N);
   const int ns = spmv_blocks(A);
   if (nd > h->part_cap || ns > h->part_cap) fail(EAMG_ERR_INVALID_ARG, "partial-sum buffer too small");
-  vcycle(h, h->r, h->z, f32, s);
-  hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
-  hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
-  hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
+  if (f32) {
+    // the FP32 V-cycle reads r's FP32 copy (written with r by the previous update) and its output
+    // z is read in FP32 by the dot product and the p update
+    vcycle_t<float>(h, 0, L0.b32, L0.x32, s);
+    hip_check(launch_dot(N, h->r, L0.x32, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
+    hip_check(launch_update_p(N, h->scal, L0.x32, h->p, s), "update_p");
+  } else {
+    vcycle(h, h->r, h->z, false, s);
+    hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+    hip_check(launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s), "reduce");
+    hip_check(launch_update_p(N, h->scal, h->z, h->p, s), "update_p");
+  }
   hip_check(launch_spmv(A, h->p, h->q, h->part, s), "spmv");
   hip_check(launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s), "reduce");
-  hip_check(launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s), "update_xr");
+  hip_check(launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s, f32 ? L0.b32 : nullptr),
+            "update_xr");
   hip_check(launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s), "reduce");
   hip_check(hipMemcpyAsync(h->scal_h, h->scal, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s),
             "copy");
@@ -727,11 +737,39 @@ struct SolveRun {
     hip_check(hipEventCreate(&e1), "event");
   }
 
+  // z = V(r): with the FP32 V-cycle z is the level-0 FP32 vector x32 (read as it is by the dot
+  // product and the p update) and the V-cycle reads r's FP32 copy b32, which the start and every
+  // r update write along with r
   void precondition() {
-    if (sp.precond)
-      vcycle(h, h->r, h->z, f32, s);
+    const Level &L0 = h->lv[0];
+    if (f32)
+      vcycle_t<float>(h, 0, L0.b32, L0.x32, s);
+    else if (sp.precond)
+      vcycle(h, h->r, h->z, false, s);
     else
       hip_check(launch_copy(N, h->r, h->z, s), "copy");
+  }
+  float *r32() const { return f32 ? h->lv[0].b32 : nullptr; }
+  // r.z (partials into part) and p = z + beta p, z in FP64 or the FP32 V-cycle's output
+  void dot_rz() {
+    if (f32)
+      timed(h, "dot", "k_dot<float>", vecb + 4.0 * N + 8.0 * nd, s,
+            [&] { return launch_dot(N, h->r, h->lv[0].x32, h->part, s); });
+    else
+      timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
+            [&] { return launch_dot(N, h->r, h->z, h->part, s); });
+  }
+  void update_p() {
+    if (f32)
+      timed(h, "update_p", "k_update_p<float>", 2.0 * vecb + 4.0 * N, s,
+            [&] { return launch_update_p(N, h->scal, h->lv[0].x32, h->p, s); });
+    else
+      timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
+            [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
+  }
+  void update_xr() {
+    timed(h, "update_xr", "k_update_xr", 6.0 * vecb + (f32 ? 4.0 * N : 0.0) + 8.0 * nd, s,
+          [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s, r32()); });
   }
 
   double spmv_bytes() const {
@@ -769,6 +807,7 @@ struct SolveRun {
       hip_check(launch_fill(N, 0.0, h->x, s), "fill");
       hip_check(launch_copy(N, h->bp, h->r, s), "copy");
     }
+    if (f32) hip_check(launch_convert<double, float>(N, h->r, r32(), s), "convert");
     copy_scalars();
   }
   void complete_start_a() {
@@ -782,8 +821,11 @@ struct SolveRun {
   }
   void enqueue_start_b() {
     precondition();
-    hip_check(launch_copy(N, h->z, h->p, s), "copy");
-    hip_check(launch_dot(N, h->r, h->z, h->part, s), "dot");
+    if (f32)
+      hip_check(launch_convert<float, double>(N, h->lv[0].x32, h->p, s), "convert");
+    else
+      hip_check(launch_copy(N, h->z, h->p, s), "copy");
+    dot_rz();
     hip_check(launch_reduce(nd, h->part, h->scal, SC_RHO, RED_STORE, s), "reduce");
     copy_scalars();
   }
@@ -807,8 +849,7 @@ struct SolveRun {
           [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
     timed(h, "reduce", "k_reduce", 8.0 * ns, s,
           [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
-    timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
-          [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+    update_xr();
     timed(h, "reduce", "k_reduce", 8.0 * nd, s,
           [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
     copy_scalars();
@@ -849,18 +890,15 @@ struct SolveRun {
     const Level &L0 = h->lv[0];
     const SolveMat &A = L0.Am;
     precondition();
-    timed(h, "dot", "k_dot", 2.0 * vecb + 8.0 * nd, s,
-          [&] { return launch_dot(N, h->r, h->z, h->part, s); });
+    dot_rz();
     timed(h, "reduce", "k_reduce", 8.0 * nd, s,
           [&] { return launch_reduce(nd, h->part, h->scal, SC_RZ, RED_BETA, s); });
-    timed(h, "update_p", "k_update_p", 3.0 * vecb, s,
-          [&] { return launch_update_p(N, h->scal, h->z, h->p, s); });
+    update_p();
     timed(h, "spmv", tname("k_spmv", L0.bs, L0.bs), spmv_bytes(), s,
           [&] { return launch_spmv(A, h->p, h->q, h->part, s); });
     timed(h, "reduce", "k_reduce", 8.0 * ns, s,
           [&] { return launch_reduce(ns, h->part, h->scal, SC_PQ, RED_ALPHA, s); });
-    timed(h, "update_xr", "k_update_xr", 6.0 * vecb + 8.0 * nd, s,
-          [&] { return launch_update_xr(N, h->scal, h->x, h->r, h->p, h->q, h->part, s); });
+    update_xr();
     timed(h, "reduce", "k_reduce", 8.0 * nd, s,
           [&] { return launch_reduce(nd, h->part, h->scal, SC_RR, RED_STORE, s); });
     fetch_scalars(h, s);
@@ -1700,8 +1738,8 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
     if (precision == EAMG_PRECOND_VCYCLE_FP32 && !h->prm.vcycle_fp32)
       fail(EAMG_ERR_INVALID_ARG, "FP32 V-cycle needs setup with vcycle_fp32 = 1");
     const bool f32 = precision == EAMG_PRECOND_VCYCLE_FP32;
-    // FP32: the two level-0 conversions (read 8 + write 4, read 4 + write 8 bytes per dof)
-    double v = f32 ? 24.0 * double(h->lv[0].n) * h->lv[0].bs : 0.0;
+    // the V-cycle as the PCG iteration runs it (FP32: on r's FP32 copy, z left in FP32)
+    double v = 0.0;
     for (size_t l = 0; l < h->lv.size(); ++l) {
       const Level &L = h->lv[l];
       if (int(l) == h->tail_level) {
@@ -1722,8 +1760,10 @@ eamg_status eamg_traffic_model(const eamg_hierarchy *h, int32_t precision, doubl
     }
     const Level &L0 = h->lv[0];
     const double vec0 = double(L0.n) * L0.bs * 8.0;
-    // PCG: SpMV with p.q, x / r update (x rw, r rw, p, q), r.z, p update (z, p rw)
-    const double it = launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) + 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0;
+    // PCG: SpMV with p.q, x / r update (x rw, r rw, p, q; FP32: r's FP32 copy written), r.z,
+    // p update (z, p rw); z in FP32 with the FP32 V-cycle
+    const double it = launch_bytes(L0.sh_spmv, LK_SPMV, L0.bs, L0.bs, 8.0, 1) +
+                      (f32 ? 6.5 * vec0 + 1.5 * vec0 + 2.5 * vec0 : 6.0 * vec0 + 2.0 * vec0 + 3.0 * vec0);
     if (vcycle_bytes) *vcycle_bytes = v;
     if (iteration_bytes) *iteration_bytes = it + v;
   });

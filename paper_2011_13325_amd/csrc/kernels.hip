@@ -586,12 +586,14 @@ __global__ void k_gather_blocks_f32(int64_t nnz, int bsz, const int64_t *src, co
   out[gid] = float(in[src[q] * bsz + e]);
 }
 
+// b in double, or the FP32 V-cycle's output read as it is (each value converted exactly)
+template <class TB>
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ a,
-                                               const double *__restrict__ b, double *part) {
+                                               const TB *__restrict__ b, double *part) {
   __shared__ double sh[kBlock];
   double s = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    s = fma(a[i], b[i], s);
+    s = fma(a[i], double(b[i]), s);
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
@@ -618,9 +620,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int nparts, const double *__r
   }
 }
 
+// r32 (optional): the FP32 copy of the new r, the next FP32 V-cycle's right-hand side.
 __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, const double *scal, double *x,
                                                      double *r, const double *__restrict__ p,
-                                                     const double *__restrict__ q, double *part) {
+                                                     const double *__restrict__ q, double *part,
+                                                     float *__restrict__ r32) {
   __shared__ double sh[kBlock];
   const double alpha = scal[SC_ALPHA];
   double s = 0.0;
@@ -628,17 +632,19 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, const double *s
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
+    if (r32) r32[i] = float(ri);
     s = fma(ri, ri, s);
   }
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+template <class TZ>
 __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const double *scal,
-                                                    const double *__restrict__ z, double *p) {
+                                                    const TZ *__restrict__ z, double *p) {
   const double beta = scal[SC_BETA];
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    p[i] = fma(beta, p[i], z[i]);
+    p[i] = fma(beta, p[i], double(z[i]));
 }
 
 __global__ void k_sub(int64_t n, const double *a, const double *b, double *y) {
@@ -892,7 +898,12 @@ int dot_blocks(int64_t n) {
 }
 
 hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, a, b, part);
+  hipLaunchKernelGGL(k_dot<double>, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, a, b, part);
+  EAMG_LAUNCH_CHECK();
+}
+
+hipError_t launch_dot(int64_t n, const double *a, const float *b, double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot<float>, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, a, b, part);
   EAMG_LAUNCH_CHECK();
 }
 
@@ -903,13 +914,18 @@ hipError_t launch_reduce(int nparts, const double *part, double *scal, int slot,
 }
 
 hipError_t launch_update_xr(int64_t n, const double *scal, double *x, double *r, const double *p,
-                            const double *q, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, scal, x, r, p, q, part);
+                            const double *q, double *part, hipStream_t s, float *r32) {
+  hipLaunchKernelGGL(k_update_xr, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, scal, x, r, p, q, part, r32);
   EAMG_LAUNCH_CHECK();
 }
 
 hipError_t launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, scal, z, p);
+  hipLaunchKernelGGL(k_update_p<double>, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, scal, z, p);
+  EAMG_LAUNCH_CHECK();
+}
+
+hipError_t launch_update_p(int64_t n, const double *scal, const float *z, double *p, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p<float>, dim3(dot_blocks(n)), dim3(kBlock), 0, s, n, scal, z, p);
   EAMG_LAUNCH_CHECK();
 }
 

@@ -129,17 +129,21 @@ hipError_t launch_gather_blocks_f32(int64_t nnz, int bsz, const int64_t *src, co
 
 // Vector operations with deterministic reductions; grid size fixed by the length.
 int dot_blocks(int64_t n);
-// part <- partials of a.b
+// part <- partials of a.b (b in double, or in float: the FP32 V-cycle's output, each value
+// converted exactly)
 hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, hipStream_t s);
+hipError_t launch_dot(int64_t n, const double *a, const float *b, double *part, hipStream_t s);
 // Reduce partials into scal[slot]; op selects what else is derived (see kernels.hip).
 enum ReduceOp : int { RED_STORE = 0, RED_ALPHA = 1, RED_BETA = 2 };
 hipError_t launch_reduce(int nparts, const double *part, double *scal, int slot, int op,
                          hipStream_t s);
-// x += alpha p ; r -= alpha q ; part <- partials of r.r   (alpha = scal[SC_ALPHA])
+// x += alpha p ; r -= alpha q ; part <- partials of r.r   (alpha = scal[SC_ALPHA]); with r32,
+// also r32 = float(r) (the next FP32 V-cycle's right-hand side)
 hipError_t launch_update_xr(int64_t n, const double *scal, double *x, double *r, const double *p,
-                            const double *q, double *part, hipStream_t s);
-// p = z + beta p (beta = scal[SC_BETA])
+                            const double *q, double *part, hipStream_t s, float *r32 = nullptr);
+// p = z + beta p (beta = scal[SC_BETA]); z in double or float
 hipError_t launch_update_p(int64_t n, const double *scal, const double *z, double *p, hipStream_t s);
+hipError_t launch_update_p(int64_t n, const double *scal, const float *z, double *p, hipStream_t s);
 // y = a - b
 hipError_t launch_sub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
 hipError_t launch_copy(int64_t n, const double *a, double *y, hipStream_t s);
