@@ -255,6 +255,20 @@ __device__ inline double2 load_pair(const float *p) {
   return make_double2(double(v.x), double(v.y));
 }
 
+// One halving exchange of the row sums: p[k] of lane l is its part of row k (k < 2 H); the lane
+// keeps the half of its rows that matches lane bit 2 H, summed with its partner's (H a constant,
+// so p stays in registers).
+template <int H>
+__device__ __forceinline__ void halve_rows(double (&p)[32], int lane) {
+  const bool up = (lane & (2 * H)) != 0;
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const double send = up ? p[k] : p[k + H];
+    const double keep = up ? p[k + H] : p[k];
+    p[k] = keep + __shfl_xor(send, 2 * H, 64);
+  }
+}
+
 // Tile t (packed index) of y = S x for one workgroup of four wavefronts (S, x and W of one
 // matrix).  Wavefront w takes rows 32 w .. 32 w + 31 of the tile, lane l columns 2 l and 2 l + 1
 // (one 16- or 8-byte load per row).  Row sums (the tile's part of y_i) are reduced across the
@@ -263,8 +277,9 @@ __device__ inline double2 load_pair(const float *p) {
 // (128 doubles: the part of output block b from source block q); every (b, q) is written exactly
 // once.
 template <class TM, class TV>
-__device__ inline void symv_tile(int n, int nb, int t, const TM *__restrict__ S, const TV *__restrict__ x,
-                                 double *__restrict__ W, double (&colp)[4][kSymTile]) {
+__device__ __forceinline__ void symv_tile(int n, int nb, int t, const TM *__restrict__ S,
+                                          const TV *__restrict__ x, double *__restrict__ W,
+                                          double (&colp)[4][kSymTile]) {
   int i, j;
   sym_tile_of(t, nb, i, j);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -292,18 +307,12 @@ __device__ inline void symv_tile(int n, int nb, int t, const TM *__restrict__ S,
     c0 = fma(v.x, xi, c0);
     c1 = fma(v.y, xi, c1);
   }
-  // p[k] of lane l is its part of row k; after the exchange over lane bit b (32, 16, .., 2) a
-  // lane keeps the half of its rows that matches that bit, summed with its partner's
-#pragma unroll
-  for (int h = 16; h >= 1; h >>= 1) {
-    const bool up = (lane & (2 * h)) != 0;
-#pragma unroll
-    for (int k = 0; k < h; ++k) {
-      const double send = up ? p[k] : p[k + h];
-      const double keep = up ? p[k + h] : p[k];
-      p[k] = keep + __shfl_xor(send, 2 * h, 64);
-    }
-  }
+  // exchanges over lane bits 32, 16, .., 2
+  halve_rows<16>(p, lane);
+  halve_rows<8>(p, lane);
+  halve_rows<4>(p, lane);
+  halve_rows<2>(p, lane);
+  halve_rows<1>(p, lane);
   const double rs = p[0] + __shfl_xor(p[0], 1, 64);   // row (lane >> 1) of this wavefront
   if ((lane & 1) == 0) W[(size_t(i) * nb + j) * kSymTile + r0 + (lane >> 1)] = rs;
   if (i != j) {
