@@ -436,9 +436,10 @@ __device__ inline T pick(const T (&v)[B], int i) {
 // (rp, col, val: the lower part) and A_ii is block `row` of dval;
 // also writes r_i = t - A_ii x_i.  BWD: x_i += Dinv_i (b_i - sum_j A_ij x_j) over the whole row
 // (rp, col, val: the full matrix).
-// Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii
-// together with the row's blocks, so a row costs one round of row loads plus the x gathers;
-// a butterfly all-reduce leaves the row sum on every lane.
+// Lane q < B owns component q: it prefetches b_i[q], row q of Dinv_i and (FWD) row q of A_ii,
+// (BWD) x_i[q], together with the row's blocks, so a row costs one round of row loads plus the
+// x gathers; a butterfly all-reduce leaves the row sum on every lane.  No other row of the
+// colour writes x_i, so the prefetched x_i[q] is the value the gathers see.
 template <class T, int B, bool FWD, int W>
 __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *__restrict__ rp,
                               const int *__restrict__ col, const T *__restrict__ val, int64_t nnz,
@@ -450,7 +451,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
     p0 = rp[row];
     p1 = rp[row + 1];
   }
-  T bq = T(0), Dq[B], Aq[B];
+  T bq = T(0), xo = T(0), Dq[B], Aq[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) {
     Dq[c] = T(0);
@@ -458,6 +459,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
   }
   if (own) {
     bq = b[int64_t(row) * B + lane];
+    if (!FWD) xo = x[int64_t(row) * B + lane];
 #pragma unroll
     for (int c = 0; c < B; ++c) {
       Dq[c] = Dinv[int64_t(row) * B * B + lane * B + c];
@@ -494,7 +496,7 @@ __device__ inline void gs_row(int row, bool valid, int lane, int G, const int *_
       r[int64_t(row) * B + lane] = rq;
     }
   } else {
-    if (own) x[int64_t(row) * B + lane] += xq;
+    if (own) x[int64_t(row) * B + lane] = xo + xq;
   }
 }
 
@@ -556,19 +558,21 @@ __global__ __launch_bounds__(kBlock) void k_rect(int n_rows, int G, const int *_
                                                 int accumulate) {
   const int lane = threadIdx.x & (G - 1);
   const int row = xcd_block() * (kBlock / G) + threadIdx.x / G;
-  T acc[BR];
+  // the old y_i is read with the row's first loads, not after the reduction
+  T acc[BR], yo[BR];
 #pragma unroll
-  for (int r = 0; r < BR; ++r) acc[r] = T(0);
+  for (int r = 0; r < BR; ++r) {
+    acc[r] = T(0);
+    yo[r] = T(0);
+  }
+  if (accumulate && row < n_rows && lane == 0)
+#pragma unroll
+    for (int r = 0; r < BR; ++r) yo[r] = y[int64_t(row) * BR + r];
   if (row < n_rows) row_accumulate<T, BR, BC>(rp[row], rp[row + 1], lane, G, col, val, nnz, x, acc);
   group_reduce<T, BR>(acc, G);
   if (row < n_rows && lane == 0) {
 #pragma unroll
-    for (int r = 0; r < BR; ++r) {
-      if (accumulate)
-        y[int64_t(row) * BR + r] += acc[r];
-      else
-        y[int64_t(row) * BR + r] = acc[r];
-    }
+    for (int r = 0; r < BR; ++r) y[int64_t(row) * BR + r] = accumulate ? yo[r] + acc[r] : acc[r];
   }
 }
 
