@@ -295,6 +295,12 @@ def _cube64(E, torch, args, stream):
         ms, info = _timed_solves(E, torch, h, b, x, stream, args.steps, args.warmup, prec)
         out[key] = {"ms_per_solve": ms, "value": p.n_free_dofs / (ms / 1e3), "unit": "dofs/s",
                     "iterations": info["iterations"], "rel_res_true": info["rel_res_true"]}
+        # the dominant kernel and the V-cycle aggregate of one profiled solve, as for the
+        # headline (the committed counter passes are the headline's: no traffic figure here)
+        roof, vagg, _ = _profiled(E, h, b, torch.zeros_like(b), 1, prec, stream)
+        out[key]["dominant"] = {k: roof[k] for k in ("kernel", "avg_launch_us", "achieved", "frac",
+                                                     "algorithmic_bytes_per_launch")}
+        out[key]["vcycle_aggregate"] = {"GBps": vagg["GBps"], "frac": vagg["frac"]}
     out["fp32_speedup_vs_fp64"] = out["fp64_vcycle"]["ms_per_solve"] / out["fp32_vcycle"]["ms_per_solve"]
     st, lv = _levels(E, h)
     out.update({"levels": st["n_levels"], "level_vertices": st["n"], "oc": round(st["oc"], 4),
