@@ -4,9 +4,11 @@ own hierarchy (caps 6 / 4 / 3, sigma 20, coarsening to < 500 dofs, dense tail <=
 fused into one block-diagonal hierarchy with V-cycles ending at 4096-dof tails it builds,
 autotuned, solved with the FP32 V-cycle in FP64 CG (section "res" per system).
 
-The oracle cannot set these up in reasonable time, so this checks what holds at any size: every
-system reaches a true relative residual of 1e-8 recomputed on the host, with the iteration count
-of its own single-system solve (within one) and the same solution up to the solver's accuracy."""
+This checks what holds at any size for the FP32 V-cycle the bench times: every system reaches a
+true relative residual of 1e-8 recomputed on the host, with the iteration count of its own
+single-system solve (within one) and the same solution up to the solver's accuracy.  The same
+workload with the FP64 V-cycle is compared with the oracle's hierarchies and solves in
+test_gpu_multi16_oracle.py."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
